@@ -1,0 +1,223 @@
+/*
+ * bsdmrg -- block-sparse two-site DMRG effective-Hamiltonian engine for
+ * AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * Method: Levy, Solomonik, Clark, "Distributed-Memory DMRG via Sparse and
+ * Dense Parallel Tensor Contractions".  The library applies the two-site form
+ * of the implicit projected Hamiltonian of Sec. II-C (environments, MPO
+ * sites, Fig. 1d) to tensors stored as lists of quantum-number blocks
+ * (Sec. II-D; the "list" format of Sec. IV-A), finds its lowest eigenpair
+ * with the Davidson routine of Alg. 1, splits the two-site tensor with a
+ * truncated per-charge SVD (Sec. II-C, Sec. IV-A) and extends environments.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Leg: sectors with integer charge tuples (1 component for U(1), 2 for
+ *   U(1)xU(1)), strictly ascending in lexicographic order, each of dimension
+ *   >= 1.  The charge of a bond is the total charge to its left.
+ * Tensor: one sign per leg; a block (tuple of sector indices) is allowed iff
+ *   sum_i sign_i * charge_i == 0 componentwise.  Signs used here:
+ *     psi / out / theta (a, s1, s2, c)  (+1, +1, +1, -1)
+ *     L environment     (a', w, a)      (-1, +1, +1)   bra, channel, ket
+ *     R environment     (c', w, c)      (-1, +1, +1)   bra, channel, ket
+ *     MPO site W        (w, s', s, w')  (+1, +1, -1, -1) bra before ket
+ *     MPS site          (a, s, b)       (+1, +1, -1)
+ * Canonical layout (byte-exact contract): the allowed blocks in
+ *   lexicographic order of their sector-index tuples; each block dense and
+ *   row-major over its legs; offsets[0] = 0,
+ *   offsets[b+1] = offsets[b] + round_up(size_b, 32) elements; padding is 0.
+ * Physical legs must have sectors of dimension 1 (spin-1/2, electrons).
+ * Memory: every device buffer (operands, outputs, workspace) is allocated and
+ *   owned by the caller; the library owns only plan tables, which
+ *   bsdmrg_plan_destroy frees.  Device pointers are FP64 in canonical layout.
+ * Batches: a plan over n_probs problems addresses concatenated operand
+ *   buffers; bsdmrg_plan_offsets gives each problem's element offsets.
+ * Errors: every call returns a status; no exception crosses the ABI;
+ *   bsdmrg_last_error() gives a thread-local message for the last failure.
+ * Streams: work is enqueued on the given stream (0 = default).  Calls are
+ *   asynchronous unless stated; a plan is immutable after creation and may be
+ *   used on several streams if each call has its own workspace.
+ */
+#ifndef BSDMRG_H
+#define BSDMRG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bsdmrg_status;
+#define BSDMRG_OK 0
+#define BSDMRG_EINVAL 1    /* bad pointer, size, option or shape            */
+#define BSDMRG_EQN 2       /* unsorted leg, charge rule violated            */
+#define BSDMRG_ENOMEM 3    /* host or device allocation failed              */
+#define BSDMRG_EHIP 4      /* HIP runtime error (text in last_error)        */
+#define BSDMRG_ESOLVER 5   /* eigensolver or SVD failure                    */
+#define BSDMRG_ECAPACITY 6 /* caller buffer too small; required size returned */
+
+#define BSDMRG_F64 0        /* all arithmetic in FP64 (MFMA f64)             */
+#define BSDMRG_F32 1        /* block GEMMs in FP32 MFMA, FP32 intermediates  */
+#define BSDMRG_F32_REFINE 2 /* eigensolve: FP32 products then FP64 refinement */
+
+#define BSDMRG_PLAN_HOST_ONLY 1 /* plan flag: build tables, no device upload */
+
+typedef struct {
+  int32_t n_sectors;
+  int32_t n_charges;      /* components per charge (1 or 2)                 */
+  const int32_t* charges; /* [n_sectors * n_charges], host memory           */
+  const int64_t* dims;    /* [n_sectors], host memory                       */
+} bsdmrg_leg;
+
+/* Canonical block table of a tensor (pure host; defined in the header
+ * comment).  legs[order], signs[order].  On success *n_blocks is set,
+ * block_sectors[n_blocks * order] and offsets[n_blocks + 1] are written.
+ * If capacity < n_blocks returns BSDMRG_ECAPACITY with *n_blocks set and the
+ * arrays untouched.  Errors: EINVAL (null pointers, order < 1 or > 8),
+ * EQN (leg not strictly ascending or a dimension < 1). */
+bsdmrg_status bsdmrg_layout(const bsdmrg_leg* legs, int32_t order, const int32_t* signs,
+                            int64_t* n_blocks, int32_t* block_sectors, int64_t* offsets,
+                            int64_t capacity);
+
+/* One isolated two-site problem (Sec. II-C, Fig. 1c-d):
+ *   out(a',s1',s2',c') = sum L(a',w,a) W1(w,s1',s1,w') W2(w',s2',s2,w'')
+ *                            R(c',w'',c) psi(a,s1,s2,c)
+ * L has legs (a, wl, a), W1 (wl, s1, s1, wm), W2 (wm, s2, s2, wr),
+ * R (c, wr, c), psi (a, s1, s2, c).  w1_host / w2_host hold the MPO sites in
+ * canonical layout (host memory, read during bsdmrg_plan only): entries that
+ * are zero there are structural zeros of the plan, and W blocks that are
+ * entirely zero are absent.  Values passed later on the device must keep
+ * that pattern. */
+typedef struct {
+  bsdmrg_leg a, s1, s2, c;
+  bsdmrg_leg wl, wm, wr;
+  const double* w1_host;
+  const double* w2_host;
+} bsdmrg_problem;
+
+typedef struct bsdmrg_plan_s* bsdmrg_plan_t;
+
+/* Build the contraction plan (Alg. 2 generalised to the four-operand
+ * product): block pairs of every stage, GEMM task and tile tables ordered
+ * longest first, MPO-mixing term lists, useful-flop counts, and (unless
+ * flags has BSDMRG_PLAN_HOST_ONLY) their device copies.  n_probs >= 1
+ * problems are planned as one batch: every stage of all problems runs in one
+ * launch.  Errors: EINVAL, EQN, ENOMEM, EHIP. */
+bsdmrg_status bsdmrg_plan(const bsdmrg_problem* probs, int32_t n_probs, int32_t flags,
+                          bsdmrg_plan_t* out);
+
+typedef struct {
+  int64_t n_probs;
+  int64_t psi_elems;   /* total elements of the concatenated psi buffers   */
+  int64_t L_elems, R_elems, W1_elems, W2_elems;
+  int64_t t1_elems, t2_elems;           /* intermediates of one product    */
+  int64_t apply_workspace_bytes;        /* workspace of bsdmrg_heff_apply  */
+  int64_t backward_workspace_bytes;     /* workspace of bsdmrg_heff_backward */
+  double flops_s1, flops_s2, flops_s3;  /* per product, all problems       */
+  int64_t n_s1_tasks, n_s3_tasks, n_s1_tiles, n_s3_tiles;
+  int64_t n_mix_terms, n_coefs;
+} bsdmrg_plan_info;
+
+bsdmrg_status bsdmrg_plan_query(bsdmrg_plan_t plan, bsdmrg_plan_info* info);
+
+/* Element offsets of problem p inside the concatenated buffers:
+ * offs[0..4] = psi, L, R, W1, W2. */
+bsdmrg_status bsdmrg_plan_offsets(bsdmrg_plan_t plan, int32_t p, int64_t* offs);
+
+/* Copy the S1 / S3 GEMM task tables of problem-batch order to the host (for
+ * tests): per task {M, N, K_total, n_segments}; capacity in tasks. */
+bsdmrg_status bsdmrg_plan_tasks(bsdmrg_plan_t plan, int32_t stage, int64_t* tasks4,
+                                int64_t capacity, int64_t* n_tasks);
+
+bsdmrg_status bsdmrg_plan_destroy(bsdmrg_plan_t plan);
+
+/* out = H_eff psi for every problem of the plan (Sec. II-C two-site form).
+ * precision BSDMRG_F64 or BSDMRG_F32 (GEMM stages in FP32 MFMA with FP32
+ * accumulation; psi, out and operands stay FP64 in memory).  Device
+ * pointers: L, W1, W2, R, psi [input], out [output, same layout as psi; the
+ * padding of out is not written], workspace [apply_workspace_bytes].
+ * out must not alias psi.  Errors: EINVAL, EHIP. */
+bsdmrg_status bsdmrg_heff_apply(bsdmrg_plan_t plan, int32_t precision, const double* L,
+                                const double* W1, const double* W2, const double* R,
+                                const double* psi, double* out, void* workspace,
+                                int64_t workspace_bytes, hipStream_t stream);
+
+/* Davidson options (Alg. 1; readings of the silent points in the docs of
+ * bsdmrg_eigensolve). */
+typedef struct {
+  int32_t max_iter;        /* basis size (number of products) of a phase     */
+  int32_t precision;       /* BSDMRG_F64 or BSDMRG_F32_REFINE               */
+  int32_t refine_max_iter; /* FP64 products after the FP32 phase (>= 1)      */
+  int32_t fixed_iters;     /* 1: exactly max_iter products, no host sync     */
+  int32_t use_graph;       /* 1 with fixed_iters: replay a captured hipGraph */
+  int32_t reserved;
+  uint64_t seed;           /* restart stream seed                            */
+  double tol;              /* stop when ||q||_2 <= tol (FP64 phase)          */
+  double tol_f32;          /* FP32 phase stops at ||q||_2 <= tol_f32         */
+  double restart_rtol;     /* restart if ||q_after|| < rtol * ||q_before||   */
+} bsdmrg_eig_opts;
+
+typedef struct {
+  int32_t iters;      /* FP64 products                                      */
+  int32_t iters_f32;  /* FP32 products                                      */
+  int32_t restarts;
+  int32_t converged;
+  double residual;    /* final ||q||_2                                       */
+} bsdmrg_eig_stats;
+
+/* Workspace of bsdmrg_eigensolve for these options. */
+bsdmrg_status bsdmrg_eig_workspace(bsdmrg_plan_t plan, const bsdmrg_eig_opts* opts,
+                                   int64_t* bytes);
+
+/* Lowest eigenpair of H_eff per problem with the Davidson routine of Alg. 1:
+ * no preconditioning; the start vector and every new basis vector are
+ * normalised; at step i the (i+1)x(i+1) projected matrix m_ij = (v^A_j)^T v_i
+ * is diagonalised (cyclic Jacobi, FP64); x = sum s_j v_j, q = sum s_j v^A_j -
+ * lambda x; stop when ||q|| <= tol; q is orthogonalised against the basis
+ * twice (classical Gram-Schmidt applied twice); if ||q|| drops below
+ * restart_rtol times its value before orthogonalisation, q is replaced by a
+ * seeded Gaussian vector (SplitMix64 + Box-Muller, key from seed, step,
+ * attempt; at most 3 attempts).  All orthogonalisation, Rayleigh quotients
+ * and the energy are FP64; with BSDMRG_F32_REFINE the products of the first
+ * phase run in FP32 and the second phase restarts from x with FP64 products.
+ * psi_inout: start vectors in, normalised eigenvectors out (device, FP64).
+ * energy[n_probs], stats[n_probs]: host arrays.  A batch (n_probs > 1)
+ * requires fixed_iters = 1.  The call synchronises the stream before
+ * returning.  Errors: EINVAL, EHIP, ESOLVER. */
+bsdmrg_status bsdmrg_eigensolve(bsdmrg_plan_t plan, const double* L, const double* W1,
+                                const double* W2, const double* R, double* psi_inout,
+                                const bsdmrg_eig_opts* opts, double* energy,
+                                bsdmrg_eig_stats* stats, void* workspace,
+                                int64_t workspace_bytes, hipStream_t stream);
+
+/* Adjoint of E = psi^T H_eff psi (real; E is linear in L, W1, W2, R):
+ * writes g_E * dE/dX into every non-NULL output (same layout as X):
+ *   d_psi = g_E (H_eff + H_eff^T) psi, d_L, d_W1, d_W2, d_R.
+ * Outputs are overwritten, not accumulated; padding is written as 0.
+ * FP64 only.  workspace: backward_workspace_bytes.  Errors: EINVAL, EHIP. */
+bsdmrg_status bsdmrg_heff_backward(bsdmrg_plan_t plan, const double* L, const double* W1,
+                                   const double* W2, const double* R, const double* psi,
+                                   double g_E, double* d_psi, double* d_L, double* d_W1,
+                                   double* d_W2, double* d_R, void* workspace,
+                                   int64_t workspace_bytes, hipStream_t stream);
+
+/* Measurement helper: runs each stage of one product `reps` times on
+ * `stream`, bracketed by HIP events recorded on that stream, and writes the
+ * average duration in milliseconds per launch to ms[4] = {WW coefficients,
+ * S1 grouped GEMM, S2 MPO mixing, S3 grouped GEMM}.  Same arguments and
+ * results as bsdmrg_heff_apply (out holds the product afterwards).
+ * Synchronises the stream.  Errors: EINVAL, EHIP. */
+bsdmrg_status bsdmrg_stage_timing(bsdmrg_plan_t plan, int32_t precision, const double* L,
+                                  const double* W1, const double* W2, const double* R,
+                                  const double* psi, double* out, void* workspace,
+                                  int64_t workspace_bytes, int32_t reps, float* ms,
+                                  hipStream_t stream);
+
+const char* bsdmrg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSDMRG_H */

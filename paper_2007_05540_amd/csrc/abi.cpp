@@ -1,0 +1,561 @@
+// C ABI of the bsdmrg library: plans, the two-site product, the Davidson
+// eigensolver.  No exception crosses this file's extern "C" functions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+
+#include "bsdmrg_internal.h"
+#include "kernels.h"
+
+bsdmrg_plan_s* build_plan(const bsdmrg_problem* probs, int n_probs);
+namespace bsd {
+const char* last_error_cstr();
+void destroy_backward(bsdmrg_plan_s* P);
+void destroy_graph(bsdmrg_plan_s* P);
+}  // namespace bsd
+
+using namespace bsd;
+
+#define HIPCHK(x)                                                                              \
+  do {                                                                                         \
+    hipError_t e_ = (x);                                                                       \
+    if (e_ != hipSuccess) throw Error{BSDMRG_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+template <class F>
+static bsdmrg_status guarded(F&& f) {
+  try {
+    f();
+    return BSDMRG_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return BSDMRG_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return BSDMRG_EINVAL;
+  } catch (...) {
+    set_error("unknown error");
+    return BSDMRG_EINVAL;
+  }
+}
+
+static inline size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Sub-allocator over a caller workspace.
+struct Carve {
+  char* base;
+  size_t used = 0, cap;
+  Carve(void* p, size_t c) : base((char*)p), cap(c) {}
+  template <class T>
+  T* take(size_t n) {
+    T* p = (T*)(base ? base + used : nullptr);
+    used += al256(n * sizeof(T));
+    return p;
+  }
+};
+
+struct ApplyWS {
+  double* T1;
+  double* T2;
+  double* coef;
+  float* L32;
+  float* R32;
+};
+
+static ApplyWS carve_apply(const bsdmrg_plan_s* P, Carve& c) {
+  ApplyWS w;
+  w.T1 = c.take<double>(P->t1_elems);
+  w.T2 = c.take<double>(P->t2_elems);
+  w.coef = c.take<double>(std::max<int64_t>(P->n_coefs, 1));
+  w.L32 = c.take<float>(P->L_elems);
+  w.R32 = c.take<float>(P->R_elems);
+  return w;
+}
+
+static size_t apply_bytes(const bsdmrg_plan_s* P) {
+  Carve c(nullptr, 0);
+  carve_apply(P, c);
+  return c.used;
+}
+
+static void upload(bsdmrg_plan_s* P) {
+  struct Part {
+    const void* src;
+    size_t bytes;
+    void** dst;
+  };
+  std::vector<Part> parts = {
+      {P->s1.tasks.data(), P->s1.tasks.size() * sizeof(GemmTask), (void**)&P->s1.d_tasks},
+      {P->s1.segs.data(), P->s1.segs.size() * sizeof(GemmSeg), (void**)&P->s1.d_segs},
+      {P->s1.tiles.data(), P->s1.tiles.size() * sizeof(GemmTile), (void**)&P->s1.d_tiles},
+      {P->s3.tasks.data(), P->s3.tasks.size() * sizeof(GemmTask), (void**)&P->s3.d_tasks},
+      {P->s3.segs.data(), P->s3.segs.size() * sizeof(GemmSeg), (void**)&P->s3.d_segs},
+      {P->s3.tiles.data(), P->s3.tiles.size() * sizeof(GemmTile), (void**)&P->s3.d_tiles},
+      {P->mix_tasks.data(), P->mix_tasks.size() * sizeof(MixTask), (void**)&P->d_mix_tasks},
+      {P->mix_terms.data(), P->mix_terms.size() * sizeof(MixTerm), (void**)&P->d_mix_terms},
+      {P->mix_items.data(), P->mix_items.size() * sizeof(MixItem), (void**)&P->d_mix_items},
+      {P->coef_ptr.data(), P->coef_ptr.size() * sizeof(int32_t), (void**)&P->d_coef_ptr},
+      {P->coef_e1.data(), P->coef_e1.size() * sizeof(int64_t), (void**)&P->d_coef_e1},
+      {P->coef_e2.data(), P->coef_e2.size() * sizeof(int64_t), (void**)&P->d_coef_e2},
+      {P->chunks.data(), P->chunks.size() * sizeof(Chunk), (void**)&P->d_chunks},
+      {P->dav_probs.data(), P->dav_probs.size() * sizeof(DavProb), (void**)&P->d_dav_probs},
+      {P->blk_off.data(), P->blk_off.size() * sizeof(int64_t), (void**)&P->d_blk_off},
+      {P->blk_ptr.data(), P->blk_ptr.size() * sizeof(int32_t), (void**)&P->d_blk_ptr},
+  };
+  size_t total = 0;
+  for (auto& p : parts) total += al256(std::max<size_t>(p.bytes, 1));
+  HIPCHK(hipMalloc(&P->d_blob, total));
+  std::vector<char> host(total, 0);
+  size_t off = 0;
+  for (auto& p : parts) {
+    if (p.bytes) std::memcpy(host.data() + off, p.src, p.bytes);
+    *p.dst = (char*)P->d_blob + off;
+    off += al256(std::max<size_t>(p.bytes, 1));
+  }
+  HIPCHK(hipMemcpy(P->d_blob, host.data(), total, hipMemcpyHostToDevice));
+  P->on_device = true;
+}
+
+static void check_ws(void* ws, int64_t have, size_t need) {
+  if (need > 0 && !ws) throw Error{BSDMRG_EINVAL, "workspace pointer is NULL"};
+  if ((size_t)have < need)
+    throw Error{BSDMRG_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes"};
+}
+
+static void need_device(const bsdmrg_plan_s* P) {
+  if (!P) throw Error{BSDMRG_EINVAL, "plan is NULL"};
+  if (!P->on_device) throw Error{BSDMRG_EINVAL, "plan was built host-only"};
+}
+
+// Operand preparation: WW coefficients (and FP32 copies of L, R).
+static void prepare(const bsdmrg_plan_s* P, int prec, const double* L, const double* W1,
+                    const double* W2, const double* R, const ApplyWS& w, hipStream_t s) {
+  HIPCHK(launch_coef(P, W1, W2, w.coef, s));
+  if (prec == BSDMRG_F32) {
+    HIPCHK(launch_cast(P->L_elems, L, w.L32, s));
+    HIPCHK(launch_cast(P->R_elems, R, w.R32, s));
+  }
+}
+
+static void matvec(const bsdmrg_plan_s* P, int prec, const double* L, const double* R,
+                   const ApplyWS& w, const double* psi, double* out, hipStream_t s) {
+  if (prec == BSDMRG_F64) {
+    HIPCHK(launch_s1_f64(P, L, psi, w.T1, s));
+    HIPCHK(launch_mix_f64(P, w.coef, w.T1, w.T2, s));
+    HIPCHK(launch_s3_f64(P, w.T2, R, out, s));
+  } else {
+    float* T1 = (float*)w.T1;
+    float* T2 = (float*)w.T2;
+    HIPCHK(launch_s1_f32(P, w.L32, psi, T1, s));
+    HIPCHK(launch_mix_f32(P, w.coef, T1, T2, s));
+    HIPCHK(launch_s3_f32(P, T2, w.R32, out, s));
+  }
+}
+
+// ------------------------------------------------------------ Davidson ------
+struct EigWS {
+  ApplyWS a;
+  DavBufs d;
+};
+
+static int basis_size(const bsdmrg_eig_opts* o) {
+  int B = o->max_iter;
+  if (o->precision == BSDMRG_F32_REFINE) B = std::max(B, o->refine_max_iter);
+  return B;
+}
+
+static EigWS carve_eig(const bsdmrg_plan_s* P, const bsdmrg_eig_opts* o, Carve& c) {
+  EigWS w;
+  w.a = carve_apply(P, c);
+  const int B = basis_size(o);
+  const int64_t n = P->psi_elems, nch = (int64_t)P->chunks.size(), np = (int64_t)P->probs.size();
+  DavBufs& d = w.d;
+  d.n = n;
+  d.B = B;
+  d.V = c.take<double>((size_t)B * n);
+  d.VA = c.take<double>((size_t)B * n);
+  d.x = c.take<double>(n);
+  d.q = c.take<double>(n);
+  d.part_a = c.take<double>((size_t)(B + 1) * nch);
+  d.part_b = c.take<double>((size_t)(B + 1) * nch);
+  d.part_n0 = c.take<double>(nch);
+  d.part_n1 = c.take<double>(nch);
+  d.M = c.take<double>((size_t)np * B * B);
+  d.svec = c.take<double>((size_t)np * B);
+  d.lam = c.take<double>(np);
+  d.scale = c.take<double>(np);
+  // restarts and status share one region of np + 1 doubles (zero-filled)
+  d.restarts = (int32_t*)c.take<double>(np + 1);
+  d.status = d.restarts + np;
+  return w;
+}
+
+static void validate_opts(const bsdmrg_plan_s* P, const bsdmrg_eig_opts* o) {
+  if (!o) throw Error{BSDMRG_EINVAL, "eig opts is NULL"};
+  if (o->max_iter < 1 || o->max_iter > 64) throw Error{BSDMRG_EINVAL, "max_iter must be in 1..64"};
+  if (o->precision != BSDMRG_F64 && o->precision != BSDMRG_F32_REFINE)
+    throw Error{BSDMRG_EINVAL, "eigensolve precision must be F64 or F32_REFINE"};
+  if (o->precision == BSDMRG_F32_REFINE && (o->refine_max_iter < 1 || o->refine_max_iter > 64))
+    throw Error{BSDMRG_EINVAL, "refine_max_iter must be in 1..64"};
+  if (P->probs.size() > 1 && !o->fixed_iters)
+    throw Error{BSDMRG_EINVAL, "a batch plan requires fixed_iters = 1"};
+  if (!(o->restart_rtol >= 0.0) || std::isnan(o->tol) || std::isnan(o->tol_f32))
+    throw Error{BSDMRG_EINVAL, "bad tolerances"};
+}
+
+struct GraphKey {
+  const void* ptrs[6];
+  bsdmrg_eig_opts o;
+  bool operator==(const GraphKey& k) const {
+    return std::memcmp(ptrs, k.ptrs, sizeof(ptrs)) == 0 && std::memcmp(&o, &k.o, sizeof(o)) == 0;
+  }
+};
+struct GraphCache {
+  GraphKey key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace bsd {
+void destroy_graph(bsdmrg_plan_s* P) {
+  if (!P->graph) return;
+  if (P->graph->exec) (void)hipGraphExecDestroy(P->graph->exec);
+  if (P->graph->graph) (void)hipGraphDestroy(P->graph->graph);
+  delete P->graph;
+  P->graph = nullptr;
+}
+}  // namespace bsd
+
+// Enqueue the whole solve.  In tol mode the host reads ||q|| after every
+// Ritz step (needs a sync); in fixed mode nothing is read back here.
+static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double* W1, const double* W2,
+                          const double* R, double* psi, const bsdmrg_eig_opts* o, EigWS& w,
+                          hipStream_t s, std::vector<int>& it64, std::vector<int>& it32,
+                          std::vector<double>& res, std::vector<int>& conv) {
+  const DavBufs& d = w.d;
+  const int64_t n = d.n;
+  const int np = (int)P->probs.size();
+  HIPCHK(launch_coef(P, W1, W2, w.a.coef, s));
+  const bool mixed = o->precision == BSDMRG_F32_REFINE;
+  if (mixed) {
+    HIPCHK(launch_cast(P->L_elems, L, w.a.L32, s));
+    HIPCHK(launch_cast(P->R_elems, R, w.a.R32, s));
+  }
+  HIPCHK(dav_fill_zero(d.VA, (int64_t)d.B * n, s));
+  HIPCHK(dav_fill_zero((double*)d.restarts, np + 1, s));
+  HIPCHK(dav_dots(P, 1, psi, 0, psi, d.part_a, s));
+  HIPCHK(dav_normalize(P, d.part_a, psi, d.V, s));
+  struct Phase {
+    int prec, maxit;
+    double tol;
+  };
+  std::vector<Phase> phases;
+  if (mixed) {
+    phases.push_back({BSDMRG_F32, o->max_iter, o->tol_f32});
+    phases.push_back({BSDMRG_F64, o->refine_max_iter, o->tol});
+  } else {
+    phases.push_back({BSDMRG_F64, o->max_iter, o->tol});
+  }
+  std::vector<double> hpart(P->chunks.size());
+  int global_it = 0;
+  for (size_t ph = 0; ph < phases.size(); ++ph) {
+    const Phase& f = phases[ph];
+    if (ph > 0) {
+      HIPCHK(dav_dots(P, 1, d.x, 0, d.x, d.part_a, s));
+      HIPCHK(dav_normalize(P, d.part_a, d.x, d.V, s));
+    }
+    matvec(P, f.prec, L, R, w.a, d.V, d.VA, s);
+    for (int i = 0; i < f.maxit; ++i, ++global_it) {
+      HIPCHK(dav_dots(P, i + 1, d.VA, n, d.V + (int64_t)i * n, d.part_a, s));
+      HIPCHK(dav_gram_eig(P, d, i, s));
+      HIPCHK(dav_ritz(P, d, i, s));
+      for (int p = 0; p < np; ++p) (f.prec == BSDMRG_F64 ? it64 : it32)[p] = i + 1;
+      if (!o->fixed_iters) {
+        HIPCHK(hipMemcpyAsync(hpart.data(), d.part_n0, hpart.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        bool all = true;
+        for (int p = 0; p < np; ++p) {
+          const DavProb& pr = P->dav_probs[p];
+          double r = 0.0;
+          for (int c = 0; c < pr.nchunk; ++c) r += hpart[pr.chunk0 + c];
+          res[p] = std::sqrt(r);
+          conv[p] = res[p] <= f.tol;
+          all = all && conv[p];
+        }
+        if (all) break;
+      }
+      if (i == f.maxit - 1) break;
+      HIPCHK(dav_dots(P, i + 1, d.V, n, d.q, d.part_a, s));
+      HIPCHK(dav_update(P, d, i + 1, d.part_a, d.part_b, 1, s));
+      HIPCHK(dav_update(P, d, i + 1, d.part_b, d.part_n1, 2, s));
+      HIPCHK(dav_finalize(P, d, i, o->seed, o->restart_rtol, P->d_blk_off, P->d_blk_ptr, s));
+      HIPCHK(dav_scale_into(P, d, d.V + (int64_t)(i + 1) * n, s));
+      matvec(P, f.prec, L, R, w.a, d.V + (int64_t)(i + 1) * n, d.VA + (int64_t)(i + 1) * n, s);
+    }
+  }
+  HIPCHK(dav_dots(P, 1, d.x, 0, d.x, d.part_a, s));
+  HIPCHK(dav_normalize(P, d.part_a, d.x, psi, s));
+  (void)global_it;
+}
+
+extern "C" {
+
+bsdmrg_status bsdmrg_layout(const bsdmrg_leg* legs, int32_t order, const int32_t* signs,
+                            int64_t* n_blocks, int32_t* block_sectors, int64_t* offsets,
+                            int64_t capacity) {
+  return guarded([&] {
+    if (!legs || !signs || !n_blocks || order < 1 || order > kMaxOrder)
+      throw Error{BSDMRG_EINVAL, "layout: bad arguments"};
+    std::vector<Leg> ls;
+    for (int i = 0; i < order; ++i) ls.push_back(leg_from(legs[i]));
+    std::vector<const Leg*> lp;
+    for (auto& l : ls) lp.push_back(&l);
+    Layout L = make_layout(lp, signs);
+    *n_blocks = (int64_t)L.keys.size();
+    if (capacity < (int64_t)L.keys.size()) throw Error{BSDMRG_ECAPACITY, "layout: capacity too small"};
+    if (!block_sectors || !offsets) throw Error{BSDMRG_EINVAL, "layout: output arrays are NULL"};
+    for (size_t b = 0; b < L.keys.size(); ++b)
+      for (int i = 0; i < order; ++i) block_sectors[b * order + i] = L.keys[b][i];
+    for (size_t b = 0; b <= L.keys.size(); ++b) offsets[b] = L.offs[b];
+  });
+}
+
+bsdmrg_status bsdmrg_plan(const bsdmrg_problem* probs, int32_t n_probs, int32_t flags,
+                          bsdmrg_plan_t* out) {
+  return guarded([&] {
+    if (!probs || n_probs < 1 || !out) throw Error{BSDMRG_EINVAL, "plan: bad arguments"};
+    *out = nullptr;
+    bsdmrg_plan_s* P = build_plan(probs, n_probs);
+    if (!(flags & BSDMRG_PLAN_HOST_ONLY)) {
+      try {
+        upload(P);
+      } catch (...) {
+        if (P->d_blob) (void)hipFree(P->d_blob);
+        delete P;
+        throw;
+      }
+    }
+    *out = P;
+  });
+}
+
+bsdmrg_status bsdmrg_plan_query(bsdmrg_plan_t P, bsdmrg_plan_info* info) {
+  return guarded([&] {
+    if (!P || !info) throw Error{BSDMRG_EINVAL, "plan_query: NULL argument"};
+    info->n_probs = (int64_t)P->probs.size();
+    info->psi_elems = P->psi_elems;
+    info->L_elems = P->L_elems;
+    info->R_elems = P->R_elems;
+    info->W1_elems = P->W1_elems;
+    info->W2_elems = P->W2_elems;
+    info->t1_elems = P->t1_elems;
+    info->t2_elems = P->t2_elems;
+    info->apply_workspace_bytes = (int64_t)apply_bytes(P);
+    info->backward_workspace_bytes = (int64_t)(al256(P->t1_elems * 8) * 2 + al256(P->t2_elems * 8) * 2 +
+                                               apply_bytes(P) + al256(std::max<int64_t>(P->n_coefs, 1) * 8) +
+                                               (1 << 20));
+    info->flops_s1 = P->s1.flops;
+    info->flops_s2 = P->flops_s2;
+    info->flops_s3 = P->s3.flops;
+    info->n_s1_tasks = (int64_t)P->s1.tasks.size();
+    info->n_s3_tasks = (int64_t)P->s3.tasks.size();
+    info->n_s1_tiles = (int64_t)P->s1.tiles.size();
+    info->n_s3_tiles = (int64_t)P->s3.tiles.size();
+    info->n_mix_terms = (int64_t)P->mix_terms.size();
+    info->n_coefs = P->n_coefs;
+  });
+}
+
+bsdmrg_status bsdmrg_plan_offsets(bsdmrg_plan_t P, int32_t p, int64_t* offs) {
+  return guarded([&] {
+    if (!P || !offs || p < 0 || p >= (int)P->probs.size()) throw Error{BSDMRG_EINVAL, "plan_offsets: bad arguments"};
+    const ProblemPlan& q = P->probs[p];
+    offs[0] = q.psi_base;
+    offs[1] = q.L_base;
+    offs[2] = q.R_base;
+    offs[3] = q.W1_base;
+    offs[4] = q.W2_base;
+  });
+}
+
+bsdmrg_status bsdmrg_plan_tasks(bsdmrg_plan_t P, int32_t stage, int64_t* tasks4, int64_t capacity,
+                                int64_t* n_tasks) {
+  return guarded([&] {
+    if (!P || !n_tasks || (stage != 1 && stage != 3)) throw Error{BSDMRG_EINVAL, "plan_tasks: bad arguments"};
+    const Stage& st = stage == 1 ? P->s1 : P->s3;
+    *n_tasks = (int64_t)st.tasks.size();
+    if (capacity < *n_tasks) throw Error{BSDMRG_ECAPACITY, "plan_tasks: capacity too small"};
+    if (!tasks4) throw Error{BSDMRG_EINVAL, "plan_tasks: NULL output"};
+    for (size_t t = 0; t < st.tasks.size(); ++t) {
+      tasks4[4 * t + 0] = st.tasks[t].M;
+      tasks4[4 * t + 1] = st.tasks[t].N;
+      tasks4[4 * t + 2] = st.tasks[t].ksum;
+      tasks4[4 * t + 3] = st.tasks[t].nseg;
+    }
+  });
+}
+
+bsdmrg_status bsdmrg_plan_destroy(bsdmrg_plan_t P) {
+  return guarded([&] {
+    if (!P) return;
+    destroy_graph(P);
+    destroy_backward(P);
+    if (P->d_blob) (void)hipFree(P->d_blob);
+    delete P;
+  });
+}
+
+bsdmrg_status bsdmrg_heff_apply(bsdmrg_plan_t P, int32_t precision, const double* L, const double* W1,
+                                const double* W2, const double* R, const double* psi, double* out,
+                                void* workspace, int64_t workspace_bytes, hipStream_t stream) {
+  return guarded([&] {
+    need_device(P);
+    if (precision != BSDMRG_F64 && precision != BSDMRG_F32)
+      throw Error{BSDMRG_EINVAL, "heff_apply: precision must be F64 or F32"};
+    if (!L || !W1 || !W2 || !R || !psi || !out) throw Error{BSDMRG_EINVAL, "heff_apply: NULL operand"};
+    if (psi == out) throw Error{BSDMRG_EINVAL, "heff_apply: out must not alias psi"};
+    const size_t need = apply_bytes(P);
+    check_ws(workspace, workspace_bytes, need);
+    Carve c(workspace, (size_t)workspace_bytes);
+    ApplyWS w = carve_apply(P, c);
+    prepare(P, precision, L, W1, W2, R, w, stream);
+    matvec(P, precision, L, R, w, psi, out, stream);
+  });
+}
+
+bsdmrg_status bsdmrg_eig_workspace(bsdmrg_plan_t P, const bsdmrg_eig_opts* o, int64_t* bytes) {
+  return guarded([&] {
+    if (!P || !bytes) throw Error{BSDMRG_EINVAL, "eig_workspace: NULL argument"};
+    validate_opts(P, o);
+    Carve c(nullptr, 0);
+    carve_eig(P, o, c);
+    *bytes = (int64_t)c.used;
+  });
+}
+
+bsdmrg_status bsdmrg_eigensolve(bsdmrg_plan_t P, const double* L, const double* W1, const double* W2,
+                                const double* R, double* psi, const bsdmrg_eig_opts* o, double* energy,
+                                bsdmrg_eig_stats* stats, void* workspace, int64_t workspace_bytes,
+                                hipStream_t s) {
+  return guarded([&] {
+    need_device(P);
+    validate_opts(P, o);
+    if (!L || !W1 || !W2 || !R || !psi || !energy || !stats)
+      throw Error{BSDMRG_EINVAL, "eigensolve: NULL argument"};
+    Carve c0(nullptr, 0);
+    carve_eig(P, o, c0);
+    check_ws(workspace, workspace_bytes, c0.used);
+    Carve c(workspace, (size_t)workspace_bytes);
+    EigWS w = carve_eig(P, o, c);
+    const int np = (int)P->probs.size();
+    std::vector<int> it64(np, 0), it32(np, 0), conv(np, 0);
+    std::vector<double> res(np, 0.0);
+    const bool graph = o->fixed_iters && o->use_graph && s != nullptr;
+    if (graph) {
+      GraphKey key{{L, W1, W2, R, psi, workspace}, *o};
+      if (!P->graph || !(P->graph->key == key)) {
+        destroy_graph(P);
+        auto* G = new GraphCache();
+        G->key = key;
+        P->graph = G;
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+          enqueue_solve(P, L, W1, W2, R, psi, o, w, s, it64, it32, res, conv);
+        } catch (...) {
+          hipGraph_t g;
+          (void)hipStreamEndCapture(s, &g);
+          if (g) (void)hipGraphDestroy(g);
+          destroy_graph(P);
+          throw;
+        }
+        HIPCHK(hipStreamEndCapture(s, &G->graph));
+        HIPCHK(hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0));
+      }
+      HIPCHK(hipGraphLaunch(P->graph->exec, s));
+      const int B = o->precision == BSDMRG_F32_REFINE ? o->refine_max_iter : o->max_iter;
+      for (int p = 0; p < np; ++p) {
+        it64[p] = B;
+        it32[p] = o->precision == BSDMRG_F32_REFINE ? o->max_iter : 0;
+      }
+    } else {
+      enqueue_solve(P, L, W1, W2, R, psi, o, w, s, it64, it32, res, conv);
+    }
+    std::vector<double> lam(np);
+    std::vector<int32_t> rs(2 * np);
+    std::vector<double> hpart(P->chunks.size());
+    HIPCHK(hipMemcpyAsync(lam.data(), w.d.lam, np * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rs.data(), w.d.restarts, 2 * np * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hpart.data(), w.d.part_n0, hpart.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    bool failed = false;
+    for (int p = 0; p < np; ++p) {
+      const DavProb& pr = P->dav_probs[p];
+      double r = 0.0;
+      for (int cc = 0; cc < pr.nchunk; ++cc) r += hpart[pr.chunk0 + cc];
+      energy[p] = lam[p];
+      stats[p].iters = it64[p];
+      stats[p].iters_f32 = it32[p];
+      stats[p].restarts = rs[p];
+      stats[p].residual = std::sqrt(r);
+      stats[p].converged = stats[p].residual <= o->tol;
+      failed = failed || rs[np + p] != 0;
+    }
+    if (failed) throw Error{BSDMRG_ESOLVER, "eigensolve: reorthogonalisation failed after 3 restarts"};
+  });
+}
+
+bsdmrg_status bsdmrg_stage_timing(bsdmrg_plan_t P, int32_t precision, const double* L, const double* W1,
+                                  const double* W2, const double* R, const double* psi, double* out,
+                                  void* workspace, int64_t workspace_bytes, int32_t reps, float* ms,
+                                  hipStream_t s) {
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bsdmrg_status st = guarded([&] {
+    need_device(P);
+    if (precision != BSDMRG_F64 && precision != BSDMRG_F32)
+      throw Error{BSDMRG_EINVAL, "stage_timing: precision must be F64 or F32"};
+    if (!L || !W1 || !W2 || !R || !psi || !out || !ms || reps < 1)
+      throw Error{BSDMRG_EINVAL, "stage_timing: bad arguments"};
+    check_ws(workspace, workspace_bytes, apply_bytes(P));
+    Carve c(workspace, (size_t)workspace_bytes);
+    ApplyWS w = carve_apply(P, c);
+    HIPCHK(hipEventCreate(&ev[0]));
+    HIPCHK(hipEventCreate(&ev[1]));
+    prepare(P, precision, L, W1, W2, R, w, s);
+    float* T1f = (float*)w.T1;
+    float* T2f = (float*)w.T2;
+    for (int stage = 0; stage < 4; ++stage) {
+      HIPCHK(hipEventRecord(ev[0], s));
+      for (int r = 0; r < reps; ++r) {
+        if (stage == 0) HIPCHK(launch_coef(P, W1, W2, w.coef, s));
+        if (precision == BSDMRG_F64) {
+          if (stage == 1) HIPCHK(launch_s1_f64(P, L, psi, w.T1, s));
+          if (stage == 2) HIPCHK(launch_mix_f64(P, w.coef, w.T1, w.T2, s));
+          if (stage == 3) HIPCHK(launch_s3_f64(P, w.T2, R, out, s));
+        } else {
+          if (stage == 1) HIPCHK(launch_s1_f32(P, w.L32, psi, T1f, s));
+          if (stage == 2) HIPCHK(launch_mix_f32(P, w.coef, T1f, T2f, s));
+          if (stage == 3) HIPCHK(launch_s3_f32(P, T2f, w.R32, out, s));
+        }
+      }
+      HIPCHK(hipEventRecord(ev[1], s));
+      HIPCHK(hipEventSynchronize(ev[1]));
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
+      ms[stage] = t / reps;
+    }
+  });
+  for (auto e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return st;
+}
+
+const char* bsdmrg_last_error(void) { return last_error_cstr(); }
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+// Internal data structures of the bsdmrg library (host and device).
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/bsdmrg.h"
+
+namespace bsd {
+
+constexpr int kAlign = 32;          // block alignment in elements (256 B in FP64)
+constexpr int kMaxOrder = 8;
+constexpr int kChunk = 4096;        // Davidson reduction chunk (elements)
+
+using Charge = std::array<int32_t, 2>;
+using Key = std::array<int32_t, kMaxOrder>;
+
+struct Leg {
+  int nc = 1;
+  std::vector<Charge> q;
+  std::vector<int64_t> d;
+  int size() const { return (int)q.size(); }
+  int find(const Charge& c) const;   // sector index with charge c, or -1
+};
+
+struct Layout {
+  int order = 0;
+  std::vector<Key> keys;
+  std::vector<int64_t> offs;         // n_blocks + 1
+  std::map<Key, int> index;
+  int lookup(const Key& k) const {
+    auto it = index.find(k);
+    return it == index.end() ? -1 : it->second;
+  }
+  int64_t elems() const { return offs.empty() ? 0 : offs.back(); }
+};
+
+// Error state (thread-local message) ----------------------------------------
+void set_error(const std::string& msg);
+struct Error {
+  bsdmrg_status code;
+  std::string msg;
+};
+
+Leg leg_from(const bsdmrg_leg& l);                          // throws Error
+Layout make_layout(const std::vector<const Leg*>& legs, const int32_t* signs);  // throws Error
+inline int64_t round_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// GEMM tables: C[M x N] (row-major, ldc) = sum over segments A_s[M x K_s] B_s
+// with A row-major (lda) and B row-major K x N (ldb) or, for the NT variant,
+// stored N x K row-major (ldb).  Offsets are element offsets into the base
+// pointers handed to the launch.
+struct GemmSeg {
+  int64_t a_off, b_off;
+  int32_t lda, ldb, K, pad;
+};
+struct GemmTask {
+  int64_t c_off;
+  int32_t ldc, M, N, seg0, nseg, ksum;
+};
+struct GemmTile {
+  int32_t task, m0, n0, pad;
+};
+
+// MPO mixing: dst rows x cols sub-matrix (row stride ld_dst) = sum over terms
+// coef[c] * src sub-matrix (row stride ld_src).
+struct MixTask {
+  int64_t dst_off;
+  int32_t ld_dst, rows, cols, term0, nterm, pad;
+};
+struct MixTerm {
+  int64_t src_off;
+  int32_t ld_src, coef;
+};
+struct MixItem {
+  int32_t task, row0, nrows, pad;
+};
+
+// Davidson reduction chunks (never straddle two problems).
+struct Chunk {
+  int64_t start;
+  int32_t len, prob;
+};
+
+// Per-problem descriptor of the Davidson kernels.
+struct DavProb {
+  int64_t base, len;      // element range of the problem inside a vector
+  int32_t chunk0, nchunk; // its reduction chunks
+};
+
+struct Stage {
+  std::vector<GemmTask> tasks;
+  std::vector<GemmSeg> segs;
+  std::vector<GemmTile> tiles;
+  GemmTask* d_tasks = nullptr;
+  GemmSeg* d_segs = nullptr;
+  GemmTile* d_tiles = nullptr;
+  double flops = 0.0;
+};
+
+struct ProblemPlan {
+  Leg a, s1, s2, c, wl, wm, wr;
+  Layout psi, L, R, W1, W2;
+  int64_t psi_base = 0, L_base = 0, R_base = 0, W1_base = 0, W2_base = 0;
+  int64_t t1_base = 0, t2_base = 0, coef_base = 0;
+  int64_t t1_elems = 0, t2_elems = 0, n_coefs = 0;
+  int32_t chunk0 = 0, nchunk = 0;
+};
+
+}  // namespace bsd
+
+struct bsdmrg_plan_s {
+  std::vector<bsd::ProblemPlan> probs;
+  int64_t psi_elems = 0, L_elems = 0, R_elems = 0, W1_elems = 0, W2_elems = 0;
+  int64_t t1_elems = 0, t2_elems = 0, n_coefs = 0;
+  bsd::Stage s1, s3;
+  std::vector<bsd::MixTask> mix_tasks;
+  std::vector<bsd::MixTerm> mix_terms;
+  std::vector<bsd::MixItem> mix_items;
+  std::vector<int32_t> coef_ptr;     // CSR over coefficient pairs
+  std::vector<int64_t> coef_e1, coef_e2;
+  std::vector<bsd::Chunk> chunks;
+  double flops_s2 = 0.0;
+  bool on_device = false;
+  void* d_blob = nullptr;            // one device allocation for all tables
+  bsd::MixTask* d_mix_tasks = nullptr;
+  bsd::MixTerm* d_mix_terms = nullptr;
+  bsd::MixItem* d_mix_items = nullptr;
+  int32_t* d_coef_ptr = nullptr;
+  int64_t* d_coef_e1 = nullptr;
+  int64_t* d_coef_e2 = nullptr;
+  bsd::Chunk* d_chunks = nullptr;
+  std::vector<bsd::DavProb> dav_probs;
+  std::vector<int64_t> blk_off;      // per psi block: (offset in problem, size)
+  std::vector<int32_t> blk_ptr;      // per problem: first block (n_probs + 1)
+  bsd::DavProb* d_dav_probs = nullptr;
+  int64_t* d_blk_off = nullptr;
+  int32_t* d_blk_ptr = nullptr;
+  // backward-pass tables (built lazily)
+  struct Backward* bwd = nullptr;
+  // cached hipGraph of a fixed-iteration eigensolve
+  struct GraphCache* graph = nullptr;
+};

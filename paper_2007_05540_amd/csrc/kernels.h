@@ -1,0 +1,61 @@
+// Launch wrappers of the device kernels (host-callable).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bsdmrg_internal.h"
+
+namespace bsd {
+
+// two-site product stages
+hipError_t launch_s1_f64(const bsdmrg_plan_s* P, const double* L, const double* psi, double* T1,
+                         hipStream_t s);
+hipError_t launch_s3_f64(const bsdmrg_plan_s* P, const double* T2, const double* R, double* out,
+                         hipStream_t s);
+hipError_t launch_s1_f32(const bsdmrg_plan_s* P, const float* L, const double* psi, float* T1,
+                         hipStream_t s);
+hipError_t launch_s3_f32(const bsdmrg_plan_s* P, const float* T2, const float* R, double* out,
+                         hipStream_t s);
+hipError_t launch_mix_f64(const bsdmrg_plan_s* P, const double* coef, const double* T1, double* T2,
+                          hipStream_t s);
+hipError_t launch_mix_f32(const bsdmrg_plan_s* P, const double* coef, const float* T1, float* T2,
+                          hipStream_t s);
+hipError_t launch_coef(const bsdmrg_plan_s* P, const double* W1, const double* W2, double* coef,
+                       hipStream_t s);
+hipError_t launch_cast(int64_t n, const double* x, float* y, hipStream_t s);
+
+// Davidson (Alg. 1) building blocks; every vector spans all problems of the
+// plan, reductions are per problem through the chunk table.
+struct DavBufs {
+  double* V;        // basis, B vectors of n elements
+  double* VA;       // products
+  double* x;
+  double* q;
+  double* part_a;   // (B + 1) * nchunk partial sums
+  double* part_b;
+  double* part_n0;  // nchunk: ||q||^2 before orthogonalisation
+  double* part_n1;  // nchunk: ||q||^2 after
+  double* M;        // n_probs * B * B projected matrices
+  double* svec;     // n_probs * B Ritz vectors of M
+  double* lam;      // n_probs
+  double* scale;    // n_probs
+  int32_t* restarts;  // n_probs
+  int32_t* status;    // n_probs, non-zero when a restart failed
+  int64_t n;        // vector length (all problems)
+  int B;            // max basis size
+};
+
+hipError_t dav_fill_zero(double* x, int64_t n, hipStream_t s);
+hipError_t dav_dots(const bsdmrg_plan_s* P, int J, const double* X, int64_t xstride, const double* y,
+                    double* part, hipStream_t s);
+hipError_t dav_normalize(const bsdmrg_plan_s* P, const double* part, const double* x, double* y,
+                         hipStream_t s);
+hipError_t dav_gram_eig(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStream_t s);
+hipError_t dav_ritz(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStream_t s);
+hipError_t dav_update(const bsdmrg_plan_s* P, const DavBufs& b, int J, const double* part_in,
+                      double* part_out, int mode, hipStream_t s);
+hipError_t dav_finalize(const bsdmrg_plan_s* P, const DavBufs& b, int i, uint64_t seed, double rtol,
+                        const int64_t* blk_off, const int32_t* blk_ptr, hipStream_t s);
+hipError_t dav_scale_into(const bsdmrg_plan_s* P, const DavBufs& b, double* dst, hipStream_t s);
+
+}  // namespace bsd

@@ -1,0 +1,267 @@
+// Contraction planner: Alg. 2 (pair the blocks whose labels agree on the
+// contracted legs, key the products by the remaining labels) generalised to
+// the four-operand two-site product of Sec. II-C,
+//   out(a',s1',s2',c') = sum L(a',w,a) W1(w,s1',s1,w') W2(w',s2',s2,w'')
+//                            R(c',w'',c) psi(a,s1,s2,c),
+// evaluated in three stages:
+//   S1  T1(a',w,s1,s2,c) = sum_a L(a',w,a) psi(a,s1,s2,c)        grouped GEMM
+//   S2  T2(a',s1',s2',w'',c) = sum WW(w,s1',s2',s1,s2,w'') T1     MPO mixing
+//       with WW = sum_w' W1 W2 combined element by element
+//   S3  out(a',s1',s2',c') = sum_{w'',c} T2 R(c',w'',c)            grouped GEMM
+// Every block of psi, T1, T2, out is a matrix (physical sectors have dim 1):
+// a T1 block is (b_a' * n_w) x b_c, a T2 block b_a' x (n_w'' * b_c).  S1 has
+// one K segment per task (a = a' - f_w is unique); S3 sums the w'' flux
+// sectors of an output block as a K-list accumulated in registers, so no
+// atomics and a fixed summation order.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "bsdmrg_internal.h"
+
+namespace bsd {
+
+constexpr int kTileM = 64, kTileN = 64;
+constexpr int kMixItemElems = 4096;
+
+static const int32_t kPsiSigns[4] = {1, 1, 1, -1};
+static const int32_t kEnvSigns[3] = {-1, 1, 1};
+static const int32_t kWSigns[4] = {1, 1, -1, -1};
+
+static Charge add(const Charge& a, const Charge& b) { return {a[0] + b[0], a[1] + b[1]}; }
+static Charge sub(const Charge& a, const Charge& b) { return {a[0] - b[0], a[1] - b[1]}; }
+
+static Key key3(int a, int b, int c) { Key k{}; k[0] = a; k[1] = b; k[2] = c; return k; }
+static Key key4(int a, int b, int c, int d) { Key k{}; k[0] = a; k[1] = b; k[2] = c; k[3] = d; return k; }
+static Key key5(int a, int b, int c, int d, int e) {
+  Key k{}; k[0] = a; k[1] = b; k[2] = c; k[3] = d; k[4] = e; return k;
+}
+
+static void add_tiles(Stage& st, int task) {
+  const GemmTask& t = st.tasks[task];
+  for (int m0 = 0; m0 < std::max(t.M, 1); m0 += kTileM)
+    for (int n0 = 0; n0 < std::max(t.N, 1); n0 += kTileN) st.tiles.push_back({task, m0, n0, 0});
+}
+
+// Longest-first (LPT) order of tiles: descending K of the task, stable.
+static void order_tiles(Stage& st) {
+  std::stable_sort(st.tiles.begin(), st.tiles.end(), [&](const GemmTile& x, const GemmTile& y) {
+    return st.tasks[x.task].ksum > st.tasks[y.task].ksum;
+  });
+}
+
+static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
+  ProblemPlan& p = P->probs[pi];
+  p.a = leg_from(in.a); p.s1 = leg_from(in.s1); p.s2 = leg_from(in.s2); p.c = leg_from(in.c);
+  p.wl = leg_from(in.wl); p.wm = leg_from(in.wm); p.wr = leg_from(in.wr);
+  for (const Leg* l : {&p.s1, &p.s2})
+    for (auto d : l->d)
+      if (d != 1) throw Error{BSDMRG_EINVAL, "plan: physical sectors must have dimension 1"};
+  if (!in.w1_host || !in.w2_host) throw Error{BSDMRG_EINVAL, "plan: W host arrays are required"};
+  p.psi = make_layout({&p.a, &p.s1, &p.s2, &p.c}, kPsiSigns);
+  p.L = make_layout({&p.a, &p.wl, &p.a}, kEnvSigns);
+  p.R = make_layout({&p.c, &p.wr, &p.c}, kEnvSigns);
+  p.W1 = make_layout({&p.wl, &p.s1, &p.s1, &p.wm}, kWSigns);
+  p.W2 = make_layout({&p.wm, &p.s2, &p.s2, &p.wr}, kWSigns);
+
+  p.psi_base = P->psi_elems; P->psi_elems += p.psi.elems();
+  p.L_base = P->L_elems;     P->L_elems += p.L.elems();
+  p.R_base = P->R_elems;     P->R_elems += p.R.elems();
+  p.W1_base = P->W1_elems;   P->W1_elems += p.W1.elems();
+  p.W2_base = P->W2_elems;   P->W2_elems += p.W2.elems();
+  p.t1_base = P->t1_elems;
+  p.t2_base = P->t2_elems;
+  p.coef_base = P->n_coefs;
+
+  // Non-zero W blocks (a W block that is entirely zero is structurally absent).
+  auto nonzero = [](const Layout& L, const double* v, int b) {
+    for (int64_t e = L.offs[b]; e < L.offs[b + 1]; ++e)
+      if (v[e] != 0.0) return true;
+    return false;
+  };
+  std::vector<char> nz1(p.W1.keys.size()), nz2(p.W2.keys.size());
+  for (size_t b = 0; b < nz1.size(); ++b) nz1[b] = nonzero(p.W1, in.w1_host, (int)b);
+  for (size_t b = 0; b < nz2.size(); ++b) nz2[b] = nonzero(p.W2, in.w2_host, (int)b);
+
+  // ---- S1: one task per (psi block, left channel sector) ---------------
+  std::map<Key, std::pair<int64_t, int>> t1;   // (a', f, s1, s2, c) -> (offset, index)
+  std::vector<int64_t> t1_off;
+  int64_t t1_cursor = 0;
+  for (size_t pb = 0; pb < p.psi.keys.size(); ++pb) {
+    const Key& k = p.psi.keys[pb];
+    int ia = k[0], i1 = k[1], i2 = k[2], ic = k[3];
+    for (int f = 0; f < p.wl.size(); ++f) {
+      int iap = p.a.find(add(p.a.q[ia], p.wl.q[f]));
+      if (iap < 0) continue;
+      int lb = p.L.lookup(key3(iap, f, ia));
+      if (lb < 0) throw Error{BSDMRG_EQN, "plan: missing L block"};
+      const int32_t M = (int32_t)(p.a.d[iap] * p.wl.d[f]);
+      const int32_t N = (int32_t)p.c.d[ic];
+      const int32_t K = (int32_t)p.a.d[ia];
+      GemmSeg s{p.L_base + p.L.offs[lb], p.psi_base + p.psi.offs[pb], K, N, K, 0};
+      GemmTask t{p.t1_base + t1_cursor, N, M, N, (int32_t)P->s1.segs.size(), 1, K};
+      P->s1.segs.push_back(s);
+      P->s1.tasks.push_back(t);
+      P->s1.flops += 2.0 * M * N * (double)K;
+      t1[key5(iap, f, i1, i2, ic)] = {t1_cursor, (int)t1_off.size()};
+      t1_off.push_back(t1_cursor);
+      t1_cursor += round_up((int64_t)M * N);
+    }
+  }
+  p.t1_elems = t1_cursor;
+
+  // ---- S2: T2 blocks (a', s1', s2', g, c) and their mixing terms ------------
+  struct CoefKey {
+    int f, iw, s1p, s1, s2p, s2, g, iwpp;
+    bool operator<(const CoefKey& o) const {
+      return std::tie(f, iw, s1p, s1, s2p, s2, g, iwpp) <
+             std::tie(o.f, o.iw, o.s1p, o.s1, o.s2p, o.s2, o.g, o.iwpp);
+    }
+  };
+  std::map<CoefKey, int> coef_index;
+  auto wstart = [](const Leg& l) {
+    std::vector<int64_t> s(l.size() + 1, 0);
+    for (int i = 0; i < l.size(); ++i) s[i + 1] = s[i] + l.d[i];
+    return s;
+  };
+  (void)wstart;
+  auto coef_of = [&](const CoefKey& ck) -> int {
+    auto it = coef_index.find(ck);
+    if (it != coef_index.end()) return it->second;
+    // pairs over the middle channel: W1(f,iw; s1p, s1; m, im) W2(m, im; s2p, s2; g, iwpp)
+    std::vector<std::pair<int64_t, int64_t>> pairs;
+    for (int m = 0; m < p.wm.size(); ++m) {
+      int b1 = p.W1.lookup(key4(ck.f, ck.s1p, ck.s1, m));
+      int b2 = p.W2.lookup(key4(m, ck.s2p, ck.s2, ck.g));
+      if (b1 < 0 || b2 < 0 || !nz1[b1] || !nz2[b2]) continue;
+      const int64_t nm = p.wm.d[m], ng = p.wr.d[ck.g];
+      for (int im = 0; im < nm; ++im) {
+        int64_t e1 = p.W1.offs[b1] + (int64_t)ck.iw * nm + im;
+        int64_t e2 = p.W2.offs[b2] + (int64_t)im * ng + ck.iwpp;
+        if (in.w1_host[e1] != 0.0 && in.w2_host[e2] != 0.0)
+          pairs.push_back({p.W1_base + e1, p.W2_base + e2});
+      }
+    }
+    if (pairs.empty()) return coef_index[ck] = -1;
+    int id = (int)(P->coef_ptr.size() - 1);
+    for (auto& pr : pairs) { P->coef_e1.push_back(pr.first); P->coef_e2.push_back(pr.second); }
+    P->coef_ptr.push_back((int32_t)P->coef_e1.size());
+    p.n_coefs++;
+    return coef_index[ck] = id;
+  };
+
+  std::map<Key, std::pair<int64_t, int>> t2;   // (a', s1', s2', g) -> (offset, c)
+  int64_t t2_cursor = 0;
+  for (int iap = 0; iap < p.a.size(); ++iap)
+    for (int s1p = 0; s1p < p.s1.size(); ++s1p)
+      for (int s2p = 0; s2p < p.s2.size(); ++s2p) {
+        Charge qout = add(add(p.a.q[iap], p.s1.q[s1p]), p.s2.q[s2p]);   // = q_c'
+        if (p.c.find(qout) < 0) continue;
+        for (int g = 0; g < p.wr.size(); ++g) {
+          int ic = p.c.find(sub(qout, p.wr.q[g]));
+          if (ic < 0) continue;
+          // block-level existence: a T1 block and non-zero W blocks connect
+          bool exists = false;
+          for (int f = 0; f < p.wl.size() && !exists; ++f)
+            for (int i1 = 0; i1 < p.s1.size() && !exists; ++i1)
+              for (int i2 = 0; i2 < p.s2.size() && !exists; ++i2) {
+                if (!t1.count(key5(iap, f, i1, i2, ic))) continue;
+                for (int m = 0; m < p.wm.size(); ++m) {
+                  int b1 = p.W1.lookup(key4(f, s1p, i1, m));
+                  int b2 = p.W2.lookup(key4(m, s2p, i2, g));
+                  if (b1 >= 0 && b2 >= 0 && nz1[b1] && nz2[b2]) { exists = true; break; }
+                }
+              }
+          if (!exists) continue;
+          const int64_t ba = p.a.d[iap], bc = p.c.d[ic], ng = p.wr.d[g];
+          t2[key4(iap, s1p, s2p, g)] = {t2_cursor, ic};
+          for (int iwpp = 0; iwpp < ng; ++iwpp) {
+            MixTask mt{p.t2_base + t2_cursor + iwpp * bc, (int32_t)(ng * bc), (int32_t)ba,
+                       (int32_t)bc, (int32_t)P->mix_terms.size(), 0, 0};
+            for (int f = 0; f < p.wl.size(); ++f)
+              for (int i1 = 0; i1 < p.s1.size(); ++i1)
+                for (int i2 = 0; i2 < p.s2.size(); ++i2) {
+                  auto it = t1.find(key5(iap, f, i1, i2, ic));
+                  if (it == t1.end()) continue;
+                  const int64_t nf = p.wl.d[f];
+                  for (int iw = 0; iw < nf; ++iw) {
+                    int cidx = coef_of(CoefKey{f, iw, s1p, i1, s2p, i2, g, iwpp});
+                    if (cidx < 0) continue;
+                    P->mix_terms.push_back(MixTerm{p.t1_base + it->second.first + iw * bc,
+                                                   (int32_t)(nf * bc), cidx});
+                  }
+                }
+            mt.nterm = (int32_t)P->mix_terms.size() - mt.term0;
+            P->flops_s2 += 2.0 * mt.nterm * (double)ba * bc;
+            const int task = (int)P->mix_tasks.size();
+            P->mix_tasks.push_back(mt);
+            int rows_per = std::max<int64_t>(1, kMixItemElems / std::max<int64_t>(1, bc));
+            for (int r0 = 0; r0 < ba; r0 += rows_per)
+              P->mix_items.push_back(MixItem{task, r0, (int32_t)std::min<int64_t>(rows_per, ba - r0), 0});
+          }
+          t2_cursor += round_up(ba * ng * bc);
+        }
+      }
+  p.t2_elems = t2_cursor;
+
+  // ---- S3: one task per output block, K-list over the w'' flux sectors ------
+  for (size_t ob = 0; ob < p.psi.keys.size(); ++ob) {
+    const Key& k = p.psi.keys[ob];
+    int iap = k[0], s1p = k[1], s2p = k[2], icp = k[3];
+    const int32_t M = (int32_t)p.a.d[iap], N = (int32_t)p.c.d[icp];
+    GemmTask t{p.psi_base + p.psi.offs[ob], N, M, N, (int32_t)P->s3.segs.size(), 0, 0};
+    for (int g = 0; g < p.wr.size(); ++g) {
+      auto it = t2.find(key4(iap, s1p, s2p, g));
+      if (it == t2.end()) continue;
+      int ic = it->second.second;
+      int rb = p.R.lookup(key3(icp, g, ic));
+      if (rb < 0) throw Error{BSDMRG_EQN, "plan: missing R block"};
+      const int32_t K = (int32_t)(p.wr.d[g] * p.c.d[ic]);
+      P->s3.segs.push_back(GemmSeg{p.t2_base + it->second.first, p.R_base + p.R.offs[rb], K, K, K, 0});
+      t.nseg++;
+      t.ksum += K;
+      P->s3.flops += 2.0 * M * N * (double)K;
+    }
+    P->s3.tasks.push_back(t);
+  }
+  P->t1_elems += p.t1_elems;
+  P->t2_elems += p.t2_elems;
+  P->n_coefs += p.n_coefs;
+}
+
+}  // namespace bsd
+
+using namespace bsd;
+
+bsdmrg_plan_s* build_plan(const bsdmrg_problem* probs, int n_probs) {
+  auto* P = new bsdmrg_plan_s();
+  try {
+    P->probs.resize(n_probs);
+    P->coef_ptr.push_back(0);
+    for (int i = 0; i < n_probs; ++i) plan_problem(P, i, probs[i]);
+    for (size_t t = 0; t < P->s1.tasks.size(); ++t) add_tiles(P->s1, (int)t);
+    for (size_t t = 0; t < P->s3.tasks.size(); ++t) add_tiles(P->s3, (int)t);
+    order_tiles(P->s1);
+    order_tiles(P->s3);
+    // Davidson reduction chunks
+    for (int i = 0; i < n_probs; ++i) {
+      ProblemPlan& p = P->probs[i];
+      p.chunk0 = (int32_t)P->chunks.size();
+      for (int64_t s = 0; s < p.psi.elems(); s += kChunk)
+        P->chunks.push_back(Chunk{p.psi_base + s, (int32_t)std::min<int64_t>(kChunk, p.psi.elems() - s), i});
+      p.nchunk = (int32_t)P->chunks.size() - p.chunk0;
+      P->dav_probs.push_back(DavProb{p.psi_base, p.psi.elems(), p.chunk0, p.nchunk});
+      P->blk_ptr.push_back((int32_t)(P->blk_off.size() / 2));
+      for (size_t b = 0; b < p.psi.keys.size(); ++b) {
+        const Key& k = p.psi.keys[b];
+        P->blk_off.push_back(p.psi.offs[b]);
+        P->blk_off.push_back(p.a.d[k[0]] * p.c.d[k[3]]);
+      }
+    }
+    P->blk_ptr.push_back((int32_t)(P->blk_off.size() / 2));
+  } catch (...) {
+    delete P;
+    throw;
+  }
+  return P;
+}

@@ -1,0 +1,102 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol the header declares, and its layout and planner agree with the
+oracle bit for bit."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.blocks import canonical_layout, allowed_keys, block_shape
+from oracle.heff import bond_operands, useful_flops, PSI_SIGNS, ENV_SIGNS, W_SIGNS
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2007_05540_amd import lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libbsdmrg.so not built")
+    L.load()
+    return L
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "bsdmrg.h")).read()
+    return sorted(set(re.findall(r"\b(bsdmrg_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol(lib):
+    so = ctypes.CDLL(lib.LIB_PATH)
+    names = declared_symbols()
+    assert "bsdmrg_heff_apply" in names and "bsdmrg_eigensolve" in names
+    for n in names:
+        assert hasattr(so, n), n
+
+
+@pytest.mark.parametrize("legs,signs", [
+    ([synth.spin_bond_leg(200), synth.SPIN_PHYS, synth.SPIN_PHYS, synth.spin_bond_leg(200)], PSI_SIGNS),
+    ([synth.spin_bond_leg(300), [((-2,), 4), ((0,), 6), ((2,), 4)], synth.spin_bond_leg(300)], ENV_SIGNS),
+    ([[((-2,), 4), ((0,), 6), ((2,), 4)], synth.SPIN_PHYS, synth.SPIN_PHYS, [((-2,), 4), ((0,), 6), ((2,), 4)]],
+     W_SIGNS),
+    ([synth.electron_bond_leg(512, center=(8, 0)), synth.HUB_PHYS, synth.HUB_PHYS,
+      synth.electron_bond_leg(512, center=(10, 0))], PSI_SIGNS),
+])
+def test_layout_bit_exact_with_oracle(lib, legs, signs):
+    keys, offs = lib.layout(legs, signs)
+    ok, oo = canonical_layout(legs, signs)
+    assert np.array_equal(keys, np.array(ok, dtype=np.int32).reshape(-1, len(legs)))
+    assert np.array_equal(offs, np.array(oo, dtype=np.int64))
+    assert keys.tobytes() == np.array(ok, dtype=np.int32).reshape(-1, len(legs)).tobytes()
+
+
+def test_layout_rejects_unsorted_leg(lib):
+    with pytest.raises(lib.BsdmrgError) as e:
+        lib.layout([[((1,), 1), ((0,), 1)], [((0,), 1)]], (1, -1))
+    assert e.value.status == lib.EQN
+
+
+@pytest.mark.parametrize("m,k,seed", [(128, 14, 1), (256, 10, 2), (200, 18, 3), (512, 20, 4)])
+def test_planner_flops_equal_oracle_block_pairs(lib, m, k, seed):
+    from paper_2007_05540_amd import problems
+    spec = synth.c2_bond(m=m, k=k, seed=seed)
+    prob, ops = problems.bond_problem(spec)
+    plan = lib.Plan([prob], host_only=True)
+    info = plan.info()
+    ops_o = bond_operands(spec)
+    assert info["flops_s1"] + info["flops_s3"] == useful_flops(*ops_o)
+    # packed operands equal the oracle's canonical packing
+    L, W1, W2, R, psi = ops_o
+    assert np.array_equal(ops["psi"], psi.pack()) and np.array_equal(ops["L"], L.pack())
+
+
+def test_planner_task_set_equals_brute_force_enumeration(lib):
+    """S1 tasks = every (psi block, channel sector) whose bra sector exists,
+    found here by brute force over all sector triples."""
+    from paper_2007_05540_amd import problems
+    spec = synth.c2_bond(m=96, k=14, seed=5)
+    prob, _ = problems.bond_problem(spec)
+    plan = lib.Plan([prob], host_only=True)
+    t1 = plan.tasks(1)
+    a, wl = spec.a_leg, spec.w_leg()
+    psi_legs = [a, spec.s_leg, spec.s_leg, spec.c_leg]
+    brute = []
+    for kp in allowed_keys(psi_legs, PSI_SIGNS):
+        for f in range(len(wl)):
+            for iap in range(len(a)):
+                if (iap, f, kp[0]) in set(map(tuple, allowed_keys([a, wl, a], ENV_SIGNS))):
+                    brute.append((a[iap][1] * wl[f][1], spec.c_leg[kp[3]][1], a[kp[0]][1], 1))
+    assert sorted(map(tuple, t1.tolist())) == sorted(brute)
+
+
+def test_plan_rejects_physical_dim_above_one(lib):
+    from paper_2007_05540_amd import problems
+    spec = synth.c2_bond(m=32, k=5, seed=1)
+    prob, _ = problems.bond_problem(spec)
+    prob = dict(prob)
+    prob["s1"] = [((-1,), 2), ((1,), 1)]
+    with pytest.raises(lib.BsdmrgError):
+        lib.Plan([prob], host_only=True)

@@ -1,0 +1,259 @@
+"""GPU parity of the two-site product and the Davidson eigensolver against the
+CPU oracle (same seeded inputs, compared element by element).
+
+Tolerances
+  FP64 product: norm-wise relative 1e-12 (the required agreement).
+  FP32 product: block GEMMs accumulate K <= 14 * 270 products in FP32; the
+    worst-case relative error of one output is ~K * 2^-24 ~ 2e-4 and the
+    typical (random-sign) one sqrt(K) * 2^-24 ~ 4e-6; the test bounds the
+    norm-wise relative error by 5e-5.
+  Ritz values (fixed iteration count): relative 1e-11 (FP64 basis built in a
+    different summation order; the Krylov sequence is stable for these steps).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle.blocks import BlockTensor
+from oracle.eig import davidson
+from oracle.dmrg import mask_of
+from oracle.heff import bond_operands, heff_blocks, PSI_SIGNS
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def setup(specs, lib, problems):
+    pairs = [problems.bond_problem(s) for s in specs]
+    plan = lib.Plan([p for p, _ in pairs])
+    ops = problems.concat(plan, [o for _, o in pairs])
+    d = {k: dev(v) for k, v in ops.items()}
+    return plan, ops, d
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def oracle_apply(spec, psi_flat=None):
+    L, W1, W2, R, psi = bond_operands(spec)
+    if psi_flat is not None:
+        psi = BlockTensor.unpack(psi_flat, psi.legs, PSI_SIGNS)
+    return heff_blocks(L, W1, W2, R, psi).pack()
+
+
+@pytest.fixture(scope="module")
+def mods(gpu_lib):
+    from paper_2007_05540_amd import problems
+    return gpu_lib, problems
+
+
+CASES = [(64, 5, 1), (96, 14, 2), (256, 14, 3), (256, 10, 4), (200, 18, 5)]
+
+
+@pytest.mark.parametrize("m,k,seed", CASES)
+def test_apply_f64_matches_oracle(mods, m, k, seed):
+    lib, problems = mods
+    spec = synth.c2_bond(m=m, k=k, seed=seed)
+    plan, ops, d = setup([spec], lib, problems)
+    info = plan.info()
+    out = torch.zeros_like(d["psi"])
+    ws = torch.empty(info["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    lib.heff_apply(plan, lib.F64, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ref = oracle_apply(spec)
+    assert rel(got, ref) < 1e-12
+    # padding of out is left untouched (zero here)
+    mask = mask_of([spec.a_leg, spec.s_leg, spec.s_leg, spec.c_leg], PSI_SIGNS)
+    assert np.all(got[~mask] == 0.0)
+
+
+def test_apply_f64_full_size_mid_chain_bond(mods):
+    """m = 1024, k = 14: the full-size isolated bond, whole output compared."""
+    lib, problems = mods
+    spec = synth.c2_bond()
+    plan, ops, d = setup([spec], lib, problems)
+    out = torch.zeros_like(d["psi"])
+    ws = torch.empty(plan.info()["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    lib.heff_apply(plan, lib.F64, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
+    torch.cuda.synchronize()
+    assert rel(out.cpu().numpy(), oracle_apply(spec)) < 1e-12
+
+
+def test_apply_f32_within_fp32_bound(mods):
+    lib, problems = mods
+    spec = synth.c2_bond(m=512, k=14, seed=7)
+    plan, ops, d = setup([spec], lib, problems)
+    out = torch.zeros_like(d["psi"])
+    ws = torch.empty(plan.info()["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    lib.heff_apply(plan, lib.F32, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
+    torch.cuda.synchronize()
+    err = rel(out.cpu().numpy(), oracle_apply(spec))
+    assert 1e-9 < err < 5e-5        # really FP32 (not silently FP64), within the bound
+
+
+def test_apply_deterministic(mods):
+    lib, problems = mods
+    spec = synth.c2_bond(m=256, k=14, seed=9)
+    plan, ops, d = setup([spec], lib, problems)
+    ws = torch.empty(plan.info()["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    outs = []
+    for prec in (lib.F64, lib.F64, lib.F32, lib.F32):
+        out = torch.zeros_like(d["psi"])
+        lib.heff_apply(plan, prec, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
+        outs.append(out.cpu())
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[2], outs[3])
+
+
+def test_apply_batch_equals_single(mods):
+    lib, problems = mods
+    specs = [synth.c2_bond(m=m, k=k, seed=s) for m, k, s in [(64, 10, 1), (128, 14, 2), (96, 18, 3)]]
+    plan, ops, d = setup(specs, lib, problems)
+    out = torch.zeros_like(d["psi"])
+    ws = torch.empty(plan.info()["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    lib.heff_apply(plan, lib.F64, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for p, spec in enumerate(specs):
+        o = plan.offsets(p)["psi"]
+        ref = oracle_apply(spec)
+        assert rel(got[o:o + ref.size], ref) < 1e-12
+
+
+def test_apply_rejects_bad_arguments(mods):
+    lib, problems = mods
+    spec = synth.c2_bond(m=64, k=5, seed=1)
+    plan, ops, d = setup([spec], lib, problems)
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    out = torch.zeros_like(d["psi"])
+    with pytest.raises(lib.BsdmrgError) as e:
+        lib.heff_apply(plan, lib.F64, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
+    assert e.value.status == lib.EINVAL
+    with pytest.raises(lib.BsdmrgError):
+        lib.heff_apply(plan, 7, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
+
+
+# ------------------------------------------------------------ eigensolver ---
+def oracle_davidson(spec, n_iter, tol=0.0, seed=0):
+    L, W1, W2, R, psi = bond_operands(spec)
+
+    def mv(v):
+        return heff_blocks(L, W1, W2, R, BlockTensor.unpack(v, psi.legs, PSI_SIGNS)).pack()
+    rec = []
+    lam, x, st = davidson(mv, psi.pack(), n_iter, tol, restart_mask=mask_of(psi.legs, PSI_SIGNS),
+                          seed=seed, record=rec)
+    return lam, x, st, rec
+
+
+def run_eig(lib, plan, d, opts, stream=None):
+    ws = torch.empty(lib.eig_workspace(plan, opts), dtype=torch.uint8, device="cuda")
+    psi = d["psi"].clone()
+    e, st = lib.eigensolve(plan, d["L"], d["W1"], d["W2"], d["R"], psi, opts, ws, stream=stream)
+    return e, st, psi
+
+
+@pytest.mark.parametrize("m,k,n_iter", [(64, 5, 8), (256, 14, 10)])
+def test_eigensolve_fixed_iterations_match_oracle(mods, m, k, n_iter):
+    lib, problems = mods
+    spec = synth.c2_bond(m=m, k=k, seed=11)
+    plan, ops, d = setup([spec], lib, problems)
+    opts = lib.eig_opts(max_iter=n_iter, fixed_iters=1)
+    e, st, psi = run_eig(lib, plan, d, opts)
+    lam, x, ost, rec = oracle_davidson(spec, n_iter)
+    assert abs(e[0] - lam) < 1e-11 * abs(lam)
+    assert st[0]["iters"] == n_iter
+    ov = abs(float(np.dot(psi.cpu().numpy(), x)))
+    assert abs(ov - 1.0) < 1e-9
+
+
+def test_eigensolve_converges_to_dense_lowest(mods):
+    lib, problems = mods
+    spec = synth.c2_bond(m=24, k=5, seed=4)
+    plan, ops, d = setup([spec], lib, problems)
+    opts = lib.eig_opts(max_iter=64, tol=1e-10)
+    e, st, psi = run_eig(lib, plan, d, opts)
+    lam, x, ost, _ = oracle_davidson(spec, 64, tol=1e-10)
+    assert st[0]["converged"] == 1
+    assert abs(e[0] - lam) < 1e-10 * abs(lam)
+    # residual of the returned vector through the GPU product
+    out = torch.zeros_like(psi)
+    ws = torch.empty(plan.info()["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    lib.heff_apply(plan, lib.F64, d["L"], d["W1"], d["W2"], d["R"], psi, out, ws)
+    r = out.cpu().numpy() - e[0] * psi.cpu().numpy()
+    assert np.linalg.norm(r) < 1e-8
+
+
+def test_eigensolve_mixed_precision_energy(mods):
+    """FP32 products, then FP64 refinement restarted from the FP32 Ritz vector:
+    the final energy agrees with the converged FP64 oracle to 1e-9."""
+    lib, problems = mods
+    spec = synth.c2_bond(m=24, k=5, seed=4)
+    plan, ops, d = setup([spec], lib, problems)
+    lam, _, ost, _ = oracle_davidson(spec, 64, tol=1e-10)
+    assert ost["converged"]
+    o = lib.eig_opts(max_iter=64, precision=lib.F32_REFINE, refine_max_iter=64, tol=1e-10, tol_f32=1e-5)
+    e32, st32, _ = run_eig(lib, plan, d, o)
+    assert st32[0]["iters_f32"] >= 1 and st32[0]["iters"] >= 1
+    assert abs(e32[0] - lam) < 1e-9 * abs(lam)
+
+
+def test_eigensolve_graph_replay_equals_eager(mods):
+    lib, problems = mods
+    spec = synth.c2_bond(m=128, k=14, seed=12)
+    plan, ops, d = setup([spec], lib, problems)
+    s = torch.cuda.Stream()
+    eager = lib.eig_opts(max_iter=6, fixed_iters=1, use_graph=0)
+    graph = lib.eig_opts(max_iter=6, fixed_iters=1, use_graph=1)
+    e0, _, p0 = run_eig(lib, plan, d, eager, stream=s)
+    ws = torch.empty(lib.eig_workspace(plan, graph), dtype=torch.uint8, device="cuda")
+    for rep in range(3):
+        psi = d["psi"].clone()
+        torch.cuda.synchronize()
+        e1, _ = lib.eigensolve(plan, d["L"], d["W1"], d["W2"], d["R"], psi, graph, ws, stream=s)
+        torch.cuda.synchronize()
+        assert e1[0] == e0[0]
+        assert torch.equal(psi.cpu(), p0.cpu())
+        # eager work between replays
+        lib.eigensolve(plan, d["L"], d["W1"], d["W2"], d["R"], d["psi"].clone(), eager,
+                       torch.empty(lib.eig_workspace(plan, eager), dtype=torch.uint8, device="cuda"),
+                       stream=s)
+
+
+def test_eigensolve_batch_matches_single(mods):
+    lib, problems = mods
+    specs = [synth.c2_bond(m=m, k=k, seed=s) for m, k, s in [(64, 10, 21), (128, 14, 22), (96, 18, 23)]]
+    plan, ops, d = setup(specs, lib, problems)
+    opts = lib.eig_opts(max_iter=8, fixed_iters=1)
+    e, st, psi = run_eig(lib, plan, d, opts)
+    for p, spec in enumerate(specs):
+        lam, x, _, _ = oracle_davidson(spec, 8)
+        assert abs(e[p] - lam) < 1e-11 * abs(lam)
+
+
+def test_eigensolve_restart_on_breakdown(mods):
+    """H_eff = identity (unit environments and MPO): q = 0 after the first
+    step, so the seeded random restart must be taken; the Ritz values and the
+    restarted basis follow the oracle's identical counter-based stream."""
+    lib, problems = mods
+    leg = synth.spin_bond_leg(40)
+    s = synth.SPIN_PHYS
+    wl = [((0,), 1)]
+    W = np.eye(2).reshape(1, 2, 2, 1)
+    prob = {"a": leg, "s1": s, "s2": s, "c": leg, "wl": wl, "wm": wl, "wr": wl,
+            "w1": problems.pack_dense(W, [wl, s, s, wl], lib.W_SIGNS),
+            "w2": problems.pack_dense(W, [wl, s, s, wl], lib.W_SIGNS)}
+    eye = lambda k: np.eye(leg[k[0]][1]).reshape(leg[k[0]][1], 1, leg[k[0]][1])
+    L = problems.pack_fn([leg, wl, leg], lib.ENV_SIGNS, eye)
+    psi = problems.pack_fn([leg, s, s, leg], lib.PSI_SIGNS,
+                           lambda k: synth.gaussian_block(3, 4, k, (leg[k[0]][1], 1, 1, leg[k[3]][1])))
+    plan = lib.Plan([prob])
+    d = {"L": dev(L), "R": dev(L), "W1": dev(prob["w1"]), "W2": dev(prob["w2"]), "psi": dev(psi)}
+    opts = lib.eig_opts(max_iter=3, fixed_iters=1, seed=5)
+    e, st, out = run_eig(lib, plan, d, opts)
+    assert st[0]["restarts"] >= 1 and abs(e[0] - 1.0) < 1e-14
