@@ -8,8 +8,9 @@
 // while the current slice is multiplied.
 //   FP64: v_mfma_f64_16x16x4f64, FP32: v_mfma_f32_16x16x4f32.
 // Operand layout of the 16x16x4 MFMA (both types): lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator element r of lane l is
-// D[4 (l / 16) + r][l % 16].
+// A[l % 16][l / 16] and B[l / 16][l % 16].  Accumulator element r of lane l is
+// D[l / 16 + 4 r][l % 16] for the FP64 instruction and D[4 (l / 16) + r][l % 16]
+// for the FP32 one (checked on gfx950).
 #include <hip/hip_runtime.h>
 
 #include "bsdmrg_internal.h"
@@ -27,6 +28,7 @@ struct Mfma<double> {
   static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 template <>
 struct Mfma<float> {
@@ -34,6 +36,7 @@ struct Mfma<float> {
   static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
 // TC: compute type; TA/TB: global operand types (converted on load);
@@ -139,7 +142,7 @@ __global__ __launch_bounds__(NTHR) void ggemm_kernel(const GemmTile* __restrict_
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = tile.m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+        const int row = tile.m0 + wm * 32 + i * 16 + Mfma<TC>::row(lane, r);
         const int col = tile.n0 + wn * 32 + j * 16 + (lane & 15);
         if (row < task.M && col < task.N) Cp[(int64_t)row * task.ldc + col] = (TO)acc[i][j][r];
       }
