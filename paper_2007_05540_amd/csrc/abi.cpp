@@ -64,6 +64,7 @@ struct Carve {
 struct ApplyWS {
   double* T1;
   double* T2;
+  double* part;     // split-K partial tiles of S3
   double* coef;
   float* L32;
   float* R32;
@@ -73,6 +74,7 @@ static ApplyWS carve_apply(const bsdmrg_plan_s* P, Carve& c) {
   ApplyWS w;
   w.T1 = c.take<double>(P->t1_elems);
   w.T2 = c.take<double>(P->t2_elems);
+  w.part = c.take<double>(std::max<int64_t>(P->s3_part_elems, 1));
   w.coef = c.take<double>(std::max<int64_t>(P->n_coefs, 1));
   w.L32 = c.take<float>(P->L_elems);
   w.R32 = c.take<float>(P->R_elems);
@@ -101,6 +103,9 @@ static void upload(bsdmrg_plan_s* P) {
       {P->mix_tasks.data(), P->mix_tasks.size() * sizeof(MixTask), (void**)&P->d_mix_tasks},
       {P->mix_terms.data(), P->mix_terms.size() * sizeof(MixTerm), (void**)&P->d_mix_terms},
       {P->mix_items.data(), P->mix_items.size() * sizeof(MixItem), (void**)&P->d_mix_items},
+      {P->red_tasks.data(), P->red_tasks.size() * sizeof(MixTask), (void**)&P->d_red_tasks},
+      {P->red_terms.data(), P->red_terms.size() * sizeof(MixTerm), (void**)&P->d_red_terms},
+      {P->red_items.data(), P->red_items.size() * sizeof(MixItem), (void**)&P->d_red_items},
       {P->coef_ptr.data(), P->coef_ptr.size() * sizeof(int32_t), (void**)&P->d_coef_ptr},
       {P->coef_e1.data(), P->coef_e1.size() * sizeof(int64_t), (void**)&P->d_coef_e1},
       {P->coef_e2.data(), P->coef_e2.size() * sizeof(int64_t), (void**)&P->d_coef_e2},
@@ -149,13 +154,13 @@ static void matvec(const bsdmrg_plan_s* P, int prec, const double* L, const doub
   if (prec == BSDMRG_F64) {
     HIPCHK(launch_s1_f64(P, L, psi, w.T1, s));
     HIPCHK(launch_mix_f64(P, w.coef, w.T1, w.T2, s));
-    HIPCHK(launch_s3_f64(P, w.T2, R, out, s));
+    HIPCHK(launch_s3_f64(P, w.T2, R, out, w.part, s));
   } else {
     float* T1 = (float*)w.T1;
     float* T2 = (float*)w.T2;
     HIPCHK(launch_s1_f32(P, w.L32, psi, T1, s));
     HIPCHK(launch_mix_f32(P, w.coef, T1, T2, s));
-    HIPCHK(launch_s3_f32(P, T2, w.R32, out, s));
+    HIPCHK(launch_s3_f32(P, T2, w.R32, out, w.part, s));
   }
 }
 
@@ -187,6 +192,7 @@ static EigWS carve_eig(const bsdmrg_plan_s* P, const bsdmrg_eig_opts* o, Carve& 
   d.part_b = c.take<double>((size_t)(B + 1) * nch);
   d.part_n0 = c.take<double>(nch);
   d.part_n1 = c.take<double>(nch);
+  d.red = c.take<double>((size_t)np * 64);
   d.M = c.take<double>((size_t)np * B * B);
   d.svec = c.take<double>((size_t)np * B);
   d.lam = c.take<double>(np);
@@ -251,7 +257,7 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
   HIPCHK(dav_fill_zero(d.VA, (int64_t)d.B * n, s));
   HIPCHK(dav_fill_zero((double*)d.restarts, np + 1, s));
   HIPCHK(dav_dots(P, 1, psi, 0, psi, d.part_a, s));
-  HIPCHK(dav_normalize(P, d.part_a, psi, d.V, s));
+  HIPCHK(dav_normalize(P, d.part_a, d.red, psi, d.V, s));
   struct Phase {
     int prec, maxit;
     double tol;
@@ -269,13 +275,13 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
     const Phase& f = phases[ph];
     if (ph > 0) {
       HIPCHK(dav_dots(P, 1, d.x, 0, d.x, d.part_a, s));
-      HIPCHK(dav_normalize(P, d.part_a, d.x, d.V, s));
+      HIPCHK(dav_normalize(P, d.part_a, d.red, d.x, d.V, s));
     }
     matvec(P, f.prec, L, R, w.a, d.V, d.VA, s);
     for (int i = 0; i < f.maxit; ++i, ++global_it) {
       HIPCHK(dav_dots(P, i + 1, d.VA, n, d.V + (int64_t)i * n, d.part_a, s));
       HIPCHK(dav_gram_eig(P, d, i, s));
-      HIPCHK(dav_ritz(P, d, i, s));
+      HIPCHK(dav_ritz(P, d, i, false, s));
       for (int p = 0; p < np; ++p) (f.prec == BSDMRG_F64 ? it64 : it32)[p] = i + 1;
       if (!o->fixed_iters) {
         HIPCHK(hipMemcpyAsync(hpart.data(), d.part_n0, hpart.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -289,9 +295,15 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
           conv[p] = res[p] <= f.tol;
           all = all && conv[p];
         }
-        if (all) break;
+        if (all) {
+          HIPCHK(dav_ritz(P, d, i, true, s));
+          break;
+        }
       }
-      if (i == f.maxit - 1) break;
+      if (i == f.maxit - 1) {
+        HIPCHK(dav_ritz(P, d, i, true, s));
+        break;
+      }
       HIPCHK(dav_dots(P, i + 1, d.V, n, d.q, d.part_a, s));
       HIPCHK(dav_update(P, d, i + 1, d.part_a, d.part_b, 1, s));
       HIPCHK(dav_update(P, d, i + 1, d.part_b, d.part_n1, 2, s));
@@ -301,7 +313,7 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
     }
   }
   HIPCHK(dav_dots(P, 1, d.x, 0, d.x, d.part_a, s));
-  HIPCHK(dav_normalize(P, d.part_a, d.x, psi, s));
+  HIPCHK(dav_normalize(P, d.part_a, d.red, d.x, psi, s));
   (void)global_it;
 }
 
@@ -537,11 +549,11 @@ bsdmrg_status bsdmrg_stage_timing(bsdmrg_plan_t P, int32_t precision, const doub
         if (precision == BSDMRG_F64) {
           if (stage == 1) HIPCHK(launch_s1_f64(P, L, psi, w.T1, s));
           if (stage == 2) HIPCHK(launch_mix_f64(P, w.coef, w.T1, w.T2, s));
-          if (stage == 3) HIPCHK(launch_s3_f64(P, w.T2, R, out, s));
+          if (stage == 3) HIPCHK(launch_s3_f64(P, w.T2, R, out, w.part, s));
         } else {
           if (stage == 1) HIPCHK(launch_s1_f32(P, w.L32, psi, T1f, s));
           if (stage == 2) HIPCHK(launch_mix_f32(P, w.coef, T1f, T2f, s));
-          if (stage == 3) HIPCHK(launch_s3_f32(P, T2f, w.R32, out, s));
+          if (stage == 3) HIPCHK(launch_s3_f32(P, T2f, w.R32, out, w.part, s));
         }
       }
       HIPCHK(hipEventRecord(ev[1], s));

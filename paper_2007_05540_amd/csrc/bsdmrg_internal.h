@@ -13,7 +13,7 @@ namespace bsd {
 
 constexpr int kAlign = 32;          // block alignment in elements (256 B in FP64)
 constexpr int kMaxOrder = 8;
-constexpr int kChunk = 4096;        // Davidson reduction chunk (elements)
+constexpr int kChunk = 2048;        // Davidson reduction chunk (elements)
 
 using Charge = std::array<int32_t, 2>;
 using Key = std::array<int32_t, kMaxOrder>;
@@ -60,6 +60,7 @@ struct GemmSeg {
 struct GemmTask {
   int64_t c_off;
   int32_t ldc, M, N, seg0, nseg, ksum;
+  int32_t cbuf, pad;   // cbuf 0: output buffer, 1: split-K partial buffer
 };
 struct GemmTile {
   int32_t task, m0, n0, pad;
@@ -117,6 +118,14 @@ struct bsdmrg_plan_s {
   int64_t psi_elems = 0, L_elems = 0, R_elems = 0, W1_elems = 0, W2_elems = 0;
   int64_t t1_elems = 0, t2_elems = 0, n_coefs = 0;
   bsd::Stage s1, s3;
+  // split-K of S3: partial tiles summed in fixed order by the mixing kernel
+  int64_t s3_part_elems = 0;
+  std::vector<bsd::MixTask> red_tasks;
+  std::vector<bsd::MixTerm> red_terms;
+  std::vector<bsd::MixItem> red_items;
+  bsd::MixTask* d_red_tasks = nullptr;
+  bsd::MixTerm* d_red_terms = nullptr;
+  bsd::MixItem* d_red_items = nullptr;
   std::vector<bsd::MixTask> mix_tasks;
   std::vector<bsd::MixTerm> mix_terms;
   std::vector<bsd::MixItem> mix_items;

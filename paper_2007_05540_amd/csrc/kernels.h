@@ -11,11 +11,11 @@ namespace bsd {
 hipError_t launch_s1_f64(const bsdmrg_plan_s* P, const double* L, const double* psi, double* T1,
                          hipStream_t s);
 hipError_t launch_s3_f64(const bsdmrg_plan_s* P, const double* T2, const double* R, double* out,
-                         hipStream_t s);
+                         double* part, hipStream_t s);
 hipError_t launch_s1_f32(const bsdmrg_plan_s* P, const float* L, const double* psi, float* T1,
                          hipStream_t s);
 hipError_t launch_s3_f32(const bsdmrg_plan_s* P, const float* T2, const float* R, double* out,
-                         hipStream_t s);
+                         double* part, hipStream_t s);
 hipError_t launch_mix_f64(const bsdmrg_plan_s* P, const double* coef, const double* T1, double* T2,
                           hipStream_t s);
 hipError_t launch_mix_f32(const bsdmrg_plan_s* P, const double* coef, const float* T1, float* T2,
@@ -35,6 +35,7 @@ struct DavBufs {
   double* part_b;
   double* part_n0;  // nchunk: ||q||^2 before orthogonalisation
   double* part_n1;  // nchunk: ||q||^2 after
+  double* red;      // n_probs * 64 per-problem sums of partials
   double* M;        // n_probs * B * B projected matrices
   double* svec;     // n_probs * B Ritz vectors of M
   double* lam;      // n_probs
@@ -48,10 +49,10 @@ struct DavBufs {
 hipError_t dav_fill_zero(double* x, int64_t n, hipStream_t s);
 hipError_t dav_dots(const bsdmrg_plan_s* P, int J, const double* X, int64_t xstride, const double* y,
                     double* part, hipStream_t s);
-hipError_t dav_normalize(const bsdmrg_plan_s* P, const double* part, const double* x, double* y,
+hipError_t dav_normalize(const bsdmrg_plan_s* P, const double* part, double* red, const double* x, double* y,
                          hipStream_t s);
 hipError_t dav_gram_eig(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStream_t s);
-hipError_t dav_ritz(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStream_t s);
+hipError_t dav_ritz(const bsdmrg_plan_s* P, const DavBufs& b, int i, bool want_x, hipStream_t s);
 hipError_t dav_update(const bsdmrg_plan_s* P, const DavBufs& b, int J, const double* part_in,
                       double* part_out, int mode, hipStream_t s);
 hipError_t dav_finalize(const bsdmrg_plan_s* P, const DavBufs& b, int i, uint64_t seed, double rtol,

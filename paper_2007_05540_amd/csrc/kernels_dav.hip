@@ -29,6 +29,33 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return sh[8];
 }
 
+// out[j] = sum over the problem's chunks of part[j * nct + chunk] for j < J
+// (thread-strided sums, then the deterministic block tree); result in LDS.
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int nct, const DavProb& pr,
+                                             int J, double* out, double* sh) {
+  for (int j = 0; j < J; ++j) {
+    double v = 0.0;
+    for (int c = threadIdx.x; c < pr.nchunk; c += blockDim.x) v += part[(int64_t)j * nct + pr.chunk0 + c];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) out[j] = v;
+  }
+  __syncthreads();
+}
+
+// red[p * ldr + j] = sum over problem p's chunks of part[j * nct + chunk]
+// (grid: problems x J); one fixed reduction order.
+__global__ __launch_bounds__(DT) void psum_kernel(const DavProb* __restrict__ probs, int nct, int J,
+                                                  const double* __restrict__ part, int ldr,
+                                                  double* __restrict__ red) {
+  __shared__ double sh[16];
+  const int p = blockIdx.x, j = blockIdx.y;
+  const DavProb pr = probs[p];
+  double v = 0.0;
+  for (int c = threadIdx.x; c < pr.nchunk; c += DT) v += part[(int64_t)j * nct + pr.chunk0 + c];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) red[(int64_t)p * ldr + j] = v;
+}
+
 // part[j * nct + ch] = sum_{e in chunk ch} X_j[e] y[e], j < J
 __global__ __launch_bounds__(DT) void dots_kernel(const Chunk* __restrict__ chunks, int nct, int J,
                                                   const double* __restrict__ X, int64_t xstride,
@@ -54,98 +81,116 @@ __global__ __launch_bounds__(DT) void dots_kernel(const Chunk* __restrict__ chun
   }
 }
 
-// y = x / ||x||_p with ||x||_p^2 = sum of the problem's chunk partials.
-__global__ __launch_bounds__(DT) void normalize_kernel(const Chunk* __restrict__ chunks,
-                                                       const DavProb* __restrict__ probs,
-                                                       const double* __restrict__ part,
+// y = x / ||x||_p with ||x||_p^2 = red[p * ldr].
+__global__ __launch_bounds__(DT) void normalize_kernel(const Chunk* __restrict__ chunks, int ldr,
+                                                       const double* __restrict__ red,
                                                        const double* __restrict__ x,
                                                        double* __restrict__ y) {
-  __shared__ double inv;
   const Chunk ch = chunks[blockIdx.x];
-  if (threadIdx.x == 0) {
-    const DavProb pr = probs[ch.prob];
-    double s = 0.0;
-    for (int c = 0; c < pr.nchunk; ++c) s += part[pr.chunk0 + c];
-    inv = 1.0 / sqrt(s);
-  }
-  __syncthreads();
+  const double inv = 1.0 / sqrt(red[(int64_t)ch.prob * ldr]);
   for (int e = threadIdx.x; e < ch.len; e += DT) y[ch.start + e] = x[ch.start + e] * inv;
 }
 
 // Gram row m_ij = m_ji = (v^A_j)^T v_i (j <= i) from the chunk partials, then
-// the lowest eigenpair of the (i+1) x (i+1) projected matrix by cyclic Jacobi
-// rotations (one wave per problem, matrix in LDS).
+// the lowest eigenpair of the (i+1) x (i+1) projected matrix by parallel
+// (round-robin ordered) Jacobi rotations: in every step the indices form
+// ne/2 disjoint pairs, all rotations of a step are computed at once and
+// applied in place as 2 x 2 block updates A <- J^T A J, V <- V J.  An odd
+// size gets a zero dummy index that is never selected.
 constexpr int kMaxBasis = 64;
-__global__ __launch_bounds__(64) void gram_eig_kernel(const DavProb* __restrict__ probs, int nct, int i,
-                                                      int B, const double* __restrict__ part,
+__global__ __launch_bounds__(DT) void gram_eig_kernel(int ldr, int i, int B, const double* __restrict__ red,
                                                       double* __restrict__ M, double* __restrict__ svec,
                                                       double* __restrict__ lam) {
   __shared__ double A[kMaxBasis][kMaxBasis + 1];
   __shared__ double V[kMaxBasis][kMaxBasis + 1];
-  const int p = blockIdx.x, k = threadIdx.x, n = i + 1;
-  const DavProb pr = probs[p];
+  __shared__ double pc[kMaxBasis / 2], ps[kMaxBasis / 2];
+  __shared__ int pp[kMaxBasis / 2], pq[kMaxBasis / 2];
+  __shared__ double sh[16];
+  const int p = blockIdx.x, tid = threadIdx.x, n = i + 1;
+  const int ne = n + (n & 1);
+  const int half = ne / 2;
   double* Mp = M + (int64_t)p * B * B;
-  if (k <= i) {
-    double s = 0.0;
-    for (int c = 0; c < pr.nchunk; ++c) s += part[(int64_t)k * nct + pr.chunk0 + c];
-    Mp[i * B + k] = s;
-    Mp[k * B + i] = s;
+  if (tid <= i) {
+    const double v = red[(int64_t)p * ldr + tid];
+    Mp[i * B + tid] = v;
+    Mp[tid * B + i] = v;
   }
   __threadfence_block();
   __syncthreads();
-  if (k < n)
-    for (int c = 0; c < n; ++c) {
-      A[k][c] = Mp[k * B + c];
-      V[k][c] = (k == c) ? 1.0 : 0.0;
-    }
+  for (int e = tid; e < ne * ne; e += DT) {
+    const int r = e / ne, c = e % ne;
+    A[r][c] = (r < n && c < n) ? Mp[r * B + c] : 0.0;
+    V[r][c] = (r == c) ? 1.0 : 0.0;
+  }
   __syncthreads();
-  // Frobenius norm (for the thresholds)
-  double fro = 0.0;
-  for (int r = 0; r < n; ++r)
-    for (int c = 0; c < n; ++c) fro += A[r][c] * A[r][c];
-  const double tiny = 1e-18 * sqrt(fro);
-  for (int sweep = 0; sweep < 50; ++sweep) {
-    double off = 0.0;
-    for (int r = 0; r < n; ++r)
-      for (int c = 0; c < n; ++c)
-        if (r != c) off += A[r][c] * A[r][c];
-    if (off <= 1e-34 * fro || off == 0.0) break;
-    for (int pp = 0; pp < n - 1; ++pp)
-      for (int qq = pp + 1; qq < n; ++qq) {
-        const double apq = A[pp][qq];
-        if (fabs(apq) <= tiny) continue;
-        const double app = A[pp][pp], aqq = A[qq][qq];
-        const double tau = (aqq - app) / (2.0 * apq);
-        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-        __syncthreads();
-        if (k < n) {
-          const double akp = A[k][pp], akq = A[k][qq];
-          A[k][pp] = c * akp - s * akq;
-          A[k][qq] = s * akp + c * akq;
+  double f = 0.0;
+  for (int e = tid; e < n * n; e += DT) f += A[e / n][e % n] * A[e / n][e % n];
+  const double fro2 = block_sum(f, sh);
+  const double tiny = 1e-17 * sqrt(fro2);
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double o = 0.0;
+    for (int e = tid; e < n * n; e += DT) {
+      const int r = e / n, c = e % n;
+      if (r != c) o += A[r][c] * A[r][c];
+    }
+    const double off = block_sum(o, sh);
+    if (off <= 1e-32 * fro2) break;
+    for (int step = 0; step < ne - 1; ++step) {
+      if (tid < half) {
+        // circle method: position 0 fixed, the others rotate by one per step
+        auto player = [&](int k) { return k == 0 ? 0 : 1 + ((k - 1 + step) % (ne - 1)); };
+        const int a = player(tid), b = player(ne - 1 - tid);
+        const int P = min(a, b), Q = max(a, b);
+        const double apq = A[P][Q];
+        double c = 1.0, sn = 0.0;
+        if (fabs(apq) > tiny) {
+          const double tau = (A[Q][Q] - A[P][P]) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          sn = t * c;
         }
-        __syncthreads();
-        if (k < n) {
-          const double apk = A[pp][k], aqk = A[qq][k];
-          A[pp][k] = c * apk - s * aqk;
-          A[qq][k] = s * apk + c * aqk;
-          const double vkp = V[k][pp], vkq = V[k][qq];
-          V[k][pp] = c * vkp - s * vkq;
-          V[k][qq] = s * vkp + c * vkq;
-        }
-        __syncthreads();
-        if (k == 0) { A[pp][qq] = 0.0; A[qq][pp] = 0.0; }
-        __syncthreads();
+        pp[tid] = P; pq[tid] = Q; pc[tid] = c; ps[tid] = sn;
       }
+      __syncthreads();
+      for (int e = tid; e < half * half; e += DT) {
+        const int kr = e / half, kc = e % half;
+        if (ps[kr] == 0.0 && ps[kc] == 0.0) continue;
+        const int r0 = pp[kr], r1 = pq[kr], c0 = pp[kc], c1 = pq[kc];
+        const double cr = pc[kr], sr = ps[kr], cc = pc[kc], sc = ps[kc];
+        const double b00 = A[r0][c0], b01 = A[r0][c1], b10 = A[r1][c0], b11 = A[r1][c1];
+        const double x00 = b00 * cc - b01 * sc, x01 = b00 * sc + b01 * cc;
+        const double x10 = b10 * cc - b11 * sc, x11 = b10 * sc + b11 * cc;
+        A[r0][c0] = cr * x00 - sr * x10;
+        A[r1][c1] = sr * x01 + cr * x11;
+        if (kr == kc) {
+          A[r0][c1] = 0.0;
+          A[r1][c0] = 0.0;
+        } else {
+          A[r0][c1] = cr * x01 - sr * x11;
+          A[r1][c0] = sr * x00 + cr * x10;
+        }
+      }
+      for (int e = tid; e < ne * half; e += DT) {
+        const int r = e / half, kc = e % half;
+        if (ps[kc] == 0.0) continue;
+        const int c0 = pp[kc], c1 = pq[kc];
+        const double cc = pc[kc], sc = ps[kc];
+        const double v0 = V[r][c0], v1 = V[r][c1];
+        V[r][c0] = v0 * cc - v1 * sc;
+        V[r][c1] = v0 * sc + v1 * cc;
+      }
+      __syncthreads();
+    }
   }
   int idx = 0;
   for (int r = 1; r < n; ++r)
     if (A[r][r] < A[idx][idx]) idx = r;
-  if (k < n) svec[(int64_t)p * B + k] = V[k][idx];
-  if (k == 0) lam[p] = A[idx][idx];
+  if (tid < n) svec[(int64_t)p * B + tid] = V[tid][idx];
+  if (tid == 0) lam[p] = A[idx][idx];
 }
 
-// x = sum s_j v_j, q = sum s_j v^A_j - lambda x, partial ||q||^2.
+// q = sum s_j v^A_j - lambda sum s_j v_j with partial ||q||^2; when x is
+// non-null the Ritz vector x = sum s_j v_j is stored too.
 __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chunks, int J, int B,
                                                   const double* __restrict__ V, const double* __restrict__ VA,
                                                   int64_t stride, const double* __restrict__ svec,
@@ -168,7 +213,7 @@ __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chun
       av += sv[j] * VA[j * stride + g];
     }
     const double qv = av - l * xv;
-    x[g] = xv;
+    if (x) x[g] = xv;
     q[g] = qv;
     nrm += qv * qv;
   }
@@ -176,23 +221,17 @@ __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chun
   if (threadIdx.x == 0) part[blockIdx.x] = nrm;
 }
 
-// q -= sum_j c_j v_j with c_j = sum of the problem's chunk partials of
-// part_in; mode 1 then writes the partial dots v_j^T q, mode 2 ||q||^2.
-__global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ chunks,
-                                                    const DavProb* __restrict__ probs, int nct, int J,
-                                                    const double* __restrict__ V, int64_t stride,
-                                                    const double* __restrict__ part_in,
+// q -= sum_j c_j v_j with c_j = red[p * ldr + j]; mode 1 then writes the
+// partial dots v_j^T q, mode 2 the partial ||q||^2.
+__global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ chunks, int nct, int J,
+                                                    const double* __restrict__ V, int64_t stride, int ldr,
+                                                    const double* __restrict__ red,
                                                     double* __restrict__ q, double* __restrict__ part_out,
                                                     int mode) {
   __shared__ double sh[16];
   __shared__ double cj[kMaxBasis];
   const Chunk ch = chunks[blockIdx.x];
-  const DavProb pr = probs[ch.prob];
-  if ((int)threadIdx.x < J) {
-    double s = 0.0;
-    for (int c = 0; c < pr.nchunk; ++c) s += part_in[(int64_t)threadIdx.x * nct + pr.chunk0 + c];
-    cj[threadIdx.x] = s;
-  }
+  if ((int)threadIdx.x < J) cj[threadIdx.x] = red[(int64_t)ch.prob * ldr + threadIdx.x];
   __syncthreads();
   double qv[PER];
 #pragma unroll
@@ -256,13 +295,12 @@ __global__ __launch_bounds__(DT) void finalize_kernel(const DavProb* __restrict_
                                                       int32_t* __restrict__ status) {
   __shared__ double sh[16];
   __shared__ double cj[kMaxBasis];
+  __shared__ double nn[2];
   const int p = blockIdx.x;
   const DavProb pr = probs[p];
-  double nb = 0.0, na = 0.0;
-  for (int c = 0; c < pr.nchunk; ++c) {
-    nb += part_n0[pr.chunk0 + c];
-    na += part_n1[pr.chunk0 + c];
-  }
+  sum_partials(part_n0, 0, pr, 1, nn, sh);
+  sum_partials(part_n1, 0, pr, 1, nn + 1, sh);
+  const double nb = nn[0], na = nn[1];
   if (na >= rtol * rtol * nb && na > 0.0) {
     if (threadIdx.x == 0) scale[p] = 1.0 / sqrt(na);
     return;
@@ -339,29 +377,40 @@ hipError_t dav_dots(const bsdmrg_plan_s* P, int J, const double* X, int64_t xstr
   return hipGetLastError();
 }
 
-hipError_t dav_normalize(const bsdmrg_plan_s* P, const double* part, const double* x, double* y,
+hipError_t dav_psum(const bsdmrg_plan_s* P, int J, const double* part, double* red, int ldr, hipStream_t s) {
+  hipLaunchKernelGGL(psum_kernel, dim3((unsigned)P->probs.size(), (unsigned)J), dim3(DT), 0, s, dav_probs(P),
+                     (int)nchunks(P), J, part, ldr, red);
+  return hipGetLastError();
+}
+
+hipError_t dav_normalize(const bsdmrg_plan_s* P, const double* part, double* red, const double* x, double* y,
                          hipStream_t s) {
-  hipLaunchKernelGGL(normalize_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, dav_probs(P), part,
-                     x, y);
+  hipError_t e = dav_psum(P, 1, part, red, 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(normalize_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, 1, red, x, y);
   return hipGetLastError();
 }
 
 hipError_t dav_gram_eig(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStream_t s) {
-  hipLaunchKernelGGL(gram_eig_kernel, dim3((unsigned)P->probs.size()), dim3(64), 0, s, dav_probs(P),
-                     (int)nchunks(P), i, b.B, b.part_a, b.M, b.svec, b.lam);
+  hipError_t e = dav_psum(P, i + 1, b.part_a, b.red, kMaxBasis, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gram_eig_kernel, dim3((unsigned)P->probs.size()), dim3(DT), 0, s, kMaxBasis, i, b.B,
+                     b.red, b.M, b.svec, b.lam);
   return hipGetLastError();
 }
 
-hipError_t dav_ritz(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStream_t s) {
+hipError_t dav_ritz(const bsdmrg_plan_s* P, const DavBufs& b, int i, bool want_x, hipStream_t s) {
   hipLaunchKernelGGL(ritz_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, i + 1, b.B, b.V, b.VA, b.n,
-                     b.svec, b.lam, b.x, b.q, b.part_n0);
+                     b.svec, b.lam, want_x ? b.x : nullptr, b.q, b.part_n0);
   return hipGetLastError();
 }
 
 hipError_t dav_update(const bsdmrg_plan_s* P, const DavBufs& b, int J, const double* part_in,
                       double* part_out, int mode, hipStream_t s) {
-  hipLaunchKernelGGL(update_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, dav_probs(P),
-                     (int)nchunks(P), J, b.V, b.n, part_in, b.q, part_out, mode);
+  hipError_t e = dav_psum(P, J, part_in, b.red, kMaxBasis, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(update_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), J, b.V,
+                     b.n, kMaxBasis, b.red, b.q, part_out, mode);
   return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ __global__ __launch_bounds__(NTHR) void ggemm_kernel(const GemmTile* __restrict_
                                                      const GemmSeg* __restrict__ segs,
                                                      const TA* __restrict__ A,
                                                      const TB* __restrict__ B,
-                                                     TO* __restrict__ C) {
+                                                     TO* __restrict__ C, TO* __restrict__ Cpart) {
   __shared__ TC As[BK][BM + 1];
   __shared__ TC Bs[BK][BN + 1];
   const GemmTile tile = tiles[blockIdx.x];
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(NTHR) void ggemm_kernel(const GemmTile* __restrict_
     }
   }
 
-  TO* Cp = C + task.c_off;
+  TO* Cp = (task.cbuf ? Cpart : C) + task.c_off;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -148,22 +148,31 @@ __global__ __launch_bounds__(NTHR) void ggemm_kernel(const GemmTile* __restrict_
       }
 }
 
-// MPO mixing (S2): each workgroup handles one row range of one task.
+// MPO mixing (S2): each workgroup handles one row range of one task; every
+// thread owns up to 16 elements and issues the 16 loads of a term together.
+// coef == nullptr means unit coefficients (the split-K reduction).
 template <typename T, typename TACC>
 __global__ __launch_bounds__(NTHR) void mix_kernel(const MixItem* __restrict__ items,
                                                    const MixTask* __restrict__ tasks,
                                                    const MixTerm* __restrict__ terms,
                                                    const double* __restrict__ coef,
                                                    const T* __restrict__ src, T* __restrict__ dst) {
+  constexpr int PER = 16;   // kMixItemElems = 4096 = 16 * 256
   __shared__ int64_t s_off[64];
   __shared__ int32_t s_ld[64];
   __shared__ TACC s_c[64];
   const MixItem it = items[blockIdx.x];
   const MixTask t = tasks[it.task];
   const int n = it.nrows * t.cols;
-  TACC accv[16];
-  // up to 16 elements per thread (kMixItemElems = 4096 = 16 * 256)
-  for (int q = 0; q < 16; ++q) accv[q] = 0;
+  int rr[PER], cc[PER];
+  TACC acc[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * NTHR;
+    rr[q] = it.row0 + e / t.cols;
+    cc[q] = e % t.cols;
+    acc[q] = 0;
+  }
   for (int t0 = 0; t0 < t.nterm; t0 += 64) {
     const int nt = min(64, t.nterm - t0);
     __syncthreads();
@@ -171,23 +180,27 @@ __global__ __launch_bounds__(NTHR) void mix_kernel(const MixItem* __restrict__ i
       const MixTerm m = terms[t.term0 + t0 + threadIdx.x];
       s_off[threadIdx.x] = m.src_off;
       s_ld[threadIdx.x] = m.ld_src;
-      s_c[threadIdx.x] = (TACC)coef[m.coef];
+      s_c[threadIdx.x] = coef ? (TACC)coef[m.coef] : (TACC)1;
     }
     __syncthreads();
-    for (int q = 0; q < 16; ++q) {
-      const int e = threadIdx.x + q * NTHR;
-      if (e >= n) break;
-      const int r = it.row0 + e / t.cols, c = e % t.cols;
-      TACC acc = accv[q];
-      for (int j = 0; j < nt; ++j) acc += s_c[j] * (TACC)src[s_off[j] + (int64_t)r * s_ld[j] + c];
-      accv[q] = acc;
+    for (int j = 0; j < nt; ++j) {
+      const T* sp = src + s_off[j];
+      const int ld = s_ld[j];
+      const TACC cj = s_c[j];
+      T v[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * NTHR;
+        v[q] = e < n ? sp[(int64_t)rr[q] * ld + cc[q]] : (T)0;
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) acc[q] += cj * (TACC)v[q];
     }
   }
-  for (int q = 0; q < 16; ++q) {
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
     const int e = threadIdx.x + q * NTHR;
-    if (e >= n) break;
-    const int r = it.row0 + e / t.cols, c = e % t.cols;
-    dst[t.dst_off + (int64_t)r * t.ld_dst + c] = (T)accv[q];
+    if (e < n) dst[t.dst_off + (int64_t)rr[q] * t.ld_dst + cc[q]] = (T)acc[q];
   }
 }
 
@@ -210,28 +223,39 @@ __global__ void cast_f64_f32_kernel(int64_t n, const double* __restrict__ x, flo
 
 // ---------------------------------------------------------------- launches --
 template <typename TC, typename TA, typename TB, typename TO, bool BT>
-static hipError_t launch_gemm(const Stage& st, const TA* A, const TB* B, TO* C, hipStream_t s) {
+static hipError_t launch_gemm(const Stage& st, const TA* A, const TB* B, TO* C, TO* Cpart, hipStream_t s) {
   if (st.tiles.empty()) return hipSuccess;
   hipLaunchKernelGGL((ggemm_kernel<TC, TA, TB, TO, BT>), dim3((unsigned)st.tiles.size()), dim3(NTHR), 0,
-                     s, st.d_tiles, st.d_tasks, st.d_segs, A, B, C);
+                     s, st.d_tiles, st.d_tasks, st.d_segs, A, B, C, Cpart);
+  return hipGetLastError();
+}
+
+static hipError_t launch_reduce(const bsdmrg_plan_s* P, const double* part, double* out, hipStream_t s) {
+  if (P->red_items.empty()) return hipSuccess;
+  hipLaunchKernelGGL((mix_kernel<double, double>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
+                     P->d_red_items, P->d_red_tasks, P->d_red_terms, (const double*)nullptr, part, out);
   return hipGetLastError();
 }
 
 hipError_t launch_s1_f64(const bsdmrg_plan_s* P, const double* L, const double* psi, double* T1,
                          hipStream_t s) {
-  return launch_gemm<double, double, double, double, false>(P->s1, L, psi, T1, s);
+  return launch_gemm<double, double, double, double, false>(P->s1, L, psi, T1, T1, s);
 }
 hipError_t launch_s3_f64(const bsdmrg_plan_s* P, const double* T2, const double* R, double* out,
-                         hipStream_t s) {
-  return launch_gemm<double, double, double, double, true>(P->s3, T2, R, out, s);
+                         double* part, hipStream_t s) {
+  hipError_t e = launch_gemm<double, double, double, double, true>(P->s3, T2, R, out, part, s);
+  if (e != hipSuccess) return e;
+  return launch_reduce(P, part, out, s);
 }
 hipError_t launch_s1_f32(const bsdmrg_plan_s* P, const float* L, const double* psi, float* T1,
                          hipStream_t s) {
-  return launch_gemm<float, float, double, float, false>(P->s1, L, psi, T1, s);
+  return launch_gemm<float, float, double, float, false>(P->s1, L, psi, T1, T1, s);
 }
 hipError_t launch_s3_f32(const bsdmrg_plan_s* P, const float* T2, const float* R, double* out,
-                         hipStream_t s) {
-  return launch_gemm<float, float, float, double, true>(P->s3, T2, R, out, s);
+                         double* part, hipStream_t s) {
+  hipError_t e = launch_gemm<float, float, float, double, true>(P->s3, T2, R, out, part, s);
+  if (e != hipSuccess) return e;
+  return launch_reduce(P, part, out, s);
 }
 
 hipError_t launch_mix_f64(const bsdmrg_plan_s* P, const double* coef, const double* T1, double* T2,

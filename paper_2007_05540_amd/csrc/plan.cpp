@@ -23,6 +23,7 @@ namespace bsd {
 
 constexpr int kTileM = 64, kTileN = 64;
 constexpr int kMixItemElems = 4096;
+constexpr int kSplitK = 512;        // S3 K pieces longer than this are split
 
 static const int32_t kPsiSigns[4] = {1, 1, 1, -1};
 static const int32_t kEnvSigns[3] = {-1, 1, 1};
@@ -99,7 +100,7 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
       const int32_t N = (int32_t)p.c.d[ic];
       const int32_t K = (int32_t)p.a.d[ia];
       GemmSeg s{p.L_base + p.L.offs[lb], p.psi_base + p.psi.offs[pb], K, N, K, 0};
-      GemmTask t{p.t1_base + t1_cursor, N, M, N, (int32_t)P->s1.segs.size(), 1, K};
+      GemmTask t{p.t1_base + t1_cursor, N, M, N, (int32_t)P->s1.segs.size(), 1, K, 0, 0};
       P->s1.segs.push_back(s);
       P->s1.tasks.push_back(t);
       P->s1.flops += 2.0 * M * N * (double)K;
@@ -174,6 +175,8 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
               }
           if (!exists) continue;
           const int64_t ba = p.a.d[iap], bc = p.c.d[ic], ng = p.wr.d[g];
+          if (bc > kMixItemElems || ba > (1 << 30))
+            throw Error{BSDMRG_EINVAL, "plan: sector dimensions above 4096 are not supported"};
           t2[key4(iap, s1p, s2p, g)] = {t2_cursor, ic};
           for (int iwpp = 0; iwpp < ng; ++iwpp) {
             MixTask mt{p.t2_base + t2_cursor + iwpp * bc, (int32_t)(ng * bc), (int32_t)ba,
@@ -209,7 +212,7 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
     const Key& k = p.psi.keys[ob];
     int iap = k[0], s1p = k[1], s2p = k[2], icp = k[3];
     const int32_t M = (int32_t)p.a.d[iap], N = (int32_t)p.c.d[icp];
-    GemmTask t{p.psi_base + p.psi.offs[ob], N, M, N, (int32_t)P->s3.segs.size(), 0, 0};
+    GemmTask t{p.psi_base + p.psi.offs[ob], N, M, N, (int32_t)P->s3.segs.size(), 0, 0, 0, 0};
     for (int g = 0; g < p.wr.size(); ++g) {
       auto it = t2.find(key4(iap, s1p, s2p, g));
       if (it == t2.end()) continue;
@@ -229,6 +232,46 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
   P->n_coefs += p.n_coefs;
 }
 
+// Split every S3 task whose K-list is longer than kSplitK into pieces of at
+// most kSplitK (segments are cut along K: the A and B offsets move by k0
+// columns).  Each piece writes an M x N partial block; the pieces of a task
+// are summed in piece order by the reduction tables.
+static void split_k(bsdmrg_plan_s* P) {
+  Stage& st = P->s3;
+  std::vector<GemmTask> tasks;
+  std::vector<GemmSeg> segs;
+  for (const GemmTask& t : st.tasks) {
+    if (t.ksum <= kSplitK) {
+      GemmTask u = t;
+      u.seg0 = (int32_t)segs.size();
+      for (int j = 0; j < t.nseg; ++j) segs.push_back(st.segs[t.seg0 + j]);
+      tasks.push_back(u);
+      continue;
+    }
+    MixTask red{t.c_off, t.ldc, t.M, t.N, (int32_t)P->red_terms.size(), 0, 0};
+    for (int j = 0; j < t.nseg; ++j) {
+      const GemmSeg& g = st.segs[t.seg0 + j];
+      for (int k0 = 0; k0 < g.K; k0 += kSplitK) {
+        const int32_t kk = std::min(kSplitK, g.K - k0);
+        GemmSeg h{g.a_off + k0, g.b_off + k0, g.lda, g.ldb, kk, 0};
+        GemmTask u{P->s3_part_elems, t.N, t.M, t.N, (int32_t)segs.size(), 1, kk, 1, 0};
+        segs.push_back(h);
+        tasks.push_back(u);
+        P->red_terms.push_back(MixTerm{P->s3_part_elems, t.N, -1});
+        P->s3_part_elems += round_up((int64_t)t.M * t.N);
+      }
+    }
+    red.nterm = (int32_t)P->red_terms.size() - red.term0;
+    const int task = (int)P->red_tasks.size();
+    P->red_tasks.push_back(red);
+    int rows_per = std::max(1, kMixItemElems / std::max(1, t.N));
+    for (int r0 = 0; r0 < t.M; r0 += rows_per)
+      P->red_items.push_back(MixItem{task, r0, std::min(rows_per, t.M - r0), 0});
+  }
+  st.tasks.swap(tasks);
+  st.segs.swap(segs);
+}
+
 }  // namespace bsd
 
 using namespace bsd;
@@ -239,6 +282,7 @@ bsdmrg_plan_s* build_plan(const bsdmrg_problem* probs, int n_probs) {
     P->probs.resize(n_probs);
     P->coef_ptr.push_back(0);
     for (int i = 0; i < n_probs; ++i) plan_problem(P, i, probs[i]);
+    split_k(P);
     for (size_t t = 0; t < P->s1.tasks.size(); ++t) add_tiles(P->s1, (int)t);
     for (size_t t = 0; t < P->s3.tasks.size(); ++t) add_tiles(P->s3, (int)t);
     order_tiles(P->s1);
