@@ -191,16 +191,119 @@ bsdmrg_status bsdmrg_eigensolve(bsdmrg_plan_t plan, const double* L, const doubl
                                 bsdmrg_eig_stats* stats, void* workspace,
                                 int64_t workspace_bytes, hipStream_t stream);
 
-/* Adjoint of E = psi^T H_eff psi (real; E is linear in L, W1, W2, R):
- * writes g_E * dE/dX into every non-NULL output (same layout as X):
- *   d_psi = g_E (H_eff + H_eff^T) psi, d_L, d_W1, d_W2, d_R.
- * Outputs are overwritten, not accumulated; padding is written as 0.
- * FP64 only.  workspace: backward_workspace_bytes.  Errors: EINVAL, EHIP. */
+/* Adjoint of the two-site energy E_p = psi_p^T H_eff,p psi_p of every
+ * problem p (real tensors; E is linear in each of L, W1, W2, R):
+ * writes g_E[p] * dE_p/dX into problem p's part of every non-NULL output
+ * (same layout as X): d_psi = g (H_eff + H_eff^T) psi, d_L, d_W1, d_W2,
+ * d_R.  g_E: host array of n_probs cotangents.  Outputs are overwritten, not
+ * accumulated; padding is written as 0.  d_W1 / d_W2 cover every element of
+ * the W blocks that are non-zero in the w1_host / w2_host given to
+ * bsdmrg_plan; the other blocks are written as 0 (plan with the sparsity
+ * pattern whose gradient is wanted).  The first call builds and uploads the
+ * adjoint tables of the plan.  FP64; every sum runs in a fixed order.
+ * Device pointers except g_E; outputs may be NULL and must not alias an
+ * input.  workspace: backward_workspace_bytes.  Synchronises the stream.
+ * Errors: EINVAL, EHIP. */
 bsdmrg_status bsdmrg_heff_backward(bsdmrg_plan_t plan, const double* L, const double* W1,
                                    const double* W2, const double* R, const double* psi,
-                                   double g_E, double* d_psi, double* d_L, double* d_W1,
+                                   const double* g_E, double* d_psi, double* d_L, double* d_W1,
                                    double* d_W2, double* d_R, void* workspace,
                                    int64_t workspace_bytes, hipStream_t stream);
+
+/* energy[p] = psi_p^T H_eff,p psi_p (host array of n_probs; FP64 product,
+ * per-problem reductions in a fixed order).  workspace:
+ * backward_workspace_bytes.  Synchronises the stream.  Errors: EINVAL, EHIP. */
+bsdmrg_status bsdmrg_heff_energy(bsdmrg_plan_t plan, const double* L, const double* W1,
+                                 const double* W2, const double* R, const double* psi,
+                                 double* energy, void* workspace, int64_t workspace_bytes,
+                                 hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Sweep operations (Sec. II-C: split, environment extension, merge).
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t direction;   /* 0: sweeping right, A = U, B = S V^T;
+                          1: sweeping left,  A = U S, B = V^T                */
+  int32_t cutoff_mode; /* 0: discard s < cutoff * ||theta|| ("removes all
+                          singular values below" the cutoff, Sec. II-C);
+                          1: discard the smallest values whose squares sum
+                          to at most cutoff * ||theta||^2                   */
+  double cutoff;
+  int64_t max_m;       /* keep at most max_m values, largest first          */
+  double degen_rtol;   /* a kept value v with v - s_first_dropped <=
+                          degen_rtol * v is dropped too (multiplets are
+                          never split); if that drops all, the plain cut
+                          stays                                             */
+} bsdmrg_trunc_opts;
+
+/* Workspace bytes of bsdmrg_truncate for a theta with legs theta_legs[4]
+ * = (a, s1, s2, c). */
+bsdmrg_status bsdmrg_truncate_workspace(const bsdmrg_leg* theta_legs, int64_t* bytes);
+
+/* Truncated SVD split theta(a,s1,s2,c) = A(a,s1,b) B(b,s2,c) (Sec. II-C,
+ * Fig. 1e; wrapped per-charge matrices of Sec. IV-A).  theta is wrapped into
+ * one matrix per charge q of the new bond (rows (a, s1) with q_a + q_s1 = q,
+ * columns (s2, c) with q_c - q_s2 = q, lexicographic), each decomposed with
+ * rocSOLVER FP64 gesvd; singular values of all charges are pooled (ties by
+ * charge index, then index within the charge) and truncated by the options;
+ * in every kept pair the entry of u of largest magnitude (first in row order
+ * within 1e-10 relative) is made positive.  Outputs: the new bond leg
+ * (new_charges[n * n_charges], new_dims[n], ascending), A and B in canonical
+ * layout (device, padding zeroed), the kept singular values in descending
+ * order (host), their number and the discarded weight (sum of squares of
+ * the dropped values).  If leg_capacity, A_capacity, B_capacity or
+ * sv_capacity is too small, returns BSDMRG_ECAPACITY with new_n_sectors,
+ * A_elems, B_elems and n_kept set.  Synchronises the stream.
+ * Errors: EINVAL, EQN, EHIP, ESOLVER (SVD failure or theta == 0). */
+bsdmrg_status bsdmrg_truncate(const bsdmrg_leg* theta_legs, const double* theta,
+                              const bsdmrg_trunc_opts* opts, int32_t* new_n_sectors,
+                              int32_t* new_charges, int64_t* new_dims, int32_t leg_capacity,
+                              double* A, int64_t A_capacity, int64_t* A_elems, double* B,
+                              int64_t B_capacity, int64_t* B_elems, double* svals,
+                              int64_t sv_capacity, int64_t* n_kept, double* discarded,
+                              void* workspace, int64_t workspace_bytes, hipStream_t stream);
+
+typedef struct bsdmrg_op_s* bsdmrg_op_t;
+
+/* Environment extension (Sec. II-C; environments are extended from centre to
+ * centre while sweeping), FP64:
+ *  side 0 (left):  L'(b',w',b) = sum A(a',s',b') L(a',w,a) W(w,s',s,w') A(a,s,b)
+ *     env (x, wl, x), mps A (x, s, y), W (wl, s, s, wr) -> env_out (y, wr, y)
+ *  side 1 (right): R'(b',w,b) = sum B(b',s',c') W(w,s',s,w') R(c',w',c) B(b,s,c)
+ *     env (x, wr, x), mps B (y, s, x), W (wl, s, s, wr) -> env_out (y, wl, y)
+ * x is the old bond, y the new one.  w_host: W in canonical layout (host,
+ * read at plan time; its zero entries are structural zeros).  The
+ * contraction runs as GEMM, MPO mixing with the entries of W, GEMM.  Every
+ * plan (also bsdmrg_plan) checks on the host that all its index tables stay
+ * inside the operand buffers and fails with EINVAL otherwise. */
+typedef struct {
+  bsdmrg_leg x, s, y, wl, wr;
+  const double* w_host;
+} bsdmrg_env_problem;
+
+bsdmrg_status bsdmrg_env_plan(const bsdmrg_env_problem* p, int32_t side, int32_t flags,
+                              bsdmrg_op_t* out);
+
+/* Two-site merge theta(a,s1,s2,c) = sum_b A(a,s1,b) B(b,s2,c) (Sec. II-C).
+ * legs[5] = (a, s1, b, s2, c).  flags: BSDMRG_PLAN_HOST_ONLY builds and
+ * checks the tables without a device copy (as for bsdmrg_env_plan). */
+bsdmrg_status bsdmrg_merge_plan(const bsdmrg_leg* legs, int32_t flags, bsdmrg_op_t* out);
+
+/* Workspace bytes, output elements and flops of an op. */
+bsdmrg_status bsdmrg_op_query(bsdmrg_op_t op, int64_t* workspace_bytes, int64_t* out_elems,
+                              double* flops);
+bsdmrg_status bsdmrg_op_destroy(bsdmrg_op_t op);
+
+/* Run an environment op; env_out must not alias the inputs.  Errors:
+ * EINVAL, EHIP. */
+bsdmrg_status bsdmrg_env_update(bsdmrg_op_t op, const double* env, const double* mps,
+                                const double* W, double* env_out, void* workspace,
+                                int64_t workspace_bytes, hipStream_t stream);
+
+/* Run a merge op (no workspace).  Errors: EINVAL, EHIP. */
+bsdmrg_status bsdmrg_merge(bsdmrg_op_t op, const double* A, const double* B, double* theta,
+                           hipStream_t stream);
 
 /* Measurement helper: runs each stage of one product `reps` times on
  * `stream`, bracketed by HIP events recorded on that stream, and writes the

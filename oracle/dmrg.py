@@ -42,11 +42,17 @@ def mask_of(legs, signs):
     return m
 
 
+CANON_CUTOFF = 1e-14
+
+
 def right_canonicalize(mps):
+    """Right-canonical form by splits from the right (S absorbed to the left).
+    Singular values below 1e-14 of the norm are numerically zero: they carry
+    no weight and their singular vectors are not unique, so they are dropped."""
     mps = [t.copy() for t in mps]
     for j in range(len(mps) - 1, 0, -1):
         theta = merge(mps[j - 1], mps[j])
-        A, B, _, _, _ = truncate(theta, "left", cutoff=0.0, m_max=1 << 60)
+        A, B, _, _, _ = truncate(theta, "left", cutoff=CANON_CUTOFF, m_max=1 << 60)
         mps[j - 1], mps[j] = A, B
     return mps
 

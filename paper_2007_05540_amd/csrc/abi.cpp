@@ -16,6 +16,12 @@ namespace bsd {
 const char* last_error_cstr();
 void destroy_backward(bsdmrg_plan_s* P);
 void destroy_graph(bsdmrg_plan_s* P);
+int64_t heff_backward_bytes(bsdmrg_plan_s* P);
+void heff_backward_run(bsdmrg_plan_s* P, const double* L, const double* W1, const double* W2, const double* R,
+                       const double* psi, const double* g_host, double* d_psi, double* d_L, double* d_W1,
+                       double* d_W2, double* d_R, void* ws, int64_t ws_bytes, hipStream_t s);
+void heff_energy_run(bsdmrg_plan_s* P, const double* L, const double* W1, const double* W2, const double* R,
+                     const double* psi, double* energy, void* ws, int64_t ws_bytes, hipStream_t s);
 }  // namespace bsd
 
 using namespace bsd;
@@ -86,6 +92,26 @@ static size_t apply_bytes(const bsdmrg_plan_s* P) {
   carve_apply(P, c);
   return c.used;
 }
+
+namespace bsd {
+int64_t heff_apply_bytes(const bsdmrg_plan_s* P) { return (int64_t)apply_bytes(P); }
+
+// FP64 product that also hands back the intermediates (for the adjoint):
+// the apply workspace sits at the start of ws.
+void heff_forward_f64(const bsdmrg_plan_s* P, const double* L, const double* W1, const double* W2, const double* R,
+                      const double* psi, double* out, void* ws, hipStream_t s, double** T1, double** T2,
+                      double** coef) {
+  Carve c(ws, (size_t)apply_bytes(P));
+  ApplyWS w = carve_apply(P, c);
+  HIPCHK(launch_coef(P, W1, W2, w.coef, s));
+  HIPCHK(launch_s1_f64(P, L, psi, w.T1, s));
+  HIPCHK(launch_mix_f64(P, w.coef, w.T1, w.T2, s));
+  HIPCHK(launch_s3_f64(P, w.T2, R, out, w.part, s));
+  *T1 = w.T1;
+  *T2 = w.T2;
+  *coef = w.coef;
+}
+}  // namespace bsd
 
 static void upload(bsdmrg_plan_s* P) {
   struct Part {
@@ -370,9 +396,7 @@ bsdmrg_status bsdmrg_plan_query(bsdmrg_plan_t P, bsdmrg_plan_info* info) {
     info->t1_elems = P->t1_elems;
     info->t2_elems = P->t2_elems;
     info->apply_workspace_bytes = (int64_t)apply_bytes(P);
-    info->backward_workspace_bytes = (int64_t)(al256(P->t1_elems * 8) * 2 + al256(P->t2_elems * 8) * 2 +
-                                               apply_bytes(P) + al256(std::max<int64_t>(P->n_coefs, 1) * 8) +
-                                               (1 << 20));
+    info->backward_workspace_bytes = heff_backward_bytes(P);
     info->flops_s1 = P->s1.flops;
     info->flops_s2 = P->flops_s2;
     info->flops_s3 = P->s3.flops;
@@ -439,6 +463,34 @@ bsdmrg_status bsdmrg_heff_apply(bsdmrg_plan_t P, int32_t precision, const double
     ApplyWS w = carve_apply(P, c);
     prepare(P, precision, L, W1, W2, R, w, stream);
     matvec(P, precision, L, R, w, psi, out, stream);
+  });
+}
+
+bsdmrg_status bsdmrg_heff_backward(bsdmrg_plan_t P, const double* L, const double* W1, const double* W2,
+                                   const double* R, const double* psi, const double* g_E, double* d_psi,
+                                   double* d_L, double* d_W1, double* d_W2, double* d_R, void* workspace,
+                                   int64_t workspace_bytes, hipStream_t stream) {
+  return guarded([&] {
+    need_device(P);
+    if (!L || !W1 || !W2 || !R || !psi || !g_E) throw Error{BSDMRG_EINVAL, "heff_backward: NULL operand"};
+    const double* ins[5] = {L, W1, W2, R, psi};
+    double* outs[5] = {d_psi, d_L, d_W1, d_W2, d_R};
+    for (double* o : outs)
+      for (const double* i : ins)
+        if (o && (const double*)o == i) throw Error{BSDMRG_EINVAL, "heff_backward: an output aliases an input"};
+    for (size_t p = 0; p < P->probs.size(); ++p)
+      if (!std::isfinite(g_E[p])) throw Error{BSDMRG_EINVAL, "heff_backward: g_E is not finite"};
+    heff_backward_run(P, L, W1, W2, R, psi, g_E, d_psi, d_L, d_W1, d_W2, d_R, workspace, workspace_bytes, stream);
+  });
+}
+
+bsdmrg_status bsdmrg_heff_energy(bsdmrg_plan_t P, const double* L, const double* W1, const double* W2,
+                                 const double* R, const double* psi, double* energy, void* workspace,
+                                 int64_t workspace_bytes, hipStream_t stream) {
+  return guarded([&] {
+    need_device(P);
+    if (!L || !W1 || !W2 || !R || !psi || !energy) throw Error{BSDMRG_EINVAL, "heff_energy: NULL argument"};
+    heff_energy_run(P, L, W1, W2, R, psi, energy, workspace, workspace_bytes, stream);
   });
 }
 

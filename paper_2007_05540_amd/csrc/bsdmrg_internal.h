@@ -92,6 +92,40 @@ struct DavProb {
   int32_t chunk0, nchunk; // its reduction chunks
 };
 
+// Strided block copy: dst[(r) * drs + (c) * dcs] = scale_c * src[r * sld + c]
+// with an optional per-column (or per-row) factor.
+struct CopyTask {
+  int64_t src_off, dst_off;
+  int32_t rows, cols;
+  int32_t src_rs, src_cs;   // source strides (row, column)
+  int32_t dst_rs, dst_cs;   // destination strides
+  int32_t fac_off;          // index of the first factor (or -1)
+  int32_t fac_on_rows;      // 1: factor indexed by row, 0: by column
+};
+
+// Sign gauge of column j of U (column-major, ld): the entry of largest
+// magnitude (the first, in row order, within 1e-10 relative of the maximum)
+// becomes positive.  One block per kept column; writes sign[col] = +-1 and
+// the factors sign*S (for the side that absorbs S) and sign.
+struct GaugeTask {
+  int64_t u_off;
+  int32_t rows, ld;
+  int32_t s_idx;    // index of the singular value
+};
+
+// Partial inner product of a G sub-matrix and a T1 sub-matrix (adjoint).
+struct BwdDot {
+  int64_t g_off, t_off;
+  int32_t ld_g, ld_t, cols, row0, nrows, pad;
+};
+
+// One-sided Jacobi SVD of one charge matrix: X (m x n, n <= m) is M or M^T.
+struct SvdTask {
+  int64_t x_off, v_off, sig_off, perm_off;   // in the work array (elements)
+  int64_t u_off, s_off, vt_off;              // outputs
+  int32_t m, n, rows, transposed;            // rows = rows of M
+};
+
 struct Stage {
   std::vector<GemmTask> tasks;
   std::vector<GemmSeg> segs;
@@ -102,14 +136,30 @@ struct Stage {
   double flops = 0.0;
 };
 
+// Forward intermediate blocks kept for the adjoint.
+struct T1Block {
+  int32_t ap, f, s1, s2, c;   // a', left channel sector, s1, s2, c
+  int64_t off;                // global offset in T1
+};
+struct T2Block {
+  int32_t ap, s1p, s2p, g, c; // a', s1', s2', right channel sector, c
+  int64_t off;                // global offset in T2
+};
+
 struct ProblemPlan {
   Leg a, s1, s2, c, wl, wm, wr;
+  std::vector<T1Block> t1;
+  std::vector<T2Block> t2;
+  std::vector<double> w1_host, w2_host;
+  std::vector<char> nz1, nz2;
   Layout psi, L, R, W1, W2;
   int64_t psi_base = 0, L_base = 0, R_base = 0, W1_base = 0, W2_base = 0;
   int64_t t1_base = 0, t2_base = 0, coef_base = 0;
   int64_t t1_elems = 0, t2_elems = 0, n_coefs = 0;
   int32_t chunk0 = 0, nchunk = 0;
 };
+
+struct Backward;   // adjoint tables (backward.cpp)
 
 }  // namespace bsd
 
@@ -149,7 +199,25 @@ struct bsdmrg_plan_s {
   int64_t* d_blk_off = nullptr;
   int32_t* d_blk_ptr = nullptr;
   // backward-pass tables (built lazily)
-  struct Backward* bwd = nullptr;
+  bsd::Backward* bwd = nullptr;
   // cached hipGraph of a fixed-iteration eigensolve
   struct GraphCache* graph = nullptr;
+};
+
+// Auxiliary operations (environment extension, two-site merge): one or two
+// grouped-GEMM stages around an MPO-mixing stage whose coefficients are the
+// entries of W itself.
+struct bsdmrg_op_s {
+  int kind = 0;                       // 1 env left, 2 env right, 3 merge
+  bsd::Stage g1, g2;                  // first and last GEMM stage
+  int layout1 = 0, layout2 = 0;       // kNN / kNT / kTN
+  std::vector<bsd::MixTask> mix_tasks;
+  std::vector<bsd::MixTerm> mix_terms;
+  std::vector<bsd::MixItem> mix_items;
+  int64_t x1_elems = 0, x2_elems = 0, out_elems = 0;
+  double flops = 0.0;
+  void* d_blob = nullptr;
+  bsd::MixTask* d_mix_tasks = nullptr;
+  bsd::MixTerm* d_mix_terms = nullptr;
+  bsd::MixItem* d_mix_items = nullptr;
 };

@@ -24,6 +24,18 @@ hipError_t launch_coef(const bsdmrg_plan_s* P, const double* W1, const double* W
                        hipStream_t s);
 hipError_t launch_cast(int64_t n, const double* x, float* y, hipStream_t s);
 
+enum { kNN = 0, kNT = 1, kTN = 2 };
+hipError_t launch_copy(const void* d_tasks, int n, const double* src, double* dst, const double* fac,
+                       hipStream_t s);
+hipError_t launch_jacobi_svd(const void* d_tasks, int n, double* work, double* U, double* S, double* Vt,
+                             hipStream_t s);
+hipError_t launch_gauge(const void* d_tasks, int n, const double* U, const double* S, double* sign,
+                        double* sgn_s, hipStream_t s);
+hipError_t launch_gemm_f64(const Stage& st, int layout, const double* A, const double* B, double* C,
+                           double* Cpart, hipStream_t s);
+hipError_t launch_mix_tables(const MixItem* items, size_t n_items, const MixTask* tasks, const MixTerm* terms,
+                             const double* coef, const double* src, double* dst, hipStream_t s);
+
 // Davidson (Alg. 1) building blocks; every vector spans all problems of the
 // plan, reductions are per problem through the chunk table.
 struct DavBufs {
@@ -49,6 +61,7 @@ struct DavBufs {
 hipError_t dav_fill_zero(double* x, int64_t n, hipStream_t s);
 hipError_t dav_dots(const bsdmrg_plan_s* P, int J, const double* X, int64_t xstride, const double* y,
                     double* part, hipStream_t s);
+hipError_t dav_psum(const bsdmrg_plan_s* P, int J, const double* part, double* red, int ldr, hipStream_t s);
 hipError_t dav_normalize(const bsdmrg_plan_s* P, const double* part, double* red, const double* x, double* y,
                          hipStream_t s);
 hipError_t dav_gram_eig(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStream_t s);
@@ -58,5 +71,24 @@ hipError_t dav_update(const bsdmrg_plan_s* P, const DavBufs& b, int J, const dou
 hipError_t dav_finalize(const bsdmrg_plan_s* P, const DavBufs& b, int i, uint64_t seed, double rtol,
                         const int64_t* blk_off, const int32_t* blk_ptr, hipStream_t s);
 hipError_t dav_scale_into(const bsdmrg_plan_s* P, const DavBufs& b, double* dst, hipStream_t s);
+
+// adjoint kernels (kernels_bwd.hip)
+hipError_t launch_bwd_dots(const BwdDot* items, int n, const double* G, const double* T1, double* part,
+                           hipStream_t s);
+hipError_t launch_bwd_coef(int n, const int32_t* ptr, const double* part, double* dcoef, hipStream_t s);
+hipError_t launch_bwd_wgrad(int64_t n, const int32_t* ptr, const int32_t* coef, const int64_t* partner,
+                            const double* dcoef, const double* Wother, double g, double* dW, hipStream_t s);
+hipError_t launch_seg_scale(int64_t n, const int64_t* base, int np, const double* g, const double* x,
+                            const double* y, double* out, hipStream_t s);
+
+// host-side table checks (validate.cpp)
+void validate_gemm(const Stage& st, int layout, int64_t a_elems, int64_t b_elems, int64_t c_elems,
+                   int64_t cpart_elems, const char* name);
+void validate_mix(const std::vector<MixTask>& tasks, const std::vector<MixTerm>& terms,
+                  const std::vector<MixItem>& items, int64_t src_elems, int64_t dst_elems, int64_t coef_elems,
+                  const char* name);
+void validate_copy(const std::vector<CopyTask>& tasks, int64_t src_elems, int64_t dst_elems, int64_t fac_elems,
+                   const char* name);
+void validate_heff_plan(const bsdmrg_plan_s* P);
 
 }  // namespace bsd

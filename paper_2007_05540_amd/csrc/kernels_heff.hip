@@ -40,8 +40,9 @@ struct Mfma<float> {
 };
 
 // TC: compute type; TA/TB: global operand types (converted on load);
-// TO: output type; BT: B stored N x K (row-major) instead of K x N.
-template <typename TC, typename TA, typename TB, typename TO, bool BT>
+// TO: output type; BT: B stored N x K (row-major) instead of K x N;
+// AT: A stored K x M (row-major) instead of M x K.
+template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT = false>
 __global__ __launch_bounds__(NTHR) void ggemm_kernel(const GemmTile* __restrict__ tiles,
                                                      const GemmTask* __restrict__ tasks,
                                                      const GemmSeg* __restrict__ segs,
@@ -62,6 +63,7 @@ __global__ __launch_bounds__(NTHR) void ggemm_kernel(const GemmTile* __restrict_
 
   // global -> register mapping
   const int a_row = tid >> 2, a_k = (tid & 3) * 4;          // A: 64 rows x 16 k
+  const int at_k = tid >> 4, at_m = (tid & 15) * 4;         // A (TN): 16 k x 64 m
   const int bn_k = tid >> 4, bn_n = (tid & 15) * 4;         // B (NN): 16 k x 64 n
   const int bt_n = tid >> 2, bt_k = (tid & 3) * 4;          // B (NT): 64 n x 16 k
   TC ra[4], rb[4];
@@ -75,11 +77,20 @@ __global__ __launch_bounds__(NTHR) void ggemm_kernel(const GemmTile* __restrict_
   auto load = [&](const GemmSeg& sg, int kk0) {
     const TA* Ap = A + sg.a_off;
     const TB* Bp = B + sg.b_off;
-    const int row = tile.m0 + a_row;
+    if (!AT) {
+      const int row = tile.m0 + a_row;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = kk0 + a_k + u;
-      ra[u] = (row < task.M && k < sg.K) ? (TC)Ap[(int64_t)row * sg.lda + k] : (TC)0;
+      for (int u = 0; u < 4; ++u) {
+        const int k = kk0 + a_k + u;
+        ra[u] = (row < task.M && k < sg.K) ? (TC)Ap[(int64_t)row * sg.lda + k] : (TC)0;
+      }
+    } else {
+      const int k = kk0 + at_k;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int m = tile.m0 + at_m + u;
+        ra[u] = (k < sg.K && m < task.M) ? (TC)Ap[(int64_t)k * sg.lda + m] : (TC)0;
+      }
     }
     if (!BT) {
       const int k = kk0 + bn_k;
@@ -102,8 +113,13 @@ __global__ __launch_bounds__(NTHR) void ggemm_kernel(const GemmTile* __restrict_
   if (have) load(s, 0);
   while (have) {
     __syncthreads();
+    if (!AT) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) As[a_k + u][a_row] = ra[u];
+      for (int u = 0; u < 4; ++u) As[a_k + u][a_row] = ra[u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) As[at_k][at_m + u] = ra[u];
+    }
     if (!BT) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) Bs[bn_k][bn_n + u] = rb[u];
@@ -222,11 +238,28 @@ __global__ void cast_f64_f32_kernel(int64_t n, const double* __restrict__ x, flo
 }
 
 // ---------------------------------------------------------------- launches --
-template <typename TC, typename TA, typename TB, typename TO, bool BT>
+template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT = false>
 static hipError_t launch_gemm(const Stage& st, const TA* A, const TB* B, TO* C, TO* Cpart, hipStream_t s) {
   if (st.tiles.empty()) return hipSuccess;
-  hipLaunchKernelGGL((ggemm_kernel<TC, TA, TB, TO, BT>), dim3((unsigned)st.tiles.size()), dim3(NTHR), 0,
+  hipLaunchKernelGGL((ggemm_kernel<TC, TA, TB, TO, BT, AT>), dim3((unsigned)st.tiles.size()), dim3(NTHR), 0,
                      s, st.d_tiles, st.d_tasks, st.d_segs, A, B, C, Cpart);
+  return hipGetLastError();
+}
+
+// FP64 grouped GEMM of any stage in one of the layouts NN, NT (B stored
+// N x K) or TN (A stored K x M).
+hipError_t launch_gemm_f64(const Stage& st, int layout, const double* A, const double* B, double* C,
+                           double* Cpart, hipStream_t s) {
+  if (layout == kNN) return launch_gemm<double, double, double, double, false, false>(st, A, B, C, Cpart, s);
+  if (layout == kNT) return launch_gemm<double, double, double, double, true, false>(st, A, B, C, Cpart, s);
+  return launch_gemm<double, double, double, double, false, true>(st, A, B, C, Cpart, s);
+}
+
+hipError_t launch_mix_tables(const MixItem* items, size_t n_items, const MixTask* tasks, const MixTerm* terms,
+                             const double* coef, const double* src, double* dst, hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL((mix_kernel<double, double>), dim3((unsigned)n_items), dim3(NTHR), 0, s, items, tasks,
+                     terms, coef, src, dst);
   return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@
 #include <numeric>
 
 #include "bsdmrg_internal.h"
+#include "kernels.h"
 
 namespace bsd {
 
@@ -83,6 +84,10 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
   std::vector<char> nz1(p.W1.keys.size()), nz2(p.W2.keys.size());
   for (size_t b = 0; b < nz1.size(); ++b) nz1[b] = nonzero(p.W1, in.w1_host, (int)b);
   for (size_t b = 0; b < nz2.size(); ++b) nz2[b] = nonzero(p.W2, in.w2_host, (int)b);
+  p.nz1 = nz1;
+  p.nz2 = nz2;
+  p.w1_host.assign(in.w1_host, in.w1_host + p.W1.elems());
+  p.w2_host.assign(in.w2_host, in.w2_host + p.W2.elems());
 
   // ---- S1: one task per (psi block, left channel sector) ---------------
   std::map<Key, std::pair<int64_t, int>> t1;   // (a', f, s1, s2, c) -> (offset, index)
@@ -105,6 +110,7 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
       P->s1.tasks.push_back(t);
       P->s1.flops += 2.0 * M * N * (double)K;
       t1[key5(iap, f, i1, i2, ic)] = {t1_cursor, (int)t1_off.size()};
+      p.t1.push_back(T1Block{iap, f, i1, i2, ic, p.t1_base + t1_cursor});
       t1_off.push_back(t1_cursor);
       t1_cursor += round_up((int64_t)M * N);
     }
@@ -178,6 +184,7 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
           if (bc > kMixItemElems || ba > (1 << 30))
             throw Error{BSDMRG_EINVAL, "plan: sector dimensions above 4096 are not supported"};
           t2[key4(iap, s1p, s2p, g)] = {t2_cursor, ic};
+          p.t2.push_back(T2Block{iap, s1p, s2p, g, ic, p.t2_base + t2_cursor});
           for (int iwpp = 0; iwpp < ng; ++iwpp) {
             MixTask mt{p.t2_base + t2_cursor + iwpp * bc, (int32_t)(ng * bc), (int32_t)ba,
                        (int32_t)bc, (int32_t)P->mix_terms.size(), 0, 0};
@@ -303,6 +310,7 @@ bsdmrg_plan_s* build_plan(const bsdmrg_problem* probs, int n_probs) {
       }
     }
     P->blk_ptr.push_back((int32_t)(P->blk_off.size() / 2));
+    validate_heff_plan(P);
   } catch (...) {
     delete P;
     throw;

@@ -1,0 +1,288 @@
+// Truncated SVD split of the two-site tensor (Sec. II-C, Fig. 1e; Sec. IV-A).
+// theta(a,s1,s2,c) is wrapped into one matrix per charge q of the new bond
+// (rows: the (a, s1) pairs with q_a + q_s1 = q; columns: the (s2, c) pairs
+// with q_c - q_s2 = q; both in lexicographic order of their sector indices),
+// each matrix is decomposed with a one-sided Jacobi SVD kernel (FP64, high
+// relative accuracy for small singular values), the singular values
+// of all charges are pooled and truncated on the host, and U, S, V^T are
+// scattered into A(a,s1,b) and B(b,s2,c) with S absorbed in the direction of
+// the sweep.  Readings of the silent points: see bsdmrg_truncate in the
+// header (cutoff modes, degenerate groups, sign gauge).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "bsdmrg_internal.h"
+#include "kernels.h"
+
+namespace bsd {
+
+static const int32_t kPsiS[4] = {1, 1, 1, -1};
+static const int32_t kMpsS[3] = {1, 1, -1};
+
+struct TSector {
+  Charge q;
+  std::vector<std::pair<int, int>> rk, ck;   // (a, s1) and (s2, c) sector pairs
+  std::vector<int64_t> r0, c0;
+  int64_t rows = 0, cols = 0, kmin = 0;
+  int64_t mat, u, s, v;                       // X, U, S, Vt offsets (elements)
+  int64_t jv, jsig, jperm;                    // Jacobi scratch offsets in the work array
+};
+
+struct TPlan {
+  Leg a, s1, s2, c;
+  Layout theta;
+  std::vector<TSector> sec;
+  int64_t n_mat = 0, n_u = 0, n_s = 0, n_v = 0, n_work = 0;
+  size_t bytes = 0;
+};
+
+static size_t al(size_t b) { return (b + 255) / 256 * 256; }
+
+static TPlan make_tplan(const bsdmrg_leg* legs) {
+  TPlan T;
+  T.a = leg_from(legs[0]); T.s1 = leg_from(legs[1]); T.s2 = leg_from(legs[2]); T.c = leg_from(legs[3]);
+  for (const Leg* l : {&T.s1, &T.s2})
+    for (auto d : l->d)
+      if (d != 1) throw Error{BSDMRG_EINVAL, "truncate: physical sectors must have dimension 1"};
+  T.theta = make_layout({&T.a, &T.s1, &T.s2, &T.c}, kPsiS);
+  std::map<Charge, std::vector<std::pair<int, int>>> rows, cols;
+  for (int ia = 0; ia < T.a.size(); ++ia)
+    for (int i1 = 0; i1 < T.s1.size(); ++i1)
+      rows[{T.a.q[ia][0] + T.s1.q[i1][0], T.a.q[ia][1] + T.s1.q[i1][1]}].push_back({ia, i1});
+  for (int i2 = 0; i2 < T.s2.size(); ++i2)
+    for (int ic = 0; ic < T.c.size(); ++ic)
+      cols[{T.c.q[ic][0] - T.s2.q[i2][0], T.c.q[ic][1] - T.s2.q[i2][1]}].push_back({i2, ic});
+  for (auto& kv : rows) {
+    auto it = cols.find(kv.first);
+    if (it == cols.end()) continue;
+    TSector s;
+    s.q = kv.first;
+    s.rk = kv.second;
+    s.ck = it->second;
+    for (auto& r : s.rk) { s.r0.push_back(s.rows); s.rows += T.a.d[r.first] * T.s1.d[r.second]; }
+    for (auto& c : s.ck) { s.c0.push_back(s.cols); s.cols += T.s2.d[c.first] * T.c.d[c.second]; }
+    s.kmin = std::min(s.rows, s.cols);
+    s.u = T.n_u; T.n_u += s.rows * s.kmin;
+    s.v = T.n_v; T.n_v += s.kmin * s.cols;
+    s.s = T.n_s; T.n_s += s.kmin;
+    // Jacobi work: X (max x min), V (min x min), sigma (min), permutation (min)
+    s.mat = T.n_work; T.n_work += s.rows * s.cols;
+    s.jv = T.n_work; T.n_work += s.kmin * s.kmin;
+    s.jsig = T.n_work; T.n_work += s.kmin;
+    s.jperm = T.n_work; T.n_work += s.kmin;
+    T.sec.push_back(s);
+  }
+  T.n_mat = T.n_work;
+  int64_t n_rk = 0, n_ck = 0;
+  for (auto& s : T.sec) { n_rk += (int64_t)s.rk.size(); n_ck += (int64_t)s.ck.size(); }
+  T.bytes = al(T.n_work * 8) + al(T.n_u * 8) + al(T.n_s * 8) + al(T.n_v * 8) + al(T.n_s * 8) * 2 +
+            al(T.theta.keys.size() * sizeof(CopyTask) + 1) + al(T.sec.size() * sizeof(SvdTask) + 1) +
+            al(T.n_s * sizeof(GaugeTask) + 1) + al((n_rk + n_ck) * sizeof(CopyTask) + 1);
+  return T;
+}
+
+// Global selection of the kept singular values (ties by charge index, then
+// index inside the charge).
+static std::vector<int64_t> select_kept(const TPlan& T, const std::vector<double>& S, const bsdmrg_trunc_opts* o,
+                                        double* discarded, std::vector<double>& kept_vals) {
+  struct E { double v; int sec; int64_t j; };
+  std::vector<E> pool;
+  for (size_t q = 0; q < T.sec.size(); ++q)
+    for (int64_t j = 0; j < T.sec[q].kmin; ++j) pool.push_back({S[T.sec[q].s + j], (int)q, j});
+  std::stable_sort(pool.begin(), pool.end(), [](const E& x, const E& y) {
+    if (x.v != y.v) return x.v > y.v;
+    if (x.sec != y.sec) return x.sec < y.sec;
+    return x.j < y.j;
+  });
+  double total2 = 0.0;
+  for (auto& p : pool) total2 += p.v * p.v;
+  const double norm = std::sqrt(total2);
+  int64_t n_keep = 0;
+  if (o->cutoff_mode == 0) {
+    for (auto& p : pool) n_keep += p.v >= o->cutoff * norm;
+  } else {
+    n_keep = (int64_t)pool.size();
+    double acc = 0.0;
+    while (n_keep > 0 && acc + pool[n_keep - 1].v * pool[n_keep - 1].v <= o->cutoff * total2) {
+      acc += pool[n_keep - 1].v * pool[n_keep - 1].v;
+      --n_keep;
+    }
+  }
+  n_keep = std::min<int64_t>(n_keep, o->max_m);
+  if (n_keep > 0 && n_keep < (int64_t)pool.size()) {
+    const double sd = pool[n_keep].v;
+    int64_t n2 = n_keep;
+    while (n2 > 0 && pool[n2 - 1].v - sd <= o->degen_rtol * pool[n2 - 1].v) --n2;
+    if (n2 > 0) n_keep = n2;
+  }
+  std::vector<int64_t> counts(T.sec.size(), 0);
+  double disc = 0.0;
+  kept_vals.clear();
+  for (int64_t i = 0; i < (int64_t)pool.size(); ++i) {
+    if (i < n_keep) {
+      counts[pool[i].sec]++;
+      kept_vals.push_back(pool[i].v);
+    } else {
+      disc += pool[i].v * pool[i].v;
+    }
+  }
+  *discarded = disc;
+  return counts;
+}
+
+#define HIPCHK(x)                                                                              \
+  do {                                                                                         \
+    hipError_t e_ = (x);                                                                       \
+    if (e_ != hipSuccess) throw Error{BSDMRG_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+void truncate_workspace(const bsdmrg_leg* legs, int64_t* bytes) { *bytes = (int64_t)make_tplan(legs).bytes; }
+
+void truncate_run(const bsdmrg_leg* legs, const double* theta, const bsdmrg_trunc_opts* o, int32_t* new_n,
+                  int32_t* new_q, int64_t* new_d, int32_t leg_cap, double* A, int64_t A_cap, int64_t* A_elems,
+                  double* B, int64_t B_cap, int64_t* B_elems, double* svals, int64_t sv_cap, int64_t* n_kept,
+                  double* discarded, void* ws, int64_t ws_bytes, hipStream_t st) {
+  if (!o || !theta || !new_n || !new_q || !new_d || !A_elems || !B_elems || !n_kept || !discarded)
+    throw Error{BSDMRG_EINVAL, "truncate: NULL argument"};
+  if (o->direction != 0 && o->direction != 1) throw Error{BSDMRG_EINVAL, "truncate: direction must be 0 or 1"};
+  if (o->cutoff_mode != 0 && o->cutoff_mode != 1) throw Error{BSDMRG_EINVAL, "truncate: bad cutoff_mode"};
+  if (!(o->cutoff >= 0.0) || o->max_m < 1 || !(o->degen_rtol >= 0.0))
+    throw Error{BSDMRG_EINVAL, "truncate: bad cutoff, max_m or degen_rtol"};
+  TPlan T = make_tplan(legs);
+  if (!ws || (size_t)ws_bytes < T.bytes) throw Error{BSDMRG_EINVAL, "truncate: workspace too small"};
+  char* p = (char*)ws;
+  auto take = [&](size_t bytes) { char* r = p; p += al(bytes); return r; };
+  double* work = (double*)take(T.n_work * 8);
+  double* U = (double*)take(T.n_u * 8);
+  double* S = (double*)take(T.n_s * 8);
+  double* V = (double*)take(T.n_v * 8);
+  double* sign = (double*)take(T.n_s * 8);
+  double* sgn_s = (double*)take(T.n_s * 8);
+  char* gather_tab = take(T.theta.keys.size() * sizeof(CopyTask) + 1);
+  char* svd_tab = take(T.sec.size() * sizeof(SvdTask) + 1);
+  char* gauge_tab = take(T.n_s * sizeof(GaugeTask) + 1);
+  char* scatter_tab = p;
+
+  // gather theta blocks into the column-major charge matrices
+  std::vector<CopyTask> gt;
+  for (size_t si = 0; si < T.sec.size(); ++si) {
+    const TSector& s = T.sec[si];
+    for (size_t r = 0; r < s.rk.size(); ++r)
+      for (size_t c = 0; c < s.ck.size(); ++c) {
+        Key k{};
+        k[0] = s.rk[r].first; k[1] = s.rk[r].second; k[2] = s.ck[c].first; k[3] = s.ck[c].second;
+        const int b = T.theta.lookup(k);
+        if (b < 0) throw Error{BSDMRG_EQN, "truncate: theta block missing"};
+        const int32_t rows = (int32_t)T.a.d[k[0]], cols = (int32_t)T.c.d[k[3]];
+        if (s.rows >= s.cols)   // X = M, column-major (ld rows)
+          gt.push_back(CopyTask{T.theta.offs[b], s.mat + s.r0[r] + s.c0[c] * s.rows, rows, cols, cols, 1, 1,
+                                (int32_t)s.rows, -1, 0});
+        else                    // X = M^T, column-major (ld cols)
+          gt.push_back(CopyTask{T.theta.offs[b], s.mat + s.c0[c] + s.r0[r] * s.cols, rows, cols, cols, 1,
+                                (int32_t)s.cols, 1, -1, 0});
+      }
+  }
+  validate_copy(gt, T.theta.elems(), T.n_work, 0, "truncate gather");
+  HIPCHK(hipMemcpyAsync(gather_tab, gt.data(), gt.size() * sizeof(CopyTask), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_copy(gather_tab, (int)gt.size(), theta, work, nullptr, st));
+  std::vector<SvdTask> sv;
+  for (const TSector& s : T.sec) {
+    const bool tr = s.rows < s.cols;
+    sv.push_back(SvdTask{s.mat, s.jv, s.jsig, s.jperm, s.u, s.s, s.v, (int32_t)std::max(s.rows, s.cols),
+                         (int32_t)s.kmin, (int32_t)s.rows, tr ? 1 : 0});
+    const SvdTask& t = sv.back();
+    if (t.x_off + (int64_t)t.m * t.n > T.n_work || t.v_off + (int64_t)t.n * t.n > T.n_work ||
+        t.perm_off + t.n > T.n_work || t.u_off + s.rows * s.kmin > T.n_u || t.vt_off + s.kmin * s.cols > T.n_v ||
+        t.s_off + t.n > T.n_s)
+      throw Error{BSDMRG_EINVAL, "internal table check failed: truncate SVD"};
+  }
+  HIPCHK(hipMemcpyAsync(svd_tab, sv.data(), sv.size() * sizeof(SvdTask), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_jacobi_svd(svd_tab, (int)sv.size(), work, U, S, V, st));
+  std::vector<double> hS(T.n_s);
+  HIPCHK(hipMemcpyAsync(hS.data(), S, T.n_s * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (double v : hS)
+    if (!std::isfinite(v)) throw Error{BSDMRG_ESOLVER, "truncate: non-finite singular value (theta not finite?)"};
+  std::vector<double> kept;
+  std::vector<int64_t> counts = select_kept(T, hS, o, discarded, kept);
+  // new leg and output layouts
+  std::vector<int> new_of(T.sec.size(), -1);
+  Leg b;
+  b.nc = T.a.nc;
+  for (size_t si = 0; si < T.sec.size(); ++si)
+    if (counts[si] > 0) {
+      new_of[si] = b.size();
+      b.q.push_back(T.sec[si].q);
+      b.d.push_back(counts[si]);
+    }
+  *new_n = b.size();
+  *n_kept = (int64_t)kept.size();
+  if (b.size() == 0) throw Error{BSDMRG_ESOLVER, "truncate: nothing kept (theta is zero?)"};
+  Layout LA = make_layout({&T.a, &T.s1, &b}, kMpsS);
+  Layout LB = make_layout({&b, &T.s2, &T.c}, kMpsS);
+  *A_elems = LA.elems();
+  *B_elems = LB.elems();
+  if (leg_cap < b.size() || A_cap < LA.elems() || B_cap < LB.elems() || sv_cap < (int64_t)kept.size())
+    throw Error{BSDMRG_ECAPACITY, "truncate: output capacity too small (required sizes returned)"};
+  if (!A || !B || !svals) throw Error{BSDMRG_EINVAL, "truncate: NULL output"};
+  for (int i = 0; i < b.size(); ++i) {
+    for (int cc = 0; cc < b.nc; ++cc) new_q[i * b.nc + cc] = b.q[i][cc];
+    new_d[i] = b.d[i];
+  }
+  std::copy(kept.begin(), kept.end(), svals);
+  // gauge of every kept column
+  std::vector<GaugeTask> gg;
+  std::vector<int64_t> gbase(T.sec.size(), 0);
+  for (size_t si = 0; si < T.sec.size(); ++si) {
+    gbase[si] = (int64_t)gg.size();
+    for (int64_t j = 0; j < counts[si]; ++j)
+      gg.push_back(GaugeTask{T.sec[si].u + j * T.sec[si].rows, (int32_t)T.sec[si].rows,
+                             (int32_t)T.sec[si].rows, (int32_t)(T.sec[si].s + j)});
+  }
+  for (const GaugeTask& g : gg)
+    if (g.u_off < 0 || g.u_off + g.rows > T.n_u || g.s_idx < 0 || g.s_idx >= T.n_s || g.rows < 1)
+      throw Error{BSDMRG_EINVAL, "internal table check failed: truncate gauge"};
+  HIPCHK(hipMemcpyAsync(gauge_tab, gg.data(), gg.size() * sizeof(GaugeTask), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_gauge(gauge_tab, (int)gg.size(), U, S, sign, sgn_s, st));
+  // scatter: A(a,s1,b) from U, B(b,s2,c) from V^T
+  std::vector<CopyTask> ta, tb;
+  for (size_t si = 0; si < T.sec.size(); ++si) {
+    if (counts[si] == 0) continue;
+    const TSector& s = T.sec[si];
+    const int ib = new_of[si];
+    const int32_t nq = (int32_t)counts[si];
+    for (size_t r = 0; r < s.rk.size(); ++r) {
+      Key k{};
+      k[0] = s.rk[r].first; k[1] = s.rk[r].second; k[2] = ib;
+      const int blk = LA.lookup(k);
+      if (blk < 0) throw Error{BSDMRG_EQN, "truncate: A block missing"};
+      ta.push_back(CopyTask{s.u + s.r0[r], LA.offs[blk], (int32_t)T.a.d[k[0]], nq, 1, (int32_t)s.rows, nq, 1,
+                            (int32_t)gbase[si], 0});
+    }
+    for (size_t c = 0; c < s.ck.size(); ++c) {
+      Key k{};
+      k[0] = ib; k[1] = s.ck[c].first; k[2] = s.ck[c].second;
+      const int blk = LB.lookup(k);
+      if (blk < 0) throw Error{BSDMRG_EQN, "truncate: B block missing"};
+      const int32_t bc = (int32_t)T.c.d[k[2]];
+      tb.push_back(CopyTask{s.v + s.c0[c] * s.kmin, LB.offs[blk], nq, bc, 1, (int32_t)s.kmin, bc, 1,
+                            (int32_t)gbase[si], 1});
+    }
+  }
+  validate_copy(ta, T.n_u, LA.elems(), (int64_t)gg.size(), "truncate scatter A");
+  validate_copy(tb, T.n_v, LB.elems(), (int64_t)gg.size(), "truncate scatter B");
+  std::vector<CopyTask> all(ta);
+  all.insert(all.end(), tb.begin(), tb.end());
+  HIPCHK(hipMemcpyAsync(scatter_tab, all.data(), all.size() * sizeof(CopyTask), hipMemcpyHostToDevice, st));
+  HIPCHK(dav_fill_zero(A, LA.elems(), st));
+  HIPCHK(dav_fill_zero(B, LB.elems(), st));
+  const bool right = o->direction == 0;
+  HIPCHK(launch_copy(scatter_tab, (int)ta.size(), U, A, right ? sign : sgn_s, st));
+  HIPCHK(launch_copy(scatter_tab + ta.size() * sizeof(CopyTask), (int)tb.size(), V, B, right ? sgn_s : sign, st));
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+}  // namespace bsd

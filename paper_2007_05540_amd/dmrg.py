@@ -1,0 +1,147 @@
+"""Two-site DMRG sweeps on one GPU (Sec. II-C, Fig. 1).
+
+Bond j sits to the left of site j; MPS site j has legs (bond j, s, bond j+1).
+Starting from a right-canonical MPS, a sweep visits the pairs (j, j+1) left
+to right and back: merge the two sites, find the lowest eigenpair of the
+two-site effective Hamiltonian with the Davidson routine started from the
+merged tensor, split it with the truncated SVD (singular values absorbed in
+the sweep direction) and extend the environment.  This module only orders the
+calls and keeps leg tables; every contraction, eigensolve and SVD runs in the
+library through its C ABI.
+"""
+import numpy as np
+
+from . import lib, problems
+
+
+class Tensor:
+    """Device tensor in canonical block layout plus its legs."""
+
+    def __init__(self, legs, data):
+        self.legs, self.data = legs, data
+
+
+class GpuDMRG:
+    def __init__(self, mpo, mps_host, target, device="cuda", precision=lib.F64, refine_max_iter=8,
+                 tol_f32=1e-6):
+        """mpo: uniform-channel MPO (W[j] dense (k, d, d, k), channels
+        sector-major); mps_host: list of (legs, packed FP64 array);
+        target: total charge of the state."""
+        import torch
+        self.torch = torch
+        self.device = device
+        self.mpo = mpo
+        self.N = len(mpo.W)
+        self.wl = mpo.w_leg()
+        s = mpo.phys
+        self.s = s
+        self.W_host = [problems.pack_dense(W, [self.wl, s, s, self.wl], lib.W_SIGNS) for W in mpo.W]
+        self.W = [torch.from_numpy(w).to(device) for w in self.W_host]
+        self.T = [Tensor(l, torch.from_numpy(np.ascontiguousarray(a)).to(device)) for l, a in mps_host]
+        self.target = tuple(target)
+        self.precision = precision
+        self.refine_max_iter = refine_max_iter
+        self.tol_f32 = tol_f32
+        r = len(s[0][0])
+        zero = tuple([0] * r)
+        self.L = [None] * (self.N + 1)
+        self.R = [None] * (self.N + 1)
+        self.L[0] = self._boundary(zero, mpo.start)
+        self.R[self.N] = self._boundary(self.target, mpo.done)
+        self.log = []
+
+    # -- helpers -------------------------------------------------------------
+    def _boundary(self, q, channel):
+        leg = [(tuple(q), 1)]
+        k = sum(n for _, n in self.wl)
+        dense = np.zeros((1, k, 1))
+        dense[0, channel, 0] = 1.0
+        data = problems.pack_dense(dense, [leg, self.wl, leg], lib.ENV_SIGNS)
+        return Tensor([leg, self.wl, leg], self.torch.from_numpy(data).to(self.device))
+
+    def _merge(self, A, B):
+        a, s1, b = A.legs
+        _, s2, c = B.legs
+        op = lib.merge_plan(a, s1, b, s2, c)
+        theta = self.torch.zeros(max(1, op.query()["out_elems"]), dtype=self.torch.float64, device=self.device)
+        lib.merge(op, A.data, B.data, theta)
+        return Tensor([a, s1, s2, c], theta)
+
+    def _split(self, theta, direction, cutoff, cutoff_mode, max_m):
+        A, B, leg, sv, disc = lib.truncate(theta.legs, theta.data, direction, cutoff, cutoff_mode, max_m)
+        a, s1, s2, c = theta.legs
+        return Tensor([a, s1, leg], A), Tensor([leg, s2, c], B), disc
+
+    def _env(self, env, site, j, side):
+        """side 0: left extension through site j (A); side 1: right (B)."""
+        if side == 0:
+            x, s, y = site.legs
+        else:
+            y, s, x = site.legs
+        op = lib.env_plan(x, s, y, self.wl, self.wl, self.W_host[j], side)
+        info = op.query()
+        out = self.torch.zeros(max(1, info["out_elems"]), dtype=self.torch.float64, device=self.device)
+        ws = self.torch.empty(max(1, info["workspace_bytes"]), dtype=self.torch.uint8, device=self.device)
+        lib.env_update(op, env.data, site.data, self.W[j], out, ws)
+        return Tensor([y, self.wl, y], out)
+
+    # -- algorithm -----------------------------------------------------------
+    def right_canonicalize(self, cutoff=1e-14, progress=False):
+        """Splits from the right with S absorbed to the left; singular values
+        below 1e-14 of the norm (numerically zero, with non-unique vectors)
+        are dropped."""
+        for j in range(self.N - 1, 0, -1):
+            if progress:
+                print(f"  canonicalize {j}", flush=True)
+            theta = self._merge(self.T[j - 1], self.T[j])
+            self.T[j - 1], self.T[j], _ = self._split(theta, 1, cutoff, 0, 1 << 62)
+        for j in range(self.N - 1, 1, -1):
+            self.R[j] = self._env(self.R[j + 1], self.T[j], j, 1)
+
+    def solve_bond(self, j, theta, max_iter, tol, seed):
+        a, s1, s2, c = theta.legs
+        prob = {"a": a, "s1": s1, "s2": s2, "c": c, "wl": self.wl, "wm": self.wl, "wr": self.wl,
+                "w1": self.W_host[j], "w2": self.W_host[j + 1]}
+        plan = lib.Plan([prob])
+        if self.precision == lib.F64:
+            opts = lib.eig_opts(max_iter=max_iter, tol=tol, seed=seed)
+        else:
+            opts = lib.eig_opts(max_iter=max_iter, precision=lib.F32_REFINE, refine_max_iter=self.refine_max_iter,
+                                tol=tol, tol_f32=self.tol_f32, seed=seed)
+        ws = self.torch.empty(lib.eig_workspace(plan, opts), dtype=self.torch.uint8, device=self.device)
+        e, st = lib.eigensolve(plan, self.L[j].data, self.W[j], self.W[j + 1], self.R[j + 2].data, theta.data,
+                               opts, ws)
+        info = plan.info()
+        plan.destroy()
+        return e[0], st[0], info["flops_s1"] + info["flops_s3"]
+
+    def run(self, n_sweeps, m_max, cutoff=1e-10, cutoff_mode=0, max_iter=40, tol=1e-12, progress=False):
+        """Two-site sweeps; m_max is an int or a per-sweep list.  Returns
+        (energies per visited bond, last energy of every sweep)."""
+        self.right_canonicalize(progress=progress)
+        mlist = m_max if isinstance(m_max, (list, tuple)) else [m_max] * n_sweeps
+        energies, sweep_e = [], []
+        step = 0
+        N = self.N
+        for sw in range(n_sweeps):
+            order = [(j, 0) for j in range(N - 1)] + [(j, 1) for j in range(N - 2, -1, -1)]
+            for j, d in order:
+                theta = self._merge(self.T[j], self.T[j + 1])
+                if progress:
+                    print(f"  sweep {sw} bond {j} dir {d}: solve", flush=True)
+                E, st, flops = self.solve_bond(j, theta, max_iter, tol, step)
+                if not np.isfinite(E):
+                    raise FloatingPointError(f"non-finite energy at sweep {sw} bond {j}")
+                A, B, disc = self._split(theta, d, cutoff, cutoff_mode, mlist[sw])
+                self.T[j], self.T[j + 1] = A, B
+                if d == 0:
+                    self.L[j + 1] = self._env(self.L[j], A, j, 0)
+                else:
+                    self.R[j + 1] = self._env(self.R[j + 2], B, j + 1, 1)
+                energies.append(E)
+                self.log.append({"sweep": sw, "bond": j, "dir": d, "E": E, "iters": st["iters"],
+                                 "iters_f32": st["iters_f32"], "res": st["residual"], "disc": disc,
+                                 "m": sum(dd for _, dd in A.legs[2]), "flops_per_product": flops})
+                step += 1
+            sweep_e.append(energies[-1])
+        return energies, sweep_e

@@ -60,11 +60,23 @@ class EigStats(ctypes.Structure):
                 ("converged", ctypes.c_int32), ("residual", ctypes.c_double)]
 
 
+class TruncOpts(ctypes.Structure):
+    _fields_ = [("direction", ctypes.c_int32), ("cutoff_mode", ctypes.c_int32), ("cutoff", ctypes.c_double),
+                ("max_m", ctypes.c_int64), ("degen_rtol", ctypes.c_double)]
+
+
+class EnvProblem(ctypes.Structure):
+    _fields_ = [("x", Leg), ("s", Leg), ("y", Leg), ("wl", Leg), ("wr", Leg),
+                ("w_host", ctypes.POINTER(ctypes.c_double))]
+
+
 _lib = None
 
 EXPORTS = ["bsdmrg_layout", "bsdmrg_plan", "bsdmrg_plan_query", "bsdmrg_plan_offsets", "bsdmrg_plan_tasks",
            "bsdmrg_plan_destroy", "bsdmrg_heff_apply", "bsdmrg_eig_workspace", "bsdmrg_eigensolve",
-           "bsdmrg_heff_backward", "bsdmrg_stage_timing", "bsdmrg_last_error"]
+           "bsdmrg_heff_backward", "bsdmrg_heff_energy", "bsdmrg_stage_timing", "bsdmrg_truncate_workspace", "bsdmrg_truncate",
+           "bsdmrg_env_plan", "bsdmrg_merge_plan", "bsdmrg_op_query", "bsdmrg_op_destroy", "bsdmrg_env_update",
+           "bsdmrg_merge", "bsdmrg_last_error"]
 
 
 def load():
@@ -90,9 +102,21 @@ def load():
     lib.bsdmrg_eig_workspace.argtypes = [vp, ctypes.POINTER(EigOpts), ctypes.POINTER(i64)]
     lib.bsdmrg_eigensolve.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(EigOpts),
                                       ctypes.POINTER(dp), ctypes.POINTER(EigStats), vp, i64, vp]
-    lib.bsdmrg_heff_backward.argtypes = [vp, vp, vp, vp, vp, vp, dp, vp, vp, vp, vp, vp, vp, i64, vp]
+    lib.bsdmrg_heff_backward.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(dp), vp, vp, vp, vp, vp, vp,
+                                         i64, vp]
+    lib.bsdmrg_heff_energy.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(dp), vp, i64, vp]
     lib.bsdmrg_stage_timing.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, i64, i32,
                                         ctypes.POINTER(ctypes.c_float), vp]
+    P = ctypes.POINTER
+    lib.bsdmrg_truncate_workspace.argtypes = [P(Leg), P(i64)]
+    lib.bsdmrg_truncate.argtypes = [P(Leg), vp, P(TruncOpts), P(i32), P(i32), P(i64), i32, vp, i64, P(i64), vp,
+                                    i64, P(i64), P(dp), i64, P(i64), P(dp), vp, i64, vp]
+    lib.bsdmrg_env_plan.argtypes = [P(EnvProblem), i32, i32, P(vp)]
+    lib.bsdmrg_merge_plan.argtypes = [P(Leg), i32, P(vp)]
+    lib.bsdmrg_op_query.argtypes = [vp, P(i64), P(i64), P(dp)]
+    lib.bsdmrg_op_destroy.argtypes = [vp]
+    lib.bsdmrg_env_update.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
+    lib.bsdmrg_merge.argtypes = [vp, vp, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -232,10 +256,21 @@ def eigensolve(plan, L, W1, W2, R, psi, opts, workspace, stream=None):
 
 
 def heff_backward(plan, L, W1, W2, R, psi, g_E, d_psi, d_L, d_W1, d_W2, d_R, workspace, stream=None):
-    check(load().bsdmrg_heff_backward(plan.handle, _ptr(L), _ptr(W1), _ptr(W2), _ptr(R), _ptr(psi),
-                                      ctypes.c_double(g_E), _ptr(d_psi), _ptr(d_L), _ptr(d_W1), _ptr(d_W2),
-                                      _ptr(d_R), _ptr(workspace), workspace.numel() * workspace.element_size(),
-                                      _stream(stream)))
+    """g_E: one cotangent per problem (a scalar is broadcast).  Outputs may be None."""
+    g = np.broadcast_to(np.asarray(g_E, dtype=np.float64), (plan.n_probs,))
+    garr = (ctypes.c_double * plan.n_probs)(*[float(x) for x in g])
+    check(load().bsdmrg_heff_backward(plan.handle, _ptr(L), _ptr(W1), _ptr(W2), _ptr(R), _ptr(psi), garr,
+                                      _ptr(d_psi), _ptr(d_L), _ptr(d_W1), _ptr(d_W2), _ptr(d_R), _ptr(workspace),
+                                      workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def heff_energy(plan, L, W1, W2, R, psi, workspace, stream=None):
+    """[psi_p^T H_eff,p psi_p for every problem p] (FP64)."""
+    e = (ctypes.c_double * plan.n_probs)()
+    check(load().bsdmrg_heff_energy(plan.handle, _ptr(L), _ptr(W1), _ptr(W2), _ptr(R), _ptr(psi), e,
+                                    _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                    _stream(stream)))
+    return list(e)
 
 
 def stage_timing(plan, precision, L, W1, W2, R, psi, out, workspace, reps=20, stream=None):
@@ -245,3 +280,110 @@ def stage_timing(plan, precision, L, W1, W2, R, psi, out, workspace, reps=20, st
                                      _ptr(out), _ptr(workspace), workspace.numel() * workspace.element_size(),
                                      reps, ms, _stream(stream)))
     return dict(zip(("coef", "s1", "s2", "s3"), list(ms)))
+
+
+# ------------------------------------------------------------ sweep ops ----
+class Op:
+    """An environment-extension or merge op (plan tables on the device)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def query(self):
+        ws, n = ctypes.c_int64(0), ctypes.c_int64(0)
+        f = ctypes.c_double(0)
+        check(load().bsdmrg_op_query(self.handle, ctypes.byref(ws), ctypes.byref(n), ctypes.byref(f)))
+        return {"workspace_bytes": ws.value, "out_elems": n.value, "flops": f.value}
+
+    def destroy(self):
+        if self.handle:
+            check(load().bsdmrg_op_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def env_plan(x, s, y, wl, wr, w_host, side, host_only=False):
+    """side 0: left extension (env (x,wl,x), A (x,s,y) -> (y,wr,y));
+    side 1: right extension (env (x,wr,x), B (y,s,x) -> (y,wl,y))."""
+    bufs = [_LegBuf(l) for l in (x, s, y, wl, wr)]
+    w = np.ascontiguousarray(w_host, dtype=np.float64)
+    prob = EnvProblem(*[b.leg for b in bufs], w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    h = ctypes.c_void_p()
+    check(load().bsdmrg_env_plan(ctypes.byref(prob), side, PLAN_HOST_ONLY if host_only else 0, ctypes.byref(h)))
+    return Op(h)
+
+
+def merge_plan(a, s1, b, s2, c, host_only=False):
+    bufs = [_LegBuf(l) for l in (a, s1, b, s2, c)]
+    arr = (Leg * 5)(*[x.leg for x in bufs])
+    h = ctypes.c_void_p()
+    check(load().bsdmrg_merge_plan(arr, PLAN_HOST_ONLY if host_only else 0, ctypes.byref(h)))
+    return Op(h)
+
+
+def env_update(op, env, mps, W, env_out, workspace, stream=None):
+    nb = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    check(load().bsdmrg_env_update(op.handle, _ptr(env), _ptr(mps), _ptr(W), _ptr(env_out), _ptr(workspace), nb,
+                                   _stream(stream)))
+
+
+def merge(op, A, B, theta, stream=None):
+    check(load().bsdmrg_merge(op.handle, _ptr(A), _ptr(B), _ptr(theta), _stream(stream)))
+
+
+def truncate_workspace(theta_legs):
+    bufs = [_LegBuf(l) for l in theta_legs]
+    arr = (Leg * 4)(*[b.leg for b in bufs])
+    n = ctypes.c_int64(0)
+    check(load().bsdmrg_truncate_workspace(arr, ctypes.byref(n)))
+    return n.value
+
+
+def truncate(theta_legs, theta, direction, cutoff=0.0, cutoff_mode=0, max_m=1 << 62, degen_rtol=1e-10,
+             stream=None):
+    """Returns (A, B, new_leg, kept singular values, discarded weight);
+    A and B are new FP64 device tensors in canonical layout."""
+    import torch
+    lib = load()
+    bufs = [_LegBuf(l) for l in theta_legs]
+    arr = (Leg * 4)(*[b.leg for b in bufs])
+    ws = torch.empty(truncate_workspace(theta_legs), dtype=torch.uint8, device=theta.device)
+    o = TruncOpts(direction, cutoff_mode, cutoff, max_m, degen_rtol)
+    nc = len(theta_legs[0][0][0])
+    a, s1, s2, c = theta_legs
+    # exact capacity bounds from the per-charge matrix sizes (kept <= min(rows, cols, max_m))
+    rows, cols = {}, {}
+    for qa, da in a:
+        for qs, ds in s1:
+            rows.setdefault(tuple(x + y for x, y in zip(qa, qs)), []).append(da * ds)
+    for qs, ds in s2:
+        for qc, dc in c:
+            cols.setdefault(tuple(x - y for x, y in zip(qc, qs)), []).append(ds * dc)
+    rup = lambda x: (x + 31) // 32 * 32
+    cap_leg, cap_sv, cap_A, cap_B = 1, 1, 1, 1
+    for qq, rl in rows.items():
+        if qq not in cols:
+            continue
+        k = min(sum(rl), sum(cols[qq]), max_m)
+        cap_leg += 1
+        cap_sv += k
+        cap_A += sum(rup(r * k) for r in rl)
+        cap_B += sum(rup(k * cc) for cc in cols[qq])
+    new_n = ctypes.c_int32(0)
+    q = (ctypes.c_int32 * (cap_leg * nc))()
+    d = (ctypes.c_int64 * cap_leg)()
+    an, bn, nk = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    disc = ctypes.c_double(0)
+    A = torch.empty(cap_A, dtype=torch.float64, device=theta.device)
+    B = torch.empty(cap_B, dtype=torch.float64, device=theta.device)
+    sv = (ctypes.c_double * cap_sv)()
+    check(lib.bsdmrg_truncate(arr, _ptr(theta), ctypes.byref(o), ctypes.byref(new_n), q, d, cap_leg, _ptr(A),
+                              cap_A, ctypes.byref(an), _ptr(B), cap_B, ctypes.byref(bn), sv, cap_sv,
+                              ctypes.byref(nk), ctypes.byref(disc), _ptr(ws), ws.numel(), _stream(stream)))
+    leg = [(tuple(q[i * nc + k] for k in range(nc)), int(d[i])) for i in range(new_n.value)]
+    return A[:an.value].clone(), B[:bn.value].clone(), leg, list(sv)[:nk.value], disc.value

@@ -100,3 +100,16 @@ def test_plan_rejects_physical_dim_above_one(lib):
     prob["s1"] = [((-1,), 2), ((1,), 1)]
     with pytest.raises(lib.BsdmrgError):
         lib.Plan([prob], host_only=True)
+
+
+@pytest.mark.parametrize("m,k,seed", [(64, 5, 1), (256, 14, 2), (1024, 14, 1)])
+def test_adjoint_tables_build_and_pass_host_checks(lib, m, k, seed):
+    """The adjoint's tables are built (and every index table checked on the
+    host) by the first query; its workspace holds the product's and more."""
+    from paper_2007_05540_amd import problems
+    spec = synth.c2_bond(m=m, k=k, seed=seed)
+    prob, _ = problems.bond_problem(spec)
+    plan = lib.Plan([prob, prob], host_only=True)
+    info = plan.info()
+    assert info["backward_workspace_bytes"] > info["apply_workspace_bytes"] + 8 * (info["t1_elems"] + info["t2_elems"])
+    assert plan.info()["backward_workspace_bytes"] == info["backward_workspace_bytes"]

@@ -1,0 +1,150 @@
+"""GPU parity of the sweep operations (merge, environment extension,
+truncated SVD split) and of full two-site sweeps against the CPU oracle and
+exact diagonalisation."""
+import numpy as np
+import pytest
+
+import synth
+from synth.blocks import mps_block
+from oracle import ed
+from oracle.blocks import BlockTensor
+from oracle.dmrg import random_mps, dmrg
+from oracle.env import left_update_blocks, right_update_blocks, merge
+from oracle.heff import w_tensor, MPS_SIGNS, ENV_SIGNS, PSI_SIGNS
+from oracle.truncate import truncate as o_truncate
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mods(gpu_lib):
+    from paper_2007_05540_amd import problems, dmrg as gdmrg
+    return gpu_lib, problems, gdmrg
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def random_sites(n=8, m0=24, seed=3, hub=False):
+    if hub:
+        mpo = synth.hubbard_mpo(n, synth.chain_bonds(n), 4.0)
+        target = (n, 0)
+    else:
+        mpo = synth.heisenberg_mpo(n, synth.chain_bonds(n))
+        target = (0,)
+    return mpo, random_mps(mpo, n, target, m0, seed, mps_block), target
+
+
+@pytest.mark.parametrize("hub", [False, True])
+def test_merge_matches_oracle(mods, hub):
+    lib, problems, _ = mods
+    mpo, mps, _ = random_sites(hub=hub)
+    A, B = mps[3], mps[4]
+    op = lib.merge_plan(A.legs[0], A.legs[1], A.legs[2], B.legs[1], B.legs[2])
+    theta = torch.zeros(op.query()["out_elems"], dtype=torch.float64, device="cuda")
+    lib.merge(op, dev(A.pack()), dev(B.pack()), theta)
+    torch.cuda.synchronize()
+    assert rel(theta.cpu().numpy(), merge(A, B).pack()) < 1e-13
+
+
+@pytest.mark.parametrize("hub", [False, True])
+def test_environment_extension_matches_oracle(mods, hub):
+    lib, problems, _ = mods
+    mpo, mps, target = random_sites(hub=hub)
+    wl = mpo.w_leg()
+    Wb = w_tensor(mpo.W[3], wl, mpo.phys, wl)
+    W_host = problems.pack_dense(mpo.W[3], [wl, mpo.phys, mpo.phys, wl], lib.W_SIGNS)
+    site = mps[3]
+    # a random environment on the site's left / right bond
+    for side in (0, 1):
+        x = site.legs[0] if side == 0 else site.legs[2]
+        env = BlockTensor.from_fn([x, wl, x], ENV_SIGNS, lambda k: synth.gaussian_block(
+            7, side, k, (x[k[0]][1], wl[k[1]][1], x[k[2]][1])))
+        if side == 0:
+            ref = left_update_blocks(env, site, Wb)
+            op = lib.env_plan(site.legs[0], mpo.phys, site.legs[2], wl, wl, W_host, 0)
+        else:
+            ref = right_update_blocks(env, site, Wb)
+            op = lib.env_plan(site.legs[2], mpo.phys, site.legs[0], wl, wl, W_host, 1)
+        info = op.query()
+        out = torch.zeros(info["out_elems"], dtype=torch.float64, device="cuda")
+        ws = torch.empty(max(1, info["workspace_bytes"]), dtype=torch.uint8, device="cuda")
+        lib.env_update(op, dev(env.pack()), dev(site.pack()), dev(W_host), out, ws)
+        torch.cuda.synchronize()
+        assert rel(out.cpu().numpy(), ref.pack()) < 1e-13, side
+
+
+@pytest.mark.parametrize("direction,max_m", [(0, 1 << 40), (1, 1 << 40), (0, 20), (1, 13)])
+def test_truncation_matches_oracle(mods, direction, max_m):
+    lib, problems, _ = mods
+    mpo, mps, _ = random_sites(m0=32, seed=5)
+    theta = merge(mps[3], mps[4])
+    A, B, leg, sv, disc = lib.truncate(theta.legs, dev(theta.pack()), direction, cutoff=1e-12, max_m=max_m)
+    oA, oB, oleg, osv, odisc = o_truncate(theta, "right" if direction == 0 else "left", cutoff=1e-12,
+                                          m_max=max_m)
+    assert leg == oleg
+    assert np.allclose(sv, osv, rtol=1e-12, atol=1e-14)
+    assert abs(disc - odisc) <= 1e-12 * max(odisc, 1e-300) + 1e-28
+    # random Gaussian blocks: no degenerate singular values, so the gauge
+    # fixes A and B uniquely
+    assert rel(A.cpu().numpy(), oA.pack()) < 1e-11
+    assert rel(B.cpu().numpy(), oB.pack()) < 1e-11
+
+
+def test_truncation_rejects_small_workspace(mods):
+    lib, problems, _ = mods
+    mpo, mps, _ = random_sites()
+    theta = merge(mps[3], mps[4])
+    import ctypes
+    L = lib.load()
+    bufs = [lib._LegBuf(l) for l in theta.legs]
+    arr = (lib.Leg * 4)(*[b.leg for b in bufs])
+    o = lib.TruncOpts(0, 0, 0.0, 10, 1e-10)
+    z = ctypes.c_int64(0)
+    n = ctypes.c_int32(0)
+    dd = ctypes.c_double(0)
+    st = L.bsdmrg_truncate(arr, lib._ptr(dev(theta.pack())), ctypes.byref(o), ctypes.byref(n), None, None, 0,
+                           None, 0, ctypes.byref(z), None, 0, ctypes.byref(z), None, 0, ctypes.byref(z),
+                           ctypes.byref(dd), None, 0, None)
+    assert st == lib.EINVAL
+
+
+def host_mps(problems, lib, mps):
+    return [(t.legs, problems.pack_fn(t.legs, MPS_SIGNS, lambda k, t=t: t.blocks[k])) for t in mps]
+
+
+def test_heisenberg_chain_l16_m64_sweeps(mods):
+    """L=16 open Heisenberg chain, k=5, m=64, cutoff 1e-10, 4 sweeps, Davidson
+    tol 1e-12 (cap 40), FP64: energies against the oracle and ED."""
+    lib, problems, gdmrg = mods
+    n = 16
+    b = synth.chain_bonds(n)
+    mpo = synth.heisenberg_mpo(n, b)
+    mps = random_mps(mpo, n, (0,), 16, 0, mps_block)
+    g = gdmrg.GpuDMRG(mpo, host_mps(problems, lib, mps), (0,))
+    E, swe = g.run(4, 64, cutoff=1e-10, max_iter=40, tol=1e-12, progress=True)
+    oE, _, oswe, _ = dmrg(mpo, mps, 4, 64, cutoff=1e-10, dav={"max_iter": 40, "tol": 1e-12})
+    e0 = ed.lowest(ed.heisenberg_sector(n, b, n // 2))
+    assert abs(swe[-1] - e0) < 1e-9 * abs(e0)
+    assert abs(swe[-1] - oswe[-1]) < 1e-9 * abs(e0)
+    for a, c in zip(swe, swe[1:]):
+        assert c <= a + 1e-12 * abs(a)
+
+
+def test_hubbard_cylinder_sweeps_against_ed(mods):
+    lib, problems, gdmrg = mods
+    W, Lx, U = 2, 3, 8.0
+    hops = synth.cylinder_j1_bonds(W, Lx)
+    n = W * Lx
+    mpo = synth.hubbard_mpo(n, hops, U)
+    mps = random_mps(mpo, n, (n, 0), 32, 1, mps_block)
+    g = gdmrg.GpuDMRG(mpo, host_mps(problems, lib, mps), (n, 0))
+    E, swe = g.run(3, 64, cutoff=1e-10, max_iter=40, tol=1e-12)
+    e0 = ed.lowest(ed.hubbard_sector(n, hops, U, n // 2, n // 2))
+    assert abs(swe[-1] - e0) < 1e-9 * abs(e0)
