@@ -301,6 +301,23 @@ bsdmrg_status bsdmrg_env_update(bsdmrg_op_t op, const double* env, const double*
                                 const double* W, double* env_out, void* workspace,
                                 int64_t workspace_bytes, hipStream_t stream);
 
+/* Adjoint of an environment op with respect to W (the extension is linear
+ * in W): for the output cotangent d_out (layout of env_out),
+ *   d_W[e] = sum over env_out of d_out * d(env_out)/d(W[e])
+ * for every element of every symmetry-allowed W block (also the blocks that
+ * are zero in the planned W); padding is written as 0.  Left op:
+ * d_W(w,s',s,w') = sum A(a',s',b') L(a',w,a) A(a,s,b) d_out(b',w',b); right
+ * op: d_W(w,s',s,w') = sum B(b',s',c') R(c',w',c) B(b,s,c) d_out(b',w,b).
+ * The cotangent of env itself is the op of the opposite side (x and y
+ * swapped, same site tensor and W) applied to d_out; the site tensor's
+ * cotangent is not provided (the MPS is held fixed).  The first call builds
+ * the adjoint tables of the op.  Device pointers; FP64; fixed summation
+ * order.  Errors: EINVAL, EHIP. */
+bsdmrg_status bsdmrg_env_backward_workspace(bsdmrg_op_t op, int64_t* bytes);
+bsdmrg_status bsdmrg_env_backward(bsdmrg_op_t op, const double* env, const double* mps,
+                                  const double* d_out, double* d_W, void* workspace,
+                                  int64_t workspace_bytes, hipStream_t stream);
+
 /* Run a merge op (no workspace).  Errors: EINVAL, EHIP. */
 bsdmrg_status bsdmrg_merge(bsdmrg_op_t op, const double* A, const double* B, double* theta,
                            hipStream_t stream);

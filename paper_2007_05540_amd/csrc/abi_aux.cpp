@@ -18,6 +18,10 @@ void truncate_run(const bsdmrg_leg* legs, const double* theta, const bsdmrg_trun
                   int32_t* new_q, int64_t* new_d, int32_t leg_cap, double* A, int64_t A_cap, int64_t* A_elems,
                   double* B, int64_t B_cap, int64_t* B_elems, double* svals, int64_t sv_cap, int64_t* n_kept,
                   double* discarded, void* ws, int64_t ws_bytes, hipStream_t st);
+void destroy_env_backward(bsdmrg_op_s* O);
+int64_t env_backward_bytes(bsdmrg_op_s* O);
+void env_backward_run(bsdmrg_op_s* O, const double* env, const double* site, const double* d_out, double* d_W,
+                      void* ws, int64_t ws_bytes, hipStream_t s);
 }  // namespace bsd
 
 using namespace bsd;
@@ -126,6 +130,7 @@ bsdmrg_status bsdmrg_op_query(bsdmrg_op_t O, int64_t* workspace_bytes, int64_t* 
 bsdmrg_status bsdmrg_op_destroy(bsdmrg_op_t O) {
   return guarded([&] {
     if (!O) return;
+    destroy_env_backward(O);
     if (O->d_blob) (void)hipFree(O->d_blob);
     delete O;
   });
@@ -146,6 +151,24 @@ bsdmrg_status bsdmrg_env_update(bsdmrg_op_t O, const double* env, const double* 
     HIPCHK(launch_gemm_f64(O->g1, O->layout1, env, mps, X1, X1, s));
     HIPCHK(launch_mix_tables(O->d_mix_items, O->mix_items.size(), O->d_mix_tasks, O->d_mix_terms, W, X1, X2, s));
     HIPCHK(launch_gemm_f64(O->g2, O->layout2, mps, X2, env_out, env_out, s));
+  });
+}
+
+bsdmrg_status bsdmrg_env_backward_workspace(bsdmrg_op_t O, int64_t* bytes) {
+  return guarded([&] {
+    if (!O || !bytes) throw Error{BSDMRG_EINVAL, "env_backward_workspace: NULL argument"};
+    if (O->kind != 1 && O->kind != 2) throw Error{BSDMRG_EINVAL, "env_backward_workspace: not an environment op"};
+    *bytes = env_backward_bytes(O);
+  });
+}
+
+bsdmrg_status bsdmrg_env_backward(bsdmrg_op_t O, const double* env, const double* mps, const double* d_out,
+                                  double* d_W, void* workspace, int64_t workspace_bytes, hipStream_t s) {
+  return guarded([&] {
+    if (!O || (O->kind != 1 && O->kind != 2)) throw Error{BSDMRG_EINVAL, "env_backward: not an environment op"};
+    if (!env || !mps || !d_out || !d_W) throw Error{BSDMRG_EINVAL, "env_backward: NULL operand"};
+    if (d_W == env || d_W == mps || d_W == d_out) throw Error{BSDMRG_EINVAL, "env_backward: d_W aliases an input"};
+    env_backward_run(O, env, mps, d_out, d_W, workspace, workspace_bytes, s);
   });
 }
 

@@ -438,7 +438,7 @@ void heff_backward_run(bsdmrg_plan_s* P, const double* L, const double* W1, cons
   }
   if (d_W1 || d_W2) {
     HIPCHK(launch_bwd_dots(B->d_dots, (int)B->dots.size(), w.G, T1, w.part, s));
-    HIPCHK(launch_bwd_coef((int)B->n_keys, B->d_dot_ptr, w.part, w.dcoef, s));
+    HIPCHK(launch_bwd_coef((int)B->n_keys, B->d_dot_ptr, w.part, nullptr, w.dcoef, s));
     if (d_W1) {
       HIPCHK(launch_bwd_wgrad(P->W1_elems, B->d_w1_ptr, B->d_w1_coef, B->d_w1_part, w.dcoef, W2, 1.0, d_W1, s));
       HIPCHK(launch_seg_scale(P->W1_elems, B->d_base + 3 * (np + 1), np, w.g, d_W1, nullptr, d_W1, s));

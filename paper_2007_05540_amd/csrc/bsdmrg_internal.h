@@ -159,7 +159,15 @@ struct ProblemPlan {
   int32_t chunk0 = 0, nchunk = 0;
 };
 
-struct Backward;   // adjoint tables (backward.cpp)
+struct Backward;      // adjoint tables of the two-site energy (backward.cpp)
+struct EnvBackward;   // adjoint tables of an environment extension (env_backward.cpp)
+
+// Stage-1 block of an environment extension: X1(x', f, s, b), row-major
+// (x' * channels of f) x b.
+struct X1Block {
+  int32_t xp, f, is, ib;
+  int64_t off;
+};
 
 }  // namespace bsd
 
@@ -220,4 +228,9 @@ struct bsdmrg_op_s {
   bsd::MixTask* d_mix_tasks = nullptr;
   bsd::MixTerm* d_mix_terms = nullptr;
   bsd::MixItem* d_mix_items = nullptr;
+  // environment ops: legs x, s, y, wl, wr and the stage-1 blocks (adjoint)
+  int side = 0;
+  std::vector<bsd::Leg> legs;
+  std::vector<bsd::X1Block> x1_blocks;
+  bsd::EnvBackward* ebwd = nullptr;
 };

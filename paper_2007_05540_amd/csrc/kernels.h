@@ -75,7 +75,8 @@ hipError_t dav_scale_into(const bsdmrg_plan_s* P, const DavBufs& b, double* dst,
 // adjoint kernels (kernels_bwd.hip)
 hipError_t launch_bwd_dots(const BwdDot* items, int n, const double* G, const double* T1, double* part,
                            hipStream_t s);
-hipError_t launch_bwd_coef(int n, const int32_t* ptr, const double* part, double* dcoef, hipStream_t s);
+hipError_t launch_bwd_coef(int n, const int32_t* ptr, const double* part, const int64_t* idx, double* out,
+                           hipStream_t s);
 hipError_t launch_bwd_wgrad(int64_t n, const int32_t* ptr, const int32_t* coef, const int64_t* partner,
                             const double* dcoef, const double* Wother, double g, double* dW, hipStream_t s);
 hipError_t launch_seg_scale(int64_t n, const int64_t* base, int np, const double* g, const double* x,

@@ -25,14 +25,14 @@ __global__ __launch_bounds__(256) void bwd_dot_kernel(const BwdDot* __restrict__
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-// dWW(k) = sum of the partial dots of key k, in order.
+// out[idx[k]] (or out[k] without idx) = sum of the partial dots of key k, in order.
 __global__ void bwd_coef_kernel(int n, const int32_t* __restrict__ ptr, const double* __restrict__ part,
-                                double* __restrict__ dcoef) {
+                                const int64_t* __restrict__ idx, double* __restrict__ out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   double s = 0.0;
   for (int j = ptr[k]; j < ptr[k + 1]; ++j) s += part[j];
-  dcoef[k] = s;
+  out[idx ? idx[k] : k] = s;
 }
 
 // dW(e) = g * sum_j dWW(coef_j) * Wother(partner_j) over the CSR row of element e.
@@ -69,9 +69,10 @@ hipError_t launch_bwd_dots(const BwdDot* items, int n, const double* G, const do
   hipLaunchKernelGGL(bwd_dot_kernel, dim3((unsigned)n), dim3(256), 0, s, items, G, T1, part);
   return hipGetLastError();
 }
-hipError_t launch_bwd_coef(int n, const int32_t* ptr, const double* part, double* dcoef, hipStream_t s) {
+hipError_t launch_bwd_coef(int n, const int32_t* ptr, const double* part, const int64_t* idx, double* out,
+                           hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(bwd_coef_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, ptr, part, dcoef);
+  hipLaunchKernelGGL(bwd_coef_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, ptr, part, idx, out);
   return hipGetLastError();
 }
 hipError_t launch_bwd_wgrad(int64_t n, const int32_t* ptr, const int32_t* coef, const int64_t* partner,

@@ -67,6 +67,8 @@ bsdmrg_op_s* build_env(const bsdmrg_env_problem& in, int side) {
     std::vector<char> nz(W.keys.size());
     for (size_t b = 0; b < nz.size(); ++b) nz[b] = w_nonzero(W, in.w_host, (int)b);
     O->kind = side == 0 ? 1 : 2;
+    O->side = side;
+    O->legs = {x, s, y, wl, wr};
     const Leg& wi = side == 0 ? wl : wr;   // channel leg of the input environment
     const Leg& wo = side == 0 ? wr : wl;   // channel leg of the output environment
     Layout E = make_layout({&x, &wi, &x}, kEnvS);
@@ -88,6 +90,7 @@ bsdmrg_op_s* build_env(const bsdmrg_env_problem& in, int side) {
           O->g1.tasks.push_back(GemmTask{cur, N, Mr, N, (int32_t)O->g1.segs.size() - 1, 1, K, 0, 0});
           O->flops += 2.0 * Mr * N * (double)K;
           x1[k4(xp, f, is, ib)] = cur;
+          O->x1_blocks.push_back(X1Block{xp, f, is, ib, cur});
           cur += round_up((int64_t)Mr * N);
         }
     }

@@ -115,6 +115,55 @@ class GpuDMRG:
         plan.destroy()
         return e[0], st[0], info["flops_s1"] + info["flops_s3"]
 
+    def energy_and_mpo_gradients(self, bond=0):
+        """E = psi^T H_eff psi at (bond, bond + 1) and dE/dW_s for every site
+        s, by reverse mode through the autograd graph EnvUpdate x sites ->
+        HeffEnergy.  The MPS must be mixed-canonical around the bond and
+        normalised (as after run(), for bond 0), so that E = <Psi|H|Psi>.
+        Returns (E, [dE/dW_s device tensors in canonical W layout])."""
+        from . import autograd
+        torch = self.torch
+        N, wl = self.N, self.wl
+        Wg = [w.detach().clone().requires_grad_(True) for w in self.W]
+        keep = []
+        L = self.L[0].data
+        for j in range(bond):
+            x, s, y = self.T[j].legs
+            op = lib.env_plan(x, s, y, wl, wl, self.W_host[j], 0)
+            adj = lib.env_plan(y, s, x, wl, wl, self.W_host[j], 1)
+            keep += [op, adj]
+            L = autograd.EnvUpdate.apply(op, adj, L, self.T[j].data, Wg[j])
+        R = self.R[N].data
+        for j in range(N - 1, bond + 1, -1):
+            y, s, x = self.T[j].legs
+            op = lib.env_plan(x, s, y, wl, wl, self.W_host[j], 1)
+            adj = lib.env_plan(y, s, x, wl, wl, self.W_host[j], 0)
+            keep += [op, adj]
+            R = autograd.EnvUpdate.apply(op, adj, R, self.T[j].data, Wg[j])
+        theta = self._merge(self.T[bond], self.T[bond + 1])
+        a, s1, s2, c = theta.legs
+        plan = lib.Plan([{"a": a, "s1": s1, "s2": s2, "c": c, "wl": wl, "wm": wl, "wr": wl,
+                          "w1": self.W_host[bond], "w2": self.W_host[bond + 1]}])
+        E = autograd.HeffEnergy.apply(plan, L, Wg[bond], Wg[bond + 1], R, theta.data)
+        E.sum().backward()
+        torch.cuda.synchronize()
+        grads = [w.grad if w.grad is not None else torch.zeros_like(w) for w in Wg]
+        plan.destroy()
+        for o in keep:
+            o.destroy()
+        return float(E[0].item()), grads
+
+    def parameter_derivative(self, grads, dW_dp):
+        """Chain rule over the sites, sum_s <dE/dW_s, dW_s/dp>, for an MPO
+        parameter p with dense per-site derivatives dW_dp[s] (w, s', s, w') from
+        the MPO builder.  This contraction over the O(k^2 d^2) MPO entries of
+        each site belongs to the model builder and runs on the host."""
+        total = 0.0
+        for g, d in zip(grads, dW_dp):
+            dp = problems.pack_dense(d, [self.wl, self.s, self.s, self.wl], lib.W_SIGNS)
+            total += float(np.dot(g.detach().cpu().numpy(), dp))
+        return total
+
     def run(self, n_sweeps, m_max, cutoff=1e-10, cutoff_mode=0, max_iter=40, tol=1e-12, progress=False):
         """Two-site sweeps; m_max is an int or a per-sweep list.  Returns
         (energies per visited bond, last energy of every sweep)."""

@@ -76,6 +76,7 @@ EXPORTS = ["bsdmrg_layout", "bsdmrg_plan", "bsdmrg_plan_query", "bsdmrg_plan_off
            "bsdmrg_plan_destroy", "bsdmrg_heff_apply", "bsdmrg_eig_workspace", "bsdmrg_eigensolve",
            "bsdmrg_heff_backward", "bsdmrg_heff_energy", "bsdmrg_stage_timing", "bsdmrg_truncate_workspace", "bsdmrg_truncate",
            "bsdmrg_env_plan", "bsdmrg_merge_plan", "bsdmrg_op_query", "bsdmrg_op_destroy", "bsdmrg_env_update",
+           "bsdmrg_env_backward_workspace", "bsdmrg_env_backward",
            "bsdmrg_merge", "bsdmrg_last_error"]
 
 
@@ -117,6 +118,8 @@ def load():
     lib.bsdmrg_op_destroy.argtypes = [vp]
     lib.bsdmrg_env_update.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
     lib.bsdmrg_merge.argtypes = [vp, vp, vp, vp, vp]
+    lib.bsdmrg_env_backward_workspace.argtypes = [vp, P(i64)]
+    lib.bsdmrg_env_backward.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
     _lib = lib
     return lib
 
@@ -330,6 +333,18 @@ def env_update(op, env, mps, W, env_out, workspace, stream=None):
     nb = 0 if workspace is None else workspace.numel() * workspace.element_size()
     check(load().bsdmrg_env_update(op.handle, _ptr(env), _ptr(mps), _ptr(W), _ptr(env_out), _ptr(workspace), nb,
                                    _stream(stream)))
+
+
+def env_backward_workspace(op):
+    n = ctypes.c_int64(0)
+    check(load().bsdmrg_env_backward_workspace(op.handle, ctypes.byref(n)))
+    return n.value
+
+
+def env_backward(op, env, mps, d_out, d_W, workspace, stream=None):
+    """d_W = cotangent of W of an environment op (see the header)."""
+    check(load().bsdmrg_env_backward(op.handle, _ptr(env), _ptr(mps), _ptr(d_out), _ptr(d_W), _ptr(workspace),
+                                     workspace.numel() * workspace.element_size(), _stream(stream)))
 
 
 def merge(op, A, B, theta, stream=None):

@@ -24,6 +24,14 @@ def lib():
     return L
 
 
+def check_env(op):
+    """An environment op and the tables of its adjoint (built and checked on
+    the host by the workspace query)."""
+    from paper_2007_05540_amd import lib
+    assert lib.env_backward_workspace(op) > 0
+    op.destroy()
+
+
 def replay(lib, mpo, n, target, m0, m_max, sweeps, dav):
     from paper_2007_05540_amd import problems
     wl = mpo.w_leg()
@@ -61,10 +69,10 @@ def replay(lib, mpo, n, target, m0, m_max, sweeps, dav):
             A, B, _, _, _ = truncate(x, d, cutoff=1e-10, m_max=m_max)
             mps[j], mps[j + 1] = A, B
             if d == "right":
-                lib.env_plan(A.legs[0], s, A.legs[2], wl, wl, Wh[j], 0, host_only=True).destroy()
+                check_env(lib.env_plan(A.legs[0], s, A.legs[2], wl, wl, Wh[j], 0, host_only=True))
                 L[j + 1] = left_update_dense(L[j], A, Ws[j])
             else:
-                lib.env_plan(B.legs[2], s, B.legs[0], wl, wl, Wh[j + 1], 1, host_only=True).destroy()
+                check_env(lib.env_plan(B.legs[2], s, B.legs[0], wl, wl, Wh[j + 1], 1, host_only=True))
                 R[j + 1] = right_update_dense(R[j + 2], B, Ws[j + 1])
             count += 1
     return count
