@@ -139,3 +139,18 @@ def test_adjoint_de_dj2_equals_hellmann_feynman(j1j2_3x4):
     # a planted mistake is seen: dropping one site's contribution changes the value
     partial = grad.parameter_derivative(dW[:-3] + [d.scale(0.0) for d in dW[-3:]], dWb)
     assert abs(partial - c["hf"]) > 1e-3
+
+
+def test_mpo_gradients_euler_identity_per_site():
+    """E = <Psi|H|Psi> is linear in every W_s: <dE/dW_s, W_s> = E for each
+    site, and the bond energy equals the MPO expectation value."""
+    n = 8
+    mpo = synth.heisenberg_mpo(n, synth.merge_bonds(synth.chain_bonds(n), {(i, i + 2): 0.4 for i in range(n - 2)}))
+    mps = right_canonicalize(random_mps(mpo, n, (0,), 12, 9, mps_block))
+    wl = mpo.w_leg()
+    Ws = [w_tensor(x, wl, mpo.phys, wl) for x in mpo.W]
+    E, dW = grad.mpo_gradients(mps, Ws, wl, mpo.start, mpo.done, (0,), 0)
+    nrm = sum(float(np.sum(v * v)) for v in mps[0].blocks.values())
+    assert abs(E / nrm - grad.expectation(mps, mpo.W, mpo.start, mpo.done)) < 1e-12 * abs(E / nrm)
+    for j in range(n):
+        assert abs(dW[j].dot(Ws[j]) - E) < 1e-12 * abs(E), j
