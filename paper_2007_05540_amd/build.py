@@ -19,6 +19,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 CFLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # MFMA accumulators in ordinary VGPRs: no AGPR copies inside the GEMM loops
+          "-mllvm", "-amdgpu-mfma-vgpr-form",
           "-I" + os.path.join(os.path.dirname(HERE), "include")]
 LDFLAGS = ["--offload-arch=gfx950", "-shared", "-fPIC"]
 

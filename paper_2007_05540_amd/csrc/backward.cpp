@@ -69,16 +69,6 @@ static Key kk3(int a, int b, int c) { Key k{}; k[0] = a; k[1] = b; k[2] = c; ret
 static Key kk4(int a, int b, int c, int d) { Key k{}; k[0] = a; k[1] = b; k[2] = c; k[3] = d; return k; }
 static Charge add2(const Charge& a, const Charge& b) { return {a[0] + b[0], a[1] + b[1]}; }
 
-static void tiles(Stage& st) {
-  st.tiles.clear();
-  for (size_t t = 0; t < st.tasks.size(); ++t)
-    for (int m0 = 0; m0 < st.tasks[t].M; m0 += 64)
-      for (int n0 = 0; n0 < st.tasks[t].N; n0 += 64) st.tiles.push_back({(int)t, m0, n0, 0});
-  std::stable_sort(st.tiles.begin(), st.tiles.end(), [&](const GemmTile& x, const GemmTile& y) {
-    return st.tasks[x.task].ksum > st.tasks[y.task].ksum;
-  });
-}
-
 #define HIPCHK(x)                                                                              \
   do {                                                                                         \
     hipError_t e_ = (x);                                                                       \
@@ -269,10 +259,10 @@ static void build_backward(bsdmrg_plan_s* P) {
     }
     if (B->w1_ptr.empty()) B->w1_ptr.push_back(0);
     if (B->w2_ptr.empty()) B->w2_ptr.push_back(0);
-    tiles(B->b1);
-    tiles(B->dl);
-    tiles(B->hpsi);
-    tiles(B->dr);
+    schedule_tiles(B->b1);
+    schedule_tiles(B->dl);
+    schedule_tiles(B->hpsi);
+    schedule_tiles(B->dr);
     // host checks of every table
     validate_gemm(B->b1, kNN, P->psi_elems, P->R_elems, P->t2_elems, 0, "backward G");
     validate_gemm(B->dl, kNT, P->t1_elems, P->psi_elems, P->L_elems, 0, "backward dL");

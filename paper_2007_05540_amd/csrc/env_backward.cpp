@@ -99,9 +99,7 @@ static void build_env_backward(bsdmrg_op_s* O) {
         }
       }
     B->y_elems = cur;
-    for (size_t t = 0; t < B->y.tasks.size(); ++t)
-      for (int m0 = 0; m0 < B->y.tasks[t].M; m0 += 64)
-        for (int n0 = 0; n0 < B->y.tasks[t].N; n0 += 64) B->y.tiles.push_back({(int)t, m0, n0, 0});
+    schedule_tiles(B->y);
     // stage-1 blocks grouped by (input channel sector, s)
     std::map<std::pair<int, int>, std::vector<X1Block>> by_fs;
     for (const X1Block& b : O->x1_blocks) by_fs[{b.f, b.is}].push_back(b);

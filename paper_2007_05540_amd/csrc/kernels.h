@@ -82,6 +82,9 @@ hipError_t launch_bwd_wgrad(int64_t n, const int32_t* ptr, const int32_t* coef, 
 hipError_t launch_seg_scale(int64_t n, const int64_t* base, int np, const double* g, const double* x,
                             const double* y, double* out, hipStream_t s);
 
+// XCD-aware tile schedule of a GEMM stage (schedule.cpp)
+void schedule_tiles(Stage& st);
+
 // host-side table checks (validate.cpp)
 void validate_gemm(const Stage& st, int layout, int64_t a_elems, int64_t b_elems, int64_t c_elems,
                    int64_t cpart_elems, const char* name);

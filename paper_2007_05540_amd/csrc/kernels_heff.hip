@@ -2,10 +2,10 @@
 //
 // ggemm: grouped block GEMM.  One workgroup (4 waves, 2 x 2) computes one
 // 64 x 64 tile of one task; the task's K-list segments are accumulated in the
-// same MFMA accumulators (fixed order, no atomics).  Tiles are staged through
-// LDS in BK = 16 slices stored k-major so that MFMA operand fetches are
-// contiguous; the next slice is fetched from global memory into registers
-// while the current slice is multiplied.
+// same MFMA accumulators (fixed order, no atomics).  Operands are staged
+// through double-buffered LDS slices (32 deep in k for FP32, 16 for FP64);
+// the next slice is fetched from global memory into registers while the
+// current slice is multiplied.
 //   FP64: v_mfma_f64_16x16x4f64, FP32: v_mfma_f32_16x16x4f32.
 // Operand layout of the 16x16x4 MFMA (both types): lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16].  Accumulator element r of lane l is
@@ -13,12 +13,14 @@
 // for the FP32 one (checked on gfx950).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "bsdmrg_internal.h"
 #include "kernels.h"
 
 namespace bsd {
 
-constexpr int BM = 64, BN = 64, BK = 16, NTHR = 256;
+constexpr int BM = 64, BN = 64, NTHR = 256;
 
 template <typename T>
 struct Mfma;
@@ -39,9 +41,209 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-// TC: compute type; TA/TB: global operand types (converted on load);
-// TO: output type; BT: B stored N x K (row-major) instead of K x N;
+// LDS slice of one operand (BKT deep in k): K-contiguous operands (A as
+// M x K, B as N x K) are kept [row][k] with a row stride of BKT + 4 (FP32) or
+// BKT + 1 (FP64), M/N-contiguous ones (A as K x M, B as K x N) [k][col] with
+// a row stride of 64 + 16 (FP32) or 64 + 8 (FP64).  With these strides the
+// MFMA operand reads (16 consecutive rows or columns at 4 k) spread evenly
+// over the LDS banks, and so do the global->LDS writes of the M/N-contiguous
+// operands (64 consecutive columns of one k).
+template <typename TC, bool KC>
+struct Slice {
+  // k depth of a slice (one barrier per slice): 32 in FP32, 16 in FP64
+  static constexpr int BKT = sizeof(TC) == 4 ? 32 : 16;
+  static constexpr int LD = KC ? BKT + (sizeof(TC) == 4 ? 4 : 1) : BM + (sizeof(TC) == 4 ? 16 : 8);
+  static constexpr int SIZE = KC ? BM * LD : BKT * LD;
+  // element (row or column r of the tile, k of the slice)
+  static __device__ __forceinline__ int at(int r, int k) { return KC ? r * LD + k : k * LD + r; }
+};
+
+// One wave's part of a grouped-GEMM tile: the whole K loop for a fixed
+// number NI x NJ (0..2 each) of valid 16 x 16 sub-tiles of the wave's
+// 32 x 32 quarter, so the MFMAs of a wave are straight-line code with the
+// accumulators in fixed registers.  Every wave of the workgroup runs the
+// same number of iterations and barriers whatever its NI x NJ.
+//
+// TC: compute type; TA/TB: global operand types (converted when written to
+// LDS); TO: output type; BT: B stored N x K (row-major) instead of K x N;
 // AT: A stored K x M (row-major) instead of M x K.
+//
+// Global -> LDS: a thread owns 4 elements of each operand slice.  For a
+// K-contiguous operand: k = tid % 16 and rows tid / 16 + 16 u, so one load
+// instruction reads 4 rows x 16 consecutive k.  For an M/N-contiguous
+// operand: column tid % 64 and k = tid / 64 + 4 u, so one load instruction
+// reads 64 consecutive columns of one k.  Addresses are a wave-uniform base
+// (segment start plus the slice's k offset) plus a per-thread 32-bit byte
+// offset fixed for the segment.  Rows and columns past the block edge are
+// read from the last one (every block is at least 1 x 1, so the address
+// stays inside the block) and zeroed when written to LDS; only the last
+// slice of a segment clamps k.  Loads keep their storage type until then, so
+// they stay in flight across the MFMAs of the current slice.  LDS holds two
+// slices (double buffer) and each iteration has one barrier.
+template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT, int NI, int NJ>
+__device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask& task,
+                                           const GemmSeg* __restrict__ segs, const TA* __restrict__ A,
+                                           const TB* __restrict__ B, TO* __restrict__ C,
+                                           TO* __restrict__ Cpart, TC* As, TC* Bs) {
+  using SA = Slice<TC, !AT>;
+  using SB = Slice<TC, BT>;
+  constexpr int BKT = SA::BKT;        // k depth of a slice
+  constexpr int EPT = BKT / 4;        // elements of each operand per thread and slice
+  constexpr int RSTEP = 256 / BKT;    // row step of a thread's K-contiguous elements
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l16 = lane & 15, g4 = lane >> 4;
+  using V4 = typename Mfma<TC>::v4;
+  V4 acc[NI > 0 ? NI : 1][NJ > 0 ? NJ : 1];
+#pragma unroll
+  for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
+#pragma unroll
+    for (int j = 0; j < (NJ > 0 ? NJ : 1); ++j) acc[i][j] = V4{0, 0, 0, 0};
+
+  // this thread's EPT elements of a slice: (row or column, k) per operand
+  const int kc_k = tid % BKT, kc_r = tid / BKT;    // K-contiguous: k, first row (+RSTEP u)
+  const int mc_c = tid & 63, mc_k = tid >> 6;      // M/N-contiguous: column, first k (+4 u)
+  // validity of rows / columns (fixed for the tile)
+  unsigned a_v = 0, b_v = 0;
+  int a_r[EPT], b_r[EPT];                          // clamped rows / columns
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int ar = tile.m0 + (AT ? mc_c : kc_r + RSTEP * u);
+    const int br = tile.n0 + (BT ? kc_r + RSTEP * u : mc_c);
+    a_r[u] = min(ar, task.M - 1);
+    b_r[u] = min(br, task.N - 1);
+    a_v |= (unsigned)(ar < task.M) << u;
+    b_v |= (unsigned)(br < task.N) << u;
+  }
+
+  TA la[EPT];
+  TB lb[EPT];
+  unsigned va = 0, vb = 0;
+  const char* a_seg = nullptr;
+  const char* b_seg = nullptr;
+  unsigned ao[EPT], bo[EPT];
+  auto setup = [&](const GemmSeg& sg) {
+    a_seg = (const char*)(A + sg.a_off);
+    b_seg = (const char*)(B + sg.b_off);
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      ao[u] = (AT ? (unsigned)(mc_k + 4 * u) * sg.lda + a_r[u] : (unsigned)a_r[u] * sg.lda + kc_k) * sizeof(TA);
+      bo[u] = (BT ? (unsigned)b_r[u] * sg.ldb + kc_k : (unsigned)(mc_k + 4 * u) * sg.ldb + b_r[u]) * sizeof(TB);
+    }
+  };
+  auto load = [&](const GemmSeg& sg, int kk0) {
+    const char* ab = a_seg + (size_t)kk0 * (AT ? sg.lda : 1) * sizeof(TA);
+    const char* bb = b_seg + (size_t)kk0 * (BT ? 1 : sg.ldb) * sizeof(TB);
+    if (kk0 + BKT <= sg.K) {
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) {
+        la[u] = *(const TA*)(ab + ao[u]);
+        lb[u] = *(const TB*)(bb + bo[u]);
+      }
+      va = a_v;
+      vb = b_v;
+    } else {
+      // last slice of the segment: k clamped to K - 1, zeroed past it
+      const int km = sg.K - 1;
+      va = vb = 0;
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) {
+        const int ka = kk0 + (AT ? mc_k + 4 * u : kc_k);
+        const int kb = kk0 + (BT ? kc_k : mc_k + 4 * u);
+        la[u] = *(const TA*)(ab + ao[u] + (min(ka, km) - ka) * (AT ? sg.lda : 1) * (int)sizeof(TA));
+        lb[u] = *(const TB*)(bb + bo[u] + (min(kb, km) - kb) * (BT ? 1 : sg.ldb) * (int)sizeof(TB));
+        va |= (ka < sg.K) ? (a_v & (1u << u)) : 0u;
+        vb |= (kb < sg.K) ? (b_v & (1u << u)) : 0u;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+    TC* as = As + buf * SA::SIZE;
+    TC* bs = Bs + buf * SB::SIZE;
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const TC x = ((va >> u) & 1) ? (TC)la[u] : (TC)0;
+      const TC y = ((vb >> u) & 1) ? (TC)lb[u] : (TC)0;
+      as[AT ? SA::at(mc_c, mc_k + 4 * u) : SA::at(kc_r + RSTEP * u, kc_k)] = x;
+      bs[BT ? SB::at(kc_r + RSTEP * u, kc_k) : SB::at(mc_c, mc_k + 4 * u)] = y;
+    }
+  };
+  // MFMA k-step q of lane group g (lanes 16 g .. 16 g + 15) takes k = g QN + q
+  // of the slice (any assignment of the slice's k to (g, q) is valid when A
+  // and B use the same one): a lane's operands of a whole slice are QN
+  // consecutive k, all read from LDS before the slice's MFMAs.
+  auto compute = [&](int buf) {
+    if (NI == 0 || NJ == 0) return;
+    constexpr int QN = BKT / 4;
+    const TC* as = As + buf * SA::SIZE;
+    const TC* bs = Bs + buf * SB::SIZE;
+    TC a[NI > 0 ? NI : 1][QN], b[NJ > 0 ? NJ : 1][QN];
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int q = 0; q < QN; ++q) a[i][q] = as[SA::at(wm * 32 + i * 16 + l16, g4 * QN + q)];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int q = 0; q < QN; ++q) b[j][q] = bs[SB::at(wn * 32 + j * 16 + l16, g4 * QN + q)];
+#pragma unroll
+    for (int q = 0; q < QN; ++q)
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[i][j] = Mfma<TC>::op(a[i][q], b[j][q], acc[i][j]);
+  };
+
+  int seg = task.seg0;
+  const int seg_end = task.seg0 + task.nseg;
+  int k0 = 0;
+  GemmSeg s;
+  bool have = seg < seg_end;
+  if (have) {
+    s = segs[seg];
+    setup(s);
+    load(s, 0);
+    store(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  while (have) {
+    // advance to the next K slice (possibly the next segment) and fetch it
+    k0 += BKT;
+    if (k0 >= s.K) {
+      ++seg;
+      k0 = 0;
+      have = seg < seg_end;
+      if (have) {
+        s = segs[seg];
+        setup(s);
+      }
+    }
+    if (have) load(s, k0);
+    compute(buf);
+    if (have) {
+      store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+  TO* Cp = (task.cbuf ? Cpart : C) + task.c_off;
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = tile.m0 + wm * 32 + i * 16 + Mfma<TC>::row(lane, r);
+        const int col = tile.n0 + wn * 32 + j * 16 + l16;
+        if (row < task.M && col < task.N) Cp[(int64_t)row * task.ldc + col] = (TO)acc[i][j][r];
+      }
+}
+
+// Grouped block GEMM: one workgroup per 64 x 64 tile of one task, the task's
+// K-list segments accumulated in the same MFMA accumulators (fixed order).
 template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT = false>
 __global__ __launch_bounds__(NTHR) void ggemm_kernel(const GemmTile* __restrict__ tiles,
                                                      const GemmTask* __restrict__ tasks,
@@ -49,119 +251,26 @@ __global__ __launch_bounds__(NTHR) void ggemm_kernel(const GemmTile* __restrict_
                                                      const TA* __restrict__ A,
                                                      const TB* __restrict__ B,
                                                      TO* __restrict__ C, TO* __restrict__ Cpart) {
-  __shared__ TC As[BK][BM + 1];
-  __shared__ TC Bs[BK][BN + 1];
+  __shared__ TC As[2 * Slice<TC, !AT>::SIZE];
+  __shared__ TC Bs[2 * Slice<TC, BT>::SIZE];
   const GemmTile tile = tiles[blockIdx.x];
+  if (tile.task < 0) return;   // padding of the per-XCD schedule
   const GemmTask task = tasks[tile.task];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  using V4 = typename Mfma<TC>::v4;
-  V4 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = V4{0, 0, 0, 0};
-
-  // global -> register mapping
-  const int a_row = tid >> 2, a_k = (tid & 3) * 4;          // A: 64 rows x 16 k
-  const int at_k = tid >> 4, at_m = (tid & 15) * 4;         // A (TN): 16 k x 64 m
-  const int bn_k = tid >> 4, bn_n = (tid & 15) * 4;         // B (NN): 16 k x 64 n
-  const int bt_n = tid >> 2, bt_k = (tid & 3) * 4;          // B (NT): 64 n x 16 k
-  TC ra[4], rb[4];
-
-  int seg = task.seg0;
-  const int seg_end = task.seg0 + task.nseg;
-  int k0 = 0;
-  GemmSeg s;
-  if (seg < seg_end) s = segs[seg];
-
-  auto load = [&](const GemmSeg& sg, int kk0) {
-    const TA* Ap = A + sg.a_off;
-    const TB* Bp = B + sg.b_off;
-    if (!AT) {
-      const int row = tile.m0 + a_row;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = kk0 + a_k + u;
-        ra[u] = (row < task.M && k < sg.K) ? (TC)Ap[(int64_t)row * sg.lda + k] : (TC)0;
-      }
-    } else {
-      const int k = kk0 + at_k;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int m = tile.m0 + at_m + u;
-        ra[u] = (k < sg.K && m < task.M) ? (TC)Ap[(int64_t)k * sg.lda + m] : (TC)0;
-      }
-    }
-    if (!BT) {
-      const int k = kk0 + bn_k;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int n = tile.n0 + bn_n + u;
-        rb[u] = (k < sg.K && n < task.N) ? (TC)Bp[(int64_t)k * sg.ldb + n] : (TC)0;
-      }
-    } else {
-      const int n = tile.n0 + bt_n;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = kk0 + bt_k + u;
-        rb[u] = (n < task.N && k < sg.K) ? (TC)Bp[(int64_t)n * sg.ldb + k] : (TC)0;
-      }
-    }
-  };
-
-  bool have = seg < seg_end;
-  if (have) load(s, 0);
-  while (have) {
-    __syncthreads();
-    if (!AT) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) As[a_k + u][a_row] = ra[u];
-    } else {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) As[at_k][at_m + u] = ra[u];
-    }
-    if (!BT) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) Bs[bn_k][bn_n + u] = rb[u];
-    } else {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) Bs[bt_k + u][bt_n] = rb[u];
-    }
-    __syncthreads();
-    // advance to the next K slice (possibly the next segment) and prefetch it
-    k0 += BK;
-    if (k0 >= s.K) {
-      ++seg;
-      k0 = 0;
-      have = seg < seg_end;
-      if (have) s = segs[seg];
-    }
-    if (have) load(s, k0);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      TC a[2], b[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[kk + (lane >> 4)][wm * 32 + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[kk + (lane >> 4)][wn * 32 + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<TC>::op(a[i], b[j], acc[i][j]);
-    }
-  }
-
-  TO* Cp = (task.cbuf ? Cpart : C) + task.c_off;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = tile.m0 + wm * 32 + i * 16 + Mfma<TC>::row(lane, r);
-        const int col = tile.n0 + wn * 32 + j * 16 + (lane & 15);
-        if (row < task.M && col < task.N) Cp[(int64_t)row * task.ldc + col] = (TO)acc[i][j][r];
-      }
+  const int wave = threadIdx.x >> 6;
+  // valid 16 x 16 sub-tiles of this wave's 32 x 32 quarter (wave-uniform)
+  const int r0 = tile.m0 + (wave >> 1) * 32, c0 = tile.n0 + (wave & 1) * 32;
+  const int ni = r0 >= task.M ? 0 : (r0 + 16 < task.M ? 2 : 1);
+  const int nj = c0 >= task.N ? 0 : (c0 + 16 < task.N ? 2 : 1);
+  if (ni == 2 && nj == 2)
+    ggemm_wave<TC, TA, TB, TO, BT, AT, 2, 2>(tile, task, segs, A, B, C, Cpart, As, Bs);
+  else if (ni == 2 && nj == 1)
+    ggemm_wave<TC, TA, TB, TO, BT, AT, 2, 1>(tile, task, segs, A, B, C, Cpart, As, Bs);
+  else if (ni == 1 && nj == 2)
+    ggemm_wave<TC, TA, TB, TO, BT, AT, 1, 2>(tile, task, segs, A, B, C, Cpart, As, Bs);
+  else if (ni == 1 && nj == 1)
+    ggemm_wave<TC, TA, TB, TO, BT, AT, 1, 1>(tile, task, segs, A, B, C, Cpart, As, Bs);
+  else
+    ggemm_wave<TC, TA, TB, TO, BT, AT, 0, 0>(tile, task, segs, A, B, C, Cpart, As, Bs);
 }
 
 // MPO mixing (S2): each workgroup handles one row range of one task; every

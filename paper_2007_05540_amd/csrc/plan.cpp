@@ -39,19 +39,6 @@ static Key key5(int a, int b, int c, int d, int e) {
   Key k{}; k[0] = a; k[1] = b; k[2] = c; k[3] = d; k[4] = e; return k;
 }
 
-static void add_tiles(Stage& st, int task) {
-  const GemmTask& t = st.tasks[task];
-  for (int m0 = 0; m0 < std::max(t.M, 1); m0 += kTileM)
-    for (int n0 = 0; n0 < std::max(t.N, 1); n0 += kTileN) st.tiles.push_back({task, m0, n0, 0});
-}
-
-// Longest-first (LPT) order of tiles: descending K of the task, stable.
-static void order_tiles(Stage& st) {
-  std::stable_sort(st.tiles.begin(), st.tiles.end(), [&](const GemmTile& x, const GemmTile& y) {
-    return st.tasks[x.task].ksum > st.tasks[y.task].ksum;
-  });
-}
-
 static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
   ProblemPlan& p = P->probs[pi];
   p.a = leg_from(in.a); p.s1 = leg_from(in.s1); p.s2 = leg_from(in.s2); p.c = leg_from(in.c);
@@ -290,10 +277,8 @@ bsdmrg_plan_s* build_plan(const bsdmrg_problem* probs, int n_probs) {
     P->coef_ptr.push_back(0);
     for (int i = 0; i < n_probs; ++i) plan_problem(P, i, probs[i]);
     split_k(P);
-    for (size_t t = 0; t < P->s1.tasks.size(); ++t) add_tiles(P->s1, (int)t);
-    for (size_t t = 0; t < P->s3.tasks.size(); ++t) add_tiles(P->s3, (int)t);
-    order_tiles(P->s1);
-    order_tiles(P->s3);
+    schedule_tiles(P->s1);
+    schedule_tiles(P->s3);
     // Davidson reduction chunks
     for (int i = 0; i < n_probs; ++i) {
       ProblemPlan& p = P->probs[i];

@@ -32,16 +32,6 @@ static Charge csub(const Charge& a, const Charge& b) { return {a[0] - b[0], a[1]
 static Key k3(int a, int b, int c) { Key k{}; k[0] = a; k[1] = b; k[2] = c; return k; }
 static Key k4(int a, int b, int c, int d) { Key k{}; k[0] = a; k[1] = b; k[2] = c; k[3] = d; return k; }
 
-static void tiles_of(Stage& st) {
-  st.tiles.clear();
-  for (size_t t = 0; t < st.tasks.size(); ++t)
-    for (int m0 = 0; m0 < std::max(st.tasks[t].M, 1); m0 += kTile)
-      for (int n0 = 0; n0 < std::max(st.tasks[t].N, 1); n0 += kTile) st.tiles.push_back({(int)t, m0, n0, 0});
-  std::stable_sort(st.tiles.begin(), st.tiles.end(), [&](const GemmTile& x, const GemmTile& y) {
-    return st.tasks[x.task].ksum > st.tasks[y.task].ksum;
-  });
-}
-
 static void add_items(bsdmrg_op_s* O, int task, int rows, int cols) {
   if (cols > kItem) throw Error{BSDMRG_EINVAL, "env: sector dimensions above 4096 are not supported"};
   int rows_per = std::max(1, kItem / std::max(1, cols));
@@ -171,8 +161,8 @@ bsdmrg_op_s* build_env(const bsdmrg_env_problem& in, int side) {
       O->g2.tasks.push_back(t);
     }
     O->layout2 = side == 0 ? kTN : kNN;
-    tiles_of(O->g1);
-    tiles_of(O->g2);
+    schedule_tiles(O->g1);
+    schedule_tiles(O->g2);
     validate_gemm(O->g1, O->layout1, E.elems(), M.elems(), O->x1_elems, 0, "env stage 1");
     validate_mix(O->mix_tasks, O->mix_terms, O->mix_items, O->x1_elems, O->x2_elems, W.elems(), "env mixing");
     validate_gemm(O->g2, O->layout2, M.elems(), O->x2_elems, O->out_elems, 0, "env stage 3");
@@ -209,7 +199,7 @@ bsdmrg_op_s* build_merge(const Leg& a, const Leg& s1, const Leg& b, const Leg& s
       O->g1.tasks.push_back(t);
     }
     O->layout1 = kNN;
-    tiles_of(O->g1);
+    schedule_tiles(O->g1);
     validate_gemm(O->g1, kNN, A.elems(), B.elems(), O->out_elems, 0, "merge");
   } catch (...) {
     delete O;

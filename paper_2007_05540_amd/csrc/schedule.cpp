@@ -1,0 +1,85 @@
+// Tile schedule of a grouped-GEMM stage for the 8 XCDs of the MI355X.
+//
+// Workgroups of one launch are dispatched to the XCDs round-robin (workgroup
+// i runs on XCD i mod 8) and every XCD has its own L2.  Tiles of one task
+// share their A row panels and B column panels, so a task's tiles are kept on
+// one XCD and run back to back there: the operand panels are fetched into
+// that XCD's L2 once instead of once per XCD.  Tasks are distributed over
+// the XCDs by longest-processing-time (LPT) bin packing on their cost
+// (tiles x K); a task heavier than a quarter of an XCD's share is cut into
+// row-panel chunks first.  Each XCD runs its chunks longest-K first, tiles of
+// a chunk in row-panel order.  The per-XCD lists are interleaved into the
+// launch order; shorter lists are padded with empty tiles (task = -1) that
+// exit at once.
+#include <algorithm>
+#include <numeric>
+
+#include "bsdmrg_internal.h"
+#include "kernels.h"
+
+namespace bsd {
+
+namespace {
+constexpr int kXcd = 8, kTile = 64;
+
+struct Unit {
+  int task, m_begin, m_end;   // row panels [m_begin, m_end) of the task (in tiles)
+  double cost;
+};
+}  // namespace
+
+void schedule_tiles(Stage& st) {
+  st.tiles.clear();
+  std::vector<Unit> units;
+  double total = 0.0;
+  for (size_t t = 0; t < st.tasks.size(); ++t) {
+    const GemmTask& k = st.tasks[t];
+    const int mt = std::max(1, (k.M + kTile - 1) / kTile), nt = std::max(1, (k.N + kTile - 1) / kTile);
+    total += (double)mt * nt * (k.ksum + 16);
+  }
+  const double cap = std::max(1.0, total / (4.0 * kXcd));
+  for (size_t t = 0; t < st.tasks.size(); ++t) {
+    const GemmTask& k = st.tasks[t];
+    const int mt = std::max(1, (k.M + kTile - 1) / kTile), nt = std::max(1, (k.N + kTile - 1) / kTile);
+    const double panel = (double)nt * (k.ksum + 16);
+    const int per = std::max(1, (int)(cap / panel));
+    for (int m = 0; m < mt; m += per) {
+      const int e = std::min(mt, m + per);
+      units.push_back(Unit{(int)t, m, e, panel * (e - m)});
+    }
+  }
+  // LPT bin packing of the units over the XCDs
+  std::vector<int> order(units.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return units[a].cost > units[b].cost; });
+  std::vector<double> load(kXcd, 0.0);
+  std::vector<std::vector<int>> bins(kXcd);
+  for (int u : order) {
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    bins[x].push_back(u);
+    load[x] += units[u].cost;
+  }
+  // per XCD: chunks longest K first, tiles in row-panel order
+  std::vector<std::vector<GemmTile>> lists(kXcd);
+  size_t longest = 0;
+  for (int x = 0; x < kXcd; ++x) {
+    std::stable_sort(bins[x].begin(), bins[x].end(), [&](int a, int b) {
+      return st.tasks[units[a].task].ksum > st.tasks[units[b].task].ksum;
+    });
+    for (int u : bins[x]) {
+      const Unit& un = units[u];
+      const GemmTask& k = st.tasks[un.task];
+      const int nt = std::max(1, (k.N + kTile - 1) / kTile);
+      for (int m = un.m_begin; m < un.m_end; ++m)
+        for (int n = 0; n < nt; ++n) lists[x].push_back(GemmTile{un.task, m * kTile, n * kTile, 0});
+    }
+    longest = std::max(longest, lists[x].size());
+  }
+  for (size_t q = 0; q < longest; ++q)
+    for (int x = 0; x < kXcd; ++x)
+      st.tiles.push_back(q < lists[x].size() ? lists[x][q] : GemmTile{-1, 0, 0, 0});
+  // drop the empty tiles at the very end of the launch
+  while (!st.tiles.empty() && st.tiles.back().task < 0) st.tiles.pop_back();
+}
+
+}  // namespace bsd

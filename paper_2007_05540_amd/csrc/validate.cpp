@@ -41,8 +41,16 @@ void validate_gemm(const Stage& st, int layout, int64_t a_elems, int64_t b_elems
       }
     }
     if (ks != k.ksum) fail(std::string(name) + ": ksum");
+    // the GEMM kernel addresses a block with 32-bit byte offsets (8-byte elements)
+    for (int j = 0; j < k.nseg; ++j) {
+      const GemmSeg& g = st.segs[k.seg0 + j];
+      const int64_t ea = layout == kTN ? (int64_t)(g.K - 1) * g.lda + k.M : (int64_t)(k.M - 1) * g.lda + g.K;
+      const int64_t eb = layout == kNT ? (int64_t)(k.N - 1) * g.ldb + g.K : (int64_t)(g.K - 1) * g.ldb + k.N;
+      if (ea > (int64_t)0x0FFFFFFF || eb > (int64_t)0x0FFFFFFF) fail(std::string(name) + ": block above 2^28 elements");
+    }
   }
   for (const GemmTile& tl : st.tiles) {
+    if (tl.task == -1) continue;   // empty tile of the XCD schedule
     if (tl.task < 0 || tl.task >= (int64_t)st.tasks.size()) fail(std::string(name) + ": tile task");
     const GemmTask& k = st.tasks[tl.task];
     if (tl.m0 < 0 || tl.m0 >= k.M || tl.n0 < 0 || tl.n0 >= k.N) fail(std::string(name) + ": tile origin");
