@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--n-f64", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-bond batch measurement")
     return ap.parse_args()
 
 
@@ -64,6 +65,60 @@ def cpu_baseline(spec, flops, budget_s):
     return {"value": round(flops / dt / 1e9, 3), "unit": "useful GFLOP/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{n} FP64 block-loop H_eff products of the m=1024 k=14 bond ({dt:.3f} s each)"}
+
+
+def batch_bench(args):
+    """64 independent bonds (widths 4/6/8 -> k = 10/14/18, m drawn from
+    256..2048) planned as one batch: every stage of a product runs as one
+    grouped launch over all 64 problems, and the fixed-step Davidson solve is
+    captured once as a hipGraph.  Returns ms per batched Davidson step and
+    useful GFLOP/s for the FP64 and the mixed schedule."""
+    import torch
+    import synth
+    from paper_2007_05540_amd import lib, problems
+
+    t0 = time.perf_counter()
+    specs = synth.c3_batch()
+    pairs = [problems.bond_problem(s) for s in specs]
+    plan = lib.Plan([p for p, _ in pairs])
+    ops = problems.concat(plan, [o for _, o in pairs])
+    del pairs
+    info = plan.info()
+    flops = info["flops_s1"] + info["flops_s3"]
+    dev = {k: torch.from_numpy(v).to("cuda") for k, v in ops.items()}
+    del ops
+    setup_s = time.perf_counter() - t0
+    stream = torch.cuda.Stream()
+    out = {"problems": len(specs), "useful_gflop_per_batched_product": round(flops / 1e9, 3),
+           "setup_s": round(setup_s, 1)}
+    for path in ("f64", "mixed"):
+        if path == "mixed":
+            o = lib.eig_opts(max_iter=args.n_f32, precision=lib.F32_REFINE, refine_max_iter=args.n_f64,
+                             fixed_iters=1, use_graph=1)
+        else:
+            o = lib.eig_opts(max_iter=args.n_f32 + args.n_f64, fixed_iters=1, use_graph=1)
+        ws = torch.empty(lib.eig_workspace(plan, o), dtype=torch.uint8, device="cuda")
+        psi = torch.empty_like(dev["psi"])
+        with torch.cuda.stream(stream):
+            for _ in range(2):
+                psi.copy_(dev["psi"])
+                lib.eigensolve(plan, dev["L"], dev["W1"], dev["W2"], dev["R"], psi, o, ws, stream=stream)
+            torch.cuda.synchronize()
+            reps = max(2, args.steps // 4)
+            t1 = time.perf_counter()
+            for _ in range(reps):
+                psi.copy_(dev["psi"])
+                e, st = lib.eigensolve(plan, dev["L"], dev["W1"], dev["W2"], dev["R"], psi, o, ws,
+                                       stream=stream)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t1) / reps
+        products = args.n_f32 + args.n_f64
+        out[path] = {"ms_per_davidson_step": round(dt * 1e3, 3),
+                     "useful_gflops": round(products * flops / dt / 1e9, 1)}
+        del ws, psi
+    out["speedup_mixed_vs_f64"] = round(out["f64"]["ms_per_davidson_step"] / out["mixed"]["ms_per_davidson_step"], 3)
+    plan.destroy()
+    return out
 
 
 def main():
@@ -150,6 +205,11 @@ def main():
         "stage_ms": {k: {s: round(v, 5) for s, v in d.items()} for k, d in stage.items()},
         "roofline": roofline,
     }
+    if not args.no_batch:
+        del dev, out, wsa
+        plan.destroy()
+        torch.cuda.empty_cache()
+        line["batch_64_bonds"] = batch_bench(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, flops, args.cpu_seconds)
     print(json.dumps(line))

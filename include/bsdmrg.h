@@ -113,7 +113,9 @@ typedef struct {
   int64_t L_elems, R_elems, W1_elems, W2_elems;
   int64_t t1_elems, t2_elems;           /* intermediates of one product    */
   int64_t apply_workspace_bytes;        /* workspace of bsdmrg_heff_apply  */
-  int64_t backward_workspace_bytes;     /* workspace of bsdmrg_heff_backward */
+  int64_t backward_workspace_bytes;     /* workspace of bsdmrg_heff_backward once its
+                                           tables exist (0 before; see
+                                           bsdmrg_heff_backward_workspace) */
   double flops_s1, flops_s2, flops_s3;  /* per product, all problems       */
   int64_t n_s1_tasks, n_s3_tasks, n_s1_tiles, n_s3_tiles;
   int64_t n_mix_terms, n_coefs;
@@ -202,8 +204,13 @@ bsdmrg_status bsdmrg_eigensolve(bsdmrg_plan_t plan, const double* L, const doubl
  * pattern whose gradient is wanted).  The first call builds and uploads the
  * adjoint tables of the plan.  FP64; every sum runs in a fixed order.
  * Device pointers except g_E; outputs may be NULL and must not alias an
- * input.  workspace: backward_workspace_bytes.  Synchronises the stream.
+ * input.  workspace: bsdmrg_heff_backward_workspace.  Synchronises the stream.
  * Errors: EINVAL, EHIP. */
+/* Builds (on the host, once per plan) and checks the adjoint tables of the
+ * plan and returns the workspace bytes of bsdmrg_heff_backward and
+ * bsdmrg_heff_energy.  Works on host-only plans.  Errors: EINVAL. */
+bsdmrg_status bsdmrg_heff_backward_workspace(bsdmrg_plan_t plan, int64_t* bytes);
+
 bsdmrg_status bsdmrg_heff_backward(bsdmrg_plan_t plan, const double* L, const double* W1,
                                    const double* W2, const double* R, const double* psi,
                                    const double* g_E, double* d_psi, double* d_L, double* d_W1,
@@ -212,7 +219,7 @@ bsdmrg_status bsdmrg_heff_backward(bsdmrg_plan_t plan, const double* L, const do
 
 /* energy[p] = psi_p^T H_eff,p psi_p (host array of n_probs; FP64 product,
  * per-problem reductions in a fixed order).  workspace:
- * backward_workspace_bytes.  Synchronises the stream.  Errors: EINVAL, EHIP. */
+ * bsdmrg_heff_backward_workspace.  Synchronises the stream.  Errors: EINVAL, EHIP. */
 bsdmrg_status bsdmrg_heff_energy(bsdmrg_plan_t plan, const double* L, const double* W1,
                                  const double* W2, const double* R, const double* psi,
                                  double* energy, void* workspace, int64_t workspace_bytes,
@@ -324,10 +331,11 @@ bsdmrg_status bsdmrg_merge(bsdmrg_op_t op, const double* A, const double* B, dou
 
 /* Measurement helper: runs each stage of one product `reps` times on
  * `stream`, bracketed by HIP events recorded on that stream, and writes the
- * average duration in milliseconds per launch to ms[4] = {WW coefficients,
- * S1 grouped GEMM, S2 MPO mixing, S3 grouped GEMM}.  Same arguments and
- * results as bsdmrg_heff_apply (out holds the product afterwards).
- * Synchronises the stream.  Errors: EINVAL, EHIP. */
+ * average duration in milliseconds per launch to ms[5] = {WW coefficients,
+ * S1 grouped GEMM, S2 MPO mixing, S3 grouped GEMM (split-K pieces), S3
+ * fixed-order sum of the split-K pieces}.  Same arguments and results as
+ * bsdmrg_heff_apply (out holds the product afterwards).  Synchronises the
+ * stream.  Errors: EINVAL, EHIP. */
 bsdmrg_status bsdmrg_stage_timing(bsdmrg_plan_t plan, int32_t precision, const double* L,
                                   const double* W1, const double* W2, const double* R,
                                   const double* psi, double* out, void* workspace,

@@ -23,7 +23,7 @@ class HeffEnergy(torch.autograd.Function):
     def forward(ctx, plan, L, W1, W2, R, psi):
         for x, n in ((L, "L"), (W1, "W1"), (W2, "W2"), (R, "R"), (psi, "psi")):
             _check(x, n)
-        ws = torch.empty(max(1, plan.info()["backward_workspace_bytes"]), dtype=torch.uint8, device=psi.device)
+        ws = torch.empty(max(1, lib.heff_backward_workspace(plan)), dtype=torch.uint8, device=psi.device)
         e = lib.heff_energy(plan, L, W1, W2, R, psi, ws)
         ctx.plan = plan
         ctx.save_for_backward(L, W1, W2, R, psi)
@@ -36,8 +36,7 @@ class HeffEnergy(torch.autograd.Function):
         outs = [torch.empty_like(x) if n else None for x, n in zip((L, W1, W2, R, psi), need)]
         if not any(n for n in need):
             return (None,) * 6
-        ws = torch.empty(max(1, ctx.plan.info()["backward_workspace_bytes"]), dtype=torch.uint8,
-                         device=psi.device)
+        ws = torch.empty(max(1, lib.heff_backward_workspace(ctx.plan)), dtype=torch.uint8, device=psi.device)
         g = g_e.detach().to("cpu", torch.float64).numpy()
         lib.heff_backward(ctx.plan, L, W1, W2, R, psi, g, outs[4], outs[0], outs[1], outs[2], outs[3], ws)
         return (None, *outs)

@@ -220,6 +220,7 @@ static EigWS carve_eig(const bsdmrg_plan_s* P, const bsdmrg_eig_opts* o, Carve& 
   d.part_n1 = c.take<double>(nch);
   d.red = c.take<double>((size_t)np * 64);
   d.M = c.take<double>((size_t)np * B * B);
+  d.evec = c.take<double>((size_t)np * B * B);
   d.svec = c.take<double>((size_t)np * B);
   d.lam = c.take<double>(np);
   d.scale = c.take<double>(np);
@@ -307,7 +308,9 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
     for (int i = 0; i < f.maxit; ++i, ++global_it) {
       HIPCHK(dav_dots(P, i + 1, d.VA, n, d.V + (int64_t)i * n, d.part_a, s));
       HIPCHK(dav_gram_eig(P, d, i, s));
-      HIPCHK(dav_ritz(P, d, i, false, s));
+      // q and (unless this is the last step) the first Gram-Schmidt dots v_j^T q
+      const bool last = i == f.maxit - 1;
+      HIPCHK(dav_ritz(P, d, i, false, last ? nullptr : d.part_a, s));
       for (int p = 0; p < np; ++p) (f.prec == BSDMRG_F64 ? it64 : it32)[p] = i + 1;
       if (!o->fixed_iters) {
         HIPCHK(hipMemcpyAsync(hpart.data(), d.part_n0, hpart.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -322,15 +325,14 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
           all = all && conv[p];
         }
         if (all) {
-          HIPCHK(dav_ritz(P, d, i, true, s));
+          HIPCHK(dav_ritz(P, d, i, true, nullptr, s));
           break;
         }
       }
-      if (i == f.maxit - 1) {
-        HIPCHK(dav_ritz(P, d, i, true, s));
+      if (last) {
+        HIPCHK(dav_ritz(P, d, i, true, nullptr, s));
         break;
       }
-      HIPCHK(dav_dots(P, i + 1, d.V, n, d.q, d.part_a, s));
       HIPCHK(dav_update(P, d, i + 1, d.part_a, d.part_b, 1, s));
       HIPCHK(dav_update(P, d, i + 1, d.part_b, d.part_n1, 2, s));
       HIPCHK(dav_finalize(P, d, i, o->seed, o->restart_rtol, P->d_blk_off, P->d_blk_ptr, s));
@@ -396,7 +398,7 @@ bsdmrg_status bsdmrg_plan_query(bsdmrg_plan_t P, bsdmrg_plan_info* info) {
     info->t1_elems = P->t1_elems;
     info->t2_elems = P->t2_elems;
     info->apply_workspace_bytes = (int64_t)apply_bytes(P);
-    info->backward_workspace_bytes = heff_backward_bytes(P);
+    info->backward_workspace_bytes = P->bwd ? heff_backward_bytes(P) : 0;
     info->flops_s1 = P->s1.flops;
     info->flops_s2 = P->flops_s2;
     info->flops_s3 = P->s3.flops;
@@ -463,6 +465,13 @@ bsdmrg_status bsdmrg_heff_apply(bsdmrg_plan_t P, int32_t precision, const double
     ApplyWS w = carve_apply(P, c);
     prepare(P, precision, L, W1, W2, R, w, stream);
     matvec(P, precision, L, R, w, psi, out, stream);
+  });
+}
+
+bsdmrg_status bsdmrg_heff_backward_workspace(bsdmrg_plan_t P, int64_t* bytes) {
+  return guarded([&] {
+    if (!P || !bytes) throw Error{BSDMRG_EINVAL, "heff_backward_workspace: NULL argument"};
+    *bytes = heff_backward_bytes(P);
   });
 }
 
@@ -594,18 +603,19 @@ bsdmrg_status bsdmrg_stage_timing(bsdmrg_plan_t P, int32_t precision, const doub
     prepare(P, precision, L, W1, W2, R, w, s);
     float* T1f = (float*)w.T1;
     float* T2f = (float*)w.T2;
-    for (int stage = 0; stage < 4; ++stage) {
+    for (int stage = 0; stage < 5; ++stage) {
       HIPCHK(hipEventRecord(ev[0], s));
       for (int r = 0; r < reps; ++r) {
         if (stage == 0) HIPCHK(launch_coef(P, W1, W2, w.coef, s));
+        if (stage == 4) HIPCHK(launch_s3_reduce(P, w.part, out, s));
         if (precision == BSDMRG_F64) {
           if (stage == 1) HIPCHK(launch_s1_f64(P, L, psi, w.T1, s));
           if (stage == 2) HIPCHK(launch_mix_f64(P, w.coef, w.T1, w.T2, s));
-          if (stage == 3) HIPCHK(launch_s3_f64(P, w.T2, R, out, w.part, s));
+          if (stage == 3) HIPCHK(launch_s3_gemm_f64(P, w.T2, R, out, w.part, s));
         } else {
           if (stage == 1) HIPCHK(launch_s1_f32(P, w.L32, psi, T1f, s));
           if (stage == 2) HIPCHK(launch_mix_f32(P, w.coef, T1f, T2f, s));
-          if (stage == 3) HIPCHK(launch_s3_f32(P, T2f, w.R32, out, w.part, s));
+          if (stage == 3) HIPCHK(launch_s3_gemm_f32(P, T2f, w.R32, out, w.part, s));
         }
       }
       HIPCHK(hipEventRecord(ev[1], s));

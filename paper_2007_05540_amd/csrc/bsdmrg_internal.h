@@ -13,7 +13,7 @@ namespace bsd {
 
 constexpr int kAlign = 32;          // block alignment in elements (256 B in FP64)
 constexpr int kMaxOrder = 8;
-constexpr int kChunk = 2048;        // Davidson reduction chunk (elements)
+constexpr int kChunk = 512;         // Davidson reduction chunk (elements)
 
 using Charge = std::array<int32_t, 2>;
 using Key = std::array<int32_t, kMaxOrder>;

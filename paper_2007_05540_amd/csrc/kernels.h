@@ -16,6 +16,12 @@ hipError_t launch_s1_f32(const bsdmrg_plan_s* P, const float* L, const double* p
                          hipStream_t s);
 hipError_t launch_s3_f32(const bsdmrg_plan_s* P, const float* T2, const float* R, double* out,
                          double* part, hipStream_t s);
+// S3 as its two launches: split-K GEMM pieces, then their fixed-order sum
+hipError_t launch_s3_gemm_f64(const bsdmrg_plan_s* P, const double* T2, const double* R, double* out,
+                              double* part, hipStream_t s);
+hipError_t launch_s3_gemm_f32(const bsdmrg_plan_s* P, const float* T2, const float* R, double* out,
+                              double* part, hipStream_t s);
+hipError_t launch_s3_reduce(const bsdmrg_plan_s* P, const double* part, double* out, hipStream_t s);
 hipError_t launch_mix_f64(const bsdmrg_plan_s* P, const double* coef, const double* T1, double* T2,
                           hipStream_t s);
 hipError_t launch_mix_f32(const bsdmrg_plan_s* P, const double* coef, const float* T1, float* T2,
@@ -49,6 +55,7 @@ struct DavBufs {
   double* part_n1;  // nchunk: ||q||^2 after
   double* red;      // n_probs * 64 per-problem sums of partials
   double* M;        // n_probs * B * B projected matrices
+  double* evec;     // n_probs * B * B eigenvectors of the previous step (warm start)
   double* svec;     // n_probs * B Ritz vectors of M
   double* lam;      // n_probs
   double* scale;    // n_probs
@@ -65,7 +72,9 @@ hipError_t dav_psum(const bsdmrg_plan_s* P, int J, const double* part, double* r
 hipError_t dav_normalize(const bsdmrg_plan_s* P, const double* part, double* red, const double* x, double* y,
                          hipStream_t s);
 hipError_t dav_gram_eig(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStream_t s);
-hipError_t dav_ritz(const bsdmrg_plan_s* P, const DavBufs& b, int i, bool want_x, hipStream_t s);
+// q (and x when want_x); with part_d also the partial dots v_j^T q, j <= i
+hipError_t dav_ritz(const bsdmrg_plan_s* P, const DavBufs& b, int i, bool want_x, double* part_d,
+                    hipStream_t s);
 hipError_t dav_update(const bsdmrg_plan_s* P, const DavBufs& b, int J, const double* part_in,
                       double* part_out, int mode, hipStream_t s);
 hipError_t dav_finalize(const bsdmrg_plan_s* P, const DavBufs& b, int i, uint64_t seed, double rtol,

@@ -11,6 +11,7 @@ namespace bsd {
 
 constexpr int DT = 256;   // threads per block of the vector kernels
 constexpr int PER = kChunk / DT;
+constexpr int kMaxBasisD = 64;   // largest basis (J) of the multi-dot kernels
 
 // Deterministic block sum (wave shuffles, then the four wave sums in order).
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -27,6 +28,14 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   }
   __syncthreads();
   return sh[8];
+}
+
+// Per-block sums of J values per thread (vals[j] for the calling thread):
+// wave butterflies, then the four wave sums added in order by thread j; one
+// barrier for all J.  Writes part[j * nct + blockIdx.x].
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
 
 // out[j] = sum over the problem's chunks of part[j * nct + chunk] for j < J
@@ -56,12 +65,14 @@ __global__ __launch_bounds__(DT) void psum_kernel(const DavProb* __restrict__ pr
   if (threadIdx.x == 0) red[(int64_t)p * ldr + j] = v;
 }
 
-// part[j * nct + ch] = sum_{e in chunk ch} X_j[e] y[e], j < J
+// part[j * nct + ch] = sum_{e in chunk ch} X_j[e] y[e], j < J (wave sums
+// per j, one barrier, the four wave sums added in order).
 __global__ __launch_bounds__(DT) void dots_kernel(const Chunk* __restrict__ chunks, int nct, int J,
                                                   const double* __restrict__ X, int64_t xstride,
                                                   const double* __restrict__ y, double* __restrict__ part) {
-  __shared__ double sh[16];
+  __shared__ double ws[kMaxBasisD][4];
   const Chunk ch = chunks[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double yv[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
@@ -76,8 +87,13 @@ __global__ __launch_bounds__(DT) void dots_kernel(const Chunk* __restrict__ chun
       const int e = threadIdx.x + u * DT;
       if (e < ch.len) s += Xj[e] * yv[u];
     }
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) part[(int64_t)j * nct + blockIdx.x] = s;
+    s = wave_sum(s);
+    if (lane == 0) ws[j][wave] = s;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < J) {
+    const int j = threadIdx.x;
+    part[(int64_t)j * nct + blockIdx.x] = ((ws[j][0] + ws[j][1]) + ws[j][2]) + ws[j][3];
   }
 }
 
@@ -96,13 +112,18 @@ __global__ __launch_bounds__(DT) void normalize_kernel(const Chunk* __restrict__
 // (round-robin ordered) Jacobi rotations: in every step the indices form
 // ne/2 disjoint pairs, all rotations of a step are computed at once and
 // applied in place as 2 x 2 block updates A <- J^T A J, V <- V J.  An odd
-// size gets a zero dummy index that is never selected.
+// size gets a zero dummy index that is never selected.  Warm start: the
+// matrix grows by one row and column per step, so Jacobi starts from
+// W^T M W with W = diag(previous eigenvectors, 1) (all but the new row and
+// column are then already diagonal) and V = W; the eigenvectors are kept in
+// evec for the next step.
 constexpr int kMaxBasis = 64;
 __global__ __launch_bounds__(DT) void gram_eig_kernel(int ldr, int i, int B, const double* __restrict__ red,
-                                                      double* __restrict__ M, double* __restrict__ svec,
-                                                      double* __restrict__ lam) {
+                                                      double* __restrict__ M, double* __restrict__ evec,
+                                                      double* __restrict__ svec, double* __restrict__ lam) {
   __shared__ double A[kMaxBasis][kMaxBasis + 1];
   __shared__ double V[kMaxBasis][kMaxBasis + 1];
+  __shared__ double T[kMaxBasis][kMaxBasis + 1];
   __shared__ double pc[kMaxBasis / 2], ps[kMaxBasis / 2];
   __shared__ int pp[kMaxBasis / 2], pq[kMaxBasis / 2];
   __shared__ double sh[16];
@@ -110,6 +131,7 @@ __global__ __launch_bounds__(DT) void gram_eig_kernel(int ldr, int i, int B, con
   const int ne = n + (n & 1);
   const int half = ne / 2;
   double* Mp = M + (int64_t)p * B * B;
+  double* Ep = evec + (int64_t)p * B * B;
   if (tid <= i) {
     const double v = red[(int64_t)p * ldr + tid];
     Mp[i * B + tid] = v;
@@ -120,9 +142,40 @@ __global__ __launch_bounds__(DT) void gram_eig_kernel(int ldr, int i, int B, con
   for (int e = tid; e < ne * ne; e += DT) {
     const int r = e / ne, c = e % ne;
     A[r][c] = (r < n && c < n) ? Mp[r * B + c] : 0.0;
-    V[r][c] = (r == c) ? 1.0 : 0.0;
+    // W = diag(previous eigenvectors (i x i), 1), identity on the dummy index
+    V[r][c] = (r < i && c < i) ? Ep[r * B + c] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
+  if (i > 0) {
+    for (int e = tid; e < n * n; e += DT) {   // T = A W
+      const int r = e / n, c = e % n;
+      double t = 0.0;
+      for (int k = 0; k < n; ++k) t += A[r][k] * V[k][c];
+      T[r][c] = t;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += DT) {   // A = W^T T
+      const int r = e / n, c = e % n;
+      double t = 0.0;
+      for (int k = 0; k < n; ++k) t += V[k][r] * T[k][c];
+      A[r][c] = t;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += DT) {   // exact symmetry of the start matrix
+      const int r = e / n, c = e % n;
+      if (r < c) {
+        const double m = 0.5 * (A[r][c] + A[c][r]);
+        T[r][c] = m;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += DT) {
+      const int r = e / n, c = e % n;
+      if (r < c) A[r][c] = T[r][c];
+      if (r > c) A[r][c] = T[c][r];
+    }
+    __syncthreads();
+  }
   double f = 0.0;
   for (int e = tid; e < n * n; e += DT) f += A[e / n][e % n] * A[e / n][e % n];
   const double fro2 = block_sum(f, sh);
@@ -187,38 +240,65 @@ __global__ __launch_bounds__(DT) void gram_eig_kernel(int ldr, int i, int B, con
     if (A[r][r] < A[idx][idx]) idx = r;
   if (tid < n) svec[(int64_t)p * B + tid] = V[tid][idx];
   if (tid == 0) lam[p] = A[idx][idx];
+  for (int e = tid; e < n * n; e += DT) Ep[(e / n) * B + e % n] = V[e / n][e % n];
 }
 
 // q = sum s_j v^A_j - lambda sum s_j v_j with partial ||q||^2; when x is
-// non-null the Ritz vector x = sum s_j v_j is stored too.
-__global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chunks, int J, int B,
+// non-null the Ritz vector x = sum s_j v_j is stored too, and when part_d is
+// non-null the partial dots v_j^T q (the first Gram-Schmidt pass) as well.
+__global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chunks, int nct, int J, int B,
                                                   const double* __restrict__ V, const double* __restrict__ VA,
                                                   int64_t stride, const double* __restrict__ svec,
                                                   const double* __restrict__ lam, double* __restrict__ x,
-                                                  double* __restrict__ q, double* __restrict__ part) {
-  __shared__ double sh[16];
+                                                  double* __restrict__ q, double* __restrict__ part,
+                                                  double* __restrict__ part_d) {
+  __shared__ double ws[kMaxBasisD + 1][4];
   __shared__ double sv[kMaxBasis];
   const Chunk ch = chunks[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if ((int)threadIdx.x < J) sv[threadIdx.x] = svec[(int64_t)ch.prob * B + threadIdx.x];
   __syncthreads();
   const double l = lam[ch.prob];
+  double qv[PER];
   double nrm = 0.0;
+#pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int e = threadIdx.x + u * DT;
-    if (e >= ch.len) break;
+    qv[u] = 0.0;
+    if (e >= ch.len) continue;
     const int64_t g = ch.start + e;
     double xv = 0.0, av = 0.0;
     for (int j = 0; j < J; ++j) {
       xv += sv[j] * V[j * stride + g];
       av += sv[j] * VA[j * stride + g];
     }
-    const double qv = av - l * xv;
+    const double v = av - l * xv;
     if (x) x[g] = xv;
-    q[g] = qv;
-    nrm += qv * qv;
+    q[g] = v;
+    qv[u] = v;
+    nrm += v * v;
   }
-  nrm = block_sum(nrm, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = nrm;
+  nrm = wave_sum(nrm);
+  if (lane == 0) ws[kMaxBasisD][wave] = nrm;
+  if (part_d) {
+    for (int j = 0; j < J; ++j) {
+      double d = 0.0;
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = threadIdx.x + u * DT;
+        if (e < ch.len) d += V[j * stride + ch.start + e] * qv[u];
+      }
+      d = wave_sum(d);
+      if (lane == 0) ws[j][wave] = d;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    part[blockIdx.x] = ((ws[kMaxBasisD][0] + ws[kMaxBasisD][1]) + ws[kMaxBasisD][2]) + ws[kMaxBasisD][3];
+  if (part_d && (int)threadIdx.x < J) {
+    const int j = threadIdx.x;
+    part_d[(int64_t)j * nct + blockIdx.x] = ((ws[j][0] + ws[j][1]) + ws[j][2]) + ws[j][3];
+  }
 }
 
 // q -= sum_j c_j v_j with c_j = red[p * ldr + j]; mode 1 then writes the
@@ -230,6 +310,7 @@ __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ ch
                                                     int mode) {
   __shared__ double sh[16];
   __shared__ double cj[kMaxBasis];
+  __shared__ double wsum[kMaxBasisD][4];
   const Chunk ch = chunks[blockIdx.x];
   if ((int)threadIdx.x < J) cj[threadIdx.x] = red[(int64_t)ch.prob * ldr + threadIdx.x];
   __syncthreads();
@@ -248,6 +329,7 @@ __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ ch
     }
   }
   if (mode == 1) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int j = 0; j < J; ++j) {
       double s = 0.0;
 #pragma unroll
@@ -255,8 +337,13 @@ __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ ch
         const int e = threadIdx.x + u * DT;
         if (e < ch.len) s += V[j * stride + ch.start + e] * qv[u];
       }
-      s = block_sum(s, sh);
-      if (threadIdx.x == 0) part_out[(int64_t)j * nct + blockIdx.x] = s;
+      s = wave_sum(s);
+      if (lane == 0) wsum[j][wave] = s;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < J) {
+      const int j = threadIdx.x;
+      part_out[(int64_t)j * nct + blockIdx.x] = ((wsum[j][0] + wsum[j][1]) + wsum[j][2]) + wsum[j][3];
     }
   } else {
     double s = 0.0;
@@ -395,13 +482,14 @@ hipError_t dav_gram_eig(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStre
   hipError_t e = dav_psum(P, i + 1, b.part_a, b.red, kMaxBasis, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(gram_eig_kernel, dim3((unsigned)P->probs.size()), dim3(DT), 0, s, kMaxBasis, i, b.B,
-                     b.red, b.M, b.svec, b.lam);
+                     b.red, b.M, b.evec, b.svec, b.lam);
   return hipGetLastError();
 }
 
-hipError_t dav_ritz(const bsdmrg_plan_s* P, const DavBufs& b, int i, bool want_x, hipStream_t s) {
-  hipLaunchKernelGGL(ritz_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, i + 1, b.B, b.V, b.VA, b.n,
-                     b.svec, b.lam, want_x ? b.x : nullptr, b.q, b.part_n0);
+hipError_t dav_ritz(const bsdmrg_plan_s* P, const DavBufs& b, int i, bool want_x, double* part_d,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(ritz_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), i + 1, b.B,
+                     b.V, b.VA, b.n, b.svec, b.lam, want_x ? b.x : nullptr, b.q, b.part_n0, part_d);
   return hipGetLastError();
 }
 

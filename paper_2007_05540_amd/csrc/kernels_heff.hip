@@ -372,7 +372,7 @@ hipError_t launch_mix_tables(const MixItem* items, size_t n_items, const MixTask
   return hipGetLastError();
 }
 
-static hipError_t launch_reduce(const bsdmrg_plan_s* P, const double* part, double* out, hipStream_t s) {
+hipError_t launch_s3_reduce(const bsdmrg_plan_s* P, const double* part, double* out, hipStream_t s) {
   if (P->red_items.empty()) return hipSuccess;
   hipLaunchKernelGGL((mix_kernel<double, double>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
                      P->d_red_items, P->d_red_tasks, P->d_red_terms, (const double*)nullptr, part, out);
@@ -385,9 +385,13 @@ hipError_t launch_s1_f64(const bsdmrg_plan_s* P, const double* L, const double* 
 }
 hipError_t launch_s3_f64(const bsdmrg_plan_s* P, const double* T2, const double* R, double* out,
                          double* part, hipStream_t s) {
-  hipError_t e = launch_gemm<double, double, double, double, true>(P->s3, T2, R, out, part, s);
+  hipError_t e = launch_s3_gemm_f64(P, T2, R, out, part, s);
   if (e != hipSuccess) return e;
-  return launch_reduce(P, part, out, s);
+  return launch_s3_reduce(P, part, out, s);
+}
+hipError_t launch_s3_gemm_f64(const bsdmrg_plan_s* P, const double* T2, const double* R, double* out,
+                              double* part, hipStream_t s) {
+  return launch_gemm<double, double, double, double, true>(P->s3, T2, R, out, part, s);
 }
 hipError_t launch_s1_f32(const bsdmrg_plan_s* P, const float* L, const double* psi, float* T1,
                          hipStream_t s) {
@@ -395,9 +399,13 @@ hipError_t launch_s1_f32(const bsdmrg_plan_s* P, const float* L, const double* p
 }
 hipError_t launch_s3_f32(const bsdmrg_plan_s* P, const float* T2, const float* R, double* out,
                          double* part, hipStream_t s) {
-  hipError_t e = launch_gemm<float, float, float, double, true>(P->s3, T2, R, out, part, s);
+  hipError_t e = launch_s3_gemm_f32(P, T2, R, out, part, s);
   if (e != hipSuccess) return e;
-  return launch_reduce(P, part, out, s);
+  return launch_s3_reduce(P, part, out, s);
+}
+hipError_t launch_s3_gemm_f32(const bsdmrg_plan_s* P, const float* T2, const float* R, double* out,
+                              double* part, hipStream_t s) {
+  return launch_gemm<float, float, float, double, true>(P->s3, T2, R, out, part, s);
 }
 
 hipError_t launch_mix_f64(const bsdmrg_plan_s* P, const double* coef, const double* T1, double* T2,

@@ -74,7 +74,7 @@ _lib = None
 
 EXPORTS = ["bsdmrg_layout", "bsdmrg_plan", "bsdmrg_plan_query", "bsdmrg_plan_offsets", "bsdmrg_plan_tasks",
            "bsdmrg_plan_destroy", "bsdmrg_heff_apply", "bsdmrg_eig_workspace", "bsdmrg_eigensolve",
-           "bsdmrg_heff_backward", "bsdmrg_heff_energy", "bsdmrg_stage_timing", "bsdmrg_truncate_workspace", "bsdmrg_truncate",
+           "bsdmrg_heff_backward", "bsdmrg_heff_backward_workspace", "bsdmrg_heff_energy", "bsdmrg_stage_timing", "bsdmrg_truncate_workspace", "bsdmrg_truncate",
            "bsdmrg_env_plan", "bsdmrg_merge_plan", "bsdmrg_op_query", "bsdmrg_op_destroy", "bsdmrg_env_update",
            "bsdmrg_env_backward_workspace", "bsdmrg_env_backward",
            "bsdmrg_merge", "bsdmrg_last_error"]
@@ -105,6 +105,7 @@ def load():
                                       ctypes.POINTER(dp), ctypes.POINTER(EigStats), vp, i64, vp]
     lib.bsdmrg_heff_backward.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(dp), vp, vp, vp, vp, vp, vp,
                                          i64, vp]
+    lib.bsdmrg_heff_backward_workspace.argtypes = [vp, ctypes.POINTER(i64)]
     lib.bsdmrg_heff_energy.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(dp), vp, i64, vp]
     lib.bsdmrg_stage_timing.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, i64, i32,
                                         ctypes.POINTER(ctypes.c_float), vp]
@@ -258,6 +259,13 @@ def eigensolve(plan, L, W1, W2, R, psi, opts, workspace, stream=None):
     return list(e), stats
 
 
+def heff_backward_workspace(plan):
+    """Workspace bytes of heff_backward / heff_energy (builds the adjoint tables once)."""
+    n = ctypes.c_int64(0)
+    check(load().bsdmrg_heff_backward_workspace(plan.handle, ctypes.byref(n)))
+    return n.value
+
+
 def heff_backward(plan, L, W1, W2, R, psi, g_E, d_psi, d_L, d_W1, d_W2, d_R, workspace, stream=None):
     """g_E: one cotangent per problem (a scalar is broadcast).  Outputs may be None."""
     g = np.broadcast_to(np.asarray(g_E, dtype=np.float64), (plan.n_probs,))
@@ -277,12 +285,13 @@ def heff_energy(plan, L, W1, W2, R, psi, workspace, stream=None):
 
 
 def stage_timing(plan, precision, L, W1, W2, R, psi, out, workspace, reps=20, stream=None):
-    """Average ms per launch of {coef, S1, S2, S3}, timed with HIP events on the stream."""
-    ms = (ctypes.c_float * 4)()
+    """Average ms per launch of {coef, S1, S2, S3 GEMM, S3 split-K sum}, timed
+    with HIP events on the stream."""
+    ms = (ctypes.c_float * 5)()
     check(load().bsdmrg_stage_timing(plan.handle, precision, _ptr(L), _ptr(W1), _ptr(W2), _ptr(R), _ptr(psi),
                                      _ptr(out), _ptr(workspace), workspace.numel() * workspace.element_size(),
                                      reps, ms, _stream(stream)))
-    return dict(zip(("coef", "s1", "s2", "s3"), list(ms)))
+    return dict(zip(("coef", "s1", "s2", "s3", "s3_sum"), list(ms)))
 
 
 # ------------------------------------------------------------ sweep ops ----

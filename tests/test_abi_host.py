@@ -111,5 +111,8 @@ def test_adjoint_tables_build_and_pass_host_checks(lib, m, k, seed):
     prob, _ = problems.bond_problem(spec)
     plan = lib.Plan([prob, prob], host_only=True)
     info = plan.info()
-    assert info["backward_workspace_bytes"] > info["apply_workspace_bytes"] + 8 * (info["t1_elems"] + info["t2_elems"])
-    assert plan.info()["backward_workspace_bytes"] == info["backward_workspace_bytes"]
+    assert info["backward_workspace_bytes"] == 0          # tables not built yet
+    need = lib.heff_backward_workspace(plan)
+    assert need > info["apply_workspace_bytes"] + 8 * (info["t1_elems"] + info["t2_elems"])
+    assert plan.info()["backward_workspace_bytes"] == need
+    assert lib.heff_backward_workspace(plan) == need

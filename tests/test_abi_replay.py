@@ -64,6 +64,7 @@ def replay(lib, mpo, n, target, m0, m_max, sweeps, dav):
             prob = {"a": a, "s1": s1, "s2": s2, "c": c, "wl": wl, "wm": wl, "wr": wl, "w1": Wh[j], "w2": Wh[j + 1]}
             p = lib.Plan([prob], host_only=True)
             assert p.info()["psi_elems"] == theta.pack().size
+            assert lib.heff_backward_workspace(p) > 0      # adjoint tables built and checked
             p.destroy()
             lam, x, st = solve_bond(L[j], Ws[j], Ws[j + 1], R[j + 2], theta, dav, "dense", seed=count)
             A, B, _, _, _ = truncate(x, d, cutoff=1e-10, m_max=m_max)

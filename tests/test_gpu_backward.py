@@ -49,7 +49,7 @@ def nz_mask(lib, legs, packed):
 
 
 def run_backward(lib, plan, d, g, want=("psi", "L", "W1", "W2", "R")):
-    ws = torch.empty(plan.info()["backward_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    ws = torch.empty(lib.heff_backward_workspace(plan), dtype=torch.uint8, device="cuda")
     out = {k: (torch.full_like(d[k], float("nan")) if k in want else None) for k in ("psi", "L", "W1", "W2", "R")}
     lib.heff_backward(plan, d["L"], d["W1"], d["W2"], d["R"], d["psi"], g, out["psi"], out["L"], out["W1"],
                       out["W2"], out["R"], ws)
@@ -84,7 +84,7 @@ def test_backward_matches_oracle(mods, m, k, seed):
     got = run_backward(lib, plan, d, 1.0)
     ref, e_ref = oracle_grads(spec)
     compare(lib, spec, got, ref, ops=ops)
-    ws = torch.empty(plan.info()["backward_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    ws = torch.empty(lib.heff_backward_workspace(plan), dtype=torch.uint8, device="cuda")
     e = lib.heff_energy(plan, d["L"], d["W1"], d["W2"], d["R"], d["psi"], ws)
     assert abs(e[0] - e_ref) <= 1e-12 * abs(e_ref)
 
@@ -116,7 +116,7 @@ def test_backward_batch_per_problem_cotangent(mods):
         _, o1 = problems.bond_problem(spec)
         piece = {k: got[k][off[k]:nxt[k]] for k in got}
         compare(lib, spec, piece, ref, scale=gs[p], ops=o1)
-    ws = torch.empty(info["backward_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    ws = torch.empty(lib.heff_backward_workspace(plan), dtype=torch.uint8, device="cuda")
     e = lib.heff_energy(plan, d["L"], d["W1"], d["W2"], d["R"], d["psi"], ws)
     for p, spec in enumerate(specs):
         _, e_ref = oracle_grads(spec)
@@ -133,7 +133,7 @@ def test_backward_deterministic_and_euler_identities_full_size(mods):
     b = run_backward(lib, plan, d, 1.0)
     for k in a:
         assert np.array_equal(a[k], b[k]), k
-    ws = torch.empty(plan.info()["backward_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    ws = torch.empty(lib.heff_backward_workspace(plan), dtype=torch.uint8, device="cuda")
     e = lib.heff_energy(plan, d["L"], d["W1"], d["W2"], d["R"], d["psi"], ws)[0]
     for k in ("L", "W1", "W2", "R"):
         assert abs(float(np.dot(a[k], ops[k])) - e) <= 1e-11 * abs(e), k
@@ -149,7 +149,7 @@ def test_backward_rejects_bad_arguments(mods):
     with pytest.raises(lib.BsdmrgError) as e:
         lib.heff_backward(plan, d["L"], d["W1"], d["W2"], d["R"], d["psi"], 1.0, None, out, None, None, None, small)
     assert e.value.status == lib.EINVAL
-    ws = torch.empty(plan.info()["backward_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    ws = torch.empty(lib.heff_backward_workspace(plan), dtype=torch.uint8, device="cuda")
     with pytest.raises(lib.BsdmrgError):   # output aliases an input
         lib.heff_backward(plan, d["L"], d["W1"], d["W2"], d["R"], d["psi"], 1.0, None, d["L"], None, None, None, ws)
     with pytest.raises(lib.BsdmrgError):
@@ -171,7 +171,7 @@ def test_autograd_function_and_directional_derivatives(mods):
     for k in ref:
         assert np.array_equal(x[k].grad.cpu().numpy(), ref[k]), k
     rng = np.random.default_rng(5)
-    ws = torch.empty(plan.info()["backward_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    ws = torch.empty(lib.heff_backward_workspace(plan), dtype=torch.uint8, device="cuda")
     grads = run_backward(lib, plan, d, 1.0)
     for k in ("L", "R", "W1", "psi"):
         dirn = rng.standard_normal(ops[k].size) * (ops[k] != 0)
