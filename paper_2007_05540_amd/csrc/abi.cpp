@@ -220,7 +220,6 @@ static EigWS carve_eig(const bsdmrg_plan_s* P, const bsdmrg_eig_opts* o, Carve& 
   d.part_n1 = c.take<double>(nch);
   d.red = c.take<double>((size_t)np * 64);
   d.M = c.take<double>((size_t)np * B * B);
-  d.evec = c.take<double>((size_t)np * B * B);
   d.svec = c.take<double>((size_t)np * B);
   d.lam = c.take<double>(np);
   d.scale = c.take<double>(np);

@@ -55,7 +55,6 @@ struct DavBufs {
   double* part_n1;  // nchunk: ||q||^2 after
   double* red;      // n_probs * 64 per-problem sums of partials
   double* M;        // n_probs * B * B projected matrices
-  double* evec;     // n_probs * B * B eigenvectors of the previous step (warm start)
   double* svec;     // n_probs * B Ritz vectors of M
   double* lam;      // n_probs
   double* scale;    // n_probs

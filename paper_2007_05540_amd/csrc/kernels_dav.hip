@@ -108,139 +108,179 @@ __global__ __launch_bounds__(DT) void normalize_kernel(const Chunk* __restrict__
 }
 
 // Gram row m_ij = m_ji = (v^A_j)^T v_i (j <= i) from the chunk partials, then
-// the lowest eigenpair of the (i+1) x (i+1) projected matrix by parallel
-// (round-robin ordered) Jacobi rotations: in every step the indices form
-// ne/2 disjoint pairs, all rotations of a step are computed at once and
-// applied in place as 2 x 2 block updates A <- J^T A J, V <- V J.  An odd
-// size gets a zero dummy index that is never selected.  Warm start: the
-// matrix grows by one row and column per step, so Jacobi starts from
-// W^T M W with W = diag(previous eigenvectors, 1) (all but the new row and
-// column are then already diagonal) and V = W; the eigenvectors are kept in
-// evec for the next step.
+// the lowest eigenpair of the (i+1) x (i+1) projected matrix M, in one wave
+// (lane r owns row r, so no step needs more than a wave-level reduction):
+//  1. Householder tridiagonalisation T = Q^T M Q, Q = H_0 ... H_{n-3},
+//     H_k = I - 2 v_k v_k^T;
+//  2. the lowest eigenvalue of T by multisection on Sturm counts: each round
+//     the 64 lanes test 64 equally spaced shifts inside the current bracket
+//     (initially the Gershgorin interval) and the bracket shrinks 65-fold,
+//     until its width is 4 eps of the eigenvalue's magnitude;
+//  3. its eigenvector by two steps of inverse iteration with
+//     (T - lambda I) / ||T|| (tridiagonal Gaussian elimination with partial
+//     pivoting, a pivot below eps replaced by eps);
+//  4. back-transformation x = Q y.
 constexpr int kMaxBasis = 64;
-__global__ __launch_bounds__(DT) void gram_eig_kernel(int ldr, int i, int B, const double* __restrict__ red,
-                                                      double* __restrict__ M, double* __restrict__ evec,
-                                                      double* __restrict__ svec, double* __restrict__ lam) {
+constexpr int GT = 64;   // one wave
+__global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, const double* __restrict__ red,
+                                                      double* __restrict__ M, double* __restrict__ svec,
+                                                      double* __restrict__ lam) {
   __shared__ double A[kMaxBasis][kMaxBasis + 1];
-  __shared__ double V[kMaxBasis][kMaxBasis + 1];
-  __shared__ double T[kMaxBasis][kMaxBasis + 1];
-  __shared__ double pc[kMaxBasis / 2], ps[kMaxBasis / 2];
-  __shared__ int pp[kMaxBasis / 2], pq[kMaxBasis / 2];
-  __shared__ double sh[16];
-  const int p = blockIdx.x, tid = threadIdx.x, n = i + 1;
-  const int ne = n + (n & 1);
-  const int half = ne / 2;
+  __shared__ double Vh[kMaxBasis][kMaxBasis];
+  __shared__ double d[kMaxBasis], e[kMaxBasis], vb[kMaxBasis], wb[kMaxBasis], y[kMaxBasis];
+  __shared__ double U0[kMaxBasis], U1[kMaxBasis], U2[kMaxBasis], ml[kMaxBasis];
+  __shared__ int sw[kMaxBasis];
+  const int p = blockIdx.x, lane = threadIdx.x, n = i + 1;
   double* Mp = M + (int64_t)p * B * B;
-  double* Ep = evec + (int64_t)p * B * B;
-  if (tid <= i) {
-    const double v = red[(int64_t)p * ldr + tid];
-    Mp[i * B + tid] = v;
-    Mp[tid * B + i] = v;
+  const double* rp = red + (int64_t)p * ldr;
+  // the new row and column come from red; the rest from the stored matrix
+  for (int e2 = lane; e2 < n * n; e2 += GT) {
+    const int r = e2 / n, c = e2 % n;
+    A[r][c] = (r == i) ? rp[c] : (c == i) ? rp[r] : Mp[r * B + c];
   }
-  __threadfence_block();
-  __syncthreads();
-  for (int e = tid; e < ne * ne; e += DT) {
-    const int r = e / ne, c = e % ne;
-    A[r][c] = (r < n && c < n) ? Mp[r * B + c] : 0.0;
-    // W = diag(previous eigenvectors (i x i), 1), identity on the dummy index
-    V[r][c] = (r < i && c < i) ? Ep[r * B + c] : (r == c ? 1.0 : 0.0);
+  if (lane <= i) {
+    const double v = rp[lane];
+    Mp[i * B + lane] = v;
+    Mp[lane * B + i] = v;
   }
   __syncthreads();
-  if (i > 0) {
-    for (int e = tid; e < n * n; e += DT) {   // T = A W
-      const int r = e / n, c = e % n;
-      double t = 0.0;
-      for (int k = 0; k < n; ++k) t += A[r][k] * V[k][c];
-      T[r][c] = t;
+  // 1. tridiagonalisation (lane r owns row r of the trailing block)
+  for (int k = 0; k + 2 < n; ++k) {
+    const bool mine = lane > k && lane < n;
+    const double xr = mine ? A[lane][k] : 0.0;
+    const double nrm2 = wave_sum(xr * xr);
+    const double x0 = A[k + 1][k];
+    const double alpha = nrm2 > 0.0 ? -copysign(sqrt(nrm2), x0) : 0.0;
+    const double vn2 = 2.0 * (nrm2 - alpha * x0);   // ||x - alpha e_{k+1}||^2
+    const double vr = vn2 > 0.0 ? (xr - (lane == k + 1 ? alpha : 0.0)) / sqrt(vn2) : 0.0;
+    vb[lane] = vr;
+    Vh[k][lane] = vr;
+    if (lane == 0) {
+      d[k] = A[k][k];
+      e[k] = alpha;
     }
     __syncthreads();
-    for (int e = tid; e < n * n; e += DT) {   // A = W^T T
-      const int r = e / n, c = e % n;
-      double t = 0.0;
-      for (int k = 0; k < n; ++k) t += V[k][r] * T[k][c];
-      A[r][c] = t;
-    }
-    __syncthreads();
-    for (int e = tid; e < n * n; e += DT) {   // exact symmetry of the start matrix
-      const int r = e / n, c = e % n;
-      if (r < c) {
-        const double m = 0.5 * (A[r][c] + A[c][r]);
-        T[r][c] = m;
-      }
-    }
-    __syncthreads();
-    for (int e = tid; e < n * n; e += DT) {
-      const int r = e / n, c = e % n;
-      if (r < c) A[r][c] = T[r][c];
-      if (r > c) A[r][c] = T[c][r];
-    }
-    __syncthreads();
-  }
-  double f = 0.0;
-  for (int e = tid; e < n * n; e += DT) f += A[e / n][e % n] * A[e / n][e % n];
-  const double fro2 = block_sum(f, sh);
-  const double tiny = 1e-17 * sqrt(fro2);
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    double o = 0.0;
-    for (int e = tid; e < n * n; e += DT) {
-      const int r = e / n, c = e % n;
-      if (r != c) o += A[r][c] * A[r][c];
-    }
-    const double off = block_sum(o, sh);
-    if (off <= 1e-32 * fro2) break;
-    for (int step = 0; step < ne - 1; ++step) {
-      if (tid < half) {
-        // circle method: position 0 fixed, the others rotate by one per step
-        auto player = [&](int k) { return k == 0 ? 0 : 1 + ((k - 1 + step) % (ne - 1)); };
-        const int a = player(tid), b = player(ne - 1 - tid);
-        const int P = min(a, b), Q = max(a, b);
-        const double apq = A[P][Q];
-        double c = 1.0, sn = 0.0;
-        if (fabs(apq) > tiny) {
-          const double tau = (A[Q][Q] - A[P][P]) / (2.0 * apq);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          sn = t * c;
-        }
-        pp[tid] = P; pq[tid] = Q; pc[tid] = c; ps[tid] = sn;
-      }
+    if (vn2 > 0.0) {
+      double pr = 0.0;
+      if (mine)
+        for (int c = k + 1; c < n; ++c) pr += A[lane][c] * vb[c];
+      const double beta = wave_sum(vr * pr);
+      const double wr = pr - beta * vr;
+      wb[lane] = wr;
       __syncthreads();
-      for (int e = tid; e < half * half; e += DT) {
-        const int kr = e / half, kc = e % half;
-        if (ps[kr] == 0.0 && ps[kc] == 0.0) continue;
-        const int r0 = pp[kr], r1 = pq[kr], c0 = pp[kc], c1 = pq[kc];
-        const double cr = pc[kr], sr = ps[kr], cc = pc[kc], sc = ps[kc];
-        const double b00 = A[r0][c0], b01 = A[r0][c1], b10 = A[r1][c0], b11 = A[r1][c1];
-        const double x00 = b00 * cc - b01 * sc, x01 = b00 * sc + b01 * cc;
-        const double x10 = b10 * cc - b11 * sc, x11 = b10 * sc + b11 * cc;
-        A[r0][c0] = cr * x00 - sr * x10;
-        A[r1][c1] = sr * x01 + cr * x11;
-        if (kr == kc) {
-          A[r0][c1] = 0.0;
-          A[r1][c0] = 0.0;
+      if (mine)
+        for (int c = k + 1; c < n; ++c) A[lane][c] -= 2.0 * (vr * wb[c] + wr * vb[c]);
+      __syncthreads();
+    }
+  }
+  if (lane == 0) {
+    if (n >= 2) {
+      d[n - 2] = A[n - 2][n - 2];
+      e[n - 2] = A[n - 1][n - 2];
+    }
+    d[n - 1] = A[n - 1][n - 1];
+  }
+  __syncthreads();
+  // 2. multisection for the lowest eigenvalue of T
+  double glo = 1e308, ghi = -1e308, tn = 0.0, emax2 = 0.0;
+  if (lane < n) {
+    const double el = lane > 0 ? fabs(e[lane - 1]) : 0.0, er = lane < n - 1 ? fabs(e[lane]) : 0.0;
+    glo = d[lane] - el - er;
+    ghi = d[lane] + el + er;
+    tn = fabs(d[lane]) + el + er;
+    emax2 = er * er;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    glo = fmin(glo, __shfl_xor(glo, o, 64));
+    ghi = fmax(ghi, __shfl_xor(ghi, o, 64));
+    tn = fmax(tn, __shfl_xor(tn, o, 64));
+    emax2 = fmax(emax2, __shfl_xor(emax2, o, 64));
+  }
+  const double eps = 2.220446049250313e-16;
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+  double lo = glo - 2.0 * eps * tn - pivmin, hi = ghi + 2.0 * eps * tn + pivmin;
+  for (int round = 0; round < 24; ++round) {
+    const double width = hi - lo;
+    if (!(width > 4.0 * eps * fmax(fabs(lo), fabs(hi))) || width <= pivmin) break;
+    const double sigma = lo + width * (double)(lane + 1) / (double)(GT + 1);
+    int cnt = 0;
+    double q = 1.0;
+    for (int j = 0; j < n; ++j) {
+      q = d[j] - sigma - (j > 0 ? e[j - 1] * e[j - 1] / q : 0.0);
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+    }
+    const unsigned long long below = __ballot(cnt >= 1);   // shifts with an eigenvalue below them
+    if (below) {
+      const int first = __ffsll((long long)below) - 1;
+      const double nhi = lo + width * (double)(first + 1) / (double)(GT + 1);
+      const double nlo = first > 0 ? lo + width * (double)first / (double)(GT + 1) : lo;
+      lo = nlo;
+      hi = nhi;
+    } else {
+      lo = lo + width * (double)GT / (double)(GT + 1);
+    }
+  }
+  const double lambda = 0.5 * (lo + hi);
+  // 3. inverse iteration (one lane: the elimination is sequential)
+  if (lane == 0 && !(tn > 0.0)) {   // T = 0: every vector is an eigenvector
+    for (int j = 0; j < n; ++j) y[j] = j == 0 ? 1.0 : 0.0;
+  } else if (lane == 0) {
+    // work with (T - lambda I) / ||T|| so that the iterates cannot overflow
+    const double sc = 1.0 / tn, tiny = eps;
+    // factor = P L U; row j of U is (U0, U1, U2) at columns j, j+1, j+2
+    double a = (d[0] - lambda) * sc, b = n > 1 ? e[0] * sc : 0.0, c = 0.0;
+    for (int j = 0; j + 1 < n; ++j) {
+      const double sub = e[j] * sc, dn = (d[j + 1] - lambda) * sc, en = j + 2 < n ? e[j + 1] * sc : 0.0;
+      if (fabs(a) >= fabs(sub)) {
+        const double m = a != 0.0 ? sub / a : 0.0;
+        U0[j] = a; U1[j] = b; U2[j] = c; ml[j] = m; sw[j] = 0;
+        a = dn - m * b;
+        b = en - m * c;
+      } else {
+        const double m = a / sub;
+        U0[j] = sub; U1[j] = dn; U2[j] = en; ml[j] = m; sw[j] = 1;
+        a = b - m * dn;
+        b = c - m * en;
+      }
+      c = 0.0;
+    }
+    U0[n - 1] = a; U1[n - 1] = 0.0; U2[n - 1] = 0.0;
+    for (int j = 0; j < n; ++j)
+      if (fabs(U0[j]) < tiny) U0[j] = U0[j] < 0.0 ? -tiny : tiny;
+    for (int j = 0; j < n; ++j) y[j] = 1.0 / sqrt((double)n);
+    for (int it = 0; it < 2; ++it) {
+      for (int j = 0; j + 1 < n; ++j) {
+        if (sw[j]) {
+          const double t = y[j];
+          y[j] = y[j + 1];
+          y[j + 1] = t - ml[j] * y[j];
         } else {
-          A[r0][c1] = cr * x01 - sr * x11;
-          A[r1][c0] = sr * x00 + cr * x10;
+          y[j + 1] -= ml[j] * y[j];
         }
       }
-      for (int e = tid; e < ne * half; e += DT) {
-        const int r = e / half, kc = e % half;
-        if (ps[kc] == 0.0) continue;
-        const int c0 = pp[kc], c1 = pq[kc];
-        const double cc = pc[kc], sc = ps[kc];
-        const double v0 = V[r][c0], v1 = V[r][c1];
-        V[r][c0] = v0 * cc - v1 * sc;
-        V[r][c1] = v0 * sc + v1 * cc;
+      for (int j = n - 1; j >= 0; --j) {
+        double t = y[j];
+        if (j + 1 < n) t -= U1[j] * y[j + 1];
+        if (j + 2 < n) t -= U2[j] * y[j + 2];
+        y[j] = t / U0[j];
       }
-      __syncthreads();
+      double s2 = 0.0;
+      for (int j = 0; j < n; ++j) s2 += y[j] * y[j];
+      const double inv = 1.0 / sqrt(s2);
+      for (int j = 0; j < n; ++j) y[j] *= inv;
     }
   }
-  int idx = 0;
-  for (int r = 1; r < n; ++r)
-    if (A[r][r] < A[idx][idx]) idx = r;
-  if (tid < n) svec[(int64_t)p * B + tid] = V[tid][idx];
-  if (tid == 0) lam[p] = A[idx][idx];
-  for (int e = tid; e < n * n; e += DT) Ep[(e / n) * B + e % n] = V[e / n][e % n];
+  __syncthreads();
+  // 4. x = H_0 (H_1 (... (H_{n-3} y)))
+  double xr = lane < n ? y[lane] : 0.0;
+  for (int k = n - 3; k >= 0; --k) {
+    const double v = Vh[k][lane];
+    const double dv = wave_sum(v * xr);
+    xr -= 2.0 * dv * v;
+  }
+  if (lane < n) svec[(int64_t)p * B + lane] = xr;
+  if (lane == 0) lam[p] = lambda;
 }
 
 // q = sum s_j v^A_j - lambda sum s_j v_j with partial ||q||^2; when x is
@@ -481,8 +521,8 @@ hipError_t dav_normalize(const bsdmrg_plan_s* P, const double* part, double* red
 hipError_t dav_gram_eig(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStream_t s) {
   hipError_t e = dav_psum(P, i + 1, b.part_a, b.red, kMaxBasis, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gram_eig_kernel, dim3((unsigned)P->probs.size()), dim3(DT), 0, s, kMaxBasis, i, b.B,
-                     b.red, b.M, b.evec, b.svec, b.lam);
+  hipLaunchKernelGGL(gram_eig_kernel, dim3((unsigned)P->probs.size()), dim3(GT), 0, s, kMaxBasis, i, b.B,
+                     b.red, b.M, b.svec, b.lam);
   return hipGetLastError();
 }
 

@@ -85,7 +85,7 @@ namespace bsd {
 // original matrix M: U (rows x k, column-major, ld rows), S (k), Vt (k x
 // cols, column-major, ld k), k = min(rows, cols); when M was wide, X holds
 // M^T and the roles of the two vector sets swap.
-__global__ __launch_bounds__(256) void jacobi_svd_kernel(const SvdTask* __restrict__ tasks, double* __restrict__ work,
+__global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdTask* __restrict__ tasks, double* __restrict__ work,
                                                          double* __restrict__ U, double* __restrict__ S,
                                                          double* __restrict__ Vt) {
   __shared__ int not_conv;
@@ -99,7 +99,9 @@ __global__ __launch_bounds__(256) void jacobi_svd_kernel(const SvdTask* __restri
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) V[e] = (e % n == e / n) ? 1.0 : 0.0;
   __syncthreads();
   const int ne = n + (n & 1), half = ne / 2;
-  const double tol = 1e-15;
+  // a pair counts as orthogonal when |x_p . x_q| <= tol ||x_p|| ||x_q||; the
+  // dot products carry rounding of about m eps, so tol follows m
+  const double tol = fmax(1e-15, 4.0 * m * 2.220446049250313e-16);
   for (int sweep = 0; sweep < 80 && ne > 1; ++sweep) {
     if (threadIdx.x == 0) not_conv = 0;
     __syncthreads();
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(256) void jacobi_svd_kernel(const SvdTask* __restri
 hipError_t launch_jacobi_svd(const void* d_tasks, int n, double* work, double* U, double* S, double* Vt,
                              hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3((unsigned)n), dim3(256), 0, s, (const SvdTask*)d_tasks, work, U, S,
+  hipLaunchKernelGGL(jacobi_svd_kernel, dim3((unsigned)n), dim3(1024), 0, s, (const SvdTask*)d_tasks, work, U, S,
                      Vt);
   return hipGetLastError();
 }

@@ -164,15 +164,21 @@ class GpuDMRG:
             total += float(np.dot(g.detach().cpu().numpy(), dp))
         return total
 
-    def run(self, n_sweeps, m_max, cutoff=1e-10, cutoff_mode=0, max_iter=40, tol=1e-12, progress=False):
-        """Two-site sweeps; m_max is an int or a per-sweep list.  Returns
-        (energies per visited bond, last energy of every sweep)."""
+    def run(self, n_sweeps, m_max, cutoff=1e-10, cutoff_mode=0, max_iter=40, tol=1e-12, progress=False,
+            on_sweep=None):
+        """Two-site sweeps; m_max is an int or a per-sweep list; on_sweep(sweep,
+        energy, seconds) is called after every sweep.  Returns (energies per
+        visited bond, last energy of every sweep)."""
+        import time
         self.right_canonicalize(progress=progress)
         mlist = m_max if isinstance(m_max, (list, tuple)) else [m_max] * n_sweeps
         energies, sweep_e = [], []
+        self.sweep_seconds = []
         step = 0
         N = self.N
         for sw in range(n_sweeps):
+            self.torch.cuda.synchronize()
+            t0 = time.perf_counter()
             order = [(j, 0) for j in range(N - 1)] + [(j, 1) for j in range(N - 2, -1, -1)]
             for j, d in order:
                 theta = self._merge(self.T[j], self.T[j + 1])
@@ -193,4 +199,12 @@ class GpuDMRG:
                                  "m": sum(dd for _, dd in A.legs[2]), "flops_per_product": flops})
                 step += 1
             sweep_e.append(energies[-1])
+            self.torch.cuda.synchronize()
+            self.sweep_seconds.append(time.perf_counter() - t0)
+            if on_sweep is not None:
+                on_sweep(sw, sweep_e[-1], self.sweep_seconds[-1])
         return energies, sweep_e
+
+    def host_mps(self):
+        """The current MPS as (legs, packed FP64 array) pairs (a warm start)."""
+        return [(t.legs, t.data.detach().cpu().numpy()) for t in self.T]

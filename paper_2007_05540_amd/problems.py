@@ -63,3 +63,22 @@ def concat(plan, ops_list):
         for k in out:
             out[k][off[k]:off[k] + ops[k].size] = ops[k]
     return out
+
+
+def initial_mps(mpo, target, m0, seed):
+    """Seeded random initial MPS in the sector of total charge ``target`` as
+    (legs, packed FP64 array) per site: bond legs from the sector model of
+    synth.mps_bond_legs, block values from synth.blocks.mps_block."""
+    from synth.sectors import mps_bond_legs
+    from synth.blocks import mps_block
+    n = len(mpo.W)
+    legs = mps_bond_legs(n, mpo.phys, tuple(target), m0)
+    out = []
+    for j in range(n):
+        lj = [legs[j], mpo.phys, legs[j + 1]]
+
+        def blk(k, j=j, lj=lj):
+            shape = tuple(lj[i][k[i]][1] for i in range(3))
+            return mps_block(seed, j, k, shape)
+        out.append((lj, pack_fn(lj, lib.MPS_SIGNS, blk)))
+    return out
