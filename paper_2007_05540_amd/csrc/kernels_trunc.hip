@@ -80,15 +80,17 @@ namespace bsd {
 // plane rotations, V accumulates them; then sigma_j = ||x_j||, the left
 // vectors are x_j / sigma_j and the right vectors the columns of V.  Pairs
 // follow the round-robin (circle) order, so the n/2 rotations of a step are
-// independent and each wave takes whole pairs.  The output is written in
+// independent; each group of 16 lanes takes whole pairs.  The output is written in
 // descending order of sigma in the layout of a LAPACK-style thin SVD of the
 // original matrix M: U (rows x k, column-major, ld rows), S (k), Vt (k x
 // cols, column-major, ld k), k = min(rows, cols); when M was wide, X holds
 // M^T and the roles of the two vector sets swap.
+constexpr int kSvdGroup = 16;   // lanes per column pair
 __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdTask* __restrict__ tasks, double* __restrict__ work,
                                                          double* __restrict__ U, double* __restrict__ S,
                                                          double* __restrict__ Vt) {
   __shared__ int not_conv;
+  __shared__ double fro[16];
   const SvdTask t = tasks[blockIdx.x];
   double* X = work + t.x_off;       // m x n, ld m
   double* V = work + t.v_off;       // n x n, ld n
@@ -96,17 +98,32 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdTask* __restr
   int* perm = (int*)(work + t.perm_off);
   const int m = t.m, n = t.n;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int gl = threadIdx.x % kSvdGroup, grp = threadIdx.x / kSvdGroup, ngrp = blockDim.x / kSvdGroup;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) V[e] = (e % n == e / n) ? 1.0 : 0.0;
   __syncthreads();
   const int ne = n + (n & 1), half = ne / 2;
   // a pair counts as orthogonal when |x_p . x_q| <= tol ||x_p|| ||x_q||; the
-  // dot products carry rounding of about m eps, so tol follows m
+  // dot products carry rounding of about m eps, so tol follows m.  Columns
+  // whose norm is below 1e-16 ||X||_F are rounding noise left by earlier
+  // rotations: they are not rotated (their singular values are zero to
+  // working precision), otherwise the noise columns would keep rotating
+  // against each other and the sweeps would never stop.
   const double tol = fmax(1e-15, 4.0 * m * 2.220446049250313e-16);
+  double f2 = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += blockDim.x) f2 += X[e] * X[e];
+  for (int o = 32; o > 0; o >>= 1) f2 += __shfl_xor(f2, o, 64);
+  if (lane == 0) fro[wave] = f2;
+  __syncthreads();
+  double fro2 = 0.0;
+  for (int w = 0; w < nw; ++w) fro2 += fro[w];
+  const double negl = 1e-32 * fro2;
   for (int sweep = 0; sweep < 80 && ne > 1; ++sweep) {
     if (threadIdx.x == 0) not_conv = 0;
     __syncthreads();
     for (int step = 0; step < ne - 1; ++step) {
-      for (int k = wave; k < half; k += nw) {
+      // one pair per group of 16 lanes (4 pairs per wave in flight): the
+      // per-pair chain of reductions and rotation arithmetic is short
+      for (int k = grp; k < half; k += ngrp) {
         auto player = [&](int j) { return j == 0 ? 0 : 1 + ((j - 1 + step) % (ne - 1)); };
         const int a = player(k), b = player(ne - 1 - k);
         const int p = min(a, b), q = max(a, b);
@@ -114,30 +131,30 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdTask* __restr
         double* xp = X + (int64_t)p * m;
         double* xq = X + (int64_t)q * m;
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int r = lane; r < m; r += 64) {
+        for (int r = gl; r < m; r += kSvdGroup) {
           const double u = xp[r], v = xq[r];
           al += u * u;
           be += v * v;
           ga += u * v;
         }
-        for (int o = 32; o > 0; o >>= 1) {
+        for (int o = kSvdGroup / 2; o > 0; o >>= 1) {   // stays inside the group
           al += __shfl_xor(al, o, 64);
           be += __shfl_xor(be, o, 64);
           ga += __shfl_xor(ga, o, 64);
         }
-        if (ga == 0.0 || fabs(ga) <= tol * sqrt(al * be)) continue;
-        if (lane == 0) not_conv = 1;
+        if (ga == 0.0 || al <= negl || be <= negl || fabs(ga) <= tol * sqrt(al * be)) continue;
+        if (gl == 0) not_conv = 1;
         const double zeta = (be - al) / (2.0 * ga);
         const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
-        for (int r = lane; r < m; r += 64) {
+        for (int r = gl; r < m; r += kSvdGroup) {
           const double u = xp[r], v = xq[r];
           xp[r] = c * u - s * v;
           xq[r] = s * u + c * v;
         }
         double* vp = V + (int64_t)p * n;
         double* vq = V + (int64_t)q * n;
-        for (int r = lane; r < n; r += 64) {
+        for (int r = gl; r < n; r += kSvdGroup) {
           const double u = vp[r], v = vq[r];
           vp[r] = c * u - s * v;
           vq[r] = s * u + c * v;
