@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-bond batch measurement")
+    ap.add_argument("--no-hubbard", action="store_true", help="skip the m=4096 Hubbard bond measurement")
     ap.add_argument("--workload", default="bond", choices=["bond", "j1j2-6x6"],
                     help="bond: the isolated-bond product bench (default); j1j2-6x6: DMRG sweeps on the "
                          "6x6 J1-J2 cylinder, dE/dJ2 by the adjoint and by finite differences")
@@ -180,40 +181,29 @@ def j1j2_bench(args):
             "one_sweep_from_converged": sweep, "data": "synthetic (seeded random initial MPS)"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(the multi-GPU sharding is a design note, not built)"}))
-        sys.exit(2)
-    if args.workload == "j1j2-6x6":
-        print(json.dumps(j1j2_bench(args)))
-        return
+def bond_measure(spec, args):
+    """Plan one isolated bond, upload its operands and time the FP64 and the
+    mixed fixed-step Davidson solves (graph replay).  Returns the plan, its
+    info, the useful flops per product, the device operands and the results."""
     import torch
-    import synth
     from paper_2007_05540_amd import lib, problems
 
-    spec = synth.c2_bond(m=1024, k=14, seed=1)
     prob, ops = problems.bond_problem(spec)
     plan = lib.Plan([prob])
     info = plan.info()
     flops = info["flops_s1"] + info["flops_s3"]
     dev = {k: torch.from_numpy(v).to("cuda") for k, v in ops.items()}
+    del ops
     stream = torch.cuda.Stream()
     psi0 = dev["psi"]
-
-    def make(prec):
-        if prec == "mixed":
+    results = {}
+    for path in ("f64", "mixed"):
+        if path == "mixed":
             o = lib.eig_opts(max_iter=args.n_f32, precision=lib.F32_REFINE, refine_max_iter=args.n_f64,
                              fixed_iters=1, use_graph=1)
         else:
             o = lib.eig_opts(max_iter=args.n_f32 + args.n_f64, fixed_iters=1, use_graph=1)
         ws = torch.empty(lib.eig_workspace(plan, o), dtype=torch.uint8, device="cuda")
-        return o, ws
-
-    results = {}
-    for path in ("f64", "mixed"):
-        o, ws = make(path)
         psi = torch.empty_like(psi0)
         energy = None
         with torch.cuda.stream(stream):
@@ -232,7 +222,52 @@ def main():
         products = args.n_f32 + args.n_f64
         results[path] = {"ms_per_step": dt * 1e3, "gflops": products * flops / dt / 1e9,
                          "energy": energy[0], "residual": st[0]["residual"], "products": products}
-        del ws
+        del ws, psi
+    return plan, info, flops, dev, results
+
+
+def hubbard_bond_bench(args):
+    """The isolated mid-chain bond of the 4x16 Hubbard cylinder at half
+    filling: electron sector model at m = 4096 (313 U(1)xU(1) sectors, largest
+    block 468), Hubbard-type MPO with k = 22, the same fixed-step solves."""
+    import torch
+    import synth
+
+    spec = synth.c4_bond(m=4096, k=22, seed=1)
+    t0 = time.perf_counter()
+    plan, info, flops, dev, res = bond_measure(spec, args)
+    out = {"workload": "isolated mid-chain two-site bond, 4x16 Hubbard cylinder, m=4096, k=22, "
+                       "313 U(1)xU(1) sectors",
+           "useful_gflop_per_product": round(flops / 1e9, 3), "s1_tasks": info["n_s1_tasks"],
+           "s3_tasks": info["n_s3_tasks"]}
+    for path in ("f64", "mixed"):
+        out[path] = {"ms_per_davidson_step": round(res[path]["ms_per_step"], 3),
+                     "useful_gflops": round(res[path]["gflops"], 1), "energy": res[path]["energy"]}
+    out["speedup_mixed_vs_f64"] = round(res["f64"]["ms_per_step"] / res["mixed"]["ms_per_step"], 3)
+    out["wall_s"] = round(time.perf_counter() - t0, 1)
+    del dev
+    plan.destroy()
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(the multi-GPU sharding is a design note, not built)"}))
+        sys.exit(2)
+    if args.workload == "j1j2-6x6":
+        print(json.dumps(j1j2_bench(args)))
+        return
+    import torch
+    import synth
+    from paper_2007_05540_amd import lib, problems
+
+    spec = synth.c2_bond(m=1024, k=14, seed=1)
+    plan, info, flops, dev, results = bond_measure(spec, args)
+    stream = torch.cuda.Stream()
+    psi0 = dev["psi"]
 
     # live per-kernel timing of one product (HIP events on the launch stream)
     out = torch.zeros_like(psi0)
@@ -267,11 +302,13 @@ def main():
         "stage_ms": {k: {s: round(v, 5) for s, v in d.items()} for k, d in stage.items()},
         "roofline": roofline,
     }
+    del dev, out, wsa
+    plan.destroy()
+    torch.cuda.empty_cache()
     if not args.no_batch:
-        del dev, out, wsa
-        plan.destroy()
-        torch.cuda.empty_cache()
         line["batch_64_bonds"] = batch_bench(args)
+    if not args.no_hubbard:
+        line["hubbard_bond_m4096"] = hubbard_bond_bench(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, flops, args.cpu_seconds)
     print(json.dumps(line))

@@ -14,14 +14,14 @@ which a consumer enumerates blocks never changes what it receives.
 
 from .lattice import chain_bonds, cylinder_j1_bonds, cylinder_j2_bonds, merge_bonds
 from .mpo import (MPO, SPIN_PHYS, HUB_PHYS, heisenberg_mpo, hubbard_mpo,
-                  synthetic_heisenberg_bond, heisenberg_j2_derivative)
+                  synthetic_heisenberg_bond, synthetic_hubbard_bond, heisenberg_j2_derivative)
 from .sectors import spin_bond_leg, electron_bond_leg, mps_bond_legs
-from .blocks import gaussian_block, env_block, BondSpec, c2_bond, c3_batch
+from .blocks import gaussian_block, env_block, BondSpec, c2_bond, c3_batch, c4_bond
 
 __all__ = [
     "chain_bonds", "cylinder_j1_bonds", "cylinder_j2_bonds", "merge_bonds",
     "MPO", "SPIN_PHYS", "HUB_PHYS", "heisenberg_mpo", "hubbard_mpo",
-    "synthetic_heisenberg_bond", "heisenberg_j2_derivative",
+    "synthetic_heisenberg_bond", "synthetic_hubbard_bond", "heisenberg_j2_derivative",
     "spin_bond_leg", "electron_bond_leg", "mps_bond_legs",
-    "gaussian_block", "env_block", "BondSpec", "c2_bond", "c3_batch",
+    "gaussian_block", "env_block", "BondSpec", "c2_bond", "c3_batch", "c4_bond",
 ]

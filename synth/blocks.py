@@ -14,8 +14,8 @@ channel (``start`` for L, ``done`` for R) is exactly the identity.
 """
 import numpy as np
 
-from .mpo import synthetic_heisenberg_bond, SPIN_PHYS
-from .sectors import spin_bond_leg
+from .mpo import synthetic_heisenberg_bond, synthetic_hubbard_bond, SPIN_PHYS
+from .sectors import spin_bond_leg, electron_bond_leg
 
 TAG_L, TAG_R, TAG_PSI, TAG_MPS = 11, 12, 13, 14
 
@@ -104,6 +104,17 @@ def c2_bond(m=1024, k=14, seed=1):
     leg = spin_bond_leg(m)
     mpo = synthetic_heisenberg_bond(k, seed)
     return BondSpec(leg, leg, mpo, seed, name=f"heisenberg-bond m={m} k={k}")
+
+
+def c4_bond(m=4096, k=22, seed=1):
+    """Mid-chain bond of a Hubbard cylinder at half filling: electron sector
+    model at bond dimension m on both bond legs (left leg centred at charge
+    (N, 2Sz) = (0, 0), right leg at (2, 0): two sites add two electrons),
+    Hubbard-type MPO with k channels, U = 8 and U(0.5, 1.5) hoppings."""
+    a = electron_bond_leg(m, center=(0, 0))
+    c = electron_bond_leg(m, center=(2, 0))
+    mpo = synthetic_hubbard_bond(k, seed)
+    return BondSpec(a, c, mpo, seed, name=f"hubbard-bond m={m} k={k}")
 
 
 def c3_batch(n=64, seed0=100, ms=(256, 512, 1024, 2048), ks=(10, 14, 18)):

@@ -239,3 +239,52 @@ def synthetic_heisenberg_bond(k, seed):
             t.append((f"pad{p}", "done", Jpad[p] * ops["Sz"]))
         sites.append(t)
     return _assemble(chans, sites, 2, SPIN_PHYS, conj)
+
+
+def synthetic_hubbard_bond(k, seed, U=8.0):
+    """Two MPO sites of a Hubbard-type FSM with exactly k channels, for
+    isolated-bond workloads of the electron model.
+
+    n = (k - 2) // 4 hopping strands per spin and direction (c+_up, c_up,
+    c+_dn, c_dn with Jordan-Wigner strings, as in ``hubbard_mpo`` with hops of
+    range 1..n); the remaining (k - 2) % 4 channels are flux-0 density strands
+    (n_tot ... n_tot).  Hoppings t_r and densities are drawn from U(0.5, 1.5)
+    with the given seed; the on-site term is U n_up n_dn.
+    """
+    o = hub_ops()
+    n = (k - 2) // 4
+    pad = (k - 2) - 4 * n
+    assert n >= 1
+    rng = np.random.default_rng([int(seed), 78])
+    left_op = {"cu+": o["cu+"] @ o["F"], "cd+": o["cd+"] @ o["F"],
+               "cu": o["F"] @ o["cu"], "cd": o["F"] @ o["cd"]}
+    comp = {"cu+": o["cu"], "cd+": o["cd"], "cu": o["cu+"], "cd": o["cd+"]}
+    ntot = o["nu"] + o["nd"]
+    chans = [("start", (0, 0))]
+    for op in ("cu+", "cu", "cd+", "cd"):
+        for r in range(1, n + 1):
+            chans.append((f"{op}@{r}", _HUB_FLUX[op]))
+    for p in range(pad):
+        chans.append((f"pad{p}", (0, 0)))
+    chans.append(("done", (0, 0)))
+    conj = {}
+    for r in range(1, n + 1):
+        conj[f"cu+@{r}"] = f"cu@{r}"; conj[f"cu@{r}"] = f"cu+@{r}"
+        conj[f"cd+@{r}"] = f"cd@{r}"; conj[f"cd@{r}"] = f"cd+@{r}"
+    sites = []
+    for _site in range(2):
+        t_hop = rng.uniform(0.5, 1.5, size=n)
+        Jpad = rng.uniform(0.5, 1.5, size=pad)
+        t = [("start", "start", o["I"]), ("done", "done", o["I"]),
+             ("start", "done", U * (o["nu"] @ o["nd"]))]
+        for op in ("cu+", "cu", "cd+", "cd"):
+            t.append(("start", f"{op}@1", left_op[op]))
+            for r in range(1, n):
+                t.append((f"{op}@{r}", f"{op}@{r + 1}", o["F"]))
+            for r in range(1, n + 1):
+                t.append((f"{op}@{r}", "done", -t_hop[r - 1] * comp[op]))
+        for p in range(pad):
+            t.append(("start", f"pad{p}", ntot))
+            t.append((f"pad{p}", "done", Jpad[p] * ntot))
+        sites.append(t)
+    return _assemble(chans, sites, 4, HUB_PHYS, conj)

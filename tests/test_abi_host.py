@@ -73,6 +73,21 @@ def test_planner_flops_equal_oracle_block_pairs(lib, m, k, seed):
     assert np.array_equal(ops["psi"], psi.pack()) and np.array_equal(ops["L"], L.pack())
 
 
+@pytest.mark.parametrize("m,k,seed", [(128, 10, 1), (512, 22, 2)])
+def test_planner_flops_equal_oracle_block_pairs_electron_bond(lib, m, k, seed):
+    """U(1)xU(1) charges (N, 2Sz), four physical sectors, fermionic MPO."""
+    from paper_2007_05540_amd import problems
+    spec = synth.c4_bond(m=m, k=k, seed=seed)
+    prob, ops = problems.bond_problem(spec)
+    plan = lib.Plan([prob], host_only=True)
+    info = plan.info()
+    ops_o = bond_operands(spec)
+    assert info["flops_s1"] + info["flops_s3"] == useful_flops(*ops_o)
+    L, W1, W2, R, psi = ops_o
+    assert np.array_equal(ops["psi"], psi.pack()) and np.array_equal(ops["L"], L.pack())
+    assert np.array_equal(ops["W1"], W1.pack())
+
+
 def test_planner_task_set_equals_brute_force_enumeration(lib):
     """S1 tasks = every (psi block, channel sector) whose bra sector exists,
     found here by brute force over all sector triples."""

@@ -86,6 +86,46 @@ def test_apply_f64_full_size_mid_chain_bond(mods):
     assert rel(out.cpu().numpy(), oracle_apply(spec)) < 1e-12
 
 
+ELECTRON_CASES = [(96, 10, 1), (256, 22, 2), (1024, 22, 3)]
+
+
+@pytest.mark.parametrize("m,k,seed", ELECTRON_CASES)
+def test_apply_f64_electron_bond_matches_oracle(mods, m, k, seed):
+    """U(1)xU(1) (N, 2Sz) bonds of the electron sector model with a
+    Hubbard-type MPO (fermionic strands, four physical sectors)."""
+    lib, problems = mods
+    spec = synth.c4_bond(m=m, k=k, seed=seed)
+    plan, ops, d = setup([spec], lib, problems)
+    out = torch.zeros_like(d["psi"])
+    ws = torch.empty(plan.info()["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    lib.heff_apply(plan, lib.F64, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert rel(got, oracle_apply(spec)) < 1e-12
+    mask = mask_of([spec.a_leg, spec.s_leg, spec.s_leg, spec.c_leg], PSI_SIGNS)
+    assert np.all(got[~mask] == 0.0)
+
+
+def test_apply_hubbard_bond_full_size(mods):
+    """m = 4096, k = 22 (313 sectors, 22476 S1 tasks): the full-size bond in
+    the bench's launch configuration; FP64 output compared element by element
+    with the oracle, FP32 output within the FP32 bound."""
+    lib, problems = mods
+    spec = synth.c4_bond(m=4096, k=22, seed=1)
+    plan, ops, d = setup([spec], lib, problems)
+    ws = torch.empty(plan.info()["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    outs = {}
+    for prec in (lib.F64, lib.F32):
+        out = torch.zeros_like(d["psi"])
+        lib.heff_apply(plan, prec, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
+        torch.cuda.synchronize()
+        outs[prec] = out.cpu().numpy()
+    del ws, d
+    ref = oracle_apply(spec)
+    assert rel(outs[lib.F64], ref) < 1e-12
+    assert 1e-9 < rel(outs[lib.F32], ref) < 5e-5
+
+
 def test_apply_f32_within_fp32_bound(mods):
     lib, problems = mods
     spec = synth.c2_bond(m=512, k=14, seed=7)
@@ -194,6 +234,18 @@ def test_eigensolve_mixed_precision_energy(mods):
     the final energy agrees with the converged FP64 oracle to 1e-9."""
     lib, problems = mods
     spec = synth.c2_bond(m=24, k=5, seed=4)
+    plan, ops, d = setup([spec], lib, problems)
+    lam, _, ost, _ = oracle_davidson(spec, 64, tol=1e-10)
+    assert ost["converged"]
+    o = lib.eig_opts(max_iter=64, precision=lib.F32_REFINE, refine_max_iter=64, tol=1e-10, tol_f32=1e-5)
+    e32, st32, _ = run_eig(lib, plan, d, o)
+    assert st32[0]["iters_f32"] >= 1 and st32[0]["iters"] >= 1
+    assert abs(e32[0] - lam) < 1e-9 * abs(lam)
+
+
+def test_eigensolve_mixed_precision_energy_electron_bond(mods):
+    lib, problems = mods
+    spec = synth.c4_bond(m=40, k=10, seed=6)
     plan, ops, d = setup([spec], lib, problems)
     lam, _, ost, _ = oracle_davidson(spec, 64, tol=1e-10)
     assert ost["converged"]
