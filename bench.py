@@ -95,7 +95,7 @@ def batch_bench(args):
     setup_s = time.perf_counter() - t0
     stream = torch.cuda.Stream()
     out = {"problems": len(specs), "useful_gflop_per_batched_product": round(flops / 1e9, 3),
-           "setup_s": round(setup_s, 1)}
+           "setup_s": round(setup_s, 1), "tiles": autotune(plan, info, dev, stream)}
     for path in ("f64", "mixed"):
         if path == "mixed":
             o = lib.eig_opts(max_iter=args.n_f32, precision=lib.F32_REFINE, refine_max_iter=args.n_f64,
@@ -181,6 +181,19 @@ def j1j2_bench(args):
             "one_sweep_from_converged": sweep, "data": "synthetic (seeded random initial MPS)"}
 
 
+def autotune(plan, info, dev, stream):
+    """Tile shape classes of the S1/S3 launches chosen by the library's
+    autotuner (timed in FP32, the precision of most products)."""
+    import torch
+    from paper_2007_05540_amd import lib
+    ws = torch.empty(info["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(dev["psi"])
+    got = lib.plan_autotune(plan, lib.F32, dev["L"], dev["W1"], dev["W2"], dev["R"], dev["psi"], out, ws,
+                            reps=10, stream=stream)
+    del ws, out
+    return {k: ("64x64 only" if v >= lib.NO_BIG_TILES else f"128x128 for M,N>={v}") for k, v in got.items()}
+
+
 def bond_measure(spec, args):
     """Plan one isolated bond, upload its operands and time the FP64 and the
     mixed fixed-step Davidson solves (graph replay).  Returns the plan, its
@@ -196,7 +209,7 @@ def bond_measure(spec, args):
     del ops
     stream = torch.cuda.Stream()
     psi0 = dev["psi"]
-    results = {}
+    results = {"tiles": autotune(plan, info, dev, stream)}
     for path in ("f64", "mixed"):
         if path == "mixed":
             o = lib.eig_opts(max_iter=args.n_f32, precision=lib.F32_REFINE, refine_max_iter=args.n_f64,
@@ -239,7 +252,7 @@ def hubbard_bond_bench(args):
     out = {"workload": "isolated mid-chain two-site bond, 4x16 Hubbard cylinder, m=4096, k=22, "
                        "313 U(1)xU(1) sectors",
            "useful_gflop_per_product": round(flops / 1e9, 3), "s1_tasks": info["n_s1_tasks"],
-           "s3_tasks": info["n_s3_tasks"]}
+           "s3_tasks": info["n_s3_tasks"], "tiles": res.pop("tiles")}
     for path in ("f64", "mixed"):
         out[path] = {"ms_per_davidson_step": round(res[path]["ms_per_step"], 3),
                      "useful_gflops": round(res[path]["gflops"], 1), "energy": res[path]["energy"]}
@@ -294,7 +307,8 @@ def main():
         "data": "synthetic (seeded Heisenberg-type bond, Hermitian-structured random environments)",
         "config": {"workload": "isolated mid-chain two-site bond, 6x6 Heisenberg cylinder, m=1024, k=14, "
                                "21 U(1) sectors", "davidson_steps": f"{args.n_f32} FP32 + {args.n_f64} FP64",
-                   "useful_gflop_per_product": round(flops / 1e9, 4), "graph": True},
+                   "useful_gflop_per_product": round(flops / 1e9, 4), "graph": True,
+                   "tiles": results["tiles"]},
         "f64_path": {"value": round(f64["gflops"], 3), "ms_per_step": round(f64["ms_per_step"], 4),
                      "energy": f64["energy"], "residual": f64["residual"]},
         "mixed_energy": mixed["energy"], "mixed_residual": mixed["residual"],

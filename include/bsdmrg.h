@@ -119,6 +119,9 @@ typedef struct {
   double flops_s1, flops_s2, flops_s3;  /* per product, all problems       */
   int64_t n_s1_tasks, n_s3_tasks, n_s1_tiles, n_s3_tiles;
   int64_t n_mix_terms, n_coefs;
+  int64_t s1_big_min, s3_big_min;       /* tile shape classes: tasks with M and N >=
+                                           this use 128 x 128 tiles, the others
+                                           64 x 64 (2^30: 64 x 64 only) */
 } bsdmrg_plan_info;
 
 bsdmrg_status bsdmrg_plan_query(bsdmrg_plan_t plan, bsdmrg_plan_info* info);
@@ -341,6 +344,31 @@ bsdmrg_status bsdmrg_stage_timing(bsdmrg_plan_t plan, int32_t precision, const d
                                   const double* psi, double* out, void* workspace,
                                   int64_t workspace_bytes, int32_t reps, float* ms,
                                   hipStream_t stream);
+
+/* Autotuner of the grouped-GEMM tile shapes (batching form of the hot
+ * path: one launch per stage over every block pair of every problem).  For
+ * each of the two GEMM stages S1 and S3 it tries the shape classes
+ * "64 x 64 tiles only" and "128 x 128 tiles for tasks with M and N >= T"
+ * (T = 384, 256, 160, 96), times `reps` launches of each distinct tile
+ * schedule with HIP events on `stream` in the given precision (operands as
+ * for bsdmrg_heff_apply; out receives one product), and keeps the fastest
+ * (a larger tile must win by 2% to replace a smaller one).  The chosen
+ * thresholds are returned in big_min[2] (S1, S3) and in
+ * bsdmrg_plan_info; the plan's captured eigensolver graph is dropped.
+ * Results are unchanged bit for bit by the choice (the K order of every
+ * output element is the same).  Synchronises the stream.  Not thread-safe
+ * with other calls on the same plan.  Errors: EINVAL, EHIP. */
+bsdmrg_status bsdmrg_plan_autotune(bsdmrg_plan_t plan, int32_t precision, const double* L,
+                                   const double* W1, const double* W2, const double* R,
+                                   const double* psi, double* out, void* workspace,
+                                   int64_t workspace_bytes, int32_t reps, int32_t* big_min,
+                                   hipStream_t stream);
+
+/* Install the tile shape classes of the two GEMM stages directly
+ * (big_min as returned by bsdmrg_plan_autotune; 2^30 or more: 64 x 64 tiles
+ * only, at least 1).  Drops the plan's captured graph.  No work using the plan
+ * may be in flight.  Errors: EINVAL, EHIP. */
+bsdmrg_status bsdmrg_plan_set_tiles(bsdmrg_plan_t plan, int32_t s1_big_min, int32_t s3_big_min);
 
 const char* bsdmrg_last_error(void);
 

@@ -154,6 +154,26 @@ static void upload(bsdmrg_plan_s* P) {
   P->on_device = true;
 }
 
+// New tile schedule of one GEMM stage: the table is rebuilt, checked and
+// uploaded to a buffer of its own; a captured graph holds the old table and
+// is dropped.
+static void reschedule_stage(bsdmrg_plan_s* P, Stage& st, int32_t big_min, const char* name) {
+  schedule_tiles(st, big_min);
+  validate_tiles(st, name);
+  destroy_graph(P);
+  const size_t bytes = std::max<size_t>(st.tiles.size() * sizeof(GemmTile), 1);
+  void* d = nullptr;
+  HIPCHK(hipMalloc(&d, bytes));
+  hipError_t e = hipMemcpy(d, st.tiles.data(), st.tiles.size() * sizeof(GemmTile), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    HIPCHK(e);
+  }
+  if (st.d_tiles_own) (void)hipFree(st.d_tiles_own);
+  st.d_tiles_own = d;
+  st.d_tiles = (GemmTile*)d;
+}
+
 static void check_ws(void* ws, int64_t have, size_t need) {
   if (need > 0 && !ws) throw Error{BSDMRG_EINVAL, "workspace pointer is NULL"};
   if ((size_t)have < need)
@@ -407,6 +427,8 @@ bsdmrg_status bsdmrg_plan_query(bsdmrg_plan_t P, bsdmrg_plan_info* info) {
     info->n_s3_tiles = (int64_t)P->s3.tiles.size();
     info->n_mix_terms = (int64_t)P->mix_terms.size();
     info->n_coefs = P->n_coefs;
+    info->s1_big_min = P->s1.big_min;
+    info->s3_big_min = P->s3.big_min;
   });
 }
 
@@ -444,6 +466,8 @@ bsdmrg_status bsdmrg_plan_destroy(bsdmrg_plan_t P) {
     if (!P) return;
     destroy_graph(P);
     destroy_backward(P);
+    if (P->s1.d_tiles_own) (void)hipFree(P->s1.d_tiles_own);
+    if (P->s3.d_tiles_own) (void)hipFree(P->s3.d_tiles_own);
     if (P->d_blob) (void)hipFree(P->d_blob);
     delete P;
   });
@@ -623,6 +647,84 @@ bsdmrg_status bsdmrg_stage_timing(bsdmrg_plan_t P, int32_t precision, const doub
       HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
       ms[stage] = t / reps;
     }
+  });
+  for (auto e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return st;
+}
+
+bsdmrg_status bsdmrg_plan_set_tiles(bsdmrg_plan_t P, int32_t s1_big_min, int32_t s3_big_min) {
+  return guarded([&] {
+    need_device(P);
+    if (s1_big_min < 1 || s3_big_min < 1) throw Error{BSDMRG_EINVAL, "plan_set_tiles: big_min must be >= 1"};
+    reschedule_stage(P, P->s1, std::min(s1_big_min, kNoBigTiles), "S1 tiles");
+    reschedule_stage(P, P->s3, std::min(s3_big_min, kNoBigTiles), "S3 tiles");
+  });
+}
+
+bsdmrg_status bsdmrg_plan_autotune(bsdmrg_plan_t P, int32_t precision, const double* L, const double* W1,
+                                   const double* W2, const double* R, const double* psi, double* out,
+                                   void* workspace, int64_t workspace_bytes, int32_t reps, int32_t* big_min,
+                                   hipStream_t s) {
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bsdmrg_status st = guarded([&] {
+    need_device(P);
+    if (precision != BSDMRG_F64 && precision != BSDMRG_F32)
+      throw Error{BSDMRG_EINVAL, "plan_autotune: precision must be F64 or F32"};
+    if (!L || !W1 || !W2 || !R || !psi || !out || !big_min || reps < 1 || psi == out)
+      throw Error{BSDMRG_EINVAL, "plan_autotune: bad arguments"};
+    check_ws(workspace, workspace_bytes, apply_bytes(P));
+    Carve c(workspace, (size_t)workspace_bytes);
+    ApplyWS w = carve_apply(P, c);
+    HIPCHK(hipEventCreate(&ev[0]));
+    HIPCHK(hipEventCreate(&ev[1]));
+    prepare(P, precision, L, W1, W2, R, w, s);
+    matvec(P, precision, L, R, w, psi, out, s);   // T1 and T2 hold the values the stages see
+    static const int32_t kCand[] = {kNoBigTiles, 384, 256, 160, 96};
+    for (int which = 0; which < 2; ++which) {
+      Stage& sg = which == 0 ? P->s1 : P->s3;
+      const char* name = which == 0 ? "S1 tiles" : "S3 tiles";
+      auto launch = [&] {
+        if (precision == BSDMRG_F64) {
+          if (which == 0) HIPCHK(launch_s1_f64(P, L, psi, w.T1, s));
+          else HIPCHK(launch_s3_gemm_f64(P, w.T2, R, out, w.part, s));
+        } else {
+          if (which == 0) HIPCHK(launch_s1_f32(P, w.L32, psi, (float*)w.T1, s));
+          else HIPCHK(launch_s3_gemm_f32(P, (float*)w.T2, w.R32, out, w.part, s));
+        }
+      };
+      int32_t best = kNoBigTiles;
+      float best_t = 0.f;
+      std::vector<std::vector<GemmTile>> seen;
+      for (int32_t cand : kCand) {
+        Stage probe;
+        probe.tasks = sg.tasks;
+        schedule_tiles(probe, cand);
+        bool dup = false;
+        for (const auto& t : seen)
+          dup = dup || (t.size() == probe.tiles.size() &&
+                        std::memcmp(t.data(), probe.tiles.data(), t.size() * sizeof(GemmTile)) == 0);
+        if (dup) continue;
+        seen.push_back(probe.tiles);
+        reschedule_stage(P, sg, cand, name);
+        launch();   // warm-up
+        HIPCHK(hipEventRecord(ev[0], s));
+        for (int r = 0; r < reps; ++r) launch();
+        HIPCHK(hipEventRecord(ev[1], s));
+        HIPCHK(hipEventSynchronize(ev[1]));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
+        if (seen.size() == 1 || t < 0.98f * best_t) {
+          best = cand;
+          best_t = t;
+        }
+      }
+      reschedule_stage(P, sg, best, name);
+      big_min[which] = best;
+    }
+    // out holds one product again (the S3 timing runs wrote split-K pieces only)
+    matvec(P, precision, L, R, w, psi, out, s);
+    HIPCHK(hipStreamSynchronize(s));
   });
   for (auto e : ev)
     if (e) (void)hipEventDestroy(e);

@@ -63,8 +63,9 @@ struct GemmTask {
   int32_t cbuf, pad;   // cbuf 0: output buffer, 1: split-K partial buffer
 };
 struct GemmTile {
-  int32_t task, m0, n0, pad;
+  int32_t task, m0, n0, shape;   // shape 0: 64 x 64 tile, 1: 128 x 128 tile
 };
+constexpr int32_t kNoBigTiles = 1 << 30;   // big_min of a stage with 64 x 64 tiles only
 
 // MPO mixing: dst rows x cols sub-matrix (row stride ld_dst) = sum over terms
 // coef[c] * src sub-matrix (row stride ld_src).
@@ -134,6 +135,9 @@ struct Stage {
   GemmSeg* d_segs = nullptr;
   GemmTile* d_tiles = nullptr;
   double flops = 0.0;
+  int32_t big_min = kNoBigTiles;   // tasks with M and N >= big_min use 128 x 128 tiles
+  bool big = false;                // the tile table holds 128 x 128 tiles
+  void* d_tiles_own = nullptr;     // device tile table allocated by a re-schedule (else inside the plan blob)
 };
 
 // Forward intermediate blocks kept for the adjoint.

@@ -91,7 +91,8 @@ hipError_t launch_seg_scale(int64_t n, const int64_t* base, int np, const double
                             const double* y, double* out, hipStream_t s);
 
 // XCD-aware tile schedule of a GEMM stage (schedule.cpp)
-void schedule_tiles(Stage& st);
+void schedule_tiles(Stage& st, int32_t big_min = kNoBigTiles);
+void validate_tiles(const Stage& st, const char* name);
 
 // host-side table checks (validate.cpp)
 void validate_gemm(const Stage& st, int layout, int64_t a_elems, int64_t b_elems, int64_t c_elems,

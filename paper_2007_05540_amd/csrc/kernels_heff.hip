@@ -1,7 +1,7 @@
 // Device kernels of the two-site effective-Hamiltonian product (gfx950).
 //
 // ggemm: grouped block GEMM.  One workgroup (4 waves, 2 x 2) computes one
-// 64 x 64 tile of one task; the task's K-list segments are accumulated in the
+// 64 x 64 or 128 x 128 tile of one task; the task's K-list segments are accumulated in the
 // same MFMA accumulators (fixed order, no atomics).  Operands are staged
 // through double-buffered LDS slices (32 deep in k for FP32, 16 for FP64);
 // the next slice is fetched from global memory into registers while the
@@ -20,7 +20,7 @@
 
 namespace bsd {
 
-constexpr int BM = 64, BN = 64, NTHR = 256;
+constexpr int NTHR = 256;
 
 template <typename T>
 struct Mfma;
@@ -41,19 +41,19 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-// LDS slice of one operand (BKT deep in k): K-contiguous operands (A as
-// M x K, B as N x K) are kept [row][k] with a row stride of BKT + 4 (FP32) or
-// BKT + 1 (FP64), M/N-contiguous ones (A as K x M, B as K x N) [k][col] with
-// a row stride of 64 + 16 (FP32) or 64 + 8 (FP64).  With these strides the
+// LDS slice of one operand of a TM x TM tile (BKT deep in k): K-contiguous
+// operands (A as M x K, B as N x K) are kept [row][k] with a row stride of
+// BKT + 4 (FP32) or BKT + 1 (FP64), M/N-contiguous ones (A as K x M, B as
+// K x N) [k][col] with a row stride of TM + 16 (FP32) or TM + 8 (FP64).  With these strides the
 // MFMA operand reads (16 consecutive rows or columns at 4 k) spread evenly
 // over the LDS banks, and so do the global->LDS writes of the M/N-contiguous
 // operands (64 consecutive columns of one k).
-template <typename TC, bool KC>
+template <typename TC, bool KC, int TM>
 struct Slice {
   // k depth of a slice (one barrier per slice): 32 in FP32, 16 in FP64
   static constexpr int BKT = sizeof(TC) == 4 ? 32 : 16;
-  static constexpr int LD = KC ? BKT + (sizeof(TC) == 4 ? 4 : 1) : BM + (sizeof(TC) == 4 ? 16 : 8);
-  static constexpr int SIZE = KC ? BM * LD : BKT * LD;
+  static constexpr int LD = KC ? BKT + (sizeof(TC) == 4 ? 4 : 1) : TM + (sizeof(TC) == 4 ? 16 : 8);
+  static constexpr int SIZE = KC ? TM * LD : BKT * LD;
   // element (row or column r of the tile, k of the slice)
   static __device__ __forceinline__ int at(int r, int k) { return KC ? r * LD + k : k * LD + r; }
 };
@@ -80,30 +80,35 @@ struct Slice {
 // slice of a segment clamps k.  Loads keep their storage type until then, so
 // they stay in flight across the MFMAs of the current slice.  LDS holds two
 // slices (double buffer) and each iteration has one barrier.
-template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT, int NI, int NJ>
+template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT, int TM, int NI, int NJ>
 __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask& task,
                                            const GemmSeg* __restrict__ segs, const TA* __restrict__ A,
                                            const TB* __restrict__ B, TO* __restrict__ C,
-                                           TO* __restrict__ Cpart, TC* As, TC* Bs) {
-  using SA = Slice<TC, !AT>;
-  using SB = Slice<TC, BT>;
+                                           TO* __restrict__ Cpart, TC* As, TC* Bs, int ni_rt, int nj_rt) {
+  using SA = Slice<TC, !AT, TM>;
+  using SB = Slice<TC, BT, TM>;
   constexpr int BKT = SA::BKT;        // k depth of a slice
-  constexpr int EPT = BKT / 4;        // elements of each operand per thread and slice
-  constexpr int RSTEP = 256 / BKT;    // row step of a thread's K-contiguous elements
+  constexpr int EPT = TM * BKT / NTHR;   // elements of each operand per thread and slice
+  constexpr int RSTEP = NTHR / BKT;   // row step of a thread's K-contiguous elements
+  constexpr int KSTEP = NTHR / TM;    // k step of a thread's M/N-contiguous elements
+  constexpr int WQ = TM / 2;          // rows / columns of a wave's quarter of the tile
+  // sub-tiles per wave: NI x NJ fixed, or (NI < 0) up to TM / 32 each, chosen
+  // at run time by wave-uniform branches
+  constexpr int MI = NI >= 0 ? NI : TM / 32, MJ = NJ >= 0 ? NJ : TM / 32;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int l16 = lane & 15, g4 = lane >> 4;
   using V4 = typename Mfma<TC>::v4;
-  V4 acc[NI > 0 ? NI : 1][NJ > 0 ? NJ : 1];
+  V4 acc[MI > 0 ? MI : 1][MJ > 0 ? MJ : 1];
 #pragma unroll
-  for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
+  for (int i = 0; i < (MI > 0 ? MI : 1); ++i)
 #pragma unroll
-    for (int j = 0; j < (NJ > 0 ? NJ : 1); ++j) acc[i][j] = V4{0, 0, 0, 0};
+    for (int j = 0; j < (MJ > 0 ? MJ : 1); ++j) acc[i][j] = V4{0, 0, 0, 0};
 
   // this thread's EPT elements of a slice: (row or column, k) per operand
   const int kc_k = tid % BKT, kc_r = tid / BKT;    // K-contiguous: k, first row (+RSTEP u)
-  const int mc_c = tid & 63, mc_k = tid >> 6;      // M/N-contiguous: column, first k (+4 u)
+  const int mc_c = tid % TM, mc_k = tid / TM;      // M/N-contiguous: column, first k (+KSTEP u)
   // validity of rows / columns (fixed for the tile)
   unsigned a_v = 0, b_v = 0;
   int a_r[EPT], b_r[EPT];                          // clamped rows / columns
@@ -128,8 +133,10 @@ __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask&
     b_seg = (const char*)(B + sg.b_off);
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
-      ao[u] = (AT ? (unsigned)(mc_k + 4 * u) * sg.lda + a_r[u] : (unsigned)a_r[u] * sg.lda + kc_k) * sizeof(TA);
-      bo[u] = (BT ? (unsigned)b_r[u] * sg.ldb + kc_k : (unsigned)(mc_k + 4 * u) * sg.ldb + b_r[u]) * sizeof(TB);
+      ao[u] = (AT ? (unsigned)(mc_k + KSTEP * u) * sg.lda + a_r[u] : (unsigned)a_r[u] * sg.lda + kc_k) *
+              sizeof(TA);
+      bo[u] = (BT ? (unsigned)b_r[u] * sg.ldb + kc_k : (unsigned)(mc_k + KSTEP * u) * sg.ldb + b_r[u]) *
+              sizeof(TB);
     }
   };
   auto load = [&](const GemmSeg& sg, int kk0) {
@@ -149,8 +156,8 @@ __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask&
       va = vb = 0;
 #pragma unroll
       for (int u = 0; u < EPT; ++u) {
-        const int ka = kk0 + (AT ? mc_k + 4 * u : kc_k);
-        const int kb = kk0 + (BT ? kc_k : mc_k + 4 * u);
+        const int ka = kk0 + (AT ? mc_k + KSTEP * u : kc_k);
+        const int kb = kk0 + (BT ? kc_k : mc_k + KSTEP * u);
         la[u] = *(const TA*)(ab + ao[u] + (min(ka, km) - ka) * (AT ? sg.lda : 1) * (int)sizeof(TA));
         lb[u] = *(const TB*)(bb + bo[u] + (min(kb, km) - kb) * (BT ? 1 : sg.ldb) * (int)sizeof(TB));
         va |= (ka < sg.K) ? (a_v & (1u << u)) : 0u;
@@ -165,8 +172,8 @@ __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask&
     for (int u = 0; u < EPT; ++u) {
       const TC x = ((va >> u) & 1) ? (TC)la[u] : (TC)0;
       const TC y = ((vb >> u) & 1) ? (TC)lb[u] : (TC)0;
-      as[AT ? SA::at(mc_c, mc_k + 4 * u) : SA::at(kc_r + RSTEP * u, kc_k)] = x;
-      bs[BT ? SB::at(kc_r + RSTEP * u, kc_k) : SB::at(mc_c, mc_k + 4 * u)] = y;
+      as[AT ? SA::at(mc_c, mc_k + KSTEP * u) : SA::at(kc_r + RSTEP * u, kc_k)] = x;
+      bs[BT ? SB::at(kc_r + RSTEP * u, kc_k) : SB::at(mc_c, mc_k + KSTEP * u)] = y;
     }
   };
   // MFMA k-step q of lane group g (lanes 16 g .. 16 g + 15) takes k = g QN + q
@@ -174,25 +181,29 @@ __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask&
   // and B use the same one): a lane's operands of a whole slice are QN
   // consecutive k, all read from LDS before the slice's MFMAs.
   auto compute = [&](int buf) {
-    if (NI == 0 || NJ == 0) return;
+    if (MI == 0 || MJ == 0) return;
     constexpr int QN = BKT / 4;
     const TC* as = As + buf * SA::SIZE;
     const TC* bs = Bs + buf * SB::SIZE;
-    TC a[NI > 0 ? NI : 1][QN], b[NJ > 0 ? NJ : 1][QN];
+    TC a[MI > 0 ? MI : 1][QN], b[MJ > 0 ? MJ : 1][QN];
 #pragma unroll
-    for (int i = 0; i < NI; ++i)
+    for (int i = 0; i < MI; ++i)
+      if (NI >= 0 || i < ni_rt)
 #pragma unroll
-      for (int q = 0; q < QN; ++q) a[i][q] = as[SA::at(wm * 32 + i * 16 + l16, g4 * QN + q)];
+        for (int q = 0; q < QN; ++q) a[i][q] = as[SA::at(wm * WQ + i * 16 + l16, g4 * QN + q)];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
+    for (int j = 0; j < MJ; ++j)
+      if (NJ >= 0 || j < nj_rt)
 #pragma unroll
-      for (int q = 0; q < QN; ++q) b[j][q] = bs[SB::at(wn * 32 + j * 16 + l16, g4 * QN + q)];
+        for (int q = 0; q < QN; ++q) b[j][q] = bs[SB::at(wn * WQ + j * 16 + l16, g4 * QN + q)];
 #pragma unroll
     for (int q = 0; q < QN; ++q)
 #pragma unroll
-      for (int i = 0; i < NI; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[i][j] = Mfma<TC>::op(a[i][q], b[j][q], acc[i][j]);
+        for (int j = 0; j < MJ; ++j)
+          if ((NI >= 0 || i < ni_rt) && (NJ >= 0 || j < nj_rt))
+            acc[i][j] = Mfma<TC>::op(a[i][q], b[j][q], acc[i][j]);
   };
 
   int seg = task.seg0;
@@ -231,46 +242,62 @@ __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask&
 
   TO* Cp = (task.cbuf ? Cpart : C) + task.c_off;
 #pragma unroll
-  for (int i = 0; i < NI; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
+    for (int j = 0; j < MJ; ++j)
+      if ((NI >= 0 || i < ni_rt) && (NJ >= 0 || j < nj_rt))
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = tile.m0 + wm * 32 + i * 16 + Mfma<TC>::row(lane, r);
-        const int col = tile.n0 + wn * 32 + j * 16 + l16;
-        if (row < task.M && col < task.N) Cp[(int64_t)row * task.ldc + col] = (TO)acc[i][j][r];
-      }
+        for (int r = 0; r < 4; ++r) {
+          const int row = tile.m0 + wm * WQ + i * 16 + Mfma<TC>::row(lane, r);
+          const int col = tile.n0 + wn * WQ + j * 16 + l16;
+          if (row < task.M && col < task.N) Cp[(int64_t)row * task.ldc + col] = (TO)acc[i][j][r];
+        }
 }
 
-// Grouped block GEMM: one workgroup per 64 x 64 tile of one task, the task's
-// K-list segments accumulated in the same MFMA accumulators (fixed order).
-template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT = false>
+// Grouped block GEMM: one workgroup per tile of one task, the task's K-list
+// segments accumulated in the same MFMA accumulators (fixed order).  A tile
+// is 64 x 64 (shape 0, each wave a 32 x 32 quarter) or, in launches built
+// with BIG, 128 x 128 (shape 1, each wave a 64 x 64 quarter: half the LDS
+// and global traffic per flop, for large blocks).
+template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT, bool BIG>
 __global__ __launch_bounds__(NTHR) void ggemm_kernel(const GemmTile* __restrict__ tiles,
                                                      const GemmTask* __restrict__ tasks,
                                                      const GemmSeg* __restrict__ segs,
                                                      const TA* __restrict__ A,
                                                      const TB* __restrict__ B,
                                                      TO* __restrict__ C, TO* __restrict__ Cpart) {
-  __shared__ TC As[2 * Slice<TC, !AT>::SIZE];
-  __shared__ TC Bs[2 * Slice<TC, BT>::SIZE];
+  constexpr int TMX = BIG ? 128 : 64;
+  __shared__ TC As[2 * Slice<TC, !AT, TMX>::SIZE];
+  __shared__ TC Bs[2 * Slice<TC, BT, TMX>::SIZE];
   const GemmTile tile = tiles[blockIdx.x];
   if (tile.task < 0) return;   // padding of the per-XCD schedule
   const GemmTask task = tasks[tile.task];
   const int wave = threadIdx.x >> 6;
+  if (BIG && tile.shape == 1) {
+    // valid 16 x 16 sub-tiles of this wave's 64 x 64 quarter (wave-uniform)
+    const int r0 = tile.m0 + (wave >> 1) * 64, c0 = tile.n0 + (wave & 1) * 64;
+    const int ni = min(4, max(0, (task.M - r0 + 15) / 16));
+    const int nj = min(4, max(0, (task.N - c0 + 15) / 16));
+    if (ni == 4 && nj == 4)
+      ggemm_wave<TC, TA, TB, TO, BT, AT, 128, 4, 4>(tile, task, segs, A, B, C, Cpart, As, Bs, 4, 4);
+    else
+      ggemm_wave<TC, TA, TB, TO, BT, AT, 128, -1, -1>(tile, task, segs, A, B, C, Cpart, As, Bs, ni, nj);
+    return;
+  }
   // valid 16 x 16 sub-tiles of this wave's 32 x 32 quarter (wave-uniform)
   const int r0 = tile.m0 + (wave >> 1) * 32, c0 = tile.n0 + (wave & 1) * 32;
   const int ni = r0 >= task.M ? 0 : (r0 + 16 < task.M ? 2 : 1);
   const int nj = c0 >= task.N ? 0 : (c0 + 16 < task.N ? 2 : 1);
   if (ni == 2 && nj == 2)
-    ggemm_wave<TC, TA, TB, TO, BT, AT, 2, 2>(tile, task, segs, A, B, C, Cpart, As, Bs);
+    ggemm_wave<TC, TA, TB, TO, BT, AT, 64, 2, 2>(tile, task, segs, A, B, C, Cpart, As, Bs, 2, 2);
   else if (ni == 2 && nj == 1)
-    ggemm_wave<TC, TA, TB, TO, BT, AT, 2, 1>(tile, task, segs, A, B, C, Cpart, As, Bs);
+    ggemm_wave<TC, TA, TB, TO, BT, AT, 64, 2, 1>(tile, task, segs, A, B, C, Cpart, As, Bs, 2, 1);
   else if (ni == 1 && nj == 2)
-    ggemm_wave<TC, TA, TB, TO, BT, AT, 1, 2>(tile, task, segs, A, B, C, Cpart, As, Bs);
+    ggemm_wave<TC, TA, TB, TO, BT, AT, 64, 1, 2>(tile, task, segs, A, B, C, Cpart, As, Bs, 1, 2);
   else if (ni == 1 && nj == 1)
-    ggemm_wave<TC, TA, TB, TO, BT, AT, 1, 1>(tile, task, segs, A, B, C, Cpart, As, Bs);
+    ggemm_wave<TC, TA, TB, TO, BT, AT, 64, 1, 1>(tile, task, segs, A, B, C, Cpart, As, Bs, 1, 1);
   else
-    ggemm_wave<TC, TA, TB, TO, BT, AT, 0, 0>(tile, task, segs, A, B, C, Cpart, As, Bs);
+    ggemm_wave<TC, TA, TB, TO, BT, AT, 64, 0, 0>(tile, task, segs, A, B, C, Cpart, As, Bs, 0, 0);
 }
 
 // MPO mixing (S2): each workgroup handles one row range of one task; every
@@ -350,8 +377,12 @@ __global__ void cast_f64_f32_kernel(int64_t n, const double* __restrict__ x, flo
 template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT = false>
 static hipError_t launch_gemm(const Stage& st, const TA* A, const TB* B, TO* C, TO* Cpart, hipStream_t s) {
   if (st.tiles.empty()) return hipSuccess;
-  hipLaunchKernelGGL((ggemm_kernel<TC, TA, TB, TO, BT, AT>), dim3((unsigned)st.tiles.size()), dim3(NTHR), 0,
-                     s, st.d_tiles, st.d_tasks, st.d_segs, A, B, C, Cpart);
+  if (st.big)
+    hipLaunchKernelGGL((ggemm_kernel<TC, TA, TB, TO, BT, AT, true>), dim3((unsigned)st.tiles.size()), dim3(NTHR),
+                       0, s, st.d_tiles, st.d_tasks, st.d_segs, A, B, C, Cpart);
+  else
+    hipLaunchKernelGGL((ggemm_kernel<TC, TA, TB, TO, BT, AT, false>), dim3((unsigned)st.tiles.size()),
+                       dim3(NTHR), 0, s, st.d_tiles, st.d_tasks, st.d_segs, A, B, C, Cpart);
   return hipGetLastError();
 }
 

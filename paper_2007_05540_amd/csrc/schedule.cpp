@@ -10,7 +10,8 @@
 // row-panel chunks first.  Each XCD runs its chunks longest-K first, tiles of
 // a chunk in row-panel order.  The per-XCD lists are interleaved into the
 // launch order; shorter lists are padded with empty tiles (task = -1) that
-// exit at once.
+// exit at once.  Tasks with M and N >= big_min are cut into 128 x 128 tiles,
+// the others into 64 x 64 tiles.
 #include <algorithm>
 #include <numeric>
 
@@ -20,7 +21,7 @@
 namespace bsd {
 
 namespace {
-constexpr int kXcd = 8, kTile = 64;
+constexpr int kXcd = 8;
 
 struct Unit {
   int task, m_begin, m_end;   // row panels [m_begin, m_end) of the task (in tiles)
@@ -28,20 +29,25 @@ struct Unit {
 };
 }  // namespace
 
-void schedule_tiles(Stage& st) {
+void schedule_tiles(Stage& st, int32_t big_min) {
   st.tiles.clear();
+  st.big_min = big_min;
+  st.big = false;
+  auto tsz = [&](const GemmTask& k) { return (k.M >= big_min && k.N >= big_min) ? 128 : 64; };
   std::vector<Unit> units;
   double total = 0.0;
   for (size_t t = 0; t < st.tasks.size(); ++t) {
     const GemmTask& k = st.tasks[t];
-    const int mt = std::max(1, (k.M + kTile - 1) / kTile), nt = std::max(1, (k.N + kTile - 1) / kTile);
-    total += (double)mt * nt * (k.ksum + 16);
+    const int ts = tsz(k);
+    const int mt = std::max(1, (k.M + ts - 1) / ts), nt = std::max(1, (k.N + ts - 1) / ts);
+    total += (double)mt * nt * (ts / 64) * (ts / 64) * (k.ksum + 16);
   }
   const double cap = std::max(1.0, total / (4.0 * kXcd));
   for (size_t t = 0; t < st.tasks.size(); ++t) {
     const GemmTask& k = st.tasks[t];
-    const int mt = std::max(1, (k.M + kTile - 1) / kTile), nt = std::max(1, (k.N + kTile - 1) / kTile);
-    const double panel = (double)nt * (k.ksum + 16);
+    const int ts = tsz(k);
+    const int mt = std::max(1, (k.M + ts - 1) / ts), nt = std::max(1, (k.N + ts - 1) / ts);
+    const double panel = (double)nt * (ts / 64) * (ts / 64) * (k.ksum + 16);
     const int per = std::max(1, (int)(cap / panel));
     for (int m = 0; m < mt; m += per) {
       const int e = std::min(mt, m + per);
@@ -69,9 +75,11 @@ void schedule_tiles(Stage& st) {
     for (int u : bins[x]) {
       const Unit& un = units[u];
       const GemmTask& k = st.tasks[un.task];
-      const int nt = std::max(1, (k.N + kTile - 1) / kTile);
+      const int ts = tsz(k);
+      const int nt = std::max(1, (k.N + ts - 1) / ts);
       for (int m = un.m_begin; m < un.m_end; ++m)
-        for (int n = 0; n < nt; ++n) lists[x].push_back(GemmTile{un.task, m * kTile, n * kTile, 0});
+        for (int n = 0; n < nt; ++n) lists[x].push_back(GemmTile{un.task, m * ts, n * ts, ts == 128 ? 1 : 0});
+      if (ts == 128) st.big = true;
     }
     longest = std::max(longest, lists[x].size());
   }

@@ -49,11 +49,16 @@ void validate_gemm(const Stage& st, int layout, int64_t a_elems, int64_t b_elems
       if (ea > (int64_t)0x0FFFFFFF || eb > (int64_t)0x0FFFFFFF) fail(std::string(name) + ": block above 2^28 elements");
     }
   }
+  validate_tiles(st, name);
+}
+
+void validate_tiles(const Stage& st, const char* name) {
   for (const GemmTile& tl : st.tiles) {
     if (tl.task == -1) continue;   // empty tile of the XCD schedule
     if (tl.task < 0 || tl.task >= (int64_t)st.tasks.size()) fail(std::string(name) + ": tile task");
     const GemmTask& k = st.tasks[tl.task];
     if (tl.m0 < 0 || tl.m0 >= k.M || tl.n0 < 0 || tl.n0 >= k.N) fail(std::string(name) + ": tile origin");
+    if (tl.shape != 0 && !(tl.shape == 1 && st.big)) fail(std::string(name) + ": tile shape");
   }
 }
 

@@ -45,7 +45,7 @@ class PlanInfo(ctypes.Structure):
                                                "apply_workspace_bytes", "backward_workspace_bytes")] + \
                [(n, ctypes.c_double) for n in ("flops_s1", "flops_s2", "flops_s3")] + \
                [(n, ctypes.c_int64) for n in ("n_s1_tasks", "n_s3_tasks", "n_s1_tiles", "n_s3_tiles",
-                                               "n_mix_terms", "n_coefs")]
+                                               "n_mix_terms", "n_coefs", "s1_big_min", "s3_big_min")]
 
 
 class EigOpts(ctypes.Structure):
@@ -74,7 +74,8 @@ _lib = None
 
 EXPORTS = ["bsdmrg_layout", "bsdmrg_plan", "bsdmrg_plan_query", "bsdmrg_plan_offsets", "bsdmrg_plan_tasks",
            "bsdmrg_plan_destroy", "bsdmrg_heff_apply", "bsdmrg_eig_workspace", "bsdmrg_eigensolve",
-           "bsdmrg_heff_backward", "bsdmrg_heff_backward_workspace", "bsdmrg_heff_energy", "bsdmrg_stage_timing", "bsdmrg_truncate_workspace", "bsdmrg_truncate",
+           "bsdmrg_heff_backward", "bsdmrg_heff_backward_workspace", "bsdmrg_heff_energy", "bsdmrg_stage_timing",
+           "bsdmrg_plan_autotune", "bsdmrg_plan_set_tiles", "bsdmrg_truncate_workspace", "bsdmrg_truncate",
            "bsdmrg_env_plan", "bsdmrg_merge_plan", "bsdmrg_op_query", "bsdmrg_op_destroy", "bsdmrg_env_update",
            "bsdmrg_env_backward_workspace", "bsdmrg_env_backward",
            "bsdmrg_merge", "bsdmrg_last_error"]
@@ -110,6 +111,8 @@ def load():
     lib.bsdmrg_stage_timing.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, i64, i32,
                                         ctypes.POINTER(ctypes.c_float), vp]
     P = ctypes.POINTER
+    lib.bsdmrg_plan_autotune.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, i64, i32, P(i32), vp]
+    lib.bsdmrg_plan_set_tiles.argtypes = [vp, i32, i32]
     lib.bsdmrg_truncate_workspace.argtypes = [P(Leg), P(i64)]
     lib.bsdmrg_truncate.argtypes = [P(Leg), vp, P(TruncOpts), P(i32), P(i32), P(i64), i32, vp, i64, P(i64), vp,
                                     i64, P(i64), P(dp), i64, P(i64), P(dp), vp, i64, vp]
@@ -292,6 +295,25 @@ def stage_timing(plan, precision, L, W1, W2, R, psi, out, workspace, reps=20, st
                                      _ptr(out), _ptr(workspace), workspace.numel() * workspace.element_size(),
                                      reps, ms, _stream(stream)))
     return dict(zip(("coef", "s1", "s2", "s3", "s3_sum"), list(ms)))
+
+
+NO_BIG_TILES = 1 << 30
+
+
+def plan_autotune(plan, precision, L, W1, W2, R, psi, out, workspace, reps=10, stream=None):
+    """Pick the tile shape classes of the S1 and S3 launches by timing (see
+    bsdmrg_plan_autotune); returns {"s1": big_min, "s3": big_min}."""
+    bm = (ctypes.c_int32 * 2)()
+    check(load().bsdmrg_plan_autotune(plan.handle, precision, _ptr(L), _ptr(W1), _ptr(W2), _ptr(R), _ptr(psi),
+                                      _ptr(out), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                      reps, bm, _stream(stream)))
+    return {"s1": int(bm[0]), "s3": int(bm[1])}
+
+
+def plan_set_tiles(plan, s1_big_min, s3_big_min):
+    """Install tile shape classes (tasks with M and N >= big_min use 128 x 128
+    tiles; NO_BIG_TILES: 64 x 64 tiles only)."""
+    check(load().bsdmrg_plan_set_tiles(plan.handle, int(s1_big_min), int(s3_big_min)))
 
 
 # ------------------------------------------------------------ sweep ops ----

@@ -179,6 +179,49 @@ def test_apply_rejects_bad_arguments(mods):
         lib.heff_apply(plan, 7, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
 
 
+@pytest.mark.parametrize("spec_fn", [lambda: synth.c2_bond(m=512, k=14, seed=31),
+                                     lambda: synth.c4_bond(m=512, k=22, seed=32)])
+def test_tile_shape_classes_bit_identical_and_autotune(mods, spec_fn):
+    """128 x 128 tiles for large tasks (forced with a low threshold, and as
+    chosen by the autotuner) give the same products bit for bit as 64 x 64
+    tiles only, in both precisions; FP64 matches the oracle."""
+    lib, problems = mods
+    spec = spec_fn()
+    plan, ops, d = setup([spec], lib, problems)
+    ws = torch.empty(plan.info()["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+
+    def products():
+        res = {}
+        for prec in (lib.F64, lib.F32):
+            out = torch.zeros_like(d["psi"])
+            lib.heff_apply(plan, prec, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
+            torch.cuda.synchronize()
+            res[prec] = out.cpu().numpy()
+        return res
+    assert plan.info()["s1_big_min"] == lib.NO_BIG_TILES
+    base = products()
+    lib.plan_set_tiles(plan, 64, 64)
+    info = plan.info()
+    assert info["s1_big_min"] == 64 and info["s3_big_min"] == 64
+    forced = products()
+    out = torch.zeros_like(d["psi"])
+    got = lib.plan_autotune(plan, lib.F32, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws, reps=3)
+    assert got["s1"] in (lib.NO_BIG_TILES, 384, 256, 160, 96) and got["s3"] in (lib.NO_BIG_TILES, 384, 256, 160, 96)
+    assert plan.info()["s3_big_min"] == got["s3"]
+    assert np.array_equal(out.cpu().numpy(), base[lib.F32])
+    tuned = products()
+    for prec in (lib.F64, lib.F32):
+        assert np.array_equal(forced[prec], base[prec])
+        assert np.array_equal(tuned[prec], base[prec])
+    assert rel(base[lib.F64], oracle_apply(spec)) < 1e-12
+    # a captured solve after a re-schedule uses the new tables
+    o = lib.eig_opts(max_iter=4, fixed_iters=1, use_graph=1)
+    e1, _, _ = run_eig(lib, plan, d, o)
+    lib.plan_set_tiles(plan, lib.NO_BIG_TILES, lib.NO_BIG_TILES)
+    e2, _, _ = run_eig(lib, plan, d, o)
+    assert e1[0] == e2[0]
+
+
 # ------------------------------------------------------------ eigensolver ---
 def oracle_davidson(spec, n_iter, tol=0.0, seed=0):
     L, W1, W2, R, psi = bond_operands(spec)
