@@ -44,9 +44,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-bond batch measurement")
     ap.add_argument("--no-hubbard", action="store_true", help="skip the m=4096 Hubbard bond measurement")
-    ap.add_argument("--workload", default="bond", choices=["bond", "j1j2-6x6"],
+    ap.add_argument("--workload", default="bond", choices=["bond", "j1j2-6x6", "chain16", "hubbard-4x16"],
                     help="bond: the isolated-bond product bench (default); j1j2-6x6: DMRG sweeps on the "
-                         "6x6 J1-J2 cylinder, dE/dJ2 by the adjoint and by finite differences")
+                         "6x6 J1-J2 cylinder, dE/dJ2 by the adjoint and by finite differences; chain16: "
+                         "sweeps of the 16-site Heisenberg chain; hubbard-4x16: sweeps of the 4x16 Hubbard "
+                         "cylinder at half filling")
     ap.add_argument("--m-max", type=int, default=512)
     return ap.parse_args()
 
@@ -181,6 +183,94 @@ def j1j2_bench(args):
             "one_sweep_from_converged": sweep, "data": "synthetic (seeded random initial MPS)"}
 
 
+def sweeps_bench(args):
+    """Two-site DMRG sweeps, FP64 path against the mixed path (FP32 products,
+    FP64 refinement) from the same seeded initial MPS: seconds per sweep and
+    the energy of every sweep.
+      chain16: 16-site Heisenberg chain, U(1) Sz = 0, m = 64 (4 sweeps),
+               cutoff 1e-10, Davidson tol 1e-12;
+      hubbard-4x16: 4 x 16 Hubbard cylinder (t = 1, U = 8, periodic width 4),
+               half filling N = 64, 2Sz = 0, U(1)xU(1), m growing to --m-max
+               (two sweeps at each of 256, 512, ..., m_max), cutoff 1e-10,
+               Davidson tol 1e-10."""
+    import torch
+    import synth
+    from paper_2007_05540_amd import lib, problems
+    from paper_2007_05540_amd import dmrg as gdmrg
+
+    if args.workload == "chain16":
+        n = 16
+        mpo = synth.heisenberg_mpo(n, synth.chain_bonds(n))
+        target, sched, opts = (0,), [64] * 4, dict(cutoff=1e-10, max_iter=40, tol=1e-12)
+        desc = "16-site Heisenberg chain, U(1) Sz=0, m=64"
+    else:
+        Wd, Lx = 4, 16
+        n = Wd * Lx
+        mpo = synth.hubbard_mpo(n, synth.cylinder_j1_bonds(Wd, Lx), 8.0)
+        target = (n, 0)
+        sched, m = [], 256
+        while m < args.m_max:
+            sched += [m, m]
+            m *= 2
+        sched += [args.m_max, args.m_max]
+        opts = dict(cutoff=1e-10, max_iter=40, tol=1e-10)
+        desc = f"4x16 Hubbard cylinder, t=1, U=8, half filling, U(1)xU(1), m up to {args.m_max}"
+    k = sum(d for _, d in mpo.w_leg())
+    out = {"metric": "two-site DMRG seconds per sweep: FP64 vs mixed (FP32 products + FP64 refinement)",
+           "config": {"workload": desc, "mpo_k": k, "m_schedule": sched, **opts},
+           "data": "synthetic (seeded random initial MPS)"}
+    mps0 = problems.initial_mps(mpo, target, 16, 0)
+    for name, prec in (("f64", lib.F64), ("mixed", lib.F32_REFINE)):
+        def log(sw, e, t):
+            print(f"{name} sweep {sw}: E = {e:.12f} ({t:.2f} s)", file=sys.stderr, flush=True)
+        g = gdmrg.GpuDMRG(mpo, mps0, target, precision=prec, refine_max_iter=10, tol_f32=1e-6)
+        _, swe = g.run(len(sched), sched, on_sweep=log, **opts)
+        out[name] = {"sweep_energies": swe, "sweep_seconds": [round(t, 3) for t in g.sweep_seconds],
+                     "final_m": max(r["m"] for r in g.log[-(n - 1):]),
+                     "davidson_products": sum(r["iters"] + r["iters_f32"] for r in g.log)}
+        del g
+        torch.cuda.empty_cache()
+    ef, em = out["f64"]["sweep_energies"][-1], out["mixed"]["sweep_energies"][-1]
+    out["final_energy_rel_diff"] = abs(em - ef) / abs(ef)
+    out["speedup_mixed_vs_f64_total"] = round(sum(out["f64"]["sweep_seconds"]) / sum(out["mixed"]["sweep_seconds"]), 3)
+    return out
+
+
+def converged_compare(plan, dev, tol=1e-9):
+    """Equal-accuracy comparison on one bond: the FP64 solve and the mixed
+    solve (FP32 products until the residual reaches 1e-5, then FP64
+    refinement from the FP32 Ritz vector) both run to the residual tolerance
+    tol; wall time per solve, products and energies."""
+    import torch
+    from paper_2007_05540_amd import lib
+    stream = torch.cuda.Stream()
+    res = {}
+    for name in ("f64", "mixed"):
+        if name == "mixed":
+            o = lib.eig_opts(max_iter=64, precision=lib.F32_REFINE, refine_max_iter=64, tol=tol, tol_f32=1e-5)
+        else:
+            o = lib.eig_opts(max_iter=64, tol=tol)
+        ws = torch.empty(lib.eig_workspace(plan, o), dtype=torch.uint8, device="cuda")
+        psi = torch.empty_like(dev["psi"])
+        times = []
+        for rep in range(3):
+            with torch.cuda.stream(stream):
+                psi.copy_(dev["psi"])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                e, st = lib.eigensolve(plan, dev["L"], dev["W1"], dev["W2"], dev["R"], psi, o, ws, stream=stream)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+        res[name] = {"ms_per_solve": round(1e3 * min(times[1:]), 3), "energy": e[0],
+                     "products_f64": st[0]["iters"], "products_f32": st[0]["iters_f32"],
+                     "residual": st[0]["residual"], "converged": bool(st[0]["converged"])}
+        del ws, psi
+    res["energy_rel_diff"] = abs(res["mixed"]["energy"] - res["f64"]["energy"]) / abs(res["f64"]["energy"])
+    res["speedup_mixed_vs_f64"] = round(res["f64"]["ms_per_solve"] / res["mixed"]["ms_per_solve"], 3)
+    res["tol"] = tol
+    return res
+
+
 def autotune(plan, info, dev, stream):
     """Tile shape classes of the S1/S3 launches chosen by the library's
     autotuner (timed in FP32, the precision of most products)."""
@@ -273,6 +363,9 @@ def main():
     if args.workload == "j1j2-6x6":
         print(json.dumps(j1j2_bench(args)))
         return
+    if args.workload in ("chain16", "hubbard-4x16"):
+        print(json.dumps(sweeps_bench(args)))
+        return
     import torch
     import synth
     from paper_2007_05540_amd import lib, problems
@@ -298,6 +391,7 @@ def main():
                 "traffic": None, "ms_per_launch": round(s32[dom], 5),
                 "flops_per_launch": dom_flops}
 
+    conv = converged_compare(plan, dev)
     mixed, f64 = results["mixed"], results["f64"]
     line = {
         "metric": "block-sparse H_eff·ψ useful GFLOP/s & s/sweep: FP64 vs mixed+batched at 1e-9 dE",
@@ -314,6 +408,7 @@ def main():
         "mixed_energy": mixed["energy"], "mixed_residual": mixed["residual"],
         "speedup_mixed_vs_f64": round(f64["ms_per_step"] / mixed["ms_per_step"], 3),
         "stage_ms": {k: {s: round(v, 5) for s, v in d.items()} for k, d in stage.items()},
+        "to_tolerance": conv,
         "roofline": roofline,
     }
     del dev, out, wsa

@@ -178,8 +178,12 @@ bsdmrg_status bsdmrg_eig_workspace(bsdmrg_plan_t plan, const bsdmrg_eig_opts* op
 /* Lowest eigenpair of H_eff per problem with the Davidson routine of Alg. 1:
  * no preconditioning; the start vector and every new basis vector are
  * normalised; at step i the (i+1)x(i+1) projected matrix m_ij = (v^A_j)^T v_i
- * is diagonalised (cyclic Jacobi, FP64); x = sum s_j v_j, q = sum s_j v^A_j -
- * lambda x; stop when ||q|| <= tol; q is orthogonalised against the basis
+ * is diagonalised in FP64 (Householder tridiagonalisation, Sturm-count
+ * multisection for the lowest eigenvalue, inverse iteration for its vector);
+ * x = sum s_j v_j, q = sum s_j v^A_j - lambda x; stop when ||q|| <= tol, or
+ * when the basis spans the whole space (its size equals the number of allowed
+ * elements of psi: the Ritz pair is then exact; in a batch the smallest
+ * problem sets this cap); q is orthogonalised against the basis
  * twice (classical Gram-Schmidt applied twice); if ||q|| drops below
  * restart_rtol times its value before orthogonalisation, q is replaced by a
  * seeded Gaussian vector (SplitMix64 + Box-Muller, key from seed, step,

@@ -14,7 +14,9 @@ listing is silent or slightly off (each listed in the design notes):
     iteration limit of the basis would otherwise stall), q is replaced by a
     seeded Gaussian vector restricted to the allowed elements and
     orthogonalised again, at most 3 attempts;
-  * ``max_iter`` is the largest basis size, i.e. the number of products with A.
+  * ``max_iter`` is the largest basis size, i.e. the number of products with A;
+    once the basis spans the whole allowed space (its size equals the number
+    of allowed elements) the Ritz pair is exact and the iteration stops.
 ``lanczos`` (full reorthogonalisation) is the independent Krylov reference:
 without preconditioning the Davidson basis spans the same Krylov space, so the
 Ritz values agree iteration by iteration.
@@ -59,6 +61,7 @@ def davidson(matvec, x0, max_iter, tol=0.0, restart_mask=None, seed=0,
     """
     n = x0.size
     mask = np.ones(n, dtype=bool) if restart_mask is None else restart_mask
+    dim = int(mask.sum())       # a basis of this size spans the whole space
     V = [x0 / np.linalg.norm(x0)]
     VA = [matvec(V[0])]
     M = np.zeros((max_iter, max_iter))
@@ -75,7 +78,7 @@ def davidson(matvec, x0, max_iter, tol=0.0, restart_mask=None, seed=0,
         qn = float(np.linalg.norm(q))
         if record is not None:
             record.append(lam)
-        if qn <= tol or i == max_iter - 1:
+        if qn <= tol or i == max_iter - 1 or i + 1 >= dim:
             break
         before = qn
         q = _mgs2(q, V)

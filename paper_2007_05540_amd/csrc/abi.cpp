@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -285,6 +286,15 @@ void destroy_graph(bsdmrg_plan_s* P) {
 }
 }  // namespace bsd
 
+// A basis as large as the space it lives in makes the Ritz pair exact and
+// leaves no new direction: a phase ends there (the smallest problem of a
+// batch sets the cap for all).
+static int64_t solve_dim(const bsdmrg_plan_s* P) {
+  int64_t dim = INT64_MAX;
+  for (const ProblemPlan& pp : P->probs) dim = std::min(dim, std::max<int64_t>(pp.dim, 1));
+  return dim;
+}
+
 // Enqueue the whole solve.  In tol mode the host reads ||q|| after every
 // Ritz step (needs a sync); in fixed mode nothing is read back here.
 static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double* W1, const double* W2,
@@ -316,9 +326,11 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
     phases.push_back({BSDMRG_F64, o->max_iter, o->tol});
   }
   std::vector<double> hpart(P->chunks.size());
+  const int64_t dim = solve_dim(P);
   int global_it = 0;
   for (size_t ph = 0; ph < phases.size(); ++ph) {
-    const Phase& f = phases[ph];
+    Phase f = phases[ph];
+    f.maxit = (int)std::min<int64_t>(f.maxit, dim);
     if (ph > 0) {
       HIPCHK(dav_dots(P, 1, d.x, 0, d.x, d.part_a, s));
       HIPCHK(dav_normalize(P, d.part_a, d.red, d.x, d.V, s));
@@ -575,10 +587,11 @@ bsdmrg_status bsdmrg_eigensolve(bsdmrg_plan_t P, const double* L, const double* 
         HIPCHK(hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0));
       }
       HIPCHK(hipGraphLaunch(P->graph->exec, s));
+      const int64_t dim = solve_dim(P);
       const int B = o->precision == BSDMRG_F32_REFINE ? o->refine_max_iter : o->max_iter;
       for (int p = 0; p < np; ++p) {
-        it64[p] = B;
-        it32[p] = o->precision == BSDMRG_F32_REFINE ? o->max_iter : 0;
+        it64[p] = (int)std::min<int64_t>(B, dim);
+        it32[p] = o->precision == BSDMRG_F32_REFINE ? (int)std::min<int64_t>(o->max_iter, dim) : 0;
       }
     } else {
       enqueue_solve(P, L, W1, W2, R, psi, o, w, s, it64, it32, res, conv);

@@ -121,10 +121,22 @@ struct BwdDot {
 };
 
 // One-sided Jacobi SVD of one charge matrix: X (m x n, n <= m) is M or M^T.
+// SVD of one charge matrix M (rows x cols); X = M or M^T is m x n, m >= n.
+// Work (elements of the work array): X (m n), AV = [A; VJ] (2n x n, ld 2n:
+// A = R^T in rows 0..n-1, the Jacobi rotations VJ in rows n..n+r-1), Z (m n),
+// aux (4 n + 2: R diagonal, reflector factors, column norms, pivots, rank),
+// sigma (n), order (n).  Block Jacobi: nb (even) blocks of b columns.
 struct SvdTask {
-  int64_t x_off, v_off, sig_off, perm_off;   // in the work array (elements)
+  int64_t x_off, av_off, z_off, aux_off, sig_off, perm_off;
   int64_t u_off, s_off, vt_off;              // outputs
   int32_t m, n, rows, transposed;            // rows = rows of M
+  int32_t b, nb, pad0, pad1;
+};
+struct SvdPair {      // one workgroup of a block-Jacobi step: sector, pair slot
+  int32_t sec, slot;
+};
+struct SvdCols {      // one workgroup of the left-vector kernel: sector, first column
+  int32_t sec, col0;
 };
 
 struct Stage {
@@ -160,6 +172,7 @@ struct ProblemPlan {
   int64_t psi_base = 0, L_base = 0, R_base = 0, W1_base = 0, W2_base = 0;
   int64_t t1_base = 0, t2_base = 0, coef_base = 0;
   int64_t t1_elems = 0, t2_elems = 0, n_coefs = 0;
+  int64_t dim = 0;   // allowed (non-padding) elements of psi: the dimension of the eigenproblem
   int32_t chunk0 = 0, nchunk = 0;
 };
 

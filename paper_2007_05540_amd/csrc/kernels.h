@@ -33,8 +33,11 @@ hipError_t launch_cast(int64_t n, const double* x, float* y, hipStream_t s);
 enum { kNN = 0, kNT = 1, kTN = 2 };
 hipError_t launch_copy(const void* d_tasks, int n, const double* src, double* dst, const double* fac,
                        hipStream_t s);
-hipError_t launch_jacobi_svd(const void* d_tasks, int n, double* work, double* U, double* S, double* Vt,
-                             hipStream_t s);
+hipError_t launch_svd_qr(const void* d_tasks, int n, double* work, double* S, hipStream_t s);
+hipError_t launch_svd_bjac(const void* d_pairs, int n_pairs, const void* d_tasks, double* work,
+                           const double* active, double* rot, int step, hipStream_t s);
+hipError_t launch_svd_finish(const void* d_tasks, int n, const void* d_cols, int n_cols, double* work, double* U,
+                             double* S, double* Vt, hipStream_t s);
 hipError_t launch_gauge(const void* d_tasks, int n, const double* U, const double* S, double* sign,
                         double* sgn_s, hipStream_t s);
 hipError_t launch_gemm_f64(const Stage& st, int layout, const double* A, const double* B, double* C,

@@ -75,136 +75,370 @@ hipError_t launch_gauge(const void* d_tasks, int n, const double* U, const doubl
 
 namespace bsd {
 
-// One-sided Jacobi SVD (Hestenes) of one matrix per workgroup.  X (m x n,
-// column-major, n <= m) is orthogonalised column pair by column pair with
-// plane rotations, V accumulates them; then sigma_j = ||x_j||, the left
-// vectors are x_j / sigma_j and the right vectors the columns of V.  Pairs
-// follow the round-robin (circle) order, so the n/2 rotations of a step are
-// independent; each group of 16 lanes takes whole pairs.  The output is written in
-// descending order of sigma in the layout of a LAPACK-style thin SVD of the
-// original matrix M: U (rows x k, column-major, ld rows), S (k), Vt (k x
-// cols, column-major, ld k), k = min(rows, cols); when M was wide, X holds
-// M^T and the roles of the two vector sets swap.
-constexpr int kSvdGroup = 16;   // lanes per column pair
-__global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdTask* __restrict__ tasks, double* __restrict__ work,
-                                                         double* __restrict__ U, double* __restrict__ S,
-                                                         double* __restrict__ Vt) {
-  __shared__ int not_conv;
-  __shared__ double fro[16];
-  const SvdTask t = tasks[blockIdx.x];
-  double* X = work + t.x_off;       // m x n, ld m
-  double* V = work + t.v_off;       // n x n, ld n
-  double* sig = work + t.sig_off;   // n
-  int* perm = (int*)(work + t.perm_off);
-  const int m = t.m, n = t.n;
+// SVD of the charge matrices of a truncation: Householder QR with column
+// pivoting, block one-sided Jacobi (Hestenes) on R^T, back-transformation.
+//
+// X (m x n, column-major, n <= m) is M or M^T.  QR with column pivoting
+// X P = Q R (the column of largest remaining norm first) stops at the
+// numerical rank r: once every remaining column has squared norm <= m eps^2
+// ||X||_F^2 the rest of R is rounding noise and is dropped (a perturbation of
+// the order of the rounding error of any SVD).  Pivoting puts the large
+// columns first, so one-sided Jacobi on A = R^T (n x r) needs a few sweeps
+// where Jacobi on X itself needs many on the graded, rank-deficient matrices
+// a truncation sees.  Jacobi works on AV = [A; VJ] (VJ = I at the start):
+// a rotation of two columns of A is applied to the same columns of VJ, so
+// that A_end = A VJ.  The columns are cut into nb blocks of b; a sweep runs
+// the nb - 1 round-robin steps of block pairs, every pair of a step in its
+// own workgroup with the 2b columns in LDS, where one inner cyclic sweep over
+// all column pairs of the union is done (a pair counts as orthogonal when
+// |a_p . a_q| <= tol ||a_p|| ||a_q||, tol following the rounding of an n-term
+// dot product; columns at the rank threshold are left alone).  Sweeps stop
+// when one makes no rotation.  Then sigma_j = ||a_j||, and with
+// R = VJ S W^T (W = A_end S^-1):  X = (Q VJ) S (P W)^T.  The left vectors
+// Q VJ come from applying the reflectors to the columns of VJ (one wave per
+// column), the right ones from W with the pivots undone.  The output is in
+// descending order of sigma in the layout of a LAPACK-style thin SVD of M:
+// U (rows x k, column-major, ld rows), S (k), Vt (k x cols, column-major,
+// ld k), k = min(rows, cols); singular values past the rank are 0 with zero
+// vectors.  When M was wide, X holds M^T and the two vector sets swap.
+
+// block-wide sum over 1024 threads (every thread gets the result)
+__device__ __forceinline__ double svd_block_sum(double v, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int gl = threadIdx.x % kSvdGroup, grp = threadIdx.x / kSvdGroup, ngrp = blockDim.x / kSvdGroup;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) V[e] = (e % n == e / n) ? 1.0 : 0.0;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   __syncthreads();
-  const int ne = n + (n & 1), half = ne / 2;
-  // a pair counts as orthogonal when |x_p . x_q| <= tol ||x_p|| ||x_q||; the
-  // dot products carry rounding of about m eps, so tol follows m.  Columns
-  // whose norm is below 1e-16 ||X||_F are rounding noise left by earlier
-  // rotations: they are not rotated (their singular values are zero to
-  // working precision), otherwise the noise columns would keep rotating
-  // against each other and the sweeps would never stop.
-  const double tol = fmax(1e-15, 4.0 * m * 2.220446049250313e-16);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += red[w];
+  return s;
+}
+// sum over an aligned group of gs lanes (gs a power of two <= 64)
+__device__ __forceinline__ double svd_group_sum(double v, int gs) {
+  for (int o = gs / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// QR with column pivoting of one matrix per workgroup (1024 threads); writes
+// the rank, AV = [R^T; I] and the reflectors (below the diagonal of X).
+__global__ __launch_bounds__(1024) void svd_qr_kernel(const SvdTask* __restrict__ tasks, double* __restrict__ work,
+                                                     double* __restrict__ S) {
+  __shared__ double red[16];
+  __shared__ int redi[16];
+  const SvdTask t = tasks[blockIdx.x];
+  const int m = t.m, n = t.n, ld = 2 * n;
+  double* X = work + t.x_off;
+  double* AV = work + t.av_off;
+  double* rdiag = work + t.aux_off;
+  double* beta = rdiag + n;
+  double* cnorm = beta + n;
+  int* qperm = (int*)(cnorm + n);
+  double* rank_out = rdiag + 4 * n;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
+  const double eps = 2.220446049250313e-16;
+  int gs = 64;
+  while (gs > 4 && gs * n > nthr) gs >>= 1;
+  const int gl = tid % gs, grp = tid / gs, ngrp = nthr / gs;
+
   double f2 = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += blockDim.x) f2 += X[e] * X[e];
-  for (int o = 32; o > 0; o >>= 1) f2 += __shfl_xor(f2, o, 64);
-  if (lane == 0) fro[wave] = f2;
+  for (int64_t e = tid; e < (int64_t)m * n; e += nthr) f2 += X[e] * X[e];
+  const double fro2 = svd_block_sum(f2, red);
+  if (!isfinite(fro2)) {   // uniform: reported to the caller as non-finite singular values
+    for (int e = tid; e < n; e += nthr) S[t.s_off + e] = fro2 - fro2;
+    if (tid == 0) rank_out[0] = -1.0;   // the later kernels skip this matrix
+    return;
+  }
+  const double thr2 = (double)m * eps * eps * fro2;   // rank threshold (squared norm)
+  for (int j = grp; j < n; j += ngrp) {
+    double c = 0.0;
+    for (int i = gl; i < m; i += gs) c += X[(int64_t)j * m + i] * X[(int64_t)j * m + i];
+    c = svd_group_sum(c, gs);
+    if (gl == 0) {
+      cnorm[j] = c;
+      qperm[j] = j;
+    }
+  }
   __syncthreads();
-  double fro2 = 0.0;
-  for (int w = 0; w < nw; ++w) fro2 += fro[w];
-  const double negl = 1e-32 * fro2;
-  for (int sweep = 0; sweep < 80 && ne > 1; ++sweep) {
-    if (threadIdx.x == 0) not_conv = 0;
+  int r = 0;
+  for (int k = 0; k < n; ++k) {
+    // pivot: largest remaining norm, the lowest column on ties
+    double bv = -1.0;
+    int bi = n;
+    for (int j = k + tid; j < n; j += nthr)
+      if (cnorm[j] > bv) { bv = cnorm[j]; bi = j; }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
     __syncthreads();
-    for (int step = 0; step < ne - 1; ++step) {
-      // one pair per group of 16 lanes (4 pairs per wave in flight): the
-      // per-pair chain of reductions and rotation arithmetic is short
-      for (int k = grp; k < half; k += ngrp) {
-        auto player = [&](int j) { return j == 0 ? 0 : 1 + ((j - 1 + step) % (ne - 1)); };
-        const int a = player(k), b = player(ne - 1 - k);
-        const int p = min(a, b), q = max(a, b);
-        if (q >= n) continue;   // dummy column of an odd n
-        double* xp = X + (int64_t)p * m;
-        double* xq = X + (int64_t)q * m;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int r = gl; r < m; r += kSvdGroup) {
-          const double u = xp[r], v = xq[r];
-          al += u * u;
-          be += v * v;
-          ga += u * v;
-        }
-        for (int o = kSvdGroup / 2; o > 0; o >>= 1) {   // stays inside the group
-          al += __shfl_xor(al, o, 64);
-          be += __shfl_xor(be, o, 64);
-          ga += __shfl_xor(ga, o, 64);
-        }
-        if (ga == 0.0 || al <= negl || be <= negl || fabs(ga) <= tol * sqrt(al * be)) continue;
-        if (gl == 0) not_conv = 1;
-        const double zeta = (be - al) / (2.0 * ga);
-        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
-        for (int r = gl; r < m; r += kSvdGroup) {
-          const double u = xp[r], v = xq[r];
-          xp[r] = c * u - s * v;
-          xq[r] = s * u + c * v;
-        }
-        double* vp = V + (int64_t)p * n;
-        double* vq = V + (int64_t)q * n;
-        for (int r = gl; r < n; r += kSvdGroup) {
-          const double u = vp[r], v = vq[r];
-          vp[r] = c * u - s * v;
-          vq[r] = s * u + c * v;
-        }
+    if (lane == 0) { red[wave] = bv; redi[wave] = bi; }
+    __syncthreads();
+    bv = red[0];
+    bi = redi[0];
+    for (int w = 1; w < nw; ++w)
+      if (red[w] > bv || (red[w] == bv && redi[w] < bi)) { bv = red[w]; bi = redi[w]; }
+    if (!(bv > thr2)) break;   // uniform: every thread computed the same bv
+    const int p = bi;
+    if (p != k) {
+      for (int i = tid; i < m; i += nthr) {
+        const double a = X[(int64_t)k * m + i];
+        X[(int64_t)k * m + i] = X[(int64_t)p * m + i];
+        X[(int64_t)p * m + i] = a;
+      }
+      if (tid == 0) {
+        const double c = cnorm[k]; cnorm[k] = cnorm[p]; cnorm[p] = c;
+        const int q = qperm[k]; qperm[k] = qperm[p]; qperm[p] = q;
       }
       __syncthreads();
     }
-    const int nc = not_conv;
+    // reflector H = I - beta v v^T with H x_k = alpha e_k
+    double part = 0.0;
+    for (int i = k + tid; i < m; i += nthr) part += X[(int64_t)k * m + i] * X[(int64_t)k * m + i];
+    const double nrm2 = svd_block_sum(part, red);
+    const double xkk = X[(int64_t)k * m + k];
+    const double alpha = -copysign(sqrt(nrm2), xkk);
+    const double v0 = xkk - alpha;
+    const double vtv = (nrm2 - xkk * xkk) + v0 * v0;
+    const double bk = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    __syncthreads();   // every thread has read x_kk
+    if (tid == 0) {
+      X[(int64_t)k * m + k] = v0;
+      rdiag[k] = alpha;
+      beta[k] = bk;
+    }
     __syncthreads();
-    if (!nc) break;
+    const double* v = X + (int64_t)k * m;
+    for (int j = k + 1 + grp; j < n; j += ngrp) {
+      double* xj = X + (int64_t)j * m;
+      double d = 0.0;
+      for (int i = k + gl; i < m; i += gs) d += v[i] * xj[i];
+      const double f = bk * svd_group_sum(d, gs);
+      double c = 0.0;
+      for (int i = k + gl; i < m; i += gs) {
+        const double y = xj[i] - f * v[i];
+        xj[i] = y;
+        if (i > k) c += y * y;
+      }
+      c = svd_group_sum(c, gs);
+      if (gl == 0) cnorm[j] = c;
+    }
+    __syncthreads();
+    r = k + 1;
   }
-  // singular values and their descending order (ties: lower index first)
-  for (int j = wave; j < n; j += nw) {
+  // AV: rows 0..n-1 of column i = row i of R; rows n..n+r-1 = identity
+  for (int64_t e = tid; e < (int64_t)ld * r; e += nthr) {
+    const int j = (int)(e % ld), i = (int)(e / ld);
+    double val;
+    if (j < n) val = j < i ? 0.0 : (j == i ? rdiag[i] : X[(int64_t)j * m + i]);
+    else val = (j - n == i) ? 1.0 : 0.0;
+    AV[e] = val;
+  }
+  if (tid == 0) {
+    rank_out[0] = (double)r;
+    rank_out[1] = thr2;
+  }
+}
+
+// One step of a block-Jacobi sweep: one workgroup (1024 threads) per block
+// pair of a matrix, the pair's columns of AV held in LDS for one inner
+// cyclic sweep.  rot[sec] is set to 1 when a rotation was applied; matrices
+// with active[sec] == 0 have converged and are skipped.
+constexpr int kSvdLds = 16384;   // doubles of LDS per workgroup (2 b (n + r) <= 4 b n)
+__global__ __launch_bounds__(1024) void svd_bjac_kernel(const SvdPair* __restrict__ pairs,
+                                                       const SvdTask* __restrict__ tasks, double* __restrict__ work,
+                                                       const double* __restrict__ active, double* __restrict__ rot,
+                                                       int step) {
+  __shared__ double col[kSvdLds];
+  __shared__ int rotated;
+  const SvdPair pr = pairs[blockIdx.x];
+  if (active[pr.sec] == 0.0) return;
+  const SvdTask t = tasks[pr.sec];
+  const int n = t.n, ld = 2 * n, b = t.b, nb = t.nb;
+  if (step >= nb - 1) return;
+  const double rr = work[t.aux_off + 4 * n];
+  if (!(rr >= 2.0)) return;   // rank 0 or 1, or a non-finite matrix: nothing to rotate
+  const int r = (int)rr;
+  const double thr2 = work[t.aux_off + 4 * n + 1];
+  auto player = [&](int j) { return j == 0 ? 0 : 1 + ((j - 1 + step) % (nb - 1)); };
+  const int pa = player(pr.slot), pb = player(nb - 1 - pr.slot);
+  const int I = min(pa, pb), J = max(pa, pb);
+  const int vI = max(0, min(b, r - I * b)), vJ = max(0, min(b, r - J * b));
+  const int nv = vI + vJ;
+  if (nv <= 1) return;
+  const int L = n + r;   // rows of AV in use
+  double* AV = work + t.av_off;
+  auto gcol = [&](int k) { return k < vI ? I * b + k : J * b + (k - vI); };
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  for (int64_t e = tid; e < (int64_t)nv * L; e += nthr) {
+    const int k = (int)(e / L), i = (int)(e % L);
+    col[e] = AV[(int64_t)gcol(k) * ld + i];
+  }
+  if (tid == 0) rotated = 0;
+  __syncthreads();
+  const double eps = 2.220446049250313e-16;
+  const double tol = fmax(1e-15, 4.0 * n * eps);
+  // columns at the rank threshold of the QR (squared norm <= thr2) are
+  // rounding noise left by rotations: not rotated, or noise columns would
+  // keep rotating against each other and the sweeps would not stop
+  const int ne = nv + (nv & 1), hp = ne / 2;
+  int gs = 64;
+  while (gs * hp > nthr) gs >>= 1;
+  const int gl = tid % gs, grp = tid / gs;
+  for (int st = 0; st < ne - 1; ++st) {
+    if (grp < hp) {
+      auto pl = [&](int j) { return j == 0 ? 0 : 1 + ((j - 1 + st) % (ne - 1)); };
+      const int a = pl(grp), c2 = pl(ne - 1 - grp);
+      const int p = min(a, c2), q = max(a, c2);
+      if (q < nv) {
+        double* ap = col + p * L;
+        double* aq = col + q * L;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = gl; i < n; i += gs) {
+          const double u = ap[i], w = aq[i];
+          al += u * u;
+          be += w * w;
+          ga += u * w;
+        }
+        al = svd_group_sum(al, gs);
+        be = svd_group_sum(be, gs);
+        ga = svd_group_sum(ga, gs);
+        if (!(ga == 0.0 || al <= thr2 || be <= thr2 || fabs(ga) <= tol * sqrt(al * be))) {
+          if (gl == 0) rotated = 1;
+          const double zeta = (be - al) / (2.0 * ga);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          for (int i = gl; i < L; i += gs) {
+            const double u = ap[i], w = aq[i];
+            ap[i] = cs * u - sn * w;
+            aq[i] = sn * u + cs * w;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int64_t e = tid; e < (int64_t)nv * L; e += nthr) {
+    const int k = (int)(e / L), i = (int)(e % L);
+    AV[(int64_t)gcol(k) * ld + i] = col[e];
+  }
+  if (tid == 0 && rotated) rot[pr.sec] = 1.0;
+}
+
+// Singular values, their order and the right vectors; one workgroup per matrix.
+__global__ __launch_bounds__(1024) void svd_sort_kernel(const SvdTask* __restrict__ tasks, double* __restrict__ work,
+                                                       double* __restrict__ U, double* __restrict__ S,
+                                                       double* __restrict__ Vt) {
+  const SvdTask t = tasks[blockIdx.x];
+  const int n = t.n, ld = 2 * n;
+  const double* aux = work + t.aux_off;
+  const double rr = aux[4 * n];
+  if (!(rr >= 0.0)) return;   // non-finite matrix: S holds NaN already
+  const int r = (int)rr;
+  const double* AV = work + t.av_off;
+  const int* qperm = (const int*)(aux + 3 * n);   // after R diagonal, reflector factors, column norms
+  double* sig = work + t.sig_off;
+  int* perm = (int*)(work + t.perm_off);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
+  for (int j = wave; j < r; j += nw) {
     double s2 = 0.0;
-    for (int r = lane; r < m; r += 64) s2 += X[(int64_t)j * m + r] * X[(int64_t)j * m + r];
+    for (int i = lane; i < n; i += 64) s2 += AV[(int64_t)j * ld + i] * AV[(int64_t)j * ld + i];
     for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
     if (lane == 0) sig[j] = sqrt(s2);
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+  for (int j = tid; j < r; j += nthr) {
     int rank = 0;
-    for (int i = 0; i < n; ++i) rank += (sig[i] > sig[j]) || (sig[i] == sig[j] && i < j);
+    for (int i = 0; i < r; ++i) rank += (sig[i] > sig[j]) || (sig[i] == sig[j] && i < j);
     perm[rank] = j;
   }
   __syncthreads();
+  for (int e = tid; e < n; e += nthr) S[t.s_off + e] = e < r ? sig[perm[e]] : 0.0;
   double* Uo = U + t.u_off;     // rows x n (ld rows)
   double* Vo = Vt + t.vt_off;   // n x cols (ld n)
-  for (int e = threadIdx.x; e < n; e += blockDim.x) S[t.s_off + e] = sig[perm[e]];
-  // left vectors of X (length m) and right vectors (length n)
-  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
-    const int r = e % m, jj = e / m;
-    const int j = perm[jj];
-    const double sj = sig[j];
-    const double xv = sj > 0.0 ? X[(int64_t)j * m + r] / sj : 0.0;
-    if (!t.transposed) Uo[(int64_t)jj * t.rows + r] = xv;       // U(r, jj), rows = m
-    else Vo[jj + (int64_t)r * n] = xv;                          // Vt(jj, r), cols = m
-  }
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int r = e % n, jj = e / n;
-    const double vv = V[(int64_t)perm[jj] * n + r];
-    if (!t.transposed) Vo[jj + (int64_t)r * n] = vv;            // Vt(jj, r), cols = n
-    else Uo[(int64_t)jj * t.rows + r] = vv;                     // U(r, jj), rows = n
+  // right vectors of X (length n): row qperm[i] of column jj = A(i, perm[jj]) / sigma
+  for (int64_t e = tid; e < (int64_t)n * n; e += nthr) {
+    const int i = (int)(e % n), jj = (int)(e / n);
+    double vv = 0.0;
+    if (jj < r) {
+      const int j = perm[jj];
+      const double sj = sig[j];
+      vv = sj > 0.0 ? AV[(int64_t)j * ld + i] / sj : 0.0;
+    }
+    const int row = qperm[i];
+    if (!t.transposed) Vo[jj + (int64_t)row * n] = vv;          // Vt(jj, row), cols = n
+    else Uo[(int64_t)jj * t.rows + row] = vv;                   // U(row, jj), rows = n
   }
 }
 
-hipError_t launch_jacobi_svd(const void* d_tasks, int n, double* work, double* U, double* S, double* Vt,
-                             hipStream_t s) {
+// Left vectors of X: column jj of Q [VJ(:, perm(jj)); 0], one wave per
+// column (16 columns per workgroup), reflectors applied last to first.
+__global__ __launch_bounds__(1024) void svd_left_kernel(const SvdCols* __restrict__ cols,
+                                                       const SvdTask* __restrict__ tasks, double* __restrict__ work,
+                                                       double* __restrict__ U, double* __restrict__ Vt) {
+  const SvdCols cb = cols[blockIdx.x];
+  const SvdTask t = tasks[cb.sec];
+  const int m = t.m, n = t.n, ld = 2 * n;
+  const double* aux = work + t.aux_off;
+  const double rr = aux[4 * n];
+  if (!(rr >= 0.0)) return;
+  const int r = (int)rr;
+  const double* X = work + t.x_off;
+  const double* beta = aux + n;
+  const double* AV = work + t.av_off;
+  const int* perm = (const int*)(work + t.perm_off);
+  double* Z = work + t.z_off;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int jj = cb.col0 + wave;
+  if (jj >= n) return;   // wave-uniform; no block barrier below
+  double* Uo = U + t.u_off;
+  double* Vo = Vt + t.vt_off;
+  if (jj >= r) {
+    for (int i = lane; i < m; i += 64) {
+      if (!t.transposed) Uo[(int64_t)jj * t.rows + i] = 0.0;
+      else Vo[jj + (int64_t)i * n] = 0.0;
+    }
+    return;
+  }
+  double* z = Z + (int64_t)jj * m;
+  const int j = perm[jj];
+  for (int i = lane; i < m; i += 64) z[i] = i < r ? AV[(int64_t)j * ld + n + i] : 0.0;
+  for (int k = r - 1; k >= 0; --k) {
+    const double* v = X + (int64_t)k * m;
+    double d = 0.0;
+    for (int i = k + lane; i < m; i += 64) d += v[i] * z[i];
+    for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+    const double f = beta[k] * d;
+    for (int i = k + lane; i < m; i += 64) z[i] -= f * v[i];
+  }
+  for (int i = lane; i < m; i += 64) {
+    if (!t.transposed) Uo[(int64_t)jj * t.rows + i] = z[i];     // U(i, jj), rows = m
+    else Vo[jj + (int64_t)i * n] = z[i];                        // Vt(jj, i), cols = m
+  }
+}
+
+hipError_t launch_svd_qr(const void* d_tasks, int n, double* work, double* S, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3((unsigned)n), dim3(1024), 0, s, (const SvdTask*)d_tasks, work, U, S,
-                     Vt);
+  hipLaunchKernelGGL(svd_qr_kernel, dim3((unsigned)n), dim3(1024), 0, s, (const SvdTask*)d_tasks, work, S);
+  return hipGetLastError();
+}
+hipError_t launch_svd_bjac(const void* d_pairs, int n_pairs, const void* d_tasks, double* work,
+                           const double* active, double* rot, int step, hipStream_t s) {
+  if (n_pairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(svd_bjac_kernel, dim3((unsigned)n_pairs), dim3(1024), 0, s, (const SvdPair*)d_pairs,
+                     (const SvdTask*)d_tasks, work, active, rot, step);
+  return hipGetLastError();
+}
+hipError_t launch_svd_finish(const void* d_tasks, int n, const void* d_cols, int n_cols, double* work, double* U,
+                             double* S, double* Vt, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(svd_sort_kernel, dim3((unsigned)n), dim3(1024), 0, s, (const SvdTask*)d_tasks, work, U, S, Vt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n_cols == 0) return e;
+  hipLaunchKernelGGL(svd_left_kernel, dim3((unsigned)n_cols), dim3(1024), 0, s, (const SvdCols*)d_cols,
+                     (const SvdTask*)d_tasks, work, U, Vt);
   return hipGetLastError();
 }
 

@@ -292,6 +292,7 @@ bsdmrg_plan_s* build_plan(const bsdmrg_problem* probs, int n_probs) {
         const Key& k = p.psi.keys[b];
         P->blk_off.push_back(p.psi.offs[b]);
         P->blk_off.push_back(p.a.d[k[0]] * p.c.d[k[3]]);
+        p.dim += p.a.d[k[0]] * p.c.d[k[3]];
       }
     }
     P->blk_ptr.push_back((int32_t)(P->blk_off.size() / 2));

@@ -28,18 +28,20 @@ struct TSector {
   std::vector<int64_t> r0, c0;
   int64_t rows = 0, cols = 0, kmin = 0;
   int64_t mat, u, s, v;                       // X, U, S, Vt offsets (elements)
-  int64_t jv, jsig, jperm;                    // Jacobi scratch offsets in the work array
+  int64_t jav, jz, jaux, jsig, jperm;         // SVD scratch offsets in the work array
+  int32_t b = 1, nb = 2;                      // block-Jacobi blocks
 };
 
 struct TPlan {
   Leg a, s1, s2, c;
   Layout theta;
   std::vector<TSector> sec;
-  int64_t n_mat = 0, n_u = 0, n_s = 0, n_v = 0, n_work = 0;
+  int64_t n_mat = 0, n_u = 0, n_s = 0, n_v = 0, n_work = 0, n_pairs = 0, n_cols = 0;
   size_t bytes = 0;
 };
 
 static size_t al(size_t b) { return (b + 255) / 256 * 256; }
+constexpr int kSvdMaxSweeps = 60;   // block-Jacobi sweeps (a converged matrix stops earlier)
 
 static TPlan make_tplan(const bsdmrg_leg* legs) {
   TPlan T;
@@ -68,11 +70,23 @@ static TPlan make_tplan(const bsdmrg_leg* legs) {
     s.u = T.n_u; T.n_u += s.rows * s.kmin;
     s.v = T.n_v; T.n_v += s.kmin * s.cols;
     s.s = T.n_s; T.n_s += s.kmin;
-    // Jacobi work: X (max x min), V (min x min), sigma (min), permutation (min)
+    // SVD work: X (max x min), AV (2 min x min), Z (max x min), aux
+    // (4 min + 2), sigma (min), order (min)
     s.mat = T.n_work; T.n_work += s.rows * s.cols;
-    s.jv = T.n_work; T.n_work += s.kmin * s.kmin;
+    s.jav = T.n_work; T.n_work += 2 * s.kmin * s.kmin;
+    s.jz = T.n_work; T.n_work += s.rows * s.cols;
+    s.jaux = T.n_work; T.n_work += 4 * s.kmin + 2;
     s.jsig = T.n_work; T.n_work += s.kmin;
     s.jperm = T.n_work; T.n_work += s.kmin;
+    // blocks of b columns: a pair of blocks (2b columns of 2 min rows at
+    // most) fills the 16384 doubles of LDS of one workgroup
+    if (s.kmin > 4096) throw Error{BSDMRG_EINVAL, "truncate: a charge sector has more than 4096 columns"};
+    while (s.b < 32 && 4 * (2 * s.b) * s.kmin <= 16384) s.b *= 2;
+    s.nb = (int32_t)((s.kmin + s.b - 1) / s.b);
+    s.nb += s.nb & 1;
+    if (s.nb < 2) s.nb = 2;
+    T.n_pairs += s.nb / 2;
+    T.n_cols += (s.kmin + 15) / 16;
     T.sec.push_back(s);
   }
   T.n_mat = T.n_work;
@@ -80,6 +94,7 @@ static TPlan make_tplan(const bsdmrg_leg* legs) {
   for (auto& s : T.sec) { n_rk += (int64_t)s.rk.size(); n_ck += (int64_t)s.ck.size(); }
   T.bytes = al(T.n_work * 8) + al(T.n_u * 8) + al(T.n_s * 8) + al(T.n_v * 8) + al(T.n_s * 8) * 2 +
             al(T.theta.keys.size() * sizeof(CopyTask) + 1) + al(T.sec.size() * sizeof(SvdTask) + 1) +
+            al(T.n_pairs * sizeof(SvdPair) + 1) + al(T.n_cols * sizeof(SvdCols) + 1) + al(T.sec.size() * 8) * 2 +
             al(T.n_s * sizeof(GaugeTask) + 1) + al((n_rk + n_ck) * sizeof(CopyTask) + 1);
   return T;
 }
@@ -163,6 +178,10 @@ void truncate_run(const bsdmrg_leg* legs, const double* theta, const bsdmrg_trun
   double* sgn_s = (double*)take(T.n_s * 8);
   char* gather_tab = take(T.theta.keys.size() * sizeof(CopyTask) + 1);
   char* svd_tab = take(T.sec.size() * sizeof(SvdTask) + 1);
+  char* pair_tab = take(T.n_pairs * sizeof(SvdPair) + 1);
+  char* cols_tab = take(T.n_cols * sizeof(SvdCols) + 1);
+  double* d_active = (double*)take(T.sec.size() * 8);
+  double* d_rot = (double*)take(T.sec.size() * 8);
   char* gauge_tab = take(T.n_s * sizeof(GaugeTask) + 1);
   char* scatter_tab = p;
 
@@ -189,18 +208,50 @@ void truncate_run(const bsdmrg_leg* legs, const double* theta, const bsdmrg_trun
   HIPCHK(hipMemcpyAsync(gather_tab, gt.data(), gt.size() * sizeof(CopyTask), hipMemcpyHostToDevice, st));
   HIPCHK(launch_copy(gather_tab, (int)gt.size(), theta, work, nullptr, st));
   std::vector<SvdTask> sv;
-  for (const TSector& s : T.sec) {
+  std::vector<SvdPair> pairs;
+  std::vector<SvdCols> colblk;
+  int nb_max = 0;
+  for (size_t si = 0; si < T.sec.size(); ++si) {
+    const TSector& s = T.sec[si];
     const bool tr = s.rows < s.cols;
-    sv.push_back(SvdTask{s.mat, s.jv, s.jsig, s.jperm, s.u, s.s, s.v, (int32_t)std::max(s.rows, s.cols),
-                         (int32_t)s.kmin, (int32_t)s.rows, tr ? 1 : 0});
+    sv.push_back(SvdTask{s.mat, s.jav, s.jz, s.jaux, s.jsig, s.jperm, s.u, s.s, s.v,
+                         (int32_t)std::max(s.rows, s.cols), (int32_t)s.kmin, (int32_t)s.rows, tr ? 1 : 0,
+                         s.b, s.nb, 0, 0});
     const SvdTask& t = sv.back();
-    if (t.x_off + (int64_t)t.m * t.n > T.n_work || t.v_off + (int64_t)t.n * t.n > T.n_work ||
-        t.perm_off + t.n > T.n_work || t.u_off + s.rows * s.kmin > T.n_u || t.vt_off + s.kmin * s.cols > T.n_v ||
-        t.s_off + t.n > T.n_s)
+    const int64_t mn = (int64_t)t.m * t.n, nn = (int64_t)t.n * t.n;
+    if (t.x_off + mn > T.n_work || t.av_off + 2 * nn > T.n_work || t.z_off + mn > T.n_work ||
+        t.aux_off + 4 * t.n + 2 > T.n_work || t.sig_off + t.n > T.n_work || t.perm_off + t.n > T.n_work ||
+        t.u_off + s.rows * s.kmin > T.n_u || t.vt_off + s.kmin * s.cols > T.n_v || t.s_off + t.n > T.n_s ||
+        t.m < t.n || t.n < 1 || (t.transposed ? s.cols : s.rows) != t.m || t.b < 1 || t.nb < 2 || (t.nb & 1) ||
+        (int64_t)t.nb * t.b < t.n || 4 * (int64_t)t.b * t.n > 16384)
       throw Error{BSDMRG_EINVAL, "internal table check failed: truncate SVD"};
+    for (int q = 0; q < t.nb / 2; ++q) pairs.push_back(SvdPair{(int32_t)si, q});
+    for (int c = 0; c < t.n; c += 16) colblk.push_back(SvdCols{(int32_t)si, c});
+    nb_max = std::max(nb_max, (int)t.nb);
   }
+  if ((int64_t)pairs.size() != T.n_pairs || (int64_t)colblk.size() != T.n_cols)
+    throw Error{BSDMRG_EINVAL, "internal table check failed: truncate SVD blocks"};
   HIPCHK(hipMemcpyAsync(svd_tab, sv.data(), sv.size() * sizeof(SvdTask), hipMemcpyHostToDevice, st));
-  HIPCHK(launch_jacobi_svd(svd_tab, (int)sv.size(), work, U, S, V, st));
+  HIPCHK(hipMemcpyAsync(pair_tab, pairs.data(), pairs.size() * sizeof(SvdPair), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(cols_tab, colblk.data(), colblk.size() * sizeof(SvdCols), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_svd_qr(svd_tab, (int)sv.size(), work, S, st));
+  // block-Jacobi sweeps until a sweep rotates nothing (per matrix)
+  std::vector<double> active(T.sec.size(), 1.0), rot(T.sec.size(), 0.0);
+  for (int sweep = 0; sweep < kSvdMaxSweeps; ++sweep) {
+    HIPCHK(hipMemcpyAsync(d_active, active.data(), active.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(dav_fill_zero(d_rot, (int64_t)T.sec.size(), st));
+    for (int step = 0; step < nb_max - 1; ++step)
+      HIPCHK(launch_svd_bjac(pair_tab, (int)pairs.size(), svd_tab, work, d_active, d_rot, step, st));
+    HIPCHK(hipMemcpyAsync(rot.data(), d_rot, rot.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool any = false;
+    for (size_t i = 0; i < active.size(); ++i) {
+      active[i] = (active[i] != 0.0 && rot[i] != 0.0) ? 1.0 : 0.0;
+      any = any || active[i] != 0.0;
+    }
+    if (!any) break;
+  }
+  HIPCHK(launch_svd_finish(svd_tab, (int)sv.size(), cols_tab, (int)colblk.size(), work, U, S, V, st));
   std::vector<double> hS(T.n_s);
   HIPCHK(hipMemcpyAsync(hS.data(), S, T.n_s * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));

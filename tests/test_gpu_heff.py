@@ -298,6 +298,26 @@ def test_eigensolve_mixed_precision_energy_electron_bond(mods):
     assert abs(e32[0] - lam) < 1e-9 * abs(lam)
 
 
+def test_eigensolve_stops_when_basis_spans_the_space(mods):
+    """dim(psi) < max_iter and a tolerance the FP32 phase cannot reach: both
+    paths stop once the basis spans the space (no restart failure) and give
+    the dense lowest eigenvalue."""
+    lib, problems = mods
+    spec = synth.c2_bond(m=4, k=5, seed=8)
+    plan, ops, d = setup([spec], lib, problems)
+    mask = mask_of([spec.a_leg, spec.s_leg, spec.s_leg, spec.c_leg], PSI_SIGNS)
+    dim = int(mask.sum())
+    assert dim < 64
+    lam, _, ost, _ = oracle_davidson(spec, 64, tol=-1.0)
+    assert ost["iters"] == dim
+    for o in (lib.eig_opts(max_iter=64, tol=1e-14),
+              lib.eig_opts(max_iter=64, precision=lib.F32_REFINE, refine_max_iter=64, tol=1e-14, tol_f32=1e-14)):
+        e, st, _ = run_eig(lib, plan, d, o)
+        assert st[0]["restarts"] == 0
+        assert abs(e[0] - lam) < 1e-11 * abs(lam)
+        assert st[0]["iters"] <= dim and st[0]["iters_f32"] <= dim
+
+
 def test_eigensolve_graph_replay_equals_eager(mods):
     lib, problems = mods
     spec = synth.c2_bond(m=128, k=14, seed=12)

@@ -206,6 +206,21 @@ def test_davidson_breakdown_triggers_seeded_restart():
     assert st["restarts"] >= 1 and abs(lam - 1.0) < 1e-14 and abs(abs(x[0]) - 1) < 1e-14
 
 
+def test_davidson_stops_when_basis_spans_the_space():
+    """A basis as large as the allowed space gives the exact eigenpair: with
+    max_iter above the dimension and an unreachable tolerance the routine
+    stops after dim products, without restarts, at the dense lowest pair."""
+    L, W1, W2, R, psi = small_bond(m=4, k=5)
+    H, mv, mask = _explicit(L, W1, W2, R, psi)
+    dim = H.shape[0]
+    assert dim < 64
+    lam, x, st = davidson(mv, psi.pack(), max_iter=64, tol=-1.0, restart_mask=mask)
+    w, U = np.linalg.eigh(H)
+    assert st["iters"] == dim and st["restarts"] == 0
+    assert abs(lam - w[0]) < 1e-12 * abs(w[0])
+    assert abs(abs(float(x[mask] @ U[:, 0])) - 1.0) < 1e-10
+
+
 # ---------------------------------------------------------- truncation -------
 def _theta(m=40, seed=3):
     leg = synth.spin_bond_leg(m)
