@@ -14,8 +14,10 @@
 // sectors of an output block as a K-list accumulated in registers, so no
 // atomics and a fixed summation order.
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <numeric>
+#include <unordered_map>
 
 #include "bsdmrg_internal.h"
 #include "kernels.h"
@@ -35,8 +37,10 @@ static Charge sub(const Charge& a, const Charge& b) { return {a[0] - b[0], a[1] 
 
 static Key key3(int a, int b, int c) { Key k{}; k[0] = a; k[1] = b; k[2] = c; return k; }
 static Key key4(int a, int b, int c, int d) { Key k{}; k[0] = a; k[1] = b; k[2] = c; k[3] = d; return k; }
-static Key key5(int a, int b, int c, int d, int e) {
-  Key k{}; k[0] = a; k[1] = b; k[2] = c; k[3] = d; k[4] = e; return k;
+// packed (a', f, s1, s2, c) of a T1 block for hashing: sector indices < 2^16,
+// channel sectors and physical sectors < 2^8 (checked by the caller)
+static uint64_t pack5(int a, int b, int c, int d, int e) {
+  return ((uint64_t)a << 40) | ((uint64_t)b << 32) | ((uint64_t)c << 24) | ((uint64_t)d << 16) | (uint64_t)e;
 }
 
 static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
@@ -77,7 +81,11 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
   p.w2_host.assign(in.w2_host, in.w2_host + p.W2.elems());
 
   // ---- S1: one task per (psi block, left channel sector) ---------------
-  std::map<Key, std::pair<int64_t, int>> t1;   // (a', f, s1, s2, c) -> (offset, index)
+  if (p.a.size() >= (1 << 16) || p.c.size() >= (1 << 16) || p.wl.size() >= 256 || p.wm.size() >= 256 ||
+      p.wr.size() >= 256 || p.s1.size() >= 256 || p.s2.size() >= 256)
+    throw Error{BSDMRG_EINVAL, "plan: too many sectors on a leg"};
+  std::unordered_map<uint64_t, std::pair<int64_t, int>> t1;   // (a', f, s1, s2, c) -> (offset, index)
+  t1.reserve(p.psi.keys.size() * p.wl.size() * 2);
   std::vector<int64_t> t1_off;
   int64_t t1_cursor = 0;
   for (size_t pb = 0; pb < p.psi.keys.size(); ++pb) {
@@ -96,7 +104,7 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
       P->s1.segs.push_back(s);
       P->s1.tasks.push_back(t);
       P->s1.flops += 2.0 * M * N * (double)K;
-      t1[key5(iap, f, i1, i2, ic)] = {t1_cursor, (int)t1_off.size()};
+      t1[pack5(iap, f, i1, i2, ic)] = {t1_cursor, (int)t1_off.size()};
       p.t1.push_back(T1Block{iap, f, i1, i2, ic, p.t1_base + t1_cursor});
       t1_off.push_back(t1_cursor);
       t1_cursor += round_up((int64_t)M * N);
@@ -107,21 +115,30 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
   // ---- S2: T2 blocks (a', s1', s2', g, c) and their mixing terms ------------
   struct CoefKey {
     int f, iw, s1p, s1, s2p, s2, g, iwpp;
-    bool operator<(const CoefKey& o) const {
-      return std::tie(f, iw, s1p, s1, s2p, s2, g, iwpp) <
-             std::tie(o.f, o.iw, o.s1p, o.s1, o.s2p, o.s2, o.g, o.iwpp);
+    uint64_t pack() const {   // f, g < 2^8; iw, iwpp < 2^12; physical sectors < 2^8
+      return ((uint64_t)f << 56) | ((uint64_t)iw << 44) | ((uint64_t)s1p << 36) | ((uint64_t)s1 << 28) |
+             ((uint64_t)s2p << 20) | ((uint64_t)s2 << 12) | ((uint64_t)g << 4) ^ ((uint64_t)iwpp * 0x9E3779B97F4A7C15ull);
     }
   };
-  std::map<CoefKey, int> coef_index;
+  struct CoefEntry {
+    CoefKey k;
+    int id;
+  };
+  std::unordered_map<uint64_t, std::vector<CoefEntry>> coef_index;
   auto wstart = [](const Leg& l) {
     std::vector<int64_t> s(l.size() + 1, 0);
     for (int i = 0; i < l.size(); ++i) s[i + 1] = s[i] + l.d[i];
     return s;
   };
   (void)wstart;
+  auto same = [](const CoefKey& a, const CoefKey& b) {
+    return a.f == b.f && a.iw == b.iw && a.s1p == b.s1p && a.s1 == b.s1 && a.s2p == b.s2p && a.s2 == b.s2 &&
+           a.g == b.g && a.iwpp == b.iwpp;
+  };
   auto coef_of = [&](const CoefKey& ck) -> int {
-    auto it = coef_index.find(ck);
-    if (it != coef_index.end()) return it->second;
+    auto& bucket = coef_index[ck.pack()];
+    for (const CoefEntry& ce : bucket)
+      if (same(ce.k, ck)) return ce.id;
     // pairs over the middle channel: W1(f,iw; s1p, s1; m, im) W2(m, im; s2p, s2; g, iwpp)
     std::vector<std::pair<int64_t, int64_t>> pairs;
     for (int m = 0; m < p.wm.size(); ++m) {
@@ -136,13 +153,39 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
           pairs.push_back({p.W1_base + e1, p.W2_base + e2});
       }
     }
-    if (pairs.empty()) return coef_index[ck] = -1;
+    if (pairs.empty()) {
+      bucket.push_back(CoefEntry{ck, -1});
+      return -1;
+    }
     int id = (int)(P->coef_ptr.size() - 1);
     for (auto& pr : pairs) { P->coef_e1.push_back(pr.first); P->coef_e2.push_back(pr.second); }
     P->coef_ptr.push_back((int32_t)P->coef_e1.size());
     p.n_coefs++;
-    return coef_index[ck] = id;
+    bucket.push_back(CoefEntry{ck, id});
+    return id;
   };
+
+  // (f, s1, s2) coupled to (s1', s2', g) through some middle channel sector
+  // with non-zero W_i and W_{i+1} blocks; independent of the bond sectors,
+  // so found once (lexicographic in (f, s1, s2))
+  const int n1 = p.s1.size(), n2 = p.s2.size();
+  std::vector<std::vector<std::array<int, 3>>> wlink((size_t)n1 * n2 * p.wr.size());
+  for (int s1p = 0; s1p < n1; ++s1p)
+    for (int s2p = 0; s2p < n2; ++s2p)
+      for (int g = 0; g < p.wr.size(); ++g) {
+        auto& lst = wlink[((size_t)s1p * n2 + s2p) * p.wr.size() + g];
+        for (int f = 0; f < p.wl.size(); ++f)
+          for (int i1 = 0; i1 < n1; ++i1)
+            for (int i2 = 0; i2 < n2; ++i2)
+              for (int m = 0; m < p.wm.size(); ++m) {
+                int b1 = p.W1.lookup(key4(f, s1p, i1, m));
+                int b2 = p.W2.lookup(key4(m, s2p, i2, g));
+                if (b1 >= 0 && b2 >= 0 && nz1[b1] && nz2[b2]) {
+                  lst.push_back({f, i1, i2});
+                  break;
+                }
+              }
+      }
 
   std::map<Key, std::pair<int64_t, int>> t2;   // (a', s1', s2', g) -> (offset, c)
   int64_t t2_cursor = 0;
@@ -155,18 +198,13 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
           int ic = p.c.find(sub(qout, p.wr.q[g]));
           if (ic < 0) continue;
           // block-level existence: a T1 block and non-zero W blocks connect
-          bool exists = false;
-          for (int f = 0; f < p.wl.size() && !exists; ++f)
-            for (int i1 = 0; i1 < p.s1.size() && !exists; ++i1)
-              for (int i2 = 0; i2 < p.s2.size() && !exists; ++i2) {
-                if (!t1.count(key5(iap, f, i1, i2, ic))) continue;
-                for (int m = 0; m < p.wm.size(); ++m) {
-                  int b1 = p.W1.lookup(key4(f, s1p, i1, m));
-                  int b2 = p.W2.lookup(key4(m, s2p, i2, g));
-                  if (b1 >= 0 && b2 >= 0 && nz1[b1] && nz2[b2]) { exists = true; break; }
-                }
-              }
-          if (!exists) continue;
+          const auto& lst = wlink[((size_t)s1p * n2 + s2p) * p.wr.size() + g];
+          std::vector<std::pair<int, const std::pair<int64_t, int>*>> src;   // (link, T1 block)
+          for (size_t li = 0; li < lst.size(); ++li) {
+            auto it = t1.find(pack5(iap, lst[li][0], lst[li][1], lst[li][2], ic));
+            if (it != t1.end()) src.push_back({(int)li, &it->second});
+          }
+          if (src.empty()) continue;
           const int64_t ba = p.a.d[iap], bc = p.c.d[ic], ng = p.wr.d[g];
           if (bc > kMixItemElems || ba > (1 << 30))
             throw Error{BSDMRG_EINVAL, "plan: sector dimensions above 4096 are not supported"};
@@ -175,19 +213,15 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
           for (int iwpp = 0; iwpp < ng; ++iwpp) {
             MixTask mt{p.t2_base + t2_cursor + iwpp * bc, (int32_t)(ng * bc), (int32_t)ba,
                        (int32_t)bc, (int32_t)P->mix_terms.size(), 0, 0};
-            for (int f = 0; f < p.wl.size(); ++f)
-              for (int i1 = 0; i1 < p.s1.size(); ++i1)
-                for (int i2 = 0; i2 < p.s2.size(); ++i2) {
-                  auto it = t1.find(key5(iap, f, i1, i2, ic));
-                  if (it == t1.end()) continue;
-                  const int64_t nf = p.wl.d[f];
-                  for (int iw = 0; iw < nf; ++iw) {
-                    int cidx = coef_of(CoefKey{f, iw, s1p, i1, s2p, i2, g, iwpp});
-                    if (cidx < 0) continue;
-                    P->mix_terms.push_back(MixTerm{p.t1_base + it->second.first + iw * bc,
-                                                   (int32_t)(nf * bc), cidx});
-                  }
-                }
+            for (const auto& sr : src) {
+              const int f = lst[sr.first][0], i1 = lst[sr.first][1], i2 = lst[sr.first][2];
+              const int64_t nf = p.wl.d[f];
+              for (int iw = 0; iw < nf; ++iw) {
+                int cidx = coef_of(CoefKey{f, iw, s1p, i1, s2p, i2, g, iwpp});
+                if (cidx < 0) continue;
+                P->mix_terms.push_back(MixTerm{p.t1_base + sr.second->first + iw * bc, (int32_t)(nf * bc), cidx});
+              }
+            }
             mt.nterm = (int32_t)P->mix_terms.size() - mt.term0;
             P->flops_s2 += 2.0 * mt.nterm * (double)ba * bc;
             const int task = (int)P->mix_tasks.size();
