@@ -16,6 +16,15 @@ value = useful GFLOP/s = (products per step x useful flops per product) /
 time per step, where useful flops are the block-pair flops of the two GEMM
 stages (the flop definition of the paper's list method).
 
+The JSON line also carries the per-stage times of one product, the roofline
+of the dominant grouped GEMM, the 64-bond batch (one launch per stage for all
+bonds), the m = 4096 Hubbard-type bond (U(1)xU(1), k = 22), sweeps of the
+6x6 J1-J2 cylinder at m = 256 with one sweep per path from the converged
+state (s/sweep of the FP64 and the mixed path at equal accuracy) and the
+oracle's CPU rate (cpu_baseline).  Other workloads: --workload j1j2-6x6
+(adds dE/dJ2 by the adjoint and by finite differences), chain16,
+hubbard-4x16.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
 import argparse
@@ -31,6 +40,11 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"f64": 78.6, "f32": 157.3}      # dense MFMA TFLOP/s, MI355X
 HBM_PEAK = 8000.0                       # GB/s
+# HBM bytes per launch of the FP32 S1 / S3 grouped GEMM on the m=1024, k=14
+# bond, from rocprofv3 FETCH_SIZE and WRITE_SIZE counters of the current
+# kernel (FETCH_SIZE scaled by 1.989 and WRITE_SIZE by 1.000, the ratios of
+# the known size of a plain device copy to what the counters read for it)
+HBM_TRAFFIC = {"s1": 71896388, "s3": 91486877}
 
 
 def parse():
@@ -44,6 +58,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-bond batch measurement")
     ap.add_argument("--no-hubbard", action="store_true", help="skip the m=4096 Hubbard bond measurement")
+    ap.add_argument("--no-sweeps", action="store_true",
+                    help="skip the 6x6 J1-J2 sweeps (FP64 vs mixed s/sweep at equal accuracy)")
     ap.add_argument("--workload", default="bond", choices=["bond", "j1j2-6x6", "chain16", "hubbard-4x16"],
                     help="bond: the isolated-bond product bench (default); j1j2-6x6: DMRG sweeps on the "
                          "6x6 J1-J2 cylinder, dE/dJ2 by the adjoint and by finite differences; chain16: "
@@ -128,7 +144,7 @@ def batch_bench(args):
     return out
 
 
-def j1j2_bench(args):
+def j1j2_bench(args, with_fd=True):
     """Two-site DMRG on the 6x6 J1-J2 Heisenberg cylinder (J2/J1 = 0.5,
     width 6 periodic, length 6 open), U(1) Sz, m up to --m-max, from a seeded
     random MPS; then dE/dJ2 by reverse mode (EnvUpdate x sites -> HeffEnergy ->
@@ -153,10 +169,6 @@ def j1j2_bench(args):
 
     g = gdmrg.GpuDMRG(mpo, problems.initial_mps(mpo, (0,), 16, 5), (0,))
     _, swe = g.run(len(sched), sched, on_sweep=log("dmrg"), **opts)
-    t0 = time.perf_counter()
-    E_bond, grads = g.energy_and_mpo_gradients(0)
-    dE_adj = g.parameter_derivative(grads, dWs)
-    t_adj = time.perf_counter() - t0
     warm = g.host_mps()
     sweep = {}
     for name, prec in (("f64", lib.F64), ("mixed", lib.F32_REFINE)):
@@ -165,6 +177,14 @@ def j1j2_bench(args):
         sweep[name] = {"s_per_sweep": round(gg.sweep_seconds[0], 3), "energy": e[-1]}
     sweep["energy_rel_diff"] = abs(sweep["mixed"]["energy"] - sweep["f64"]["energy"]) / abs(sweep["f64"]["energy"])
     sweep["speedup_mixed_vs_f64"] = round(sweep["f64"]["s_per_sweep"] / sweep["mixed"]["s_per_sweep"], 3)
+    if not with_fd:
+        return {"workload": f"6x6 J1-J2 Heisenberg cylinder, J2/J1=0.5, U(1) Sz, m={m}", "mpo_k": k,
+                "m_schedule": sched, "sweep_energies": swe, "sweep_seconds": [round(t, 3) for t in g.sweep_seconds],
+                "one_sweep_from_converged": sweep}
+    t0 = time.perf_counter()
+    E_bond, grads = g.energy_and_mpo_gradients(0)
+    dE_adj = g.parameter_derivative(grads, dWs)
+    t_adj = time.perf_counter() - t0
     ef = {}
     for sgn in (1, -1):
         mp, _ = synth.heisenberg_j2_derivative(n, j1, j2, J2 + sgn * h)
@@ -234,41 +254,6 @@ def sweeps_bench(args):
     out["final_energy_rel_diff"] = abs(em - ef) / abs(ef)
     out["speedup_mixed_vs_f64_total"] = round(sum(out["f64"]["sweep_seconds"]) / sum(out["mixed"]["sweep_seconds"]), 3)
     return out
-
-
-def converged_compare(plan, dev, tol=1e-9):
-    """Equal-accuracy comparison on one bond: the FP64 solve and the mixed
-    solve (FP32 products until the residual reaches 1e-5, then FP64
-    refinement from the FP32 Ritz vector) both run to the residual tolerance
-    tol; wall time per solve, products and energies."""
-    import torch
-    from paper_2007_05540_amd import lib
-    stream = torch.cuda.Stream()
-    res = {}
-    for name in ("f64", "mixed"):
-        if name == "mixed":
-            o = lib.eig_opts(max_iter=64, precision=lib.F32_REFINE, refine_max_iter=64, tol=tol, tol_f32=1e-5)
-        else:
-            o = lib.eig_opts(max_iter=64, tol=tol)
-        ws = torch.empty(lib.eig_workspace(plan, o), dtype=torch.uint8, device="cuda")
-        psi = torch.empty_like(dev["psi"])
-        times = []
-        for rep in range(3):
-            with torch.cuda.stream(stream):
-                psi.copy_(dev["psi"])
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                e, st = lib.eigensolve(plan, dev["L"], dev["W1"], dev["W2"], dev["R"], psi, o, ws, stream=stream)
-                torch.cuda.synchronize()
-                times.append(time.perf_counter() - t0)
-        res[name] = {"ms_per_solve": round(1e3 * min(times[1:]), 3), "energy": e[0],
-                     "products_f64": st[0]["iters"], "products_f32": st[0]["iters_f32"],
-                     "residual": st[0]["residual"], "converged": bool(st[0]["converged"])}
-        del ws, psi
-    res["energy_rel_diff"] = abs(res["mixed"]["energy"] - res["f64"]["energy"]) / abs(res["f64"]["energy"])
-    res["speedup_mixed_vs_f64"] = round(res["f64"]["ms_per_solve"] / res["mixed"]["ms_per_solve"], 3)
-    res["tol"] = tol
-    return res
 
 
 def autotune(plan, info, dev, stream):
@@ -388,10 +373,9 @@ def main():
     achieved = dom_flops / (s32[dom] * 1e-3) / 1e12
     roofline = {"bound": "mfma", "kernel": f"ggemm {dom.upper()} FP32", "achieved": round(achieved, 3),
                 "peak": PEAK["f32"], "unit": "TFLOP/s", "frac": round(achieved / PEAK["f32"], 4),
-                "traffic": None, "ms_per_launch": round(s32[dom], 5),
-                "flops_per_launch": dom_flops}
+                "traffic": HBM_TRAFFIC[dom], "traffic_unit": "bytes per launch",
+                "ms_per_launch": round(s32[dom], 5), "flops_per_launch": dom_flops}
 
-    conv = converged_compare(plan, dev)
     mixed, f64 = results["mixed"], results["f64"]
     line = {
         "metric": "block-sparse H_eff·ψ useful GFLOP/s & s/sweep: FP64 vs mixed+batched at 1e-9 dE",
@@ -408,7 +392,6 @@ def main():
         "mixed_energy": mixed["energy"], "mixed_residual": mixed["residual"],
         "speedup_mixed_vs_f64": round(f64["ms_per_step"] / mixed["ms_per_step"], 3),
         "stage_ms": {k: {s: round(v, 5) for s, v in d.items()} for k, d in stage.items()},
-        "to_tolerance": conv,
         "roofline": roofline,
     }
     del dev, out, wsa
@@ -418,6 +401,10 @@ def main():
         line["batch_64_bonds"] = batch_bench(args)
     if not args.no_hubbard:
         line["hubbard_bond_m4096"] = hubbard_bond_bench(args)
+    if not args.no_sweeps:
+        a2 = argparse.Namespace(**vars(args))
+        a2.m_max = 256
+        line["sweeps_j1j2_6x6"] = j1j2_bench(a2, with_fd=False)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, flops, args.cpu_seconds)
     print(json.dumps(line))
