@@ -71,23 +71,43 @@ def parse():
 
 def cpu_baseline(spec, flops, budget_s):
     """The oracle's block-loop product (one NumPy matmul per block pair),
-    timed on the host cores on a bounded number of products."""
+    timed on the host cores on a bounded number of products: with the host
+    BLAS threads on all cores (the reported value) and on one core."""
     from oracle.heff import bond_operands, heff_blocks
+    blas, cores, limit = "unknown", os.cpu_count(), None
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        from threadpoolctl import threadpool_info, threadpool_limits
+        info = threadpool_info()
+        cores = max([i.get("num_threads", 1) for i in info] + [1])
+        blas = ", ".join(sorted({f"{i.get('internal_api', '?')} {i.get('version', '')}".strip() for i in info}))
+        limit = threadpool_limits
     except Exception:
-        cores = os.cpu_count()
+        pass
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except Exception:
+        pass
     L, W1, W2, R, psi = bond_operands(spec)
-    heff_blocks(L, W1, W2, R, psi)          # warm-up
-    n, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        heff_blocks(L, W1, W2, R, psi)
-        n += 1
-    dt = (time.perf_counter() - t0) / n
-    return {"value": round(flops / dt / 1e9, 3), "unit": "useful GFLOP/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{n} FP64 block-loop H_eff products of the m=1024 k=14 bond ({dt:.3f} s each)"}
+
+    def rate(budget):
+        heff_blocks(L, W1, W2, R, psi)          # warm-up
+        n, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget or n == 0:
+            heff_blocks(L, W1, W2, R, psi)
+            n += 1
+        return n, (time.perf_counter() - t0) / n
+    n, dt = rate(budget_s)
+    out = {"value": round(flops / dt / 1e9, 3), "unit": "useful GFLOP/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n} FP64 block-loop H_eff products of the m=1024 k=14 bond ({dt:.3f} s each)",
+           "cpu_model": model, "nproc": os.cpu_count(), "blas": blas}
+    if limit is not None:
+        with limit(limits=1):
+            n1, dt1 = rate(budget_s / 3)
+        out["value_1_core"] = round(flops / dt1 / 1e9, 3)
+        out["sample_1_core"] = f"{n1} products ({dt1:.3f} s each)"
+    return out
 
 
 def batch_bench(args):

@@ -278,12 +278,15 @@ def test_eigensolve_mixed_precision_energy(mods):
     lib, problems = mods
     spec = synth.c2_bond(m=24, k=5, seed=4)
     plan, ops, d = setup([spec], lib, problems)
-    lam, _, ost, _ = oracle_davidson(spec, 64, tol=1e-10)
+    lam, x, ost, _ = oracle_davidson(spec, 64, tol=1e-10)
     assert ost["converged"]
     o = lib.eig_opts(max_iter=64, precision=lib.F32_REFINE, refine_max_iter=64, tol=1e-10, tol_f32=1e-5)
-    e32, st32, _ = run_eig(lib, plan, d, o)
+    e32, st32, psi = run_eig(lib, plan, d, o)
     assert st32[0]["iters_f32"] >= 1 and st32[0]["iters"] >= 1
     assert abs(e32[0] - lam) < 1e-9 * abs(lam)
+    # eigenvector error 1 - |<psi, psi_oracle>| (both normalised): a residual
+    # of 1e-10 bounds it by ~(1e-10 / gap)^2
+    assert 1.0 - abs(float(np.dot(psi.cpu().numpy(), x))) < 1e-12
 
 
 def test_eigensolve_mixed_precision_energy_electron_bond(mods):

@@ -97,6 +97,42 @@ def test_truncation_matches_oracle(mods, direction, max_m):
     assert rel(B.cpu().numpy(), oB.pack()) < 1e-11
 
 
+def _big_theta(seed, low_rank):
+    """theta with charge sectors of up to 250 x 270, so the block Jacobi of
+    the truncation runs many block pairs per step; low_rank builds it as the
+    merge of two random sites over an inner bond of at most 60 states per
+    sector (rank-deficient sectors, as in a sweep)."""
+    from oracle.blocks import block_shape
+    a = [((-2,), 90), ((0,), 160), ((2,), 90)]
+    c = [((-2,), 70), ((0,), 200), ((2,), 70)]
+    s = synth.SPIN_PHYS
+    if not low_rank:
+        legs = [a, s, s, c]
+        return BlockTensor.from_fn(legs, PSI_SIGNS, lambda k: synth.gaussian_block(seed, 9, k, block_shape(legs, k)))
+    b = [((-3,), 20), ((-1,), 60), ((1,), 60), ((3,), 20)]
+    A = BlockTensor.from_fn([a, s, b], MPS_SIGNS, lambda k: synth.gaussian_block(seed, 10, k, block_shape([a, s, b], k)))
+    B = BlockTensor.from_fn([b, s, c], MPS_SIGNS, lambda k: synth.gaussian_block(seed, 11, k, block_shape([b, s, c], k)))
+    return merge(A, B)
+
+
+@pytest.mark.parametrize("low_rank,direction,max_m", [(False, 0, 1 << 40), (False, 1, 300), (True, 0, 1 << 40),
+                                                      (True, 1, 100)])
+def test_truncation_large_sectors_matches_oracle(mods, low_rank, direction, max_m):
+    lib, problems, _ = mods
+    theta = _big_theta(21, low_rank)
+    A, B, leg, sv, disc = lib.truncate(theta.legs, dev(theta.pack()), direction, cutoff=1e-12, max_m=max_m)
+    oA, oB, oleg, osv, odisc = o_truncate(theta, "right" if direction == 0 else "left", cutoff=1e-12, m_max=max_m)
+    assert leg == oleg
+    assert np.allclose(sv, osv, rtol=1e-12, atol=1e-14 * osv[0])
+    # singular values at the rounding level of the SVD (below sqrt(m) eps
+    # ||theta||) are reported as 0, so the discarded weight agrees up to that
+    # level squared
+    norm2 = float(np.sum(theta.pack() ** 2))
+    assert abs(disc - odisc) <= 1e-12 * max(odisc, 1e-300) + 1e-20 * norm2
+    assert rel(A.cpu().numpy(), oA.pack()) < 1e-10
+    assert rel(B.cpu().numpy(), oB.pack()) < 1e-10
+
+
 def test_truncation_rejects_small_workspace(mods):
     lib, problems, _ = mods
     mpo, mps, _ = random_sites()
