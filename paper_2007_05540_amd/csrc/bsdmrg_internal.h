@@ -130,7 +130,7 @@ struct SvdTask {
   int64_t x_off, av_off, z_off, aux_off, sig_off, perm_off;
   int64_t u_off, s_off, vt_off;              // outputs
   int32_t m, n, rows, transposed;            // rows = rows of M
-  int32_t b, nb, pad0, pad1;
+  int32_t b, nb, big_qr, pad1;               // big_qr: QR by the multi-workgroup kernels
 };
 struct SvdPair {      // one workgroup of a block-Jacobi step: sector, pair slot
   int32_t sec, slot;

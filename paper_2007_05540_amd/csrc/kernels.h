@@ -34,6 +34,8 @@ enum { kNN = 0, kNT = 1, kTN = 2 };
 hipError_t launch_copy(const void* d_tasks, int n, const double* src, double* dst, const double* fac,
                        hipStream_t s);
 hipError_t launch_svd_qr(const void* d_tasks, int n, double* work, double* S, hipStream_t s);
+hipError_t launch_svd_qr_big(const void* d_big, int n_big, const void* d_cols, int n_cols, int n_max,
+                             const void* d_tasks, double* work, double* S, hipStream_t s);
 hipError_t launch_svd_bjac(const void* d_pairs, int n_pairs, const void* d_tasks, double* work,
                            const double* active, double* rot, int step, hipStream_t s);
 hipError_t launch_svd_finish(const void* d_tasks, int n, const void* d_cols, int n_cols, double* work, double* U,

@@ -119,126 +119,204 @@ __device__ __forceinline__ double svd_group_sum(double v, int gs) {
   return v;
 }
 
-// QR with column pivoting of one matrix per workgroup (1024 threads); writes
-// the rank, AV = [R^T; I] and the reflectors (below the diagonal of X).
+// Pieces of the QR with column pivoting; every one runs on a workgroup of
+// 1024 threads working on one matrix.  Aux layout: R diagonal (n),
+// reflector factors (n), squared norms of the remaining columns (n), pivots
+// (n ints), then the rank and the rank threshold.
+struct QrView {
+  int m, n;
+  double *X, *AV, *rdiag, *beta, *cnorm, *rank_out;
+  int* qperm;
+  __device__ QrView(const SvdTask& t, double* work)
+      : m(t.m), n(t.n), X(work + t.x_off), AV(work + t.av_off), rdiag(work + t.aux_off), beta(rdiag + t.n),
+        cnorm(rdiag + 2 * t.n), rank_out(rdiag + 4 * t.n), qperm((int*)(rdiag + 3 * t.n)) {}
+};
+
+// ||X||_F^2, the rank threshold, column norms and pivots; false (S = NaN,
+// rank -1) for a matrix with non-finite entries.
+__device__ bool qr_init(const SvdTask& t, const QrView& q, double* S, double* red) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const double eps = 2.220446049250313e-16;
+  double f2 = 0.0;
+  for (int64_t e = tid; e < (int64_t)q.m * q.n; e += nthr) f2 += q.X[e] * q.X[e];
+  const double fro2 = svd_block_sum(f2, red);
+  if (!isfinite(fro2)) {   // uniform: reported to the caller as non-finite singular values
+    for (int e = tid; e < q.n; e += nthr) S[t.s_off + e] = fro2 - fro2;
+    if (tid == 0) q.rank_out[0] = -1.0;   // the later kernels skip this matrix
+    return false;
+  }
+  int gs = 64;
+  while (gs > 4 && gs * q.n > nthr) gs >>= 1;
+  const int gl = tid % gs, grp = tid / gs, ngrp = nthr / gs;
+  for (int j = grp; j < q.n; j += ngrp) {
+    double c = 0.0;
+    for (int i = gl; i < q.m; i += gs) c += q.X[(int64_t)j * q.m + i] * q.X[(int64_t)j * q.m + i];
+    c = svd_group_sum(c, gs);
+    if (gl == 0) {
+      q.cnorm[j] = c;
+      q.qperm[j] = j;
+    }
+  }
+  if (tid == 0) q.rank_out[1] = (double)q.m * eps * eps * fro2;   // rank threshold (squared norm)
+  __syncthreads();
+  return true;
+}
+
+// Step k up to the reflector: pivot (largest remaining norm, the lowest
+// column on ties), swap, H = I - beta v v^T with H x_k = alpha e_k.  false
+// when every remaining column is at the rank threshold.
+__device__ bool qr_head(const QrView& q, int k, double* red, int* redi) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
+  const double thr2 = q.rank_out[1];
+  double bv = -1.0;
+  int bi = q.n;
+  for (int j = k + tid; j < q.n; j += nthr)
+    if (q.cnorm[j] > bv) { bv = q.cnorm[j]; bi = j; }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(bv, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+  }
+  __syncthreads();
+  if (lane == 0) { red[wave] = bv; redi[wave] = bi; }
+  __syncthreads();
+  bv = red[0];
+  bi = redi[0];
+  for (int w = 1; w < nw; ++w)
+    if (red[w] > bv || (red[w] == bv && redi[w] < bi)) { bv = red[w]; bi = redi[w]; }
+  if (!(bv > thr2)) return false;   // uniform: every thread computed the same bv
+  const int p = bi, m = q.m;
+  if (p != k) {
+    for (int i = tid; i < m; i += nthr) {
+      const double a = q.X[(int64_t)k * m + i];
+      q.X[(int64_t)k * m + i] = q.X[(int64_t)p * m + i];
+      q.X[(int64_t)p * m + i] = a;
+    }
+    if (tid == 0) {
+      const double c = q.cnorm[k]; q.cnorm[k] = q.cnorm[p]; q.cnorm[p] = c;
+      const int x = q.qperm[k]; q.qperm[k] = q.qperm[p]; q.qperm[p] = x;
+    }
+    __syncthreads();
+  }
+  double part = 0.0;
+  for (int i = k + tid; i < m; i += nthr) part += q.X[(int64_t)k * m + i] * q.X[(int64_t)k * m + i];
+  const double nrm2 = svd_block_sum(part, red);
+  const double xkk = q.X[(int64_t)k * m + k];
+  const double alpha = -copysign(sqrt(nrm2), xkk);
+  const double v0 = xkk - alpha;
+  const double vtv = (nrm2 - xkk * xkk) + v0 * v0;
+  __syncthreads();   // every thread has read x_kk
+  if (tid == 0) {
+    q.X[(int64_t)k * m + k] = v0;
+    q.rdiag[k] = alpha;
+    q.beta[k] = vtv > 0.0 ? 2.0 / vtv : 0.0;
+  }
+  __syncthreads();
+  return true;
+}
+
+// Reflector k applied to column j (> k) by a group of gs lanes, and the
+// squared norm of the column's remaining part (rows > k).
+__device__ __forceinline__ void qr_apply_col(const QrView& q, int k, int j, int gl, int gs) {
+  const int m = q.m;
+  const double* v = q.X + (int64_t)k * m;
+  double* xj = q.X + (int64_t)j * m;
+  double d = 0.0;
+  for (int i = k + gl; i < m; i += gs) d += v[i] * xj[i];
+  const double f = q.beta[k] * svd_group_sum(d, gs);
+  double c = 0.0;
+  for (int i = k + gl; i < m; i += gs) {
+    const double y = xj[i] - f * v[i];
+    xj[i] = y;
+    if (i > k) c += y * y;
+  }
+  c = svd_group_sum(c, gs);
+  if (gl == 0) q.cnorm[j] = c;
+}
+
+// AV: rows 0..n-1 of column i = row i of R; rows n..n+r-1 = identity.
+__device__ void qr_build_av(const QrView& q, int r) {
+  const int tid = threadIdx.x, nthr = blockDim.x, n = q.n, ld = 2 * q.n;
+  for (int64_t e = tid; e < (int64_t)ld * r; e += nthr) {
+    const int j = (int)(e % ld), i = (int)(e / ld);
+    double val;
+    if (j < n) val = j < i ? 0.0 : (j == i ? q.rdiag[i] : q.X[(int64_t)j * q.m + i]);
+    else val = (j - n == i) ? 1.0 : 0.0;
+    q.AV[e] = val;
+  }
+  if (tid == 0) q.rank_out[0] = (double)r;
+}
+
+// QR of one matrix per workgroup (matrices of the single-workgroup class).
 __global__ __launch_bounds__(1024) void svd_qr_kernel(const SvdTask* __restrict__ tasks, double* __restrict__ work,
                                                      double* __restrict__ S) {
   __shared__ double red[16];
   __shared__ int redi[16];
   const SvdTask t = tasks[blockIdx.x];
-  const int m = t.m, n = t.n, ld = 2 * n;
-  double* X = work + t.x_off;
-  double* AV = work + t.av_off;
-  double* rdiag = work + t.aux_off;
-  double* beta = rdiag + n;
-  double* cnorm = beta + n;
-  int* qperm = (int*)(cnorm + n);
-  double* rank_out = rdiag + 4 * n;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
-  const double eps = 2.220446049250313e-16;
+  if (t.big_qr) return;   // multi-workgroup class
+  const QrView q(t, work);
+  if (!qr_init(t, q, S, red)) return;
   int gs = 64;
-  while (gs > 4 && gs * n > nthr) gs >>= 1;
-  const int gl = tid % gs, grp = tid / gs, ngrp = nthr / gs;
-
-  double f2 = 0.0;
-  for (int64_t e = tid; e < (int64_t)m * n; e += nthr) f2 += X[e] * X[e];
-  const double fro2 = svd_block_sum(f2, red);
-  if (!isfinite(fro2)) {   // uniform: reported to the caller as non-finite singular values
-    for (int e = tid; e < n; e += nthr) S[t.s_off + e] = fro2 - fro2;
-    if (tid == 0) rank_out[0] = -1.0;   // the later kernels skip this matrix
-    return;
-  }
-  const double thr2 = (double)m * eps * eps * fro2;   // rank threshold (squared norm)
-  for (int j = grp; j < n; j += ngrp) {
-    double c = 0.0;
-    for (int i = gl; i < m; i += gs) c += X[(int64_t)j * m + i] * X[(int64_t)j * m + i];
-    c = svd_group_sum(c, gs);
-    if (gl == 0) {
-      cnorm[j] = c;
-      qperm[j] = j;
-    }
-  }
-  __syncthreads();
+  while (gs > 4 && gs * q.n > (int)blockDim.x) gs >>= 1;
+  const int gl = threadIdx.x % gs, grp = threadIdx.x / gs, ngrp = blockDim.x / gs;
   int r = 0;
-  for (int k = 0; k < n; ++k) {
-    // pivot: largest remaining norm, the lowest column on ties
-    double bv = -1.0;
-    int bi = n;
-    for (int j = k + tid; j < n; j += nthr)
-      if (cnorm[j] > bv) { bv = cnorm[j]; bi = j; }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(bv, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-    }
-    __syncthreads();
-    if (lane == 0) { red[wave] = bv; redi[wave] = bi; }
-    __syncthreads();
-    bv = red[0];
-    bi = redi[0];
-    for (int w = 1; w < nw; ++w)
-      if (red[w] > bv || (red[w] == bv && redi[w] < bi)) { bv = red[w]; bi = redi[w]; }
-    if (!(bv > thr2)) break;   // uniform: every thread computed the same bv
-    const int p = bi;
-    if (p != k) {
-      for (int i = tid; i < m; i += nthr) {
-        const double a = X[(int64_t)k * m + i];
-        X[(int64_t)k * m + i] = X[(int64_t)p * m + i];
-        X[(int64_t)p * m + i] = a;
-      }
-      if (tid == 0) {
-        const double c = cnorm[k]; cnorm[k] = cnorm[p]; cnorm[p] = c;
-        const int q = qperm[k]; qperm[k] = qperm[p]; qperm[p] = q;
-      }
-      __syncthreads();
-    }
-    // reflector H = I - beta v v^T with H x_k = alpha e_k
-    double part = 0.0;
-    for (int i = k + tid; i < m; i += nthr) part += X[(int64_t)k * m + i] * X[(int64_t)k * m + i];
-    const double nrm2 = svd_block_sum(part, red);
-    const double xkk = X[(int64_t)k * m + k];
-    const double alpha = -copysign(sqrt(nrm2), xkk);
-    const double v0 = xkk - alpha;
-    const double vtv = (nrm2 - xkk * xkk) + v0 * v0;
-    const double bk = vtv > 0.0 ? 2.0 / vtv : 0.0;
-    __syncthreads();   // every thread has read x_kk
-    if (tid == 0) {
-      X[(int64_t)k * m + k] = v0;
-      rdiag[k] = alpha;
-      beta[k] = bk;
-    }
-    __syncthreads();
-    const double* v = X + (int64_t)k * m;
-    for (int j = k + 1 + grp; j < n; j += ngrp) {
-      double* xj = X + (int64_t)j * m;
-      double d = 0.0;
-      for (int i = k + gl; i < m; i += gs) d += v[i] * xj[i];
-      const double f = bk * svd_group_sum(d, gs);
-      double c = 0.0;
-      for (int i = k + gl; i < m; i += gs) {
-        const double y = xj[i] - f * v[i];
-        xj[i] = y;
-        if (i > k) c += y * y;
-      }
-      c = svd_group_sum(c, gs);
-      if (gl == 0) cnorm[j] = c;
-    }
+  for (int k = 0; k < q.n; ++k) {
+    if (!qr_head(q, k, red, redi)) break;
+    for (int j = k + 1 + grp; j < q.n; j += ngrp) qr_apply_col(q, k, j, gl, gs);
     __syncthreads();
     r = k + 1;
   }
-  // AV: rows 0..n-1 of column i = row i of R; rows n..n+r-1 = identity
-  for (int64_t e = tid; e < (int64_t)ld * r; e += nthr) {
-    const int j = (int)(e % ld), i = (int)(e / ld);
-    double val;
-    if (j < n) val = j < i ? 0.0 : (j == i ? rdiag[i] : X[(int64_t)j * m + i]);
-    else val = (j - n == i) ? 1.0 : 0.0;
-    AV[e] = val;
+  qr_build_av(q, r);
+}
+
+// Multi-workgroup class (large matrices): one launch per phase and step; the
+// rank is -2 while the factorisation runs.
+__global__ __launch_bounds__(1024) void svd_qr_init_kernel(const int32_t* __restrict__ big,
+                                                          const SvdTask* __restrict__ tasks,
+                                                          double* __restrict__ work, double* __restrict__ S) {
+  __shared__ double red[16];
+  const SvdTask t = tasks[big[blockIdx.x]];
+  const QrView q(t, work);
+  if (qr_init(t, q, S, red) && threadIdx.x == 0) q.rank_out[0] = -2.0;
+}
+__global__ __launch_bounds__(1024) void svd_qr_head_kernel(const int32_t* __restrict__ big,
+                                                          const SvdTask* __restrict__ tasks,
+                                                          double* __restrict__ work, int k) {
+  __shared__ double red[16];
+  __shared__ int redi[16];
+  const SvdTask t = tasks[big[blockIdx.x]];
+  const QrView q(t, work);
+  if (q.rank_out[0] != -2.0) return;   // finished (or non-finite)
+  if (k >= q.n) {
+    __syncthreads();
+    if (threadIdx.x == 0) q.rank_out[0] = (double)q.n;
+    return;
   }
-  if (tid == 0) {
-    rank_out[0] = (double)r;
-    rank_out[1] = thr2;
-  }
+  if (!qr_head(q, k, red, redi) && threadIdx.x == 0) q.rank_out[0] = (double)k;
+}
+// grid: (matrix, block of 16 columns); one wave per column
+__global__ __launch_bounds__(1024) void svd_qr_apply_kernel(const SvdCols* __restrict__ cols,
+                                                           const SvdTask* __restrict__ tasks,
+                                                           double* __restrict__ work, int k) {
+  const SvdCols cb = cols[blockIdx.x];
+  const SvdTask t = tasks[cb.sec];
+  const QrView q(t, work);
+  if (q.rank_out[0] != -2.0) return;
+  const int j = cb.col0 + (int)(threadIdx.x >> 6);
+  if (j <= k || j >= q.n) return;   // wave-uniform; no barrier in this kernel
+  qr_apply_col(q, k, j, threadIdx.x & 63, 64);
+}
+__global__ __launch_bounds__(1024) void svd_qr_finish_kernel(const int32_t* __restrict__ big,
+                                                            const SvdTask* __restrict__ tasks,
+                                                            double* __restrict__ work) {
+  const SvdTask t = tasks[big[blockIdx.x]];
+  const QrView q(t, work);
+  const double rr = q.rank_out[0];
+  if (rr == -1.0) return;   // non-finite
+  const int r = rr == -2.0 ? q.n : (int)rr;
+  __syncthreads();   // every thread has read the rank before it is rewritten
+  qr_build_av(q, r);
 }
 
 // One step of a block-Jacobi sweep: one workgroup (1024 threads) per block
@@ -271,8 +349,8 @@ __global__ __launch_bounds__(1024) void svd_bjac_kernel(const SvdPair* __restric
   double* AV = work + t.av_off;
   auto gcol = [&](int k) { return k < vI ? I * b + k : J * b + (k - vI); };
   const int tid = threadIdx.x, nthr = blockDim.x;
-  for (int64_t e = tid; e < (int64_t)nv * L; e += nthr) {
-    const int k = (int)(e / L), i = (int)(e % L);
+  for (int e = tid; e < nv * L; e += nthr) {   // nv * L <= kSvdLds: 32-bit index arithmetic
+    const int k = e / L, i = e - k * L;
     col[e] = AV[(int64_t)gcol(k) * ld + i];
   }
   if (tid == 0) rotated = 0;
@@ -319,8 +397,8 @@ __global__ __launch_bounds__(1024) void svd_bjac_kernel(const SvdPair* __restric
     }
     __syncthreads();
   }
-  for (int64_t e = tid; e < (int64_t)nv * L; e += nthr) {
-    const int k = (int)(e / L), i = (int)(e % L);
+  for (int e = tid; e < nv * L; e += nthr) {
+    const int k = e / L, i = e - k * L;
     AV[(int64_t)gcol(k) * ld + i] = col[e];
   }
   if (tid == 0 && rotated) rot[pr.sec] = 1.0;
@@ -422,6 +500,22 @@ __global__ __launch_bounds__(1024) void svd_left_kernel(const SvdCols* __restric
 hipError_t launch_svd_qr(const void* d_tasks, int n, double* work, double* S, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(svd_qr_kernel, dim3((unsigned)n), dim3(1024), 0, s, (const SvdTask*)d_tasks, work, S);
+  return hipGetLastError();
+}
+hipError_t launch_svd_qr_big(const void* d_big, int n_big, const void* d_cols, int n_cols, int n_max,
+                             const void* d_tasks, double* work, double* S, hipStream_t s) {
+  if (n_big == 0) return hipSuccess;
+  hipLaunchKernelGGL(svd_qr_init_kernel, dim3((unsigned)n_big), dim3(1024), 0, s, (const int32_t*)d_big,
+                     (const SvdTask*)d_tasks, work, S);
+  for (int k = 0; k <= n_max; ++k) {
+    hipLaunchKernelGGL(svd_qr_head_kernel, dim3((unsigned)n_big), dim3(1024), 0, s, (const int32_t*)d_big,
+                       (const SvdTask*)d_tasks, work, k);
+    if (k < n_max)
+      hipLaunchKernelGGL(svd_qr_apply_kernel, dim3((unsigned)n_cols), dim3(1024), 0, s, (const SvdCols*)d_cols,
+                         (const SvdTask*)d_tasks, work, k);
+  }
+  hipLaunchKernelGGL(svd_qr_finish_kernel, dim3((unsigned)n_big), dim3(1024), 0, s, (const int32_t*)d_big,
+                     (const SvdTask*)d_tasks, work);
   return hipGetLastError();
 }
 hipError_t launch_svd_bjac(const void* d_pairs, int n_pairs, const void* d_tasks, double* work,

@@ -36,12 +36,15 @@ struct TPlan {
   Leg a, s1, s2, c;
   Layout theta;
   std::vector<TSector> sec;
-  int64_t n_mat = 0, n_u = 0, n_s = 0, n_v = 0, n_work = 0, n_pairs = 0, n_cols = 0;
+  int64_t n_mat = 0, n_u = 0, n_s = 0, n_v = 0, n_work = 0, n_pairs = 0, n_cols = 0, n_big = 0, n_bigcols = 0;
   size_t bytes = 0;
 };
 
 static size_t al(size_t b) { return (b + 255) / 256 * 256; }
 constexpr int kSvdMaxSweeps = 60;   // block-Jacobi sweeps (a converged matrix stops earlier)
+// Matrices with more columns than this are factorised by the multi-workgroup
+// QR (one launch per step and phase); smaller ones by one workgroup each.
+constexpr int64_t kQrBig = 256;
 
 static TPlan make_tplan(const bsdmrg_leg* legs) {
   TPlan T;
@@ -87,6 +90,10 @@ static TPlan make_tplan(const bsdmrg_leg* legs) {
     if (s.nb < 2) s.nb = 2;
     T.n_pairs += s.nb / 2;
     T.n_cols += (s.kmin + 15) / 16;
+    if (s.kmin > kQrBig) {
+      T.n_big += 1;
+      T.n_bigcols += (s.kmin + 15) / 16;
+    }
     T.sec.push_back(s);
   }
   T.n_mat = T.n_work;
@@ -95,6 +102,7 @@ static TPlan make_tplan(const bsdmrg_leg* legs) {
   T.bytes = al(T.n_work * 8) + al(T.n_u * 8) + al(T.n_s * 8) + al(T.n_v * 8) + al(T.n_s * 8) * 2 +
             al(T.theta.keys.size() * sizeof(CopyTask) + 1) + al(T.sec.size() * sizeof(SvdTask) + 1) +
             al(T.n_pairs * sizeof(SvdPair) + 1) + al(T.n_cols * sizeof(SvdCols) + 1) + al(T.sec.size() * 8) * 2 +
+            al(T.n_big * sizeof(int32_t) + 1) + al(T.n_bigcols * sizeof(SvdCols) + 1) +
             al(T.n_s * sizeof(GaugeTask) + 1) + al((n_rk + n_ck) * sizeof(CopyTask) + 1);
   return T;
 }
@@ -182,6 +190,8 @@ void truncate_run(const bsdmrg_leg* legs, const double* theta, const bsdmrg_trun
   char* cols_tab = take(T.n_cols * sizeof(SvdCols) + 1);
   double* d_active = (double*)take(T.sec.size() * 8);
   double* d_rot = (double*)take(T.sec.size() * 8);
+  char* big_tab = take(T.n_big * sizeof(int32_t) + 1);
+  char* bigcols_tab = take(T.n_bigcols * sizeof(SvdCols) + 1);
   char* gauge_tab = take(T.n_s * sizeof(GaugeTask) + 1);
   char* scatter_tab = p;
 
@@ -209,14 +219,15 @@ void truncate_run(const bsdmrg_leg* legs, const double* theta, const bsdmrg_trun
   HIPCHK(launch_copy(gather_tab, (int)gt.size(), theta, work, nullptr, st));
   std::vector<SvdTask> sv;
   std::vector<SvdPair> pairs;
-  std::vector<SvdCols> colblk;
-  int nb_max = 0;
+  std::vector<SvdCols> colblk, bigcols;
+  std::vector<int32_t> big;
+  int nb_max = 0, n_big_max = 0;
   for (size_t si = 0; si < T.sec.size(); ++si) {
     const TSector& s = T.sec[si];
     const bool tr = s.rows < s.cols;
     sv.push_back(SvdTask{s.mat, s.jav, s.jz, s.jaux, s.jsig, s.jperm, s.u, s.s, s.v,
                          (int32_t)std::max(s.rows, s.cols), (int32_t)s.kmin, (int32_t)s.rows, tr ? 1 : 0,
-                         s.b, s.nb, 0, 0});
+                         s.b, s.nb, s.kmin > kQrBig ? 1 : 0, 0});
     const SvdTask& t = sv.back();
     const int64_t mn = (int64_t)t.m * t.n, nn = (int64_t)t.n * t.n;
     if (t.x_off + mn > T.n_work || t.av_off + 2 * nn > T.n_work || t.z_off + mn > T.n_work ||
@@ -228,20 +239,48 @@ void truncate_run(const bsdmrg_leg* legs, const double* theta, const bsdmrg_trun
     for (int q = 0; q < t.nb / 2; ++q) pairs.push_back(SvdPair{(int32_t)si, q});
     for (int c = 0; c < t.n; c += 16) colblk.push_back(SvdCols{(int32_t)si, c});
     nb_max = std::max(nb_max, (int)t.nb);
+    if (t.big_qr) {
+      big.push_back((int32_t)si);
+      for (int c = 0; c < t.n; c += 16) bigcols.push_back(SvdCols{(int32_t)si, c});
+      n_big_max = std::max(n_big_max, (int)t.n);
+    }
   }
+  if ((int64_t)big.size() != T.n_big || (int64_t)bigcols.size() != T.n_bigcols)
+    throw Error{BSDMRG_EINVAL, "internal table check failed: truncate QR blocks"};
   if ((int64_t)pairs.size() != T.n_pairs || (int64_t)colblk.size() != T.n_cols)
     throw Error{BSDMRG_EINVAL, "internal table check failed: truncate SVD blocks"};
   HIPCHK(hipMemcpyAsync(svd_tab, sv.data(), sv.size() * sizeof(SvdTask), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(pair_tab, pairs.data(), pairs.size() * sizeof(SvdPair), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(cols_tab, colblk.data(), colblk.size() * sizeof(SvdCols), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(big_tab, big.data(), big.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bigcols_tab, bigcols.data(), bigcols.size() * sizeof(SvdCols), hipMemcpyHostToDevice, st));
   HIPCHK(launch_svd_qr(svd_tab, (int)sv.size(), work, S, st));
-  // block-Jacobi sweeps until a sweep rotates nothing (per matrix)
+  HIPCHK(launch_svd_qr_big(big_tab, (int)big.size(), bigcols_tab, (int)bigcols.size(), n_big_max, svd_tab, work, S,
+                           st));
+  // block-Jacobi sweeps until a sweep rotates nothing (per matrix).  The
+  // workgroup table of a sweep lists the pairs of the still active matrices,
+  // those with the most blocks first, so that step t launches only the
+  // prefix of matrices that have a step t (nb - 1 > t).
   std::vector<double> active(T.sec.size(), 1.0), rot(T.sec.size(), 0.0);
+  std::vector<int> order(T.sec.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sv[a].nb > sv[b].nb; });
+  std::vector<SvdPair> live;
+  std::vector<int> prefix(nb_max > 1 ? nb_max - 1 : 0, 0);
   for (int sweep = 0; sweep < kSvdMaxSweeps; ++sweep) {
+    live.clear();
+    std::fill(prefix.begin(), prefix.end(), 0);
+    for (int si : order) {
+      if (active[si] == 0.0) continue;
+      for (int q = 0; q < sv[si].nb / 2; ++q) live.push_back(SvdPair{si, q});
+      for (int t = 0; t < sv[si].nb - 1; ++t) prefix[t] = (int)live.size();
+    }
+    if (live.empty()) break;
+    HIPCHK(hipMemcpyAsync(pair_tab, live.data(), live.size() * sizeof(SvdPair), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d_active, active.data(), active.size() * 8, hipMemcpyHostToDevice, st));
     HIPCHK(dav_fill_zero(d_rot, (int64_t)T.sec.size(), st));
     for (int step = 0; step < nb_max - 1; ++step)
-      HIPCHK(launch_svd_bjac(pair_tab, (int)pairs.size(), svd_tab, work, d_active, d_rot, step, st));
+      if (prefix[step] > 0)
+        HIPCHK(launch_svd_bjac(pair_tab, prefix[step], svd_tab, work, d_active, d_rot, step, st));
     HIPCHK(hipMemcpyAsync(rot.data(), d_rot, rot.size() * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     bool any = false;

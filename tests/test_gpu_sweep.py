@@ -97,14 +97,15 @@ def test_truncation_matches_oracle(mods, direction, max_m):
     assert rel(B.cpu().numpy(), oB.pack()) < 1e-11
 
 
-def _big_theta(seed, low_rank):
-    """theta with charge sectors of up to 250 x 270, so the block Jacobi of
-    the truncation runs many block pairs per step; low_rank builds it as the
-    merge of two random sites over an inner bond of at most 60 states per
-    sector (rank-deficient sectors, as in a sweep)."""
+def _big_theta(seed, low_rank, huge=False):
+    """theta with charge sectors of up to 250 x 270 (huge: 390 x 390, which the
+    truncation factorises with the multi-workgroup QR), so the block Jacobi
+    runs many block pairs per step; low_rank builds it as the merge of two
+    random sites over an inner bond of at most 60 states per sector
+    (rank-deficient sectors, as in a sweep)."""
     from oracle.blocks import block_shape
-    a = [((-2,), 90), ((0,), 160), ((2,), 90)]
-    c = [((-2,), 70), ((0,), 200), ((2,), 70)]
+    a = [((-2,), 90), ((0,), 300 if huge else 160), ((2,), 90)]
+    c = [((-2,), 70), ((0,), 320 if huge else 200), ((2,), 70)]
     s = synth.SPIN_PHYS
     if not low_rank:
         legs = [a, s, s, c]
@@ -115,11 +116,12 @@ def _big_theta(seed, low_rank):
     return merge(A, B)
 
 
-@pytest.mark.parametrize("low_rank,direction,max_m", [(False, 0, 1 << 40), (False, 1, 300), (True, 0, 1 << 40),
-                                                      (True, 1, 100)])
-def test_truncation_large_sectors_matches_oracle(mods, low_rank, direction, max_m):
+@pytest.mark.parametrize("low_rank,direction,max_m,huge", [(False, 0, 1 << 40, False), (False, 1, 300, False),
+                                                           (True, 0, 1 << 40, False), (True, 1, 100, False),
+                                                           (False, 0, 1 << 40, True), (True, 1, 1 << 40, True)])
+def test_truncation_large_sectors_matches_oracle(mods, low_rank, direction, max_m, huge):
     lib, problems, _ = mods
-    theta = _big_theta(21, low_rank)
+    theta = _big_theta(21, low_rank, huge)
     A, B, leg, sv, disc = lib.truncate(theta.legs, dev(theta.pack()), direction, cutoff=1e-12, max_m=max_m)
     oA, oB, oleg, osv, odisc = o_truncate(theta, "right" if direction == 0 else "left", cutoff=1e-12, m_max=max_m)
     assert leg == oleg
