@@ -258,8 +258,11 @@ bsdmrg_status bsdmrg_truncate_workspace(const bsdmrg_leg* theta_legs, int64_t* b
 /* Truncated SVD split theta(a,s1,s2,c) = A(a,s1,b) B(b,s2,c) (Sec. II-C,
  * Fig. 1e; wrapped per-charge matrices of Sec. IV-A).  theta is wrapped into
  * one matrix per charge q of the new bond (rows (a, s1) with q_a + q_s1 = q,
- * columns (s2, c) with q_c - q_s2 = q, lexicographic), each decomposed with
- * rocSOLVER FP64 gesvd; singular values of all charges are pooled (ties by
+ * columns (s2, c) with q_c - q_s2 = q, lexicographic), each decomposed in
+ * FP64 on the device (QR with column pivoting cut at the numerical rank, then
+ * block one-sided Jacobi on R^T; singular values to ~eps ||theta||, those at
+ * the rounding level reported as 0); singular values of all charges are
+ * pooled (ties by
  * charge index, then index within the charge) and truncated by the options;
  * in every kept pair the entry of u of largest magnitude (first in row order
  * within 1e-10 relative) is made positive.  Outputs: the new bond leg
@@ -269,7 +272,8 @@ bsdmrg_status bsdmrg_truncate_workspace(const bsdmrg_leg* theta_legs, int64_t* b
  * the dropped values).  If leg_capacity, A_capacity, B_capacity or
  * sv_capacity is too small, returns BSDMRG_ECAPACITY with new_n_sectors,
  * A_elems, B_elems and n_kept set.  Synchronises the stream.
- * Errors: EINVAL, EQN, EHIP, ESOLVER (SVD failure or theta == 0). */
+ * Errors: EINVAL (also a charge matrix above 4096 columns), EQN, EHIP,
+ * ESOLVER (theta not finite, or theta == 0). */
 bsdmrg_status bsdmrg_truncate(const bsdmrg_leg* theta_legs, const double* theta,
                               const bsdmrg_trunc_opts* opts, int32_t* new_n_sectors,
                               int32_t* new_charges, int64_t* new_dims, int32_t leg_capacity,
