@@ -199,14 +199,24 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
   const double eps = 2.220446049250313e-16;
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
   double lo = glo - 2.0 * eps * tn - pivmin, hi = ghi + 2.0 * eps * tn + pivmin;
+  // squared off-diagonal in LDS once (the Sturm recurrence reads it every round)
+  if (lane + 1 < n) wb[lane] = e[lane] * e[lane];
+  __syncthreads();
   for (int round = 0; round < 24; ++round) {
     const double width = hi - lo;
     if (!(width > 4.0 * eps * fmax(fabs(lo), fabs(hi))) || width <= pivmin) break;
     const double sigma = lo + width * (double)(lane + 1) / (double)(GT + 1);
     int cnt = 0;
-    double q = 1.0;
-    for (int j = 0; j < n; ++j) {
-      q = d[j] - sigma - (j > 0 ? e[j - 1] * e[j - 1] / q : 0.0);
+    double q = d[0] - sigma;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+    for (int j = 1; j < n; ++j) {
+      // e_{j-1}^2 / q with the hardware reciprocal refined by one Newton step
+      // (relative error ~1e-16, like a rounded division; only the sign of the
+      // recurrence is used)
+      double r = __builtin_amdgcn_rcp(q);
+      r = fma(r, fma(-q, r, 1.0), r);
+      q = (d[j] - sigma) - wb[j - 1] * r;
       if (fabs(q) < pivmin) q = -pivmin;
       cnt += q < 0.0;
     }
