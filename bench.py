@@ -20,8 +20,9 @@ The JSON line also carries the per-stage times of one product, the roofline
 of the dominant grouped GEMM, the 64-bond batch (one launch per stage for all
 bonds), the m = 4096 Hubbard-type bond (U(1)xU(1), k = 22), sweeps of the
 6x6 J1-J2 cylinder at m = 256 with one sweep per path from the converged
-state (s/sweep of the FP64 and the mixed path at equal accuracy) and the
-oracle's CPU rate (cpu_baseline).  Other workloads: --workload j1j2-6x6
+state (s/sweep of the FP64 and the mixed path at equal accuracy), four
+sweeps of the 16-site Heisenberg chain at m = 64 per path, and the oracle's
+CPU rate (cpu_baseline).  Other workloads: --workload j1j2-6x6
 (adds dE/dJ2 by the adjoint and by finite differences), chain16,
 hubbard-4x16.
 
@@ -59,7 +60,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-bond batch measurement")
     ap.add_argument("--no-hubbard", action="store_true", help="skip the m=4096 Hubbard bond measurement")
     ap.add_argument("--no-sweeps", action="store_true",
-                    help="skip the 6x6 J1-J2 sweeps (FP64 vs mixed s/sweep at equal accuracy)")
+                    help="skip the sweeps of the 6x6 J1-J2 cylinder and of the 16-site chain (FP64 vs mixed "
+                         "s/sweep at equal accuracy)")
     ap.add_argument("--workload", default="bond", choices=["bond", "j1j2-6x6", "chain16", "hubbard-4x16"],
                     help="bond: the isolated-bond product bench (default); j1j2-6x6: DMRG sweeps on the "
                          "6x6 J1-J2 cylinder, dE/dJ2 by the adjoint and by finite differences; chain16: "
@@ -425,6 +427,9 @@ def main():
         a2 = argparse.Namespace(**vars(args))
         a2.m_max = 256
         line["sweeps_j1j2_6x6"] = j1j2_bench(a2, with_fd=False)
+        a3 = argparse.Namespace(**vars(args))
+        a3.workload = "chain16"
+        line["sweeps_chain16"] = sweeps_bench(a3)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, flops, args.cpu_seconds)
     print(json.dumps(line))

@@ -89,8 +89,9 @@ namespace bsd {
 // a rotation of two columns of A is applied to the same columns of VJ, so
 // that A_end = A VJ.  The columns are cut into nb blocks of b; a sweep runs
 // the nb - 1 round-robin steps of block pairs, every pair of a step in its
-// own workgroup with the 2b columns in LDS, where one inner cyclic sweep over
-// all column pairs of the union is done (a pair counts as orthogonal when
+// own workgroup with the 2b columns in LDS: the first step of a sweep runs one
+// inner cyclic sweep over all column pairs of the union, the later ones only
+// the pairs across the two blocks (a pair counts as orthogonal when
 // |a_p . a_q| <= tol ||a_p|| ||a_q||, tol following the rounding of an n-term
 // dot product; columns at the rank threshold are left alone).  Sweeps stop
 // when one makes no rotation.  Then sigma_j = ||a_j||, and with
@@ -360,38 +361,56 @@ __global__ __launch_bounds__(1024) void svd_bjac_kernel(const SvdPair* __restric
   // columns at the rank threshold of the QR (squared norm <= thr2) are
   // rounding noise left by rotations: not rotated, or noise columns would
   // keep rotating against each other and the sweeps would not stop
-  const int ne = nv + (nv & 1), hp = ne / 2;
+  // Step 0 of a sweep runs a full cyclic sweep over all column pairs of the
+  // union (this is where the pairs inside a block meet); the later steps
+  // only rotate the vI x vJ pairs across the two blocks, in P = max(vI, vJ)
+  // rounds of disjoint pairs (i, (i + t) mod P).
+  const bool full = step == 0;
+  const int ne = nv + (nv & 1);
+  const int P = max(vI, vJ);
+  const int hp = full ? ne / 2 : P;                  // pairs per round
+  const int rounds = full ? ne - 1 : P;
   int gs = 64;
   while (gs * hp > nthr) gs >>= 1;
   const int gl = tid % gs, grp = tid / gs;
-  for (int st = 0; st < ne - 1; ++st) {
+  for (int st = 0; st < rounds; ++st) {
+    int p = 0, q = nv;                                // q >= nv: no pair for this group
     if (grp < hp) {
-      auto pl = [&](int j) { return j == 0 ? 0 : 1 + ((j - 1 + st) % (ne - 1)); };
-      const int a = pl(grp), c2 = pl(ne - 1 - grp);
-      const int p = min(a, c2), q = max(a, c2);
-      if (q < nv) {
-        double* ap = col + p * L;
-        double* aq = col + q * L;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = gl; i < n; i += gs) {
-          const double u = ap[i], w = aq[i];
-          al += u * u;
-          be += w * w;
-          ga += u * w;
+      if (full) {
+        auto pl = [&](int j) { return j == 0 ? 0 : 1 + ((j - 1 + st) % (ne - 1)); };
+        const int a = pl(grp), c2 = pl(ne - 1 - grp);
+        p = min(a, c2);
+        q = max(a, c2);
+      } else {
+        const int i = grp, j = (grp + st) % P;
+        if (i < vI && j < vJ) {
+          p = i;
+          q = vI + j;
         }
-        al = svd_group_sum(al, gs);
-        be = svd_group_sum(be, gs);
-        ga = svd_group_sum(ga, gs);
-        if (!(ga == 0.0 || al <= thr2 || be <= thr2 || fabs(ga) <= tol * sqrt(al * be))) {
-          if (gl == 0) rotated = 1;
-          const double zeta = (be - al) / (2.0 * ga);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-          for (int i = gl; i < L; i += gs) {
-            const double u = ap[i], w = aq[i];
-            ap[i] = cs * u - sn * w;
-            aq[i] = sn * u + cs * w;
-          }
+      }
+    }
+    if (q < nv) {
+      double* ap = col + p * L;
+      double* aq = col + q * L;
+      double al = 0.0, be = 0.0, ga = 0.0;
+      for (int i = gl; i < n; i += gs) {
+        const double u = ap[i], w = aq[i];
+        al += u * u;
+        be += w * w;
+        ga += u * w;
+      }
+      al = svd_group_sum(al, gs);
+      be = svd_group_sum(be, gs);
+      ga = svd_group_sum(ga, gs);
+      if (!(ga == 0.0 || al <= thr2 || be <= thr2 || fabs(ga) <= tol * sqrt(al * be))) {
+        if (gl == 0) rotated = 1;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        for (int i = gl; i < L; i += gs) {
+          const double u = ap[i], w = aq[i];
+          ap[i] = cs * u - sn * w;
+          aq[i] = sn * u + cs * w;
         }
       }
     }
