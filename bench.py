@@ -17,7 +17,8 @@ time per step, where useful flops are the block-pair flops of the two GEMM
 stages (the flop definition of the paper's list method).
 
 The JSON line also carries the per-stage times of one product, the roofline
-of the dominant grouped GEMM, the 64-bond batch (one launch per stage for all
+of the dominant grouped GEMM, the same product in the sparse-dense format
+(dense operands, one library GEMM per stage: the work the blocks avoid), the 64-bond batch (one launch per stage for all
 bonds), the m = 4096 Hubbard-type bond (U(1)xU(1), k = 22), sweeps of the
 6x6 J1-J2 cylinder at m = 256 with one sweep per path from the converged
 state (s/sweep of the FP64 and the mixed path at equal accuracy), four
@@ -278,6 +279,47 @@ def sweeps_bench(args):
     return out
 
 
+def dense_ablation(spec, plan, dev, reps=5):
+    """The same product in the sparse-dense format (all operands dense, one
+    library GEMM per stage; the work the block structure avoids is done):
+    ms per product in FP64 and FP32 and its agreement with the block-sparse
+    product."""
+    import torch
+    from paper_2007_05540_amd import lib, problems, dense
+    wl, s = spec.w_leg(), spec.s_leg
+    legs_psi = [spec.a_leg, s, s, spec.c_leg]
+    host = {"L": problems.unpack_dense(dev["L"].cpu().numpy(), [spec.a_leg, wl, spec.a_leg], lib.ENV_SIGNS),
+            "R": problems.unpack_dense(dev["R"].cpu().numpy(), [spec.c_leg, wl, spec.c_leg], lib.ENV_SIGNS),
+            "psi": problems.unpack_dense(dev["psi"].cpu().numpy(), legs_psi, lib.PSI_SIGNS),
+            "W1": spec.W1, "W2": spec.W2}
+    ma, k, _ = host["L"].shape
+    mc, d = host["R"].shape[0], host["psi"].shape[1]
+    f1, f2, f3 = dense.dense_flops(ma, mc, k, d)
+    out = {"dense_gflop_per_product": round((f1 + f2 + f3) / 1e9, 2)}
+    ref = torch.zeros_like(dev["psi"])
+    ws = torch.empty(plan.info()["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    lib.heff_apply(plan, lib.F64, dev["L"], dev["W1"], dev["W2"], dev["R"], dev["psi"], ref, ws)
+    ref = ref.cpu().numpy()
+    del ws
+    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        t = {kk: torch.from_numpy(v).to("cuda", dt) for kk, v in host.items()}
+        y = dense.heff_dense(t["L"], t["W1"], t["W2"], t["R"], t["psi"])
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            y = dense.heff_dense(t["L"], t["W1"], t["W2"], t["R"], t["psi"])
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        got = problems.pack_dense(y.double().cpu().numpy(), legs_psi, lib.PSI_SIGNS)
+        out[name] = {"ms_per_product": round(ms, 3), "dense_tflops": round((f1 + f2 + f3) / ms / 1e9, 1),
+                     "rel_diff_vs_block_sparse_f64": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+        del t, y
+        torch.cuda.empty_cache()
+    return out
+
+
 def autotune(plan, info, dev, stream):
     """Tile shape classes of the S1/S3 launches chosen by the library's
     autotuner (timed in FP32, the precision of most products)."""
@@ -398,6 +440,7 @@ def main():
                 "traffic": HBM_TRAFFIC[dom], "traffic_unit": "bytes per launch",
                 "ms_per_launch": round(s32[dom], 5), "flops_per_launch": dom_flops}
 
+    ablation = dense_ablation(spec, plan, dev)
     mixed, f64 = results["mixed"], results["f64"]
     line = {
         "metric": "block-sparse H_eff·ψ useful GFLOP/s & s/sweep: FP64 vs mixed+batched at 1e-9 dE",
@@ -414,6 +457,7 @@ def main():
         "mixed_energy": mixed["energy"], "mixed_residual": mixed["residual"],
         "speedup_mixed_vs_f64": round(f64["ms_per_step"] / mixed["ms_per_step"], 3),
         "stage_ms": {k: {s: round(v, 5) for s, v in d.items()} for k, d in stage.items()},
+        "dense_format_ablation": ablation,
         "roofline": roofline,
     }
     del dev, out, wsa

@@ -82,3 +82,16 @@ def initial_mps(mpo, target, m0, seed):
             return mps_block(seed, j, k, shape)
         out.append((lj, pack_fn(lj, lib.MPS_SIGNS, blk)))
     return out
+
+
+def unpack_dense(flat, legs, signs):
+    """Dense array of a tensor in canonical layout (zeros outside the allowed
+    blocks): the inverse of pack_dense."""
+    keys, offs = lib.layout(legs, signs)
+    starts = [leg_starts(l) for l in legs]
+    dense = np.zeros(tuple(sum(d for _, d in l) for l in legs))
+    for b, k in enumerate(keys):
+        shape = tuple(legs[i][k[i]][1] for i in range(len(legs)))
+        sl = tuple(slice(starts[i][k[i]], starts[i][k[i]] + shape[i]) for i in range(len(legs)))
+        dense[sl] = np.asarray(flat[offs[b]:offs[b] + int(np.prod(shape))]).reshape(shape)
+    return dense
