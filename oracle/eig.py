@@ -3,10 +3,11 @@
 ``davidson`` follows Alg. 1 (Sec. III): no preconditioning, Gram row from the
 stored products, smallest Ritz pair of the projected matrix, residual, modified
 Gram-Schmidt, randomisation when reorthogonalisation fails.  Readings where the
-listing is silent or slightly off (each listed in the design notes):
+listing is silent or slightly off:
   * the start vector and every new basis vector are normalised;
-  * at iteration i the projected matrix is (i+1) x (i+1) (the listing's
-    "leading i x i block" is one short: it must contain the newest vector);
+  * at iteration i the projected matrix is (i+1) x (i+1) (the block the
+    listing diagonalises is one row and column short of that: it must
+    contain the newest vector);
   * m_ij = m_ji = (v^A_j)^T v_i for j <= i;
   * convergence when ||q||_2 <= tol (after q = sum s_j v^A_j - lambda x);
   * modified Gram-Schmidt is applied twice (robustness; ~1e-15 effect);

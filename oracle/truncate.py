@@ -7,7 +7,7 @@ indices and then row-major inside the block.  Each matrix is decomposed with a
 plain SVD; the singular values of all charges are pooled and truncated; the
 singular values are absorbed in the direction of the sweep.
 
-Readings where the paper is silent or loose (listed in the design notes):
+Readings where the paper is silent or loose:
   * cutoff_mode 'sv' (default; "removes all singular values below 1e-12"):
     discard s < cutoff * ||theta||;  'weight': discard the smallest values
     whose squares sum to at most cutoff * ||theta||^2;
