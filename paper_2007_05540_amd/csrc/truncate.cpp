@@ -294,8 +294,12 @@ void truncate_run(const bsdmrg_leg* legs, const double* theta, const bsdmrg_trun
   std::vector<double> hS(T.n_s);
   HIPCHK(hipMemcpyAsync(hS.data(), S, T.n_s * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  for (double v : hS)
+  bool any_nonzero = false;
+  for (double v : hS) {
     if (!std::isfinite(v)) throw Error{BSDMRG_ESOLVER, "truncate: non-finite singular value (theta not finite?)"};
+    any_nonzero = any_nonzero || v != 0.0;
+  }
+  if (!any_nonzero) throw Error{BSDMRG_ESOLVER, "truncate: theta is zero (no singular vector to keep)"};
   std::vector<double> kept;
   std::vector<int64_t> counts = select_kept(T, hS, o, discarded, kept);
   // new leg and output layouts

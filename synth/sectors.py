@@ -28,7 +28,7 @@ def spin_bond_leg(m, q=4.0, r=0.6, center=0):
             dims[center + 2 * l] = b
             dims[center - 2 * l] = b
         l += 1
-    dims[center] += m - sum(dims.values())
+    dims[center] = dims.get(center, 0) + m - sum(dims.values())   # m < q: the centre sector only
     return [((c,), dims[c]) for c in sorted(dims)]
 
 

@@ -131,3 +131,30 @@ def test_adjoint_tables_build_and_pass_host_checks(lib, m, k, seed):
     assert need > info["apply_workspace_bytes"] + 8 * (info["t1_elems"] + info["t2_elems"])
     assert plan.info()["backward_workspace_bytes"] == need
     assert lib.heff_backward_workspace(plan) == need
+
+
+def test_truncate_rejects_charge_matrix_above_4096_columns(lib):
+    """The truncation SVD holds a pair of column blocks of a charge matrix in
+    the 128 KB of LDS of one workgroup: charge matrices above 4096 columns
+    are refused on the host (EINVAL) before any launch."""
+    big = [((0,), 4100)]
+    legs = [big, synth.SPIN_PHYS, synth.SPIN_PHYS, big]
+    with pytest.raises(lib.BsdmrgError) as e:
+        lib.truncate_workspace(legs)
+    assert e.value.status == lib.EINVAL
+    ok = [((0,), 4000)]
+    assert lib.truncate_workspace([ok, synth.SPIN_PHYS, synth.SPIN_PHYS, ok]) > 0
+
+
+def test_plan_rejects_bond_sector_above_4096(lib):
+    """A bond sector above 4096 states exceeds one mixing work item: refused
+    on the host (EINVAL)."""
+    from paper_2007_05540_amd import problems
+    spec = synth.c2_bond(m=64, k=5, seed=1)
+    wl, s = spec.w_leg(), spec.s_leg
+    prob = {"a": [((0,), 8)], "s1": s, "s2": s, "c": [((0,), 5000)], "wl": wl, "wm": wl, "wr": wl,
+            "w1": problems.pack_dense(spec.W1, [wl, s, s, wl], lib.W_SIGNS),
+            "w2": problems.pack_dense(spec.W2, [wl, s, s, wl], lib.W_SIGNS)}
+    with pytest.raises(lib.BsdmrgError) as e:
+        lib.Plan([prob], host_only=True)
+    assert e.value.status == lib.EINVAL

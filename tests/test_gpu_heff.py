@@ -74,6 +74,24 @@ def test_apply_f64_matches_oracle(mods, m, k, seed):
     assert np.all(got[~mask] == 0.0)
 
 
+def test_smallest_bond_apply_and_eigensolve(mods):
+    """m = 2: one sector per bond leg, two 2 x 2 psi blocks (dimension 8):
+    product against the oracle, and a solve capped by the dimension that
+    returns the dense lowest eigenvalue."""
+    lib, problems = mods
+    spec = synth.c2_bond(m=2, k=5, seed=2)
+    assert len(spec.a_leg) == 1
+    plan, ops, d = setup([spec], lib, problems)
+    out = torch.zeros_like(d["psi"])
+    ws = torch.empty(plan.info()["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    lib.heff_apply(plan, lib.F64, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
+    torch.cuda.synchronize()
+    assert rel(out.cpu().numpy(), oracle_apply(spec)) < 1e-12
+    lam, _, ost, _ = oracle_davidson(spec, 40, tol=-1.0)
+    e, st, _ = run_eig(lib, plan, d, lib.eig_opts(max_iter=40, tol=1e-14))
+    assert abs(e[0] - lam) < 1e-12 * abs(lam) and st[0]["iters"] <= 8
+
+
 def test_apply_f64_full_size_mid_chain_bond(mods):
     """m = 1024, k = 14: the full-size isolated bond, whole output compared."""
     lib, problems = mods

@@ -135,6 +135,18 @@ def test_truncation_large_sectors_matches_oracle(mods, low_rank, direction, max_
     assert rel(B.cpu().numpy(), oB.pack()) < 1e-10
 
 
+def test_truncation_of_zero_theta_is_an_error(mods):
+    """theta = 0 has no singular vector to keep: ESOLVER, not a zero-width
+    bond."""
+    lib, problems, _ = mods
+    mpo, mps, _ = random_sites()
+    theta = merge(mps[3], mps[4])
+    z = torch.zeros(theta.pack().size, dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.BsdmrgError) as e:
+        lib.truncate(theta.legs, z, 0, cutoff=1e-12)
+    assert e.value.status == lib.ESOLVER
+
+
 def test_truncation_rejects_small_workspace(mods):
     lib, problems, _ = mods
     mpo, mps, _ = random_sites()
