@@ -161,15 +161,27 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
     }
     __syncthreads();
     if (vn2 > 0.0) {
-      double pr = 0.0;
-      if (mine)
-        for (int c = k + 1; c < n; ++c) pr += A[lane][c] * vb[c];
+      // four partial sums so that the LDS loads of a row are in flight together
+      double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+      if (mine) {
+        int c = k + 1;
+        for (; c + 3 < n; c += 4) {
+          p0 += A[lane][c] * vb[c];
+          p1 += A[lane][c + 1] * vb[c + 1];
+          p2 += A[lane][c + 2] * vb[c + 2];
+          p3 += A[lane][c + 3] * vb[c + 3];
+        }
+        for (; c < n; ++c) p0 += A[lane][c] * vb[c];
+      }
+      const double pr = (p0 + p1) + (p2 + p3);
       const double beta = wave_sum(vr * pr);
       const double wr = pr - beta * vr;
       wb[lane] = wr;
       __syncthreads();
-      if (mine)
+      if (mine) {
+#pragma unroll 4
         for (int c = k + 1; c < n; ++c) A[lane][c] -= 2.0 * (vr * wb[c] + wr * vb[c]);
+      }
       __syncthreads();
     }
   }
@@ -210,6 +222,7 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
     double q = d[0] - sigma;
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
+#pragma unroll 4
     for (int j = 1; j < n; ++j) {
       // e_{j-1}^2 / q with the hardware reciprocal refined by one Newton step
       // (relative error ~1e-16, like a rounded division; only the sign of the
@@ -256,27 +269,35 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
       c = 0.0;
     }
     U0[n - 1] = a; U1[n - 1] = 0.0; U2[n - 1] = 0.0;
-    for (int j = 0; j < n; ++j)
-      if (fabs(U0[j]) < tiny) U0[j] = U0[j] < 0.0 ? -tiny : tiny;
+    // pivots below eps replaced by eps; their reciprocals kept (in U0)
+    for (int j = 0; j < n; ++j) {
+      const double u = fabs(U0[j]) < tiny ? (U0[j] < 0.0 ? -tiny : tiny) : U0[j];
+      U0[j] = 1.0 / u;
+    }
     for (int j = 0; j < n; ++j) y[j] = 1.0 / sqrt((double)n);
     for (int it = 0; it < 2; ++it) {
+      // y <- L^-1 P y, the running entry carried in a register
+      double cur = y[0];
       for (int j = 0; j + 1 < n; ++j) {
+        const double nxt = y[j + 1];
         if (sw[j]) {
-          const double t = y[j];
-          y[j] = y[j + 1];
-          y[j + 1] = t - ml[j] * y[j];
+          y[j] = nxt;
+          cur = cur - ml[j] * nxt;
         } else {
-          y[j + 1] -= ml[j] * y[j];
+          y[j] = cur;
+          cur = nxt - ml[j] * cur;
         }
       }
+      y[n - 1] = cur;
+      // y <- U^-1 y, the two entries below carried in registers
+      double y1 = 0.0, y2 = 0.0, s2 = 0.0;
       for (int j = n - 1; j >= 0; --j) {
-        double t = y[j];
-        if (j + 1 < n) t -= U1[j] * y[j + 1];
-        if (j + 2 < n) t -= U2[j] * y[j + 2];
-        y[j] = t / U0[j];
+        const double t = (y[j] - U1[j] * y1 - U2[j] * y2) * U0[j];
+        y[j] = t;
+        s2 += t * t;
+        y2 = y1;
+        y1 = t;
       }
-      double s2 = 0.0;
-      for (int j = 0; j < n; ++j) s2 += y[j] * y[j];
       const double inv = 1.0 / sqrt(s2);
       for (int j = 0; j < n; ++j) y[j] *= inv;
     }
