@@ -41,6 +41,22 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
+// Raw buffer resource (gfx9 family: untyped, stride 0) over nbytes from p;
+// loads at byte offsets at or past nbytes return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int64_t nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
 // LDS slice of one operand of a TM x TM tile (BKT deep in k): K-contiguous
 // operands (A as M x K, B as N x K) are kept [row][k] with a row stride of
 // BKT + 4 (FP32) or BKT + 1 (FP64), M/N-contiguous ones (A as K x M, B as
@@ -68,18 +84,18 @@ struct Slice {
 // LDS); TO: output type; BT: B stored N x K (row-major) instead of K x N;
 // AT: A stored K x M (row-major) instead of M x K.
 //
-// Global -> LDS: a thread owns 4 elements of each operand slice.  For a
-// K-contiguous operand: k = tid % 16 and rows tid / 16 + 16 u, so one load
-// instruction reads 4 rows x 16 consecutive k.  For an M/N-contiguous
-// operand: column tid % 64 and k = tid / 64 + 4 u, so one load instruction
-// reads 64 consecutive columns of one k.  Addresses are a wave-uniform base
-// (segment start plus the slice's k offset) plus a per-thread 32-bit byte
-// offset fixed for the segment.  Rows and columns past the block edge are
-// read from the last one (every block is at least 1 x 1, so the address
-// stays inside the block) and zeroed when written to LDS; only the last
-// slice of a segment clamps k.  Loads keep their storage type until then, so
-// they stay in flight across the MFMAs of the current slice.  LDS holds two
-// slices (double buffer) and each iteration has one barrier.
+// Global -> LDS: a thread owns EPT = TM * BKT / 256 elements of each operand
+// slice.  For a K-contiguous operand: k = tid % BKT and rows tid / BKT +
+// (256 / BKT) u, so one load instruction reads consecutive k of a few rows.
+// For an M/N-contiguous operand: column tid % TM and k = tid / TM +
+// (256 / TM) u, so one load instruction reads 64 consecutive columns of one
+// k.  Each load is a raw buffer load: a wave-uniform resource (the segment's
+// block from the slice's first k to the block's end, rebuilt per slice in
+// scalar registers) plus a per-thread 32-bit byte offset fixed for the
+// segment, so a load costs no vector address arithmetic and a read past the
+// block returns zero.  Loads keep their storage type until they are written
+// to LDS, so they stay in flight across the MFMAs of the current slice.  LDS
+// holds two slices (double buffer) and each iteration has one barrier.
 template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT, int TM, int NI, int NJ>
 __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask& task,
                                            const GemmSeg* __restrict__ segs, const TA* __restrict__ A,
@@ -111,59 +127,53 @@ __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask&
   const int mc_c = tid % TM, mc_k = tid / TM;      // M/N-contiguous: column, first k (+KSTEP u)
   // validity of rows / columns (fixed for the tile)
   unsigned a_v = 0, b_v = 0;
-  int a_r[EPT], b_r[EPT];                          // clamped rows / columns
 #pragma unroll
   for (int u = 0; u < EPT; ++u) {
-    const int ar = tile.m0 + (AT ? mc_c : kc_r + RSTEP * u);
-    const int br = tile.n0 + (BT ? kc_r + RSTEP * u : mc_c);
-    a_r[u] = min(ar, task.M - 1);
-    b_r[u] = min(br, task.N - 1);
-    a_v |= (unsigned)(ar < task.M) << u;
-    b_v |= (unsigned)(br < task.N) << u;
+    a_v |= (unsigned)(tile.m0 + (AT ? mc_c : kc_r + RSTEP * u) < task.M) << u;
+    b_v |= (unsigned)(tile.n0 + (BT ? kc_r + RSTEP * u : mc_c) < task.N) << u;
   }
 
   TA la[EPT];
   TB lb[EPT];
   unsigned va = 0, vb = 0;
-  const char* a_seg = nullptr;
-  const char* b_seg = nullptr;
-  unsigned ao[EPT], bo[EPT];
+  // Operands are read through buffer resources spanning exactly the
+  // segment's block from the slice's first k on: a read past the block (rows
+  // past the last one of a K-contiguous block, k past K of an M/N-contiguous
+  // one) returns zero and touches no memory.  Reads that stay inside the
+  // block but leave the tile (k past K within a K-contiguous row, columns
+  // past the edge of an M/N-contiguous row) are zeroed by the masks.
+  const TA* a_seg = nullptr;
+  const TB* b_seg = nullptr;
+  int64_t a_ext = 0, b_ext = 0;      // elements of the block from its start
+  unsigned ao[EPT], bo[EPT];         // byte offsets of this thread's elements
   auto setup = [&](const GemmSeg& sg) {
-    a_seg = (const char*)(A + sg.a_off);
-    b_seg = (const char*)(B + sg.b_off);
+    a_seg = A + sg.a_off;
+    b_seg = B + sg.b_off;
+    a_ext = AT ? (int64_t)(sg.K - 1) * sg.lda + task.M : (int64_t)(task.M - 1) * sg.lda + sg.K;
+    b_ext = BT ? (int64_t)(task.N - 1) * sg.ldb + sg.K : (int64_t)(sg.K - 1) * sg.ldb + task.N;
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
-      ao[u] = (AT ? (unsigned)(mc_k + KSTEP * u) * sg.lda + a_r[u] : (unsigned)a_r[u] * sg.lda + kc_k) *
-              sizeof(TA);
-      bo[u] = (BT ? (unsigned)b_r[u] * sg.ldb + kc_k : (unsigned)(mc_k + KSTEP * u) * sg.ldb + b_r[u]) *
-              sizeof(TB);
+      const unsigned ar = tile.m0 + (AT ? mc_c : kc_r + RSTEP * u);
+      const unsigned br = tile.n0 + (BT ? kc_r + RSTEP * u : mc_c);
+      ao[u] = (AT ? (unsigned)(mc_k + KSTEP * u) * sg.lda + ar : ar * sg.lda + kc_k) * sizeof(TA);
+      bo[u] = (BT ? br * sg.ldb + kc_k : (unsigned)(mc_k + KSTEP * u) * sg.ldb + br) * sizeof(TB);
     }
   };
   auto load = [&](const GemmSeg& sg, int kk0) {
-    const char* ab = a_seg + (size_t)kk0 * (AT ? sg.lda : 1) * sizeof(TA);
-    const char* bb = b_seg + (size_t)kk0 * (BT ? 1 : sg.ldb) * sizeof(TB);
-    if (kk0 + BKT <= sg.K) {
+    const int64_t ash = (int64_t)kk0 * (AT ? sg.lda : 1);
+    const int64_t bsh = (int64_t)kk0 * (BT ? 1 : sg.ldb);
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(a_seg + ash, (a_ext - ash) * (int64_t)sizeof(TA));
+    const __amdgpu_buffer_rsrc_t rb = make_rsrc(b_seg + bsh, (b_ext - bsh) * (int64_t)sizeof(TB));
 #pragma unroll
-      for (int u = 0; u < EPT; ++u) {
-        la[u] = *(const TA*)(ab + ao[u]);
-        lb[u] = *(const TB*)(bb + bo[u]);
-      }
-      va = a_v;
-      vb = b_v;
-    } else {
-      // last slice of the segment: k clamped to K - 1, zeroed past it
-      const int km = sg.K - 1;
-      va = vb = 0;
-#pragma unroll
-      for (int u = 0; u < EPT; ++u) {
-        const int ka = kk0 + (AT ? mc_k + KSTEP * u : kc_k);
-        const int kb = kk0 + (BT ? kc_k : mc_k + KSTEP * u);
-        la[u] = *(const TA*)(ab + ao[u] + (min(ka, km) - ka) * (AT ? sg.lda : 1) * (int)sizeof(TA));
-        lb[u] = *(const TB*)(bb + bo[u] + (min(kb, km) - kb) * (BT ? 1 : sg.ldb) * (int)sizeof(TB));
-        va |= (ka < sg.K) ? (a_v & (1u << u)) : 0u;
-        vb |= (kb < sg.K) ? (b_v & (1u << u)) : 0u;
-      }
+    for (int u = 0; u < EPT; ++u) {
+      la[u] = buf_load<TA>(ra, ao[u]);
+      lb[u] = buf_load<TB>(rb, bo[u]);
     }
+    // K-contiguous operands: k past K of a row inside the block is the next
+    // row's data; every element of a thread shares its k
+    const bool kin = kk0 + kc_k < sg.K;
+    va = (AT || kin) ? a_v : 0u;
+    vb = (!BT || kin) ? b_v : 0u;
   };
   auto store = [&](int buf) {
     TC* as = As + buf * SA::SIZE;

@@ -41,7 +41,8 @@ void validate_gemm(const Stage& st, int layout, int64_t a_elems, int64_t b_elems
       }
     }
     if (ks != k.ksum) fail(std::string(name) + ": ksum");
-    // the GEMM kernel addresses a block with 32-bit byte offsets (8-byte elements)
+    // the GEMM kernel reads a block through a buffer resource whose length in
+    // bytes is a 31-bit number, with 32-bit byte offsets (8-byte elements)
     for (int j = 0; j < k.nseg; ++j) {
       const GemmSeg& g = st.segs[k.seg0 + j];
       const int64_t ea = layout == kTN ? (int64_t)(g.K - 1) * g.lda + k.M : (int64_t)(k.M - 1) * g.lda + g.K;
