@@ -38,6 +38,36 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sum over the 64 lanes of a wave, the same value on every lane, in one
+// fixed order: DPP exchanges inside each row of 16 lanes (pairs, quads, half
+// rows, rows), then the four row sums read from lanes 0, 16, 32, 48 and
+// added pairwise.  Register-only (no LDS crossbar); every lane must be active.
+template <int CTRL>
+__device__ __forceinline__ double mov_dpp_d(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+// old with lane l replaced by v (a per-lane select)
+template <typename T>
+__device__ __forceinline__ T writelane(T v, int l, T old) {
+  return (int)(threadIdx.x & 63) == l ? v : old;
+}
+__device__ __forceinline__ double wave_total(double v) {
+  v += mov_dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
+  v += mov_dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
+  v += mov_dpp_d<0x141>(v);   // row_half_mirror: the other quad of the half row
+  v += mov_dpp_d<0x140>(v);   // row_mirror: the other half of the row
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
 // out[j] = sum over the problem's chunks of part[j * nct + chunk] for j < J
 // (thread-strided sums, then the deterministic block tree); result in LDS.
 __device__ __forceinline__ void sum_partials(const double* __restrict__ part, int nct, const DavProb& pr,
@@ -122,14 +152,13 @@ __global__ __launch_bounds__(DT) void normalize_kernel(const Chunk* __restrict__
 //  4. back-transformation x = Q y.
 constexpr int kMaxBasis = 64;
 constexpr int GT = 64;   // one wave
+constexpr int kRegRows = 16;   // register path of the tridiagonalisation
 __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, const double* __restrict__ red,
                                                       double* __restrict__ M, double* __restrict__ svec,
                                                       double* __restrict__ lam) {
   __shared__ double A[kMaxBasis][kMaxBasis + 1];
   __shared__ double Vh[kMaxBasis][kMaxBasis];
-  __shared__ double d[kMaxBasis], e[kMaxBasis], vb[kMaxBasis], wb[kMaxBasis], y[kMaxBasis];
-  __shared__ double U0[kMaxBasis], U1[kMaxBasis], U2[kMaxBasis], ml[kMaxBasis];
-  __shared__ int sw[kMaxBasis];
+  __shared__ double d[kMaxBasis], e[kMaxBasis], vb[kMaxBasis], wb[kMaxBasis];
   const int p = blockIdx.x, lane = threadIdx.x, n = i + 1;
   double* Mp = M + (int64_t)p * B * B;
   const double* rp = red + (int64_t)p * ldr;
@@ -144,53 +173,112 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
     Mp[lane * B + i] = v;
   }
   __syncthreads();
-  // 1. tridiagonalisation (lane r owns row r of the trailing block)
-  for (int k = 0; k + 2 < n; ++k) {
-    const bool mine = lane > k && lane < n;
-    const double xr = mine ? A[lane][k] : 0.0;
-    const double nrm2 = wave_sum(xr * xr);
-    const double x0 = A[k + 1][k];
-    const double alpha = nrm2 > 0.0 ? -copysign(sqrt(nrm2), x0) : 0.0;
-    const double vn2 = 2.0 * (nrm2 - alpha * x0);   // ||x - alpha e_{k+1}||^2
-    const double vr = vn2 > 0.0 ? (xr - (lane == k + 1 ? alpha : 0.0)) / sqrt(vn2) : 0.0;
-    vb[lane] = vr;
-    Vh[k][lane] = vr;
-    if (lane == 0) {
-      d[k] = A[k][k];
-      e[k] = alpha;
-    }
-    __syncthreads();
-    if (vn2 > 0.0) {
-      // four partial sums so that the LDS loads of a row are in flight together
-      double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-      if (mine) {
-        int c = k + 1;
-        for (; c + 3 < n; c += 4) {
-          p0 += A[lane][c] * vb[c];
-          p1 += A[lane][c + 1] * vb[c + 1];
-          p2 += A[lane][c + 2] * vb[c + 2];
-          p3 += A[lane][c + 3] * vb[c + 3];
+  // 1. tridiagonalisation (lane r owns row r of the trailing block).  Up to
+  // kRegRows rows the row is held in registers and the Householder vector
+  // and its image are broadcast with lane reads; larger matrices stay in LDS.
+  if (n <= kRegRows) {
+    double ar[kRegRows];
+#pragma unroll
+    for (int c = 0; c < kRegRows; ++c) ar[c] = (lane < n && c < n) ? A[lane][c] : 0.0;
+#pragma unroll
+    for (int k = 0; k + 2 < kRegRows; ++k) {
+      if (k + 2 < n) {
+        const bool mine = lane > k && lane < n;
+        const double xr = mine ? ar[k] : 0.0;
+        const double nrm2 = wave_total(xr * xr);
+        const double x0 = readlane_d(ar[k], k + 1);
+        const double alpha = nrm2 > 0.0 ? -copysign(sqrt(nrm2), x0) : 0.0;
+        const double vn2 = 2.0 * (nrm2 - alpha * x0);   // ||x - alpha e_{k+1}||^2
+        const double vr = vn2 > 0.0 ? (xr - (lane == k + 1 ? alpha : 0.0)) / sqrt(vn2) : 0.0;
+        Vh[k][lane] = vr;
+        const double dk = readlane_d(ar[k], k);
+        if (lane == 0) {
+          d[k] = dk;
+          e[k] = alpha;
         }
-        for (; c < n; ++c) p0 += A[lane][c] * vb[c];
+        if (vn2 > 0.0) {
+          // p = A v over the trailing columns (zero past n on both sides)
+          double vc[kRegRows];
+          double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+          for (int c = k + 1; c < kRegRows; ++c) {
+            vc[c] = readlane_d(vr, c);
+            if ((c - k) & 1) p0 += ar[c] * vc[c];
+            else p1 += ar[c] * vc[c];
+          }
+          const double pr = mine ? p0 + p1 : 0.0;
+          const double beta = wave_total(vr * pr);
+          const double wr = pr - beta * vr;
+#pragma unroll
+          for (int c = k + 1; c < kRegRows; ++c) ar[c] -= 2.0 * (vr * readlane_d(wr, c) + wr * vc[c]);
+        }
       }
-      const double pr = (p0 + p1) + (p2 + p3);
-      const double beta = wave_sum(vr * pr);
-      const double wr = pr - beta * vr;
-      wb[lane] = wr;
+    }
+    // the last 2 x 2 block
+    double dl = 0.0, dm = 0.0, el = 0.0;
+#pragma unroll
+    for (int c = 0; c < kRegRows; ++c) {
+      if (c == n - 2) {
+        dl = readlane_d(ar[c], c);
+        el = readlane_d(ar[c], c + 1);
+      }
+      if (c == n - 1) dm = readlane_d(ar[c], c);
+    }
+    if (lane == 0) {
+      if (n >= 2) {
+        d[n - 2] = dl;
+        e[n - 2] = el;
+      }
+      d[n - 1] = dm;
+    }
+  } else {
+    for (int k = 0; k + 2 < n; ++k) {
+      const bool mine = lane > k && lane < n;
+      const double xr = mine ? A[lane][k] : 0.0;
+      const double nrm2 = wave_total(xr * xr);
+      const double x0 = A[k + 1][k];
+      const double alpha = nrm2 > 0.0 ? -copysign(sqrt(nrm2), x0) : 0.0;
+      const double vn2 = 2.0 * (nrm2 - alpha * x0);   // ||x - alpha e_{k+1}||^2
+      const double vr = vn2 > 0.0 ? (xr - (lane == k + 1 ? alpha : 0.0)) / sqrt(vn2) : 0.0;
+      vb[lane] = vr;
+      Vh[k][lane] = vr;
+      if (lane == 0) {
+        d[k] = A[k][k];
+        e[k] = alpha;
+      }
       __syncthreads();
-      if (mine) {
+      if (vn2 > 0.0) {
+        // four partial sums so that the LDS loads of a row are in flight together
+        double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+        if (mine) {
+          int c = k + 1;
+          for (; c + 3 < n; c += 4) {
+            p0 += A[lane][c] * vb[c];
+            p1 += A[lane][c + 1] * vb[c + 1];
+            p2 += A[lane][c + 2] * vb[c + 2];
+            p3 += A[lane][c + 3] * vb[c + 3];
+          }
+          for (; c < n; ++c) p0 += A[lane][c] * vb[c];
+        }
+        const double pr = (p0 + p1) + (p2 + p3);
+        const double beta = wave_total(vr * pr);
+        const double wr = pr - beta * vr;
+        wb[lane] = wr;
+        __syncthreads();
+        if (mine) {
 #pragma unroll 4
-        for (int c = k + 1; c < n; ++c) A[lane][c] -= 2.0 * (vr * wb[c] + wr * vb[c]);
+          for (int c = k + 1; c < n; ++c) A[lane][c] -= 2.0 * (vr * wb[c] + wr * vb[c]);
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
-  }
-  if (lane == 0) {
-    if (n >= 2) {
-      d[n - 2] = A[n - 2][n - 2];
-      e[n - 2] = A[n - 1][n - 2];
+    if (lane == 0) {
+      if (n >= 2) {
+        d[n - 2] = A[n - 2][n - 2];
+        e[n - 2] = A[n - 1][n - 2];
+      }
+      d[n - 1] = A[n - 1][n - 1];
     }
-    d[n - 1] = A[n - 1][n - 1];
   }
   __syncthreads();
   // 2. multisection for the lowest eigenvalue of T
@@ -245,69 +333,84 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
     }
   }
   const double lambda = 0.5 * (lo + hi);
-  // 3. inverse iteration (one lane: the elimination is sequential)
-  if (lane == 0 && !(tn > 0.0)) {   // T = 0: every vector is an eigenvector
-    for (int j = 0; j < n; ++j) y[j] = j == 0 ? 1.0 : 0.0;
-  } else if (lane == 0) {
+  // 3. inverse iteration.  The elimination is sequential: every lane runs it
+  // on the same (uniform) values, and each array is one register spread over
+  // the lanes (element j in lane j), read and written with lane operations.
+  const double dv = lane < n ? d[lane] : 0.0, ev = lane + 1 < n ? e[lane] : 0.0;
+  double yv;
+  if (!(tn > 0.0)) {   // T = 0: every vector is an eigenvector
+    yv = lane == 0 ? 1.0 : 0.0;
+  } else {
     // work with (T - lambda I) / ||T|| so that the iterates cannot overflow
     const double sc = 1.0 / tn, tiny = eps;
     // factor = P L U; row j of U is (U0, U1, U2) at columns j, j+1, j+2
-    double a = (d[0] - lambda) * sc, b = n > 1 ? e[0] * sc : 0.0, c = 0.0;
+    double u0v = 0.0, u1v = 0.0, u2v = 0.0, mlv = 0.0;
+    int swv = 0;
+    double a = (readlane_d(dv, 0) - lambda) * sc, b = n > 1 ? readlane_d(ev, 0) * sc : 0.0, c = 0.0;
     for (int j = 0; j + 1 < n; ++j) {
-      const double sub = e[j] * sc, dn = (d[j + 1] - lambda) * sc, en = j + 2 < n ? e[j + 1] * sc : 0.0;
+      const double sub = readlane_d(ev, j) * sc, dn = (readlane_d(dv, j + 1) - lambda) * sc;
+      const double en = j + 2 < n ? readlane_d(ev, j + 1) * sc : 0.0;
+      double r0, r1, r2, m;
+      int swj;
       if (fabs(a) >= fabs(sub)) {
-        const double m = a != 0.0 ? sub / a : 0.0;
-        U0[j] = a; U1[j] = b; U2[j] = c; ml[j] = m; sw[j] = 0;
+        m = a != 0.0 ? sub / a : 0.0;
+        r0 = a; r1 = b; r2 = c; swj = 0;
         a = dn - m * b;
         b = en - m * c;
       } else {
-        const double m = a / sub;
-        U0[j] = sub; U1[j] = dn; U2[j] = en; ml[j] = m; sw[j] = 1;
+        m = a / sub;
+        r0 = sub; r1 = dn; r2 = en; swj = 1;
         a = b - m * dn;
         b = c - m * en;
       }
       c = 0.0;
+      u0v = writelane(r0, j, u0v);
+      u1v = writelane(r1, j, u1v);
+      u2v = writelane(r2, j, u2v);
+      mlv = writelane(m, j, mlv);
+      swv = writelane(swj, j, swv);
     }
-    U0[n - 1] = a; U1[n - 1] = 0.0; U2[n - 1] = 0.0;
-    // pivots below eps replaced by eps; their reciprocals kept (in U0)
-    for (int j = 0; j < n; ++j) {
-      const double u = fabs(U0[j]) < tiny ? (U0[j] < 0.0 ? -tiny : tiny) : U0[j];
-      U0[j] = 1.0 / u;
+    u0v = writelane(a, n - 1, u0v);
+    u1v = writelane(0.0, n - 1, u1v);
+    u2v = writelane(0.0, n - 1, u2v);
+    // pivots below eps replaced by eps; their reciprocals kept (all lanes at once)
+    {
+      const double u = fabs(u0v) < tiny ? (u0v < 0.0 ? -tiny : tiny) : u0v;
+      u0v = lane < n ? 1.0 / u : 0.0;
     }
-    for (int j = 0; j < n; ++j) y[j] = 1.0 / sqrt((double)n);
+    yv = lane < n ? 1.0 / sqrt((double)n) : 0.0;
     for (int it = 0; it < 2; ++it) {
       // y <- L^-1 P y, the running entry carried in a register
-      double cur = y[0];
+      double cur = readlane_d(yv, 0);
       for (int j = 0; j + 1 < n; ++j) {
-        const double nxt = y[j + 1];
-        if (sw[j]) {
-          y[j] = nxt;
-          cur = cur - ml[j] * nxt;
+        const double nxt = readlane_d(yv, j + 1), m = readlane_d(mlv, j);
+        if (__builtin_amdgcn_readlane(swv, j)) {
+          yv = writelane(nxt, j, yv);
+          cur = cur - m * nxt;
         } else {
-          y[j] = cur;
-          cur = nxt - ml[j] * cur;
+          yv = writelane(cur, j, yv);
+          cur = nxt - m * cur;
         }
       }
-      y[n - 1] = cur;
+      yv = writelane(cur, n - 1, yv);
       // y <- U^-1 y, the two entries below carried in registers
       double y1 = 0.0, y2 = 0.0, s2 = 0.0;
       for (int j = n - 1; j >= 0; --j) {
-        const double t = (y[j] - U1[j] * y1 - U2[j] * y2) * U0[j];
-        y[j] = t;
+        const double t = (readlane_d(yv, j) - readlane_d(u1v, j) * y1 - readlane_d(u2v, j) * y2) *
+                         readlane_d(u0v, j);
+        yv = writelane(t, j, yv);
         s2 += t * t;
         y2 = y1;
         y1 = t;
       }
-      const double inv = 1.0 / sqrt(s2);
-      for (int j = 0; j < n; ++j) y[j] *= inv;
+      yv *= 1.0 / sqrt(s2);
     }
   }
-  __syncthreads();
   // 4. x = H_0 (H_1 (... (H_{n-3} y)))
-  double xr = lane < n ? y[lane] : 0.0;
+  double xr = lane < n ? yv : 0.0;
   for (int k = n - 3; k >= 0; --k) {
     const double v = Vh[k][lane];
-    const double dv = wave_sum(v * xr);
+    const double dv = wave_total(v * xr);
     xr -= 2.0 * dv * v;
   }
   if (lane < n) svec[(int64_t)p * B + lane] = xr;
