@@ -13,31 +13,6 @@ constexpr int DT = 256;   // threads per block of the vector kernels
 constexpr int PER = kChunk / DT;
 constexpr int kMaxBasisD = 64;   // largest basis (J) of the multi-dot kernels
 
-// Deterministic block sum (wave shuffles, then the four wave sums in order).
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[wave] = v;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) / 64;
-    for (int w = 0; w < nw; ++w) r += sh[w];
-    sh[8] = r;
-  }
-  __syncthreads();
-  return sh[8];
-}
-
-// Per-block sums of J values per thread (vals[j] for the calling thread):
-// wave butterflies, then the four wave sums added in order by thread j; one
-// barrier for all J.  Writes part[j * nct + blockIdx.x].
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 // Sum over the 64 lanes of a wave, the same value on every lane, in one
 // fixed order: DPP exchanges inside each row of 16 lanes (pairs, quads, half
 // rows, rows), then the four row sums read from lanes 0, 16, 32, 48 and
@@ -67,6 +42,26 @@ __device__ __forceinline__ double wave_total(double v) {
   v += mov_dpp_d<0x140>(v);   // row_mirror: the other half of the row
   return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
+
+// Sum over the threads of a block: wave sums, then the wave sums added in
+// wave order by thread 0; the result is returned to every thread.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_total(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) / 64;
+    for (int w = 0; w < nw; ++w) r += sh[w];
+    sh[8] = r;
+  }
+  __syncthreads();
+  return sh[8];
+}
+
+__device__ __forceinline__ double wave_sum(double v) { return wave_total(v); }
 
 // out[j] = sum over the problem's chunks of part[j * nct + chunk] for j < J
 // (thread-strided sums, then the deterministic block tree); result in LDS.
@@ -109,6 +104,7 @@ __global__ __launch_bounds__(DT) void dots_kernel(const Chunk* __restrict__ chun
     const int e = threadIdx.x + u * DT;
     yv[u] = e < ch.len ? y[ch.start + e] : 0.0;
   }
+#pragma unroll 4
   for (int j = 0; j < J; ++j) {
     const double* Xj = X + j * xstride + ch.start;
     double s = 0.0;
@@ -442,6 +438,7 @@ __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chun
     if (e >= ch.len) continue;
     const int64_t g = ch.start + e;
     double xv = 0.0, av = 0.0;
+#pragma unroll 4
     for (int j = 0; j < J; ++j) {
       xv += sv[j] * V[j * stride + g];
       av += sv[j] * VA[j * stride + g];
@@ -455,6 +452,7 @@ __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chun
   nrm = wave_sum(nrm);
   if (lane == 0) ws[kMaxBasisD][wave] = nrm;
   if (part_d) {
+#pragma unroll 4
     for (int j = 0; j < J; ++j) {
       double d = 0.0;
 #pragma unroll
@@ -495,6 +493,7 @@ __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ ch
     if (e < ch.len) {
       const int64_t g = ch.start + e;
       double v = q[g];
+#pragma unroll 4
       for (int j = 0; j < J; ++j) v -= cj[j] * V[j * stride + g];
       q[g] = v;
       qv[u] = v;
@@ -504,6 +503,7 @@ __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ ch
   }
   if (mode == 1) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll 4
     for (int j = 0; j < J; ++j) {
       double s = 0.0;
 #pragma unroll
