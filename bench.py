@@ -46,7 +46,7 @@ HBM_PEAK = 8000.0                       # GB/s
 # bond, from rocprofv3 FETCH_SIZE and WRITE_SIZE counters of the current
 # kernel (FETCH_SIZE scaled by 1.989 and WRITE_SIZE by 1.000, the ratios of
 # the known size of a plain device copy to what the counters read for it)
-HBM_TRAFFIC = {"s1": 71896388, "s3": 91486877}
+HBM_TRAFFIC = {"s1": 72457089, "s3": 93191677}
 
 
 def parse():
@@ -322,7 +322,8 @@ def dense_ablation(spec, plan, dev, reps=5):
 
 def autotune(plan, info, dev, stream):
     """Tile shape classes of the S1/S3 launches chosen by the library's
-    autotuner (timed in FP32, the precision of most products)."""
+    autotuner (timed in FP32, the precision of most products), and the S3
+    split-K width the plan chose."""
     import torch
     from paper_2007_05540_amd import lib
     ws = torch.empty(info["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
@@ -330,7 +331,9 @@ def autotune(plan, info, dev, stream):
     got = lib.plan_autotune(plan, lib.F32, dev["L"], dev["W1"], dev["W2"], dev["R"], dev["psi"], out, ws,
                             reps=10, stream=stream)
     del ws, out
-    return {k: ("64x64 only" if v >= lib.NO_BIG_TILES else f"128x128 for M,N>={v}") for k, v in got.items()}
+    res = {k: ("64x64 only" if v >= lib.NO_BIG_TILES else f"128x128 for M,N>={v}") for k, v in got.items()}
+    res["s3_split_k"] = info["s3_split_k"] if info["s3_split_k"] > 0 else "none"
+    return res
 
 
 def bond_measure(spec, args):

@@ -122,6 +122,12 @@ typedef struct {
   int64_t s1_big_min, s3_big_min;       /* tile shape classes: tasks with M and N >=
                                            this use 128 x 128 tiles, the others
                                            64 x 64 (2^30: 64 x 64 only) */
+  int64_t s3_split_k;                   /* S3 split-K width chosen by the plan: tasks
+                                           whose K-list is longer are cut into pieces
+                                           of at most this width and summed in a fixed
+                                           order (0: no task is split).  The widest of
+                                           none, 4096, 2048, 1024 that leaves at least
+                                           3072 S3 tiles of 64 x 64, else 512. */
 } bsdmrg_plan_info;
 
 bsdmrg_status bsdmrg_plan_query(bsdmrg_plan_t plan, bsdmrg_plan_info* info);

@@ -441,6 +441,7 @@ bsdmrg_status bsdmrg_plan_query(bsdmrg_plan_t P, bsdmrg_plan_info* info) {
     info->n_coefs = P->n_coefs;
     info->s1_big_min = P->s1.big_min;
     info->s3_big_min = P->s3.big_min;
+    info->s3_split_k = P->s3_split;
   });
 }
 

@@ -195,6 +195,7 @@ struct bsdmrg_plan_s {
   bsd::Stage s1, s3;
   // split-K of S3: partial tiles summed in fixed order by the mixing kernel
   int64_t s3_part_elems = 0;
+  int32_t s3_split = 0;   // S3 split-K width (0: tasks not split)
   std::vector<bsd::MixTask> red_tasks;
   std::vector<bsd::MixTerm> red_terms;
   std::vector<bsd::MixItem> red_items;

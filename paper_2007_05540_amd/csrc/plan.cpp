@@ -26,7 +26,15 @@ namespace bsd {
 
 constexpr int kTileM = 64, kTileN = 64;
 constexpr int kMixItemElems = 4096;
-constexpr int kSplitK = 512;        // S3 K pieces longer than this are split
+// S3 split-K: a task whose K-list is longer than the width is cut into pieces
+// of at most that width, summed afterwards in a fixed order.  The width is the
+// widest of kSplitWidths (0: no split) that still leaves at least kMinS3Tiles
+// tiles of 64 x 64 (three rounds of four workgroups on each of the 256 CUs),
+// else kSplitK: splitting only to fill the chip, since every piece adds a
+// partial block to write and sum.
+constexpr int kSplitK = 512;
+constexpr int kSplitWidths[] = {0, 4096, 2048, 1024};
+constexpr int64_t kMinS3Tiles = 3072;
 
 static const int32_t kPsiSigns[4] = {1, 1, 1, -1};
 static const int32_t kEnvSigns[3] = {-1, 1, 1};
@@ -260,16 +268,40 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
   P->n_coefs += p.n_coefs;
 }
 
-// Split every S3 task whose K-list is longer than kSplitK into pieces of at
-// most kSplitK (segments are cut along K: the A and B offsets move by k0
-// columns).  Each piece writes an M x N partial block; the pieces of a task
-// are summed in piece order by the reduction tables.
+// 64 x 64 tiles of S3 if tasks with a K-list longer than w (> 0) are split.
+static int64_t s3_tiles_at(const Stage& st, int w) {
+  int64_t n = 0;
+  for (const GemmTask& t : st.tasks) {
+    const int64_t tiles = (int64_t)((t.M + kTileM - 1) / kTileM) * ((t.N + kTileN - 1) / kTileN);
+    int64_t pieces = 1;
+    if (w > 0 && t.ksum > w) {
+      pieces = 0;
+      for (int j = 0; j < t.nseg; ++j) pieces += (st.segs[t.seg0 + j].K + w - 1) / w;
+    }
+    n += tiles * pieces;
+  }
+  return n;
+}
+
+static int choose_split(const Stage& st) {
+  for (int w : kSplitWidths)
+    if (s3_tiles_at(st, w) >= kMinS3Tiles) return w;
+  return kSplitK;
+}
+
+// Split every S3 task whose K-list is longer than the chosen width into
+// pieces of at most that width (segments are cut along K: the A and B offsets
+// move by k0 columns).  Each piece writes an M x N partial block; the pieces
+// of a task are summed in piece order by the reduction tables.
 static void split_k(bsdmrg_plan_s* P) {
   Stage& st = P->s3;
+  const int w = choose_split(st);
+  P->s3_split = w;
+  if (w == 0) return;
   std::vector<GemmTask> tasks;
   std::vector<GemmSeg> segs;
   for (const GemmTask& t : st.tasks) {
-    if (t.ksum <= kSplitK) {
+    if (t.ksum <= w) {
       GemmTask u = t;
       u.seg0 = (int32_t)segs.size();
       for (int j = 0; j < t.nseg; ++j) segs.push_back(st.segs[t.seg0 + j]);
@@ -279,8 +311,8 @@ static void split_k(bsdmrg_plan_s* P) {
     MixTask red{t.c_off, t.ldc, t.M, t.N, (int32_t)P->red_terms.size(), 0, 0};
     for (int j = 0; j < t.nseg; ++j) {
       const GemmSeg& g = st.segs[t.seg0 + j];
-      for (int k0 = 0; k0 < g.K; k0 += kSplitK) {
-        const int32_t kk = std::min(kSplitK, g.K - k0);
+      for (int k0 = 0; k0 < g.K; k0 += w) {
+        const int32_t kk = std::min(w, g.K - k0);
         GemmSeg h{g.a_off + k0, g.b_off + k0, g.lda, g.ldb, kk, 0};
         GemmTask u{P->s3_part_elems, t.N, t.M, t.N, (int32_t)segs.size(), 1, kk, 1, 0};
         segs.push_back(h);

@@ -45,7 +45,8 @@ class PlanInfo(ctypes.Structure):
                                                "apply_workspace_bytes", "backward_workspace_bytes")] + \
                [(n, ctypes.c_double) for n in ("flops_s1", "flops_s2", "flops_s3")] + \
                [(n, ctypes.c_int64) for n in ("n_s1_tasks", "n_s3_tasks", "n_s1_tiles", "n_s3_tiles",
-                                               "n_mix_terms", "n_coefs", "s1_big_min", "s3_big_min")]
+                                               "n_mix_terms", "n_coefs", "s1_big_min", "s3_big_min",
+                                               "s3_split_k")]
 
 
 class EigOpts(ctypes.Structure):

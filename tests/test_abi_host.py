@@ -158,3 +158,23 @@ def test_plan_rejects_bond_sector_above_4096(lib):
     with pytest.raises(lib.BsdmrgError) as e:
         lib.Plan([prob], host_only=True)
     assert e.value.status == lib.EINVAL
+
+
+@pytest.mark.parametrize("name,spec_fn,expect", [
+    ("spin m=128", lambda: synth.c2_bond(m=128, k=14, seed=3), 512),
+    ("spin m=1024", lambda: synth.c2_bond(m=1024, k=14, seed=1), 512),
+    ("spin m=2048", lambda: synth.c2_bond(m=2048, k=14, seed=1), 1024),
+    ("electron m=4096", lambda: synth.c4_bond(m=4096, k=22, seed=1), 0),
+])
+def test_s3_split_width_rule(lib, name, spec_fn, expect):
+    """S3 split-K width: the widest of none, 4096, 2048, 1024 that keeps at
+    least 3072 S3 tiles, else 512."""
+    from paper_2007_05540_amd import problems
+    prob, _ = problems.bond_problem(spec_fn())
+    plan = lib.Plan([prob], host_only=True)
+    info = plan.info()
+    plan.destroy()
+    assert info["s3_split_k"] in (0, 4096, 2048, 1024, 512)
+    assert info["s3_split_k"] == expect, name
+    if info["s3_split_k"] != 512:
+        assert info["n_s3_tiles"] >= 3072
