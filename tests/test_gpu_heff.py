@@ -144,6 +144,30 @@ def test_apply_hubbard_bond_full_size(mods):
     assert 1e-9 < rel(outs[lib.F32], ref) < 5e-5
 
 
+@pytest.mark.parametrize("spec_fn,width", [(lambda: synth.c2_bond(m=1024, k=14, seed=1), 512),
+                                            (lambda: synth.c2_bond(m=2048, k=14, seed=1), 1024)])
+def test_apply_split_k_widths_match_oracle(mods, spec_fn, width):
+    """The plan's S3 split-K width (512 at m=1024, 1024 at m=2048; the m=4096
+    electron bond is unsplit): FP64 output element by element against the
+    oracle, FP32 within the FP32 bound."""
+    lib, problems = mods
+    spec = spec_fn()
+    plan, ops, d = setup([spec], lib, problems)
+    info = plan.info()
+    assert info["s3_split_k"] == width
+    ws = torch.empty(info["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    outs = {}
+    for prec in (lib.F64, lib.F32):
+        out = torch.zeros_like(d["psi"])
+        lib.heff_apply(plan, prec, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
+        torch.cuda.synchronize()
+        outs[prec] = out.cpu().numpy()
+    del ws, d
+    ref = oracle_apply(spec)
+    assert rel(outs[lib.F64], ref) < 1e-12
+    assert 1e-9 < rel(outs[lib.F32], ref) < 5e-5
+
+
 def test_apply_f32_within_fp32_bound(mods):
     lib, problems = mods
     spec = synth.c2_bond(m=512, k=14, seed=7)
