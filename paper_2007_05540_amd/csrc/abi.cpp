@@ -239,6 +239,7 @@ static EigWS carve_eig(const bsdmrg_plan_s* P, const bsdmrg_eig_opts* o, Carve& 
   d.part_b = c.take<double>((size_t)(B + 1) * nch);
   d.part_n0 = c.take<double>(nch);
   d.part_n1 = c.take<double>(nch);
+  d.nq0 = c.take<double>(np);
   d.red = c.take<double>((size_t)np * 64);
   d.M = c.take<double>((size_t)np * B * B);
   d.svec = c.take<double>((size_t)np * B);

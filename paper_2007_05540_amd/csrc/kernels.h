@@ -58,6 +58,7 @@ struct DavBufs {
   double* part_b;
   double* part_n0;  // nchunk: ||q||^2 before orthogonalisation
   double* part_n1;  // nchunk: ||q||^2 after
+  double* nq0;      // n_probs: ||q||^2 before orthogonalisation (total)
   double* red;      // n_probs * 64 per-problem sums of partials
   double* M;        // n_probs * B * B projected matrices
   double* svec;     // n_probs * B Ritz vectors of M

@@ -415,7 +415,8 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
 
 // q = sum s_j v^A_j - lambda sum s_j v_j with partial ||q||^2; when x is
 // non-null the Ritz vector x = sum s_j v_j is stored too, and when part_d is
-// non-null the partial dots v_j^T q (the first Gram-Schmidt pass) as well.
+// non-null the partial dots v_j^T q (the first Gram-Schmidt pass, columns
+// j < J) and the partial ||q||^2 again (column J) as well.
 __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chunks, int nct, int J, int B,
                                                   const double* __restrict__ V, const double* __restrict__ VA,
                                                   int64_t stride, const double* __restrict__ svec,
@@ -471,21 +472,33 @@ __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chun
     const int j = threadIdx.x;
     part_d[(int64_t)j * nct + blockIdx.x] = ((ws[j][0] + ws[j][1]) + ws[j][2]) + ws[j][3];
   }
+  // column J of the first-pass partials: ||q||^2 before orthogonalisation
+  if (part_d && threadIdx.x == 0)
+    part_d[(int64_t)J * nct + blockIdx.x] =
+        ((ws[kMaxBasisD][0] + ws[kMaxBasisD][1]) + ws[kMaxBasisD][2]) + ws[kMaxBasisD][3];
 }
 
-// q -= sum_j c_j v_j with c_j = red[p * ldr + j]; mode 1 then writes the
-// partial dots v_j^T q, mode 2 the partial ||q||^2.
+// Classical Gram-Schmidt pass q -= sum_j c_j v_j with c_j = red[p * ldr + j].
+// Mode 1 (first pass): red[p * ldr + J] holds ||q||^2 before the pass, kept
+// in nq0[p]; writes the partial dots v_j^T q (columns j < J) and the partial
+// ||q||^2 after the pass (column J).  Mode 2 (second pass): red[p * ldr + J]
+// holds ||q||^2 after the first pass; the pass is made only when the first
+// one lost more than half of ||q||^2 ("twice is enough": otherwise q is
+// already orthogonal to working accuracy), and the partial ||q||^2 is written.
 __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ chunks, int nct, int J,
                                                     const double* __restrict__ V, int64_t stride, int ldr,
                                                     const double* __restrict__ red,
                                                     double* __restrict__ q, double* __restrict__ part_out,
-                                                    int mode) {
+                                                    double* __restrict__ nq0, int mode) {
   __shared__ double sh[16];
   __shared__ double cj[kMaxBasis];
   __shared__ double wsum[kMaxBasisD][4];
   const Chunk ch = chunks[blockIdx.x];
   if ((int)threadIdx.x < J) cj[threadIdx.x] = red[(int64_t)ch.prob * ldr + threadIdx.x];
+  const double nred = red[(int64_t)ch.prob * ldr + J];
+  if (mode == 1 && threadIdx.x == 0) nq0[ch.prob] = nred;   // same value from every block
   __syncthreads();
+  const bool pass = mode == 1 || !(nred >= 0.5 * nq0[ch.prob]);
   double qv[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
@@ -493,9 +506,11 @@ __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ ch
     if (e < ch.len) {
       const int64_t g = ch.start + e;
       double v = q[g];
+      if (pass) {
 #pragma unroll 4
-      for (int j = 0; j < J; ++j) v -= cj[j] * V[j * stride + g];
-      q[g] = v;
+        for (int j = 0; j < J; ++j) v -= cj[j] * V[j * stride + g];
+        q[g] = v;
+      }
       qv[u] = v;
     } else {
       qv[u] = 0.0;
@@ -514,8 +529,13 @@ __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ ch
       s = wave_sum(s);
       if (lane == 0) wsum[j][wave] = s;
     }
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) s += qv[u] * qv[u];
+    s = wave_sum(s);
+    if (lane == 0) wsum[J][wave] = s;
     __syncthreads();
-    if ((int)threadIdx.x < J) {
+    if ((int)threadIdx.x <= J) {
       const int j = threadIdx.x;
       part_out[(int64_t)j * nct + blockIdx.x] = ((wsum[j][0] + wsum[j][1]) + wsum[j][2]) + wsum[j][3];
     }
@@ -669,10 +689,11 @@ hipError_t dav_ritz(const bsdmrg_plan_s* P, const DavBufs& b, int i, bool want_x
 
 hipError_t dav_update(const bsdmrg_plan_s* P, const DavBufs& b, int J, const double* part_in,
                       double* part_out, int mode, hipStream_t s) {
-  hipError_t e = dav_psum(P, J, part_in, b.red, kMaxBasis, s);
+  if (J < 1 || J >= kMaxBasisD) return hipErrorInvalidValue;   // column J holds a norm
+  hipError_t e = dav_psum(P, J + 1, part_in, b.red, kMaxBasis, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(update_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), J, b.V,
-                     b.n, kMaxBasis, b.red, b.q, part_out, mode);
+                     b.n, kMaxBasis, b.red, b.q, part_out, b.nq0, mode);
   return hipGetLastError();
 }
 
