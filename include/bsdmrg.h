@@ -189,8 +189,9 @@ bsdmrg_status bsdmrg_eig_workspace(bsdmrg_plan_t plan, const bsdmrg_eig_opts* op
  * x = sum s_j v_j, q = sum s_j v^A_j - lambda x; stop when ||q|| <= tol, or
  * when the basis spans the whole space (its size equals the number of allowed
  * elements of psi: the Ritz pair is then exact; in a batch the smallest
- * problem sets this cap); q is orthogonalised against the basis
- * twice (classical Gram-Schmidt applied twice); if ||q|| drops below
+ * problem sets this cap); q is orthogonalised against the basis by
+ * classical Gram-Schmidt, with a second pass only when the first removed
+ * more than half of ||q||^2 ("twice is enough"); if ||q|| drops below
  * restart_rtol times its value before orthogonalisation, q is replaced by a
  * seeded Gaussian vector (SplitMix64 + Box-Muller, key from seed, step,
  * attempt; at most 3 attempts).  All orthogonalisation, Rayleigh quotients
