@@ -26,6 +26,8 @@ namespace bsd {
 
 constexpr int kTileM = 64, kTileN = 64;
 constexpr int kMixItemElems = 4096;
+constexpr int kRedItemSmall = 1024;
+constexpr int64_t kMinRedItems = 256;
 // S3 split-K: a task whose K-list is longer than the width is cut into pieces
 // of at most that width, summed afterwards in a fixed order.  The width is the
 // widest of kSplitWidths (0: no split) that still leaves at least kMinS3Tiles
@@ -322,14 +324,22 @@ static void split_k(bsdmrg_plan_s* P) {
       }
     }
     red.nterm = (int32_t)P->red_terms.size() - red.term0;
-    const int task = (int)P->red_tasks.size();
     P->red_tasks.push_back(red);
-    int rows_per = std::max(1, kMixItemElems / std::max(1, t.N));
-    for (int r0 = 0; r0 < t.M; r0 += rows_per)
-      P->red_items.push_back(MixItem{task, r0, std::min(rows_per, t.M - r0), 0});
   }
   st.tasks.swap(tasks);
   st.segs.swap(segs);
+  // reduction workgroups of whole rows, up to kMixItemElems outputs each, or
+  // up to kRedItemSmall when the larger ones would number fewer than one per
+  // CU (kMinRedItems)
+  auto rows_per = [](const MixTask& r, int item) { return std::max(1, item / std::max(1, r.cols)); };
+  int64_t n_big = 0;
+  for (const MixTask& r : P->red_tasks) n_big += (r.rows + rows_per(r, kMixItemElems) - 1) / rows_per(r, kMixItemElems);
+  const int item = n_big < kMinRedItems ? kRedItemSmall : kMixItemElems;
+  for (int task = 0; task < (int)P->red_tasks.size(); ++task) {
+    const MixTask& r = P->red_tasks[task];
+    const int rp = rows_per(r, item);
+    for (int r0 = 0; r0 < r.rows; r0 += rp) P->red_items.push_back(MixItem{task, r0, std::min(rp, r.rows - r0), 0});
+  }
 }
 
 }  // namespace bsd
