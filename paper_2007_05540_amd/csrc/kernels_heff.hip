@@ -311,7 +311,9 @@ __global__ __launch_bounds__(NTHR) void ggemm_kernel(const GemmTile* __restrict_
 }
 
 // MPO mixing (S2): each workgroup handles one row range of one task; every
-// thread owns up to 16 elements and issues the 16 loads of a term together.
+// thread owns up to 16 elements and issues the 16 loads of a term together,
+// from the term's block base (scalar registers) plus a 32-bit byte offset
+// (source blocks below 2^29 elements: checked on the host).
 // coef == nullptr means unit coefficients (the split-K reduction).
 template <typename T, typename TACC>
 __global__ __launch_bounds__(NTHR) void mix_kernel(const MixItem* __restrict__ items,
@@ -320,9 +322,6 @@ __global__ __launch_bounds__(NTHR) void mix_kernel(const MixItem* __restrict__ i
                                                    const double* __restrict__ coef,
                                                    const T* __restrict__ src, T* __restrict__ dst) {
   constexpr int PER = 16;   // kMixItemElems = 4096 = 16 * 256
-  __shared__ int64_t s_off[64];
-  __shared__ int32_t s_ld[64];
-  __shared__ TACC s_c[64];
   const MixItem it = items[blockIdx.x];
   const MixTask t = tasks[it.task];
   const int n = it.nrows * t.cols;
@@ -335,29 +334,24 @@ __global__ __launch_bounds__(NTHR) void mix_kernel(const MixItem* __restrict__ i
     cc[q] = e % t.cols;
     acc[q] = 0;
   }
-  for (int t0 = 0; t0 < t.nterm; t0 += 64) {
-    const int nt = min(64, t.nterm - t0);
-    __syncthreads();
-    if ((int)threadIdx.x < nt) {
-      const MixTerm m = terms[t.term0 + t0 + threadIdx.x];
-      s_off[threadIdx.x] = m.src_off;
-      s_ld[threadIdx.x] = m.ld_src;
-      s_c[threadIdx.x] = coef ? (TACC)coef[m.coef] : (TACC)1;
-    }
-    __syncthreads();
-    for (int j = 0; j < nt; ++j) {
-      const T* sp = src + s_off[j];
-      const int ld = s_ld[j];
-      const TACC cj = s_c[j];
-      T v[PER];
+  // terms read with a uniform index (scalar registers), the next one fetched
+  // while the current one is applied; element offsets within a source block
+  // are 32-bit
+  MixTerm m = t.nterm > 0 ? terms[t.term0] : MixTerm{0, 0, 0};
+  for (int j = 0; j < t.nterm; ++j) {
+    const MixTerm cur = m;
+    if (j + 1 < t.nterm) m = terms[t.term0 + j + 1];
+    const T* sp = src + cur.src_off;
+    const TACC cj = coef ? (TACC)coef[cur.coef] : (TACC)1;
+    T v[PER];
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int e = threadIdx.x + q * NTHR;
-        v[q] = e < n ? sp[(int64_t)rr[q] * ld + cc[q]] : (T)0;
-      }
-#pragma unroll
-      for (int q = 0; q < PER; ++q) acc[q] += cj * (TACC)v[q];
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * NTHR;
+      v[q] = e < n ? *(const T*)((const char*)sp + (unsigned)(rr[q] * cur.ld_src + cc[q]) * (unsigned)sizeof(T))
+                   : (T)0;
     }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) acc[q] += cj * (TACC)v[q];
   }
 #pragma unroll
   for (int q = 0; q < PER; ++q) {

@@ -75,6 +75,9 @@ void validate_mix(const std::vector<MixTask>& tasks, const std::vector<MixTerm>&
       const MixTerm& m = terms[t.term0 + j];
       if (t.cols > m.ld_src || m.src_off < 0 || m.src_off + (int64_t)(t.rows - 1) * m.ld_src + t.cols > src_elems)
         fail(std::string(name) + ": src extent");
+      // the mixing kernel addresses a source block with 32-bit byte offsets
+      if ((int64_t)(t.rows - 1) * m.ld_src + t.cols > ((int64_t)1 << 29))
+        fail(std::string(name) + ": source block above 2^29 elements");
       if (coef_elems >= 0 && (m.coef < 0 || m.coef >= coef_elems)) fail(std::string(name) + ": coef index");
     }
   }
