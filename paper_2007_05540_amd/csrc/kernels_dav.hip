@@ -13,6 +13,15 @@ constexpr int DT = 256;   // threads per block of the vector kernels
 constexpr int PER = kChunk / DT;
 constexpr int kMaxBasisD = 64;   // largest basis (J) of the multi-dot kernels
 
+// Element i of a chunk-local array: a wave-uniform base plus a 32-bit byte
+// offset (chunks hold kChunk elements), so loads and stores take a scalar base.
+__device__ __forceinline__ double ld_at(const double* base, unsigned i) {
+  return *(const double*)((const char*)base + i * 8u);
+}
+__device__ __forceinline__ void st_at(double* base, unsigned i, double v) {
+  *(double*)((char*)base + i * 8u) = v;
+}
+
 // Sum over the 64 lanes of a wave, the same value on every lane, in one
 // fixed order: DPP exchanges inside each row of 16 lanes (pairs, quads, half
 // rows, rows), then the four row sums read from lanes 0, 16, 32, 48 and
@@ -102,7 +111,7 @@ __global__ __launch_bounds__(DT) void dots_kernel(const Chunk* __restrict__ chun
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int e = threadIdx.x + u * DT;
-    yv[u] = e < ch.len ? y[ch.start + e] : 0.0;
+    yv[u] = e < ch.len ? ld_at(y + ch.start, e) : 0.0;
   }
 #pragma unroll 4
   for (int j = 0; j < J; ++j) {
@@ -111,7 +120,7 @@ __global__ __launch_bounds__(DT) void dots_kernel(const Chunk* __restrict__ chun
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = threadIdx.x + u * DT;
-      if (e < ch.len) s += Xj[e] * yv[u];
+      if (e < ch.len) s += ld_at(Xj, e) * yv[u];
     }
     s = wave_sum(s);
     if (lane == 0) ws[j][wave] = s;
@@ -437,16 +446,15 @@ __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chun
     const int e = threadIdx.x + u * DT;
     qv[u] = 0.0;
     if (e >= ch.len) continue;
-    const int64_t g = ch.start + e;
     double xv = 0.0, av = 0.0;
 #pragma unroll 4
     for (int j = 0; j < J; ++j) {
-      xv += sv[j] * V[j * stride + g];
-      av += sv[j] * VA[j * stride + g];
+      xv += sv[j] * ld_at(V + j * stride + ch.start, e);
+      av += sv[j] * ld_at(VA + j * stride + ch.start, e);
     }
     const double v = av - l * xv;
-    if (x) x[g] = xv;
-    q[g] = v;
+    if (x) st_at(x + ch.start, e, xv);
+    st_at(q + ch.start, e, v);
     qv[u] = v;
     nrm += v * v;
   }
@@ -459,7 +467,7 @@ __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chun
 #pragma unroll
       for (int u = 0; u < PER; ++u) {
         const int e = threadIdx.x + u * DT;
-        if (e < ch.len) d += V[j * stride + ch.start + e] * qv[u];
+        if (e < ch.len) d += ld_at(V + j * stride + ch.start, e) * qv[u];
       }
       d = wave_sum(d);
       if (lane == 0) ws[j][wave] = d;
@@ -504,12 +512,11 @@ __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ ch
   for (int u = 0; u < PER; ++u) {
     const int e = threadIdx.x + u * DT;
     if (e < ch.len) {
-      const int64_t g = ch.start + e;
-      double v = q[g];
+      double v = ld_at(q + ch.start, e);
       if (pass) {
 #pragma unroll 4
-        for (int j = 0; j < J; ++j) v -= cj[j] * V[j * stride + g];
-        q[g] = v;
+        for (int j = 0; j < J; ++j) v -= cj[j] * ld_at(V + j * stride + ch.start, e);
+        st_at(q + ch.start, e, v);
       }
       qv[u] = v;
     } else {
@@ -524,7 +531,7 @@ __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ ch
 #pragma unroll
       for (int u = 0; u < PER; ++u) {
         const int e = threadIdx.x + u * DT;
-        if (e < ch.len) s += V[j * stride + ch.start + e] * qv[u];
+        if (e < ch.len) s += ld_at(V + j * stride + ch.start, e) * qv[u];
       }
       s = wave_sum(s);
       if (lane == 0) wsum[j][wave] = s;
@@ -632,7 +639,7 @@ __global__ __launch_bounds__(DT) void scale_kernel(const Chunk* __restrict__ chu
                                                    const double* __restrict__ x, double* __restrict__ y) {
   const Chunk ch = chunks[blockIdx.x];
   const double s = scale[ch.prob];
-  for (int e = threadIdx.x; e < ch.len; e += DT) y[ch.start + e] = x[ch.start + e] * s;
+  for (int e = threadIdx.x; e < ch.len; e += DT) st_at(y + ch.start, e, ld_at(x + ch.start, e) * s);
 }
 
 __global__ void fill_zero_kernel(double* x, int64_t n) {
