@@ -154,6 +154,27 @@ bsdmrg_status bsdmrg_heff_apply(bsdmrg_plan_t plan, int32_t precision, const dou
                                 const double* psi, double* out, void* workspace,
                                 int64_t workspace_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (work captured into a
+ * graph, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as bsdmrg_heff_apply, same arguments and results (bit for bit),
+ * without a workspace argument.  Its workspace is a library-owned array of
+ * BSDMRG_NOALLOC_SCRATCH_BYTES in device memory, one per GPU, created when
+ * the library's code is loaded on that GPU and held until the process ends;
+ * the call itself allocates nothing (no hipMalloc, no host-side library
+ * allocation of device memory).  Plans whose product needs more scratch in
+ * the requested precision (FP64: T1 and T2 in FP64 plus the split-K pieces;
+ * FP32: T1 and T2 in FP32, the pieces and FP32 copies of L and R; at most
+ * apply_workspace_bytes) are rejected with EINVAL before any work is
+ * enqueued; the m = 1024, k = 14 bond needs 144 MB in FP64.  Every call on a
+ * GPU uses that GPU's one array: calls whose work overlaps on one GPU (two
+ * streams, two threads, or a captured graph replayed concurrently with
+ * another call) race and give wrong results; order them on one stream.
+ * Nothing in the array needs to start at zero.  Errors: EINVAL, EHIP. */
+#define BSDMRG_NOALLOC_SCRATCH_BYTES (160ll << 20)
+bsdmrg_status bsdmrg_heff_apply_noalloc(bsdmrg_plan_t plan, int32_t precision, const double* L,
+                                        const double* W1, const double* W2, const double* R,
+                                        const double* psi, double* out, hipStream_t stream);
+
 /* Davidson options (Alg. 1; readings of the silent points in the docs of
  * bsdmrg_eigensolve). */
 typedef struct {

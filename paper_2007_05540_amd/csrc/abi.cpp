@@ -94,6 +94,23 @@ static size_t apply_bytes(const bsdmrg_plan_s* P) {
   return c.used;
 }
 
+// Workspace of one product that holds only what the kernels of one
+// precision touch: FP64 keeps T1 and T2 in FP64; FP32 keeps them in FP32
+// plus the FP32 copies of L and R.  Same kernels as carve_apply's layout.
+static ApplyWS carve_apply_prec(const bsdmrg_plan_s* P, int prec, Carve& c) {
+  ApplyWS w{};
+  const size_t el = prec == BSDMRG_F64 ? sizeof(double) : sizeof(float);
+  w.T1 = (double*)c.take<char>((size_t)P->t1_elems * el);
+  w.T2 = (double*)c.take<char>((size_t)P->t2_elems * el);
+  w.part = c.take<double>(std::max<int64_t>(P->s3_part_elems, 1));
+  w.coef = c.take<double>(std::max<int64_t>(P->n_coefs, 1));
+  if (prec == BSDMRG_F32) {
+    w.L32 = c.take<float>(P->L_elems);
+    w.R32 = c.take<float>(P->R_elems);
+  }
+  return w;
+}
+
 namespace bsd {
 int64_t heff_apply_bytes(const bsdmrg_plan_s* P) { return (int64_t)apply_bytes(P); }
 
@@ -210,6 +227,24 @@ static void matvec(const bsdmrg_plan_s* P, int prec, const double* L, const doub
     HIPCHK(launch_s3_f32(P, T2, w.R32, out, w.part, s));
   }
 }
+
+namespace bsd {
+int64_t heff_apply_bytes_prec(const bsdmrg_plan_s* P, int prec) {
+  Carve c(nullptr, 0);
+  carve_apply_prec(P, prec, c);
+  return (int64_t)c.used;
+}
+
+// One product with the per-precision workspace layout (carve_apply_prec);
+// the caller has checked the plan, the operands and the workspace size.
+void heff_apply_compact(const bsdmrg_plan_s* P, int prec, const double* L, const double* W1, const double* W2,
+                        const double* R, const double* psi, double* out, void* ws, hipStream_t s) {
+  Carve c(ws, (size_t)heff_apply_bytes_prec(P, prec));
+  ApplyWS w = carve_apply_prec(P, prec, c);
+  prepare(P, prec, L, W1, W2, R, w, s);
+  matvec(P, prec, L, R, w, psi, out, s);
+}
+}  // namespace bsd
 
 // ------------------------------------------------------------ Davidson ------
 struct EigWS {

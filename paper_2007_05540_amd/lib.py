@@ -74,7 +74,8 @@ class EnvProblem(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["bsdmrg_layout", "bsdmrg_plan", "bsdmrg_plan_query", "bsdmrg_plan_offsets", "bsdmrg_plan_tasks",
-           "bsdmrg_plan_destroy", "bsdmrg_heff_apply", "bsdmrg_eig_workspace", "bsdmrg_eigensolve",
+           "bsdmrg_plan_destroy", "bsdmrg_heff_apply", "bsdmrg_heff_apply_noalloc", "bsdmrg_eig_workspace",
+           "bsdmrg_eigensolve",
            "bsdmrg_heff_backward", "bsdmrg_heff_backward_workspace", "bsdmrg_heff_energy", "bsdmrg_stage_timing",
            "bsdmrg_plan_autotune", "bsdmrg_plan_set_tiles", "bsdmrg_truncate_workspace", "bsdmrg_truncate",
            "bsdmrg_env_plan", "bsdmrg_merge_plan", "bsdmrg_op_query", "bsdmrg_op_destroy", "bsdmrg_env_update",
@@ -102,6 +103,7 @@ def load():
     lib.bsdmrg_plan_tasks.argtypes = [vp, i32, ctypes.POINTER(i64), i64, ctypes.POINTER(i64)]
     lib.bsdmrg_plan_destroy.argtypes = [vp]
     lib.bsdmrg_heff_apply.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, i64, vp]
+    lib.bsdmrg_heff_apply_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.bsdmrg_eig_workspace.argtypes = [vp, ctypes.POINTER(EigOpts), ctypes.POINTER(i64)]
     lib.bsdmrg_eigensolve.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(EigOpts),
                                       ctypes.POINTER(dp), ctypes.POINTER(EigStats), vp, i64, vp]
@@ -237,6 +239,16 @@ def heff_apply(plan, precision, L, W1, W2, R, psi, out, workspace, stream=None):
     check(load().bsdmrg_heff_apply(plan.handle, precision, _ptr(L), _ptr(W1), _ptr(W2), _ptr(R), _ptr(psi),
                                    _ptr(out), _ptr(workspace), workspace.numel() * workspace.element_size(),
                                    _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 160 << 20
+
+
+def heff_apply_noalloc(plan, precision, L, W1, W2, R, psi, out, stream=None):
+    """out = H_eff psi with the library's own per-GPU scratch array (no
+    workspace argument, nothing allocated by the call)."""
+    check(load().bsdmrg_heff_apply_noalloc(plan.handle, precision, _ptr(L), _ptr(W1), _ptr(W2), _ptr(R),
+                                           _ptr(psi), _ptr(out), _stream(stream)))
 
 
 def eig_opts(max_iter=10, precision=F64, refine_max_iter=4, fixed_iters=0, use_graph=0, seed=0, tol=1e-12,
