@@ -21,6 +21,19 @@ listing is silent or slightly off:
 ``lanczos`` (full reorthogonalisation) is the independent Krylov reference:
 without preconditioning the Davidson basis spans the same Krylov space, so the
 Ritz values agree iteration by iteration.
+
+Two extensions for long solves (the paper keeps the subspace at 2 vectors and
+leaves preconditioning out for its cost on CPUs; both are silent on details):
+  * bounded basis with thick restart: when the basis holds ``basis`` vectors
+    and the solve goes on, it is replaced by the ``keep`` lowest Ritz vectors
+    plus the previous step's Ritz vector orthogonalised against them (twice;
+    when less than 1e-8 of it remains, the next Ritz vector is taken instead);
+    the products of the new basis are the same combinations of the stored
+    products, so a restart costs no product and keeps the current Ritz pair;
+  * diagonal preconditioning (Davidson's original correction): the new
+    direction is t = q / (D - lambda), D the diagonal of H_eff, every
+    denominator of magnitude below 1e-8 max(|lambda|, 1) replaced by that
+    floor with its sign (+ for zero); t is then orthogonalised like q.
 """
 import numpy as np
 
@@ -51,57 +64,93 @@ def lanczos(matvec, x0, n_iter):
 
 
 def davidson(matvec, x0, max_iter, tol=0.0, restart_mask=None, seed=0,
-             restart_rtol=1e-10, max_attempts=3, record=None):
+             restart_rtol=1e-10, max_attempts=3, record=None, basis=None, keep=0,
+             precond=None):
     """Alg. 1.  Returns (lambda, x normalised, stats dict).
 
     matvec        function: flat vector -> flat vector (the implicit H_eff)
     x0            start vector (any norm)
+    max_iter      number of products with A (the basis size when there is no
+                  restart)
     restart_mask  boolean array of allowed elements for random restarts
                   (padding of the block layout stays zero); None = all
     record        optional list receiving the Ritz value of every iteration
+    basis, keep   bounded basis: at most ``basis`` vectors, thick restart to
+                  keep + 1 vectors (keep >= 1, keep + 2 <= basis)
+    precond       the diagonal D of the operator (flat, same layout) for the
+                  preconditioned correction, or None (Alg. 1 as printed)
     """
     n = x0.size
     mask = np.ones(n, dtype=bool) if restart_mask is None else restart_mask
     dim = int(mask.sum())       # a basis of this size spans the whole space
+    B = max_iter if basis is None else int(basis)
+    if basis is not None and not (1 <= keep and keep + 2 <= B):
+        raise ValueError("thick restart needs 1 <= keep <= basis - 2")
     V = [x0 / np.linalg.norm(x0)]
     VA = [matvec(V[0])]
-    M = np.zeros((max_iter, max_iter))
-    restarts = 0
-    lam, x, qn = 0.0, V[0], np.inf
-    for i in range(max_iter):
-        for j in range(i + 1):
-            M[i, j] = M[j, i] = float(VA[j] @ V[i])
-        evals, evecs = np.linalg.eigh(M[:i + 1, :i + 1])
+    products, restarts, thick = 1, 0, 0
+    sprev = None                # previous Ritz vector, coordinates of the current basis
+    while True:
+        j = len(V)
+        M = np.zeros((j, j))
+        for r in range(j):
+            for c in range(r + 1):
+                M[r, c] = M[c, r] = float(VA[c] @ V[r])
+        evals, evecs = np.linalg.eigh(M)
         lam = float(evals[0])
         s = evecs[:, 0]
-        x = sum(s[j] * V[j] for j in range(i + 1))
-        q = sum(s[j] * VA[j] for j in range(i + 1)) - lam * x
+        x = sum(s[c] * V[c] for c in range(j))
+        q = sum(s[c] * VA[c] for c in range(j)) - lam * x
         qn = float(np.linalg.norm(q))
         if record is not None:
             record.append(lam)
-        if qn <= tol or i == max_iter - 1 or i + 1 >= dim:
+        if qn <= tol or products >= max_iter or j >= dim:
             break
-        before = qn
-        q = _mgs2(q, V)
-        after = float(np.linalg.norm(q))
+        if j == B:
+            # thick restart: keep lowest Ritz vectors + the previous Ritz vector
+            S = evecs[:, :keep]
+            p = np.zeros(j) if sprev is None else np.concatenate([sprev, np.zeros(j - sprev.size)])
+            for _ in range(2):
+                p = p - S @ (S.T @ p)
+            pn = float(np.linalg.norm(p))
+            extra = p / pn if pn > 1e-8 else evecs[:, keep]
+            S = np.column_stack([S, extra])
+            V = [sum(S[c, t] * V[c] for c in range(j)) for t in range(S.shape[1])]
+            VA = [sum(S[c, t] * VA[c] for c in range(j)) for t in range(S.shape[1])]
+            thick += 1
+            sprev = np.zeros(len(V))
+            sprev[0] = 1.0          # the current Ritz vector is the first kept one
+        else:
+            sprev = s.copy()
+        if precond is None:
+            t = q
+        else:
+            den = precond - lam
+            floor = 1e-8 * max(abs(lam), 1.0)
+            den = np.where(np.abs(den) < floor, np.where(den < 0.0, -floor, floor), den)
+            t = q / den
+        before = float(np.linalg.norm(t))
+        t = _mgs2(t, V)
+        after = float(np.linalg.norm(t))
         attempt = 0
         while after < restart_rtol * before or after == 0.0:
             if attempt >= max_attempts:
                 raise RuntimeError("Davidson: reorthogonalisation failed after restarts")
-            key = rng.restart_key(seed, i, attempt)
+            key = rng.restart_key(seed, products - 1, attempt)
             r = np.zeros(n)
             idx = np.nonzero(mask)[0]
             r[idx] = rng.gaussian_at(key, idx)
             before = float(np.linalg.norm(r))
-            q = _mgs2(r, V)
-            after = float(np.linalg.norm(q))
+            t = _mgs2(r, V)
+            after = float(np.linalg.norm(t))
             attempt += 1
             restarts += 1
-        V.append(q / after)
+        V.append(t / after)
         VA.append(matvec(V[-1]))
+        products += 1
     xn = x / np.linalg.norm(x)
-    return lam, xn, {"iters": i + 1, "residual": qn, "restarts": restarts,
-                     "converged": bool(qn <= tol)}
+    return lam, xn, {"iters": products, "residual": qn, "restarts": restarts,
+                     "thick_restarts": thick, "converged": bool(qn <= tol)}
 
 
 def _mgs2(q, V):

@@ -100,6 +100,21 @@ def useful_flops(L, W1, W2, R, psi):
     return f["s1"] + f["s3"]
 
 
+def heff_diagonal(L, W1, W2, R, psi_legs):
+    """Diagonal of H_eff on the packed canonical vector: the matrix element
+    <e|H_eff|e> of every basis tensor e, i.e. the two-site formula with the
+    bra indices equal to the ket indices,
+      D(a,s1,s2,c) = sum L(a,w,a) W_i(w,s1,s1,w') W_{i+1}(w',s2,s2,w'') R(c,w'',c),
+    evaluated on the dense embeddings (padding entries 0)."""
+    Ld, W1d, W2d, Rd = (t.to_dense() for t in (L, W1, W2, R))
+    ldg = np.einsum("awa->aw", Ld)
+    rdg = np.einsum("cwc->cw", Rd)
+    w1 = np.einsum("wssv->wsv", W1d)
+    w2 = np.einsum("vttz->vtz", W2d)
+    D = np.einsum("aw,wsv,vtz,cz->astc", ldg, w1, w2, rdg)
+    return BlockTensor.from_dense(D, psi_legs, PSI_SIGNS, check_zero=False).pack()
+
+
 def heff_dense_matrix(L, W1, W2, R, psi_legs):
     """Explicit matrix of H_eff on the packed canonical vector (tiny cases)."""
     z = BlockTensor.zeros(psi_legs, PSI_SIGNS)
