@@ -178,46 +178,78 @@ bsdmrg_status bsdmrg_heff_apply_noalloc(bsdmrg_plan_t plan, int32_t precision, c
 /* Davidson options (Alg. 1; readings of the silent points in the docs of
  * bsdmrg_eigensolve). */
 typedef struct {
-  int32_t max_iter;        /* basis size (number of products) of a phase     */
+  int32_t max_iter;        /* products of the first phase (the FP64 phase, or
+                              the FP32 phase of BSDMRG_F32_REFINE), 1..4096;
+                              without thick restart at most 64 (the basis)   */
   int32_t precision;       /* BSDMRG_F64 or BSDMRG_F32_REFINE               */
-  int32_t refine_max_iter; /* FP64 products after the FP32 phase (>= 1)      */
-  int32_t fixed_iters;     /* 1: exactly max_iter products, no host sync     */
+  int32_t refine_max_iter; /* FP64 products of the refinement phase (>= 1;
+                              it starts with the products of the 1 or 2
+                              vectors kept from the FP32 phase)              */
+  int32_t fixed_iters;     /* 1: exactly the budgeted products, no host sync */
   int32_t use_graph;       /* 1 with fixed_iters: replay a captured hipGraph */
-  int32_t reserved;
+  int32_t restart_keep;    /* thick restart: 0 = none (a phase ends when its
+                              basis is full), 1 = keep the lowest Ritz vector
+                              and the previous one (orthogonalised)          */
   uint64_t seed;           /* restart stream seed                            */
   double tol;              /* stop when ||q||_2 <= tol (FP64 phase)          */
   double tol_f32;          /* FP32 phase stops at ||q||_2 <= tol_f32         */
-  double restart_rtol;     /* restart if ||q_after|| < rtol * ||q_before||   */
+  double restart_rtol;     /* restart if ||t_after|| < rtol * ||t_before||   */
+  int32_t basis;           /* basis size with thick restart (3..64; 0: 64)   */
+  int32_t precond;         /* 0: none (Alg. 1); 1: Davidson's diagonal
+                              preconditioner (see bsdmrg_eigensolve)        */
 } bsdmrg_eig_opts;
 
 typedef struct {
   int32_t iters;      /* FP64 products                                      */
   int32_t iters_f32;  /* FP32 products                                      */
-  int32_t restarts;
+  int32_t restarts;   /* random restarts (failed orthogonalisation)         */
   int32_t converged;
   double residual;    /* final ||q||_2                                       */
+  int32_t thick_restarts;  /* basis restarts (thick restart and the FP32 -> FP64 switch) */
+  int32_t pad;
 } bsdmrg_eig_stats;
+
+/* Diagonal of H_eff for every problem of the plan (Davidson's diagonal
+ * preconditioner, see bsdmrg_eigensolve):
+ * D[e] = <e|H_eff|e> for every allowed element e of psi, i.e.
+ *   D(a,s1,s2,c) = sum L(a,w,a) W1(w,s1,s1,w') W2(w',s2,s2,w'') R(c,w'',c)
+ * (only flux-0 channels contribute); D has psi's layout, padding written 0.
+ * Device pointers, FP64, asynchronous.  Errors: EINVAL, EHIP. */
+bsdmrg_status bsdmrg_heff_diagonal(bsdmrg_plan_t plan, const double* L, const double* W1, const double* W2,
+                                   const double* R, double* D, hipStream_t stream);
 
 /* Workspace of bsdmrg_eigensolve for these options. */
 bsdmrg_status bsdmrg_eig_workspace(bsdmrg_plan_t plan, const bsdmrg_eig_opts* opts,
                                    int64_t* bytes);
 
 /* Lowest eigenpair of H_eff per problem with the Davidson routine of Alg. 1:
- * no preconditioning; the start vector and every new basis vector are
- * normalised; at step i the (i+1)x(i+1) projected matrix m_ij = (v^A_j)^T v_i
- * is diagonalised in FP64 (Householder tridiagonalisation, Sturm-count
- * multisection for the lowest eigenvalue, inverse iteration for its vector);
- * x = sum s_j v_j, q = sum s_j v^A_j - lambda x; stop when ||q|| <= tol, or
- * when the basis spans the whole space (its size equals the number of allowed
- * elements of psi: the Ritz pair is then exact; in a batch the smallest
- * problem sets this cap); q is orthogonalised against the basis by
- * classical Gram-Schmidt, with a second pass only when the first removed
- * more than half of ||q||^2 ("twice is enough"); if ||q|| drops below
- * restart_rtol times its value before orthogonalisation, q is replaced by a
- * seeded Gaussian vector (SplitMix64 + Box-Muller, key from seed, step,
+ * the start vector and every new basis vector are normalised; at basis size
+ * j the j x j projected matrix m_rc = (v^A_c)^T v_r is diagonalised in FP64
+ * (Householder tridiagonalisation, Sturm-count multisection for the lowest
+ * eigenvalue, inverse iteration for its vector); x = sum s_c v_c,
+ * q = sum s_c v^A_c - lambda x; stop when ||q|| <= tol, when the phase's
+ * products are spent, or when the basis spans the whole space (its size
+ * equals the number of allowed elements of psi: the Ritz pair is then exact;
+ * in a batch the smallest problem sets this cap).  The new direction is
+ * t = q (Alg. 1) or, with precond = 1, t = q / max(D - lambda, delta) with
+ * D the diagonal of H_eff and delta = 1e-3 max(|lambda|, 1) (a positive
+ * preconditioner: the plain D - lambda has near-zero denominators while the
+ * Ritz value lies above some diagonal entries).  With restart_keep = 1
+ * a full basis (basis vectors) is replaced by x and the previous step's Ritz
+ * vector orthogonalised against it twice (or, if less than 1e-8 of it
+ * remains, the newest basis vector orthogonalised the same way); their
+ * products are the same combinations of the stored products, so the restart
+ * costs no product.  t is orthogonalised against the basis by classical
+ * Gram-Schmidt, with a second pass only when the first removed more than
+ * half of ||t||^2 ("twice is enough"); if ||t|| drops below restart_rtol
+ * times its value before orthogonalisation, t is replaced by a seeded
+ * Gaussian vector (SplitMix64 + Box-Muller, key from seed, product index,
  * attempt; at most 3 attempts).  All orthogonalisation, Rayleigh quotients
- * and the energy are FP64; with BSDMRG_F32_REFINE the products of the first
- * phase run in FP32 and the second phase restarts from x with FP64 products.
+ * and the energy are FP64.  With BSDMRG_F32_REFINE the products of the first
+ * phase run in FP32 (FP32 MFMA, FP32 accumulation); when it ends (||q|| <=
+ * tol_f32 or max_iter products) its basis is reduced as by a restart to x
+ * and the previous Ritz vector, their products are recomputed in FP64, and
+ * the solve goes on with FP64 products until ||q|| <= tol.
  * psi_inout: start vectors in, normalised eigenvectors out (device, FP64).
  * energy[n_probs], stats[n_probs]: host arrays.  A batch (n_probs > 1)
  * requires fixed_iters = 1.  The call synchronises the stream before

@@ -27,13 +27,17 @@ leaves preconditioning out for its cost on CPUs; both are silent on details):
   * bounded basis with thick restart: when the basis holds ``basis`` vectors
     and the solve goes on, it is replaced by the ``keep`` lowest Ritz vectors
     plus the previous step's Ritz vector orthogonalised against them (twice;
-    when less than 1e-8 of it remains, the next Ritz vector is taken instead);
+    when less than 1e-8 of it remains, the newest basis vector orthogonalised
+    the same way is taken instead);
     the products of the new basis are the same combinations of the stored
     products, so a restart costs no product and keeps the current Ritz pair;
-  * diagonal preconditioning (Davidson's original correction): the new
-    direction is t = q / (D - lambda), D the diagonal of H_eff, every
-    denominator of magnitude below 1e-8 max(|lambda|, 1) replaced by that
-    floor with its sign (+ for zero); t is then orthogonalised like q.
+  * diagonal preconditioning (Davidson's correction): the new direction is
+    t = q / max(D - lambda, delta), D the diagonal of H_eff and
+    delta = 1e-3 max(|lambda|, 1): a positive preconditioner whose
+    amplification is bounded by 1 / delta (with the plain D - lambda, a
+    Ritz value above some diagonal entries meets near-zero denominators and
+    the iteration becomes chaotic: rounding-level differences change the
+    trajectory); t is then orthogonalised like q.
 """
 import numpy as np
 
@@ -90,12 +94,17 @@ def davidson(matvec, x0, max_iter, tol=0.0, restart_mask=None, seed=0,
     VA = [matvec(V[0])]
     products, restarts, thick = 1, 0, 0
     sprev = None                # previous Ritz vector, coordinates of the current basis
+    M = np.zeros((0, 0))
     while True:
         j = len(V)
-        M = np.zeros((j, j))
-        for r in range(j):
+        # projected matrix m_rc = (v^A_c)^T v_r: the new row (all rows after a restart)
+        Mn = np.zeros((j, j))
+        k0 = M.shape[0]
+        Mn[:k0, :k0] = M
+        for r in range(k0, j):
             for c in range(r + 1):
-                M[r, c] = M[c, r] = float(VA[c] @ V[r])
+                Mn[r, c] = Mn[c, r] = float(VA[c] @ V[r])
+        M = Mn
         evals, evecs = np.linalg.eigh(M)
         lam = float(evals[0])
         s = evecs[:, 0]
@@ -113,10 +122,17 @@ def davidson(matvec, x0, max_iter, tol=0.0, restart_mask=None, seed=0,
             for _ in range(2):
                 p = p - S @ (S.T @ p)
             pn = float(np.linalg.norm(p))
-            extra = p / pn if pn > 1e-8 else evecs[:, keep]
+            if not pn > 1e-8:
+                p = np.zeros(j)
+                p[j - 1] = 1.0
+                for _ in range(2):
+                    p = p - S @ (S.T @ p)
+                pn = float(np.linalg.norm(p))
+            extra = p / pn
             S = np.column_stack([S, extra])
             V = [sum(S[c, t] * V[c] for c in range(j)) for t in range(S.shape[1])]
             VA = [sum(S[c, t] * VA[c] for c in range(j)) for t in range(S.shape[1])]
+            M = np.zeros((0, 0))
             thick += 1
             sprev = np.zeros(len(V))
             sprev[0] = 1.0          # the current Ritz vector is the first kept one
@@ -125,9 +141,7 @@ def davidson(matvec, x0, max_iter, tol=0.0, restart_mask=None, seed=0,
         if precond is None:
             t = q
         else:
-            den = precond - lam
-            floor = 1e-8 * max(abs(lam), 1.0)
-            den = np.where(np.abs(den) < floor, np.where(den < 0.0, -floor, floor), den)
+            den = np.maximum(precond - lam, 1e-3 * max(abs(lam), 1.0))
             t = q / den
         before = float(np.linalg.norm(t))
         t = _mgs2(t, V)

@@ -6,6 +6,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 
@@ -157,6 +158,7 @@ static void upload(bsdmrg_plan_s* P) {
       {P->dav_probs.data(), P->dav_probs.size() * sizeof(DavProb), (void**)&P->d_dav_probs},
       {P->blk_off.data(), P->blk_off.size() * sizeof(int64_t), (void**)&P->d_blk_off},
       {P->blk_ptr.data(), P->blk_ptr.size() * sizeof(int32_t), (void**)&P->d_blk_ptr},
+      {P->diag_tasks.data(), P->diag_tasks.size() * sizeof(DiagTask), (void**)&P->d_diag_tasks},
   };
   size_t total = 0;
   for (auto& p : parts) total += al256(std::max<size_t>(p.bytes, 1));
@@ -252,10 +254,13 @@ struct EigWS {
   DavBufs d;
 };
 
+// Basis size: the products of a phase without thick restart (<= 64), else
+// the option's basis (0: 64).
 static int basis_size(const bsdmrg_eig_opts* o) {
+  if (o->restart_keep > 0) return o->basis > 0 ? o->basis : 64;
   int B = o->max_iter;
   if (o->precision == BSDMRG_F32_REFINE) B = std::max(B, o->refine_max_iter);
-  return B;
+  return std::min(B, 64);
 }
 
 static EigWS carve_eig(const bsdmrg_plan_s* P, const bsdmrg_eig_opts* o, Carve& c) {
@@ -274,31 +279,49 @@ static EigWS carve_eig(const bsdmrg_plan_s* P, const bsdmrg_eig_opts* o, Carve& 
   d.part_b = c.take<double>((size_t)(B + 1) * nch);
   d.part_n0 = c.take<double>(nch);
   d.part_n1 = c.take<double>(nch);
+  d.part_res = c.take<double>(nch);
   d.nq0 = c.take<double>(np);
-  d.red = c.take<double>((size_t)np * 64);
+  d.red = c.take<double>((size_t)np * 65);
   d.M = c.take<double>((size_t)np * B * B);
   d.svec = c.take<double>((size_t)np * B);
+  d.svec_prev = c.take<double>((size_t)np * B);
+  d.Srot = c.take<double>((size_t)np * 2 * B);
   d.lam = c.take<double>(np);
   d.scale = c.take<double>(np);
   // restarts and status share one region of np + 1 doubles (zero-filled)
   d.restarts = (int32_t*)c.take<double>(np + 1);
   d.status = d.restarts + np;
+  d.D = o->precond ? c.take<double>(n) : nullptr;
   return w;
 }
 
 static void validate_opts(const bsdmrg_plan_s* P, const bsdmrg_eig_opts* o) {
   if (!o) throw Error{BSDMRG_EINVAL, "eig opts is NULL"};
-  if (o->max_iter < 1 || o->max_iter > 64) throw Error{BSDMRG_EINVAL, "max_iter must be in 1..64"};
   if (o->precision != BSDMRG_F64 && o->precision != BSDMRG_F32_REFINE)
     throw Error{BSDMRG_EINVAL, "eigensolve precision must be F64 or F32_REFINE"};
-  if (o->precision == BSDMRG_F32_REFINE && (o->refine_max_iter < 1 || o->refine_max_iter > 64))
-    throw Error{BSDMRG_EINVAL, "refine_max_iter must be in 1..64"};
+  if (o->restart_keep != 0 && o->restart_keep != 1) throw Error{BSDMRG_EINVAL, "restart_keep must be 0 or 1"};
+  if (o->precond != 0 && o->precond != 1) throw Error{BSDMRG_EINVAL, "precond must be 0 or 1"};
+  const bool mixed = o->precision == BSDMRG_F32_REFINE;
+  if (o->restart_keep == 0) {
+    if (o->max_iter < 1 || o->max_iter > 64) throw Error{BSDMRG_EINVAL, "max_iter must be in 1..64"};
+    if (mixed && (o->refine_max_iter < 1 || o->refine_max_iter > 64))
+      throw Error{BSDMRG_EINVAL, "refine_max_iter must be in 1..64"};
+  } else {
+    if (o->basis != 0 && (o->basis < 3 || o->basis > 64)) throw Error{BSDMRG_EINVAL, "basis must be 0 or 3..64"};
+    if (o->max_iter < 1 || o->max_iter > 4096) throw Error{BSDMRG_EINVAL, "max_iter must be in 1..4096"};
+    if (mixed && (o->refine_max_iter < 1 || o->refine_max_iter > 4096))
+      throw Error{BSDMRG_EINVAL, "refine_max_iter must be in 1..4096"};
+  }
   if (P->probs.size() > 1 && !o->fixed_iters)
     throw Error{BSDMRG_EINVAL, "a batch plan requires fixed_iters = 1"};
   if (!(o->restart_rtol >= 0.0) || std::isnan(o->tol) || std::isnan(o->tol_f32))
     throw Error{BSDMRG_EINVAL, "bad tolerances"};
 }
 
+// Captured solves of a plan, keyed by every pointer and option of the call
+// (a fixed-iteration solve is fully determined by them).  Looked up, captured
+// and launched under the plan's mutex, so calls from several threads with
+// their own workspaces keep their own graphs.
 struct GraphKey {
   const void* ptrs[6];
   bsdmrg_eig_opts o;
@@ -306,17 +329,27 @@ struct GraphKey {
     return std::memcmp(ptrs, k.ptrs, sizeof(ptrs)) == 0 && std::memcmp(&o, &k.o, sizeof(o)) == 0;
   }
 };
-struct GraphCache {
+struct SolveCounts {
+  int it64 = 0, it32 = 0, thick = 0;
+};
+struct GraphEntry {
   GraphKey key;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  SolveCounts counts;
 };
+struct GraphCache {
+  std::vector<GraphEntry> entries;   // oldest first
+};
+constexpr size_t kMaxGraphs = 8;
 
 namespace bsd {
 void destroy_graph(bsdmrg_plan_s* P) {
   if (!P->graph) return;
-  if (P->graph->exec) (void)hipGraphExecDestroy(P->graph->exec);
-  if (P->graph->graph) (void)hipGraphDestroy(P->graph->graph);
+  for (GraphEntry& g : P->graph->entries) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
   delete P->graph;
   P->graph = nullptr;
 }
@@ -331,27 +364,30 @@ static int64_t solve_dim(const bsdmrg_plan_s* P) {
   return dim;
 }
 
-// Enqueue the whole solve.  In tol mode the host reads ||q|| after every
-// Ritz step (needs a sync); in fixed mode nothing is read back here.
+// Enqueue the whole solve (Alg. 1 with the bounded basis, the preconditioner
+// and the FP32 -> FP64 switch documented in the header).  The sequence of
+// launches depends only on the options and the plan, except in tol mode,
+// where the host reads ||q|| after every Ritz step (one sync per step).
 static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double* W1, const double* W2,
                           const double* R, double* psi, const bsdmrg_eig_opts* o, EigWS& w,
-                          hipStream_t s, std::vector<int>& it64, std::vector<int>& it32,
-                          std::vector<double>& res, std::vector<int>& conv) {
+                          hipStream_t s, SolveCounts& cnt, std::vector<double>& res, std::vector<int>& conv) {
   const DavBufs& d = w.d;
   const int64_t n = d.n;
   const int np = (int)P->probs.size();
+  const int B = d.B;
   HIPCHK(launch_coef(P, W1, W2, w.a.coef, s));
   const bool mixed = o->precision == BSDMRG_F32_REFINE;
   if (mixed) {
     HIPCHK(launch_cast(P->L_elems, L, w.a.L32, s));
     HIPCHK(launch_cast(P->R_elems, R, w.a.R32, s));
   }
-  HIPCHK(dav_fill_zero(d.VA, (int64_t)d.B * n, s));
+  if (d.D) HIPCHK(dav_diag(P, L, W1, W2, R, d.D, s));
+  HIPCHK(dav_fill_zero(d.VA, (int64_t)B * n, s));
   HIPCHK(dav_fill_zero((double*)d.restarts, np + 1, s));
   HIPCHK(dav_dots(P, 1, psi, 0, psi, d.part_a, s));
   HIPCHK(dav_normalize(P, d.part_a, d.red, psi, d.V, s));
   struct Phase {
-    int prec, maxit;
+    int prec, budget;
     double tol;
   };
   std::vector<Phase> phases;
@@ -363,24 +399,45 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
   }
   std::vector<double> hpart(P->chunks.size());
   const int64_t dim = solve_dim(P);
-  int global_it = 0;
+  const bool thick = o->restart_keep > 0;
+  int j = 1;          // basis size
+  int step = 0;       // products so far (all phases): the random-restart key index
+  cnt = SolveCounts{};
   for (size_t ph = 0; ph < phases.size(); ++ph) {
-    Phase f = phases[ph];
-    f.maxit = (int)std::min<int64_t>(f.maxit, dim);
-    if (ph > 0) {
-      HIPCHK(dav_dots(P, 1, d.x, 0, d.x, d.part_a, s));
-      HIPCHK(dav_normalize(P, d.part_a, d.red, d.x, d.V, s));
+    const Phase& f = phases[ph];
+    int products = 0;
+    int& counter = f.prec == BSDMRG_F64 ? cnt.it64 : cnt.it32;
+    if (ph == 0) {
+      matvec(P, f.prec, L, R, w.a, d.V, d.VA, s);
+      products = 1;
+      ++step;
+    } else {
+      // switch: keep x and the previous Ritz vector (or x alone), then
+      // recompute their products and the projected matrix in this precision
+      const int nkeep = std::min({2, j, f.budget});
+      HIPCHK(dav_restart(P, d, j, nkeep, s));
+      HIPCHK(dav_rotate(P, d, j, nkeep, false, s));
+      cnt.thick++;
+      j = nkeep;
+      for (int r = 0; r < j; ++r) {
+        matvec(P, f.prec, L, R, w.a, d.V + (int64_t)r * n, d.VA + (int64_t)r * n, s);
+        ++products;
+        ++step;
+        if (r + 1 < j) {
+          HIPCHK(dav_dots(P, r + 1, d.VA, n, d.V + (int64_t)r * n, d.part_a, s));
+          HIPCHK(dav_gram_eig(P, d, r, s));
+        }
+      }
     }
-    matvec(P, f.prec, L, R, w.a, d.V, d.VA, s);
-    for (int i = 0; i < f.maxit; ++i, ++global_it) {
-      HIPCHK(dav_dots(P, i + 1, d.VA, n, d.V + (int64_t)i * n, d.part_a, s));
+    for (;;) {
+      const int i = j - 1;
+      HIPCHK(dav_dots(P, j, d.VA, n, d.V + (int64_t)i * n, d.part_a, s));
       HIPCHK(dav_gram_eig(P, d, i, s));
-      // q and (unless this is the last step) the first Gram-Schmidt dots v_j^T q
-      const bool last = i == f.maxit - 1;
-      HIPCHK(dav_ritz(P, d, i, false, last ? nullptr : d.part_a, s));
-      for (int p = 0; p < np; ++p) (f.prec == BSDMRG_F64 ? it64 : it32)[p] = i + 1;
+      const bool last = products >= f.budget || j >= dim;
+      // q, t and (unless this is the last step) the first Gram-Schmidt dots v_c^T t
+      HIPCHK(dav_ritz(P, d, i, false, last ? nullptr : d.part_a, d.D, s));
       if (!o->fixed_iters) {
-        HIPCHK(hipMemcpyAsync(hpart.data(), d.part_n0, hpart.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hpart.data(), d.part_res, hpart.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         bool all = true;
         for (int p = 0; p < np; ++p) {
@@ -392,24 +449,36 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
           all = all && conv[p];
         }
         if (all) {
-          HIPCHK(dav_ritz(P, d, i, true, nullptr, s));
+          HIPCHK(dav_ritz(P, d, i, true, nullptr, d.D, s));
           break;
         }
       }
       if (last) {
-        HIPCHK(dav_ritz(P, d, i, true, nullptr, s));
+        HIPCHK(dav_ritz(P, d, i, true, nullptr, d.D, s));
         break;
       }
-      HIPCHK(dav_update(P, d, i + 1, d.part_a, d.part_b, 1, s));
-      HIPCHK(dav_update(P, d, i + 1, d.part_b, d.part_n1, 2, s));
-      HIPCHK(dav_finalize(P, d, i, o->seed, o->restart_rtol, P->d_blk_off, P->d_blk_ptr, s));
-      HIPCHK(dav_scale_into(P, d, d.V + (int64_t)(i + 1) * n, s));
-      matvec(P, f.prec, L, R, w.a, d.V + (int64_t)(i + 1) * n, d.VA + (int64_t)(i + 1) * n, s);
+      if (thick && j == B) {
+        // thick restart to x and the previous Ritz vector; the dots of t
+        // against the new basis (and ||t||^2) are taken again
+        HIPCHK(dav_restart(P, d, j, 2, s));
+        HIPCHK(dav_rotate(P, d, j, 2, true, s));
+        cnt.thick++;
+        j = 2;
+        HIPCHK(dav_dots(P, j, d.V, n, d.q, d.part_a, s, true));
+      }
+      HIPCHK(dav_update(P, d, j, d.part_a, d.part_b, 1, s));
+      HIPCHK(dav_update(P, d, j, d.part_b, d.part_n1, 2, s));
+      HIPCHK(dav_finalize(P, d, j, step - 1, o->seed, o->restart_rtol, P->d_blk_off, P->d_blk_ptr, s));
+      HIPCHK(dav_scale_into(P, d, d.V + (int64_t)j * n, s));
+      matvec(P, f.prec, L, R, w.a, d.V + (int64_t)j * n, d.VA + (int64_t)j * n, s);
+      ++j;
+      ++products;
+      ++step;
     }
+    counter = products;
   }
   HIPCHK(dav_dots(P, 1, d.x, 0, d.x, d.part_a, s));
   HIPCHK(dav_normalize(P, d.part_a, d.red, d.x, psi, s));
-  (void)global_it;
 }
 
 extern "C" {
@@ -575,6 +644,15 @@ bsdmrg_status bsdmrg_heff_energy(bsdmrg_plan_t P, const double* L, const double*
   });
 }
 
+bsdmrg_status bsdmrg_heff_diagonal(bsdmrg_plan_t P, const double* L, const double* W1, const double* W2,
+                                   const double* R, double* D, hipStream_t stream) {
+  return guarded([&] {
+    need_device(P);
+    if (!L || !W1 || !W2 || !R || !D) throw Error{BSDMRG_EINVAL, "heff_diagonal: NULL argument"};
+    HIPCHK(dav_diag(P, L, W1, W2, R, D, stream));
+  });
+}
+
 bsdmrg_status bsdmrg_eig_workspace(bsdmrg_plan_t P, const bsdmrg_eig_opts* o, int64_t* bytes) {
   return guarded([&] {
     if (!P || !bytes) throw Error{BSDMRG_EINVAL, "eig_workspace: NULL argument"};
@@ -600,45 +678,56 @@ bsdmrg_status bsdmrg_eigensolve(bsdmrg_plan_t P, const double* L, const double* 
     Carve c(workspace, (size_t)workspace_bytes);
     EigWS w = carve_eig(P, o, c);
     const int np = (int)P->probs.size();
-    std::vector<int> it64(np, 0), it32(np, 0), conv(np, 0);
+    std::vector<int> conv(np, 0);
     std::vector<double> res(np, 0.0);
+    SolveCounts cnt;
     const bool graph = o->fixed_iters && o->use_graph && s != nullptr;
     if (graph) {
+      std::lock_guard<std::mutex> lk(P->mu);
+      if (!P->graph) P->graph = new GraphCache();
       GraphKey key{{L, W1, W2, R, psi, workspace}, *o};
-      if (!P->graph || !(P->graph->key == key)) {
-        destroy_graph(P);
-        auto* G = new GraphCache();
-        G->key = key;
-        P->graph = G;
+      GraphEntry* hit = nullptr;
+      for (GraphEntry& g : P->graph->entries)
+        if (g.key == key) hit = &g;
+      if (!hit) {
+        GraphEntry G;
+        G.key = key;
         HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         try {
-          enqueue_solve(P, L, W1, W2, R, psi, o, w, s, it64, it32, res, conv);
+          enqueue_solve(P, L, W1, W2, R, psi, o, w, s, G.counts, res, conv);
         } catch (...) {
-          hipGraph_t g;
+          hipGraph_t g = nullptr;
           (void)hipStreamEndCapture(s, &g);
           if (g) (void)hipGraphDestroy(g);
-          destroy_graph(P);
           throw;
         }
-        HIPCHK(hipStreamEndCapture(s, &G->graph));
-        HIPCHK(hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0));
+        HIPCHK(hipStreamEndCapture(s, &G.graph));
+        hipError_t e = hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+          (void)hipGraphDestroy(G.graph);
+          HIPCHK(e);
+        }
+        if (P->graph->entries.size() >= kMaxGraphs) {
+          // an in-flight launch of the evicted graph completes normally
+          GraphEntry& old = P->graph->entries.front();
+          (void)hipGraphExecDestroy(old.exec);
+          (void)hipGraphDestroy(old.graph);
+          P->graph->entries.erase(P->graph->entries.begin());
+        }
+        P->graph->entries.push_back(G);
+        hit = &P->graph->entries.back();
       }
-      HIPCHK(hipGraphLaunch(P->graph->exec, s));
-      const int64_t dim = solve_dim(P);
-      const int B = o->precision == BSDMRG_F32_REFINE ? o->refine_max_iter : o->max_iter;
-      for (int p = 0; p < np; ++p) {
-        it64[p] = (int)std::min<int64_t>(B, dim);
-        it32[p] = o->precision == BSDMRG_F32_REFINE ? (int)std::min<int64_t>(o->max_iter, dim) : 0;
-      }
+      HIPCHK(hipGraphLaunch(hit->exec, s));
+      cnt = hit->counts;
     } else {
-      enqueue_solve(P, L, W1, W2, R, psi, o, w, s, it64, it32, res, conv);
+      enqueue_solve(P, L, W1, W2, R, psi, o, w, s, cnt, res, conv);
     }
     std::vector<double> lam(np);
     std::vector<int32_t> rs(2 * np);
     std::vector<double> hpart(P->chunks.size());
     HIPCHK(hipMemcpyAsync(lam.data(), w.d.lam, np * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(rs.data(), w.d.restarts, 2 * np * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hpart.data(), w.d.part_n0, hpart.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hpart.data(), w.d.part_res, hpart.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     bool failed = false;
     for (int p = 0; p < np; ++p) {
@@ -646,11 +735,13 @@ bsdmrg_status bsdmrg_eigensolve(bsdmrg_plan_t P, const double* L, const double* 
       double r = 0.0;
       for (int cc = 0; cc < pr.nchunk; ++cc) r += hpart[pr.chunk0 + cc];
       energy[p] = lam[p];
-      stats[p].iters = it64[p];
-      stats[p].iters_f32 = it32[p];
+      stats[p].iters = cnt.it64;
+      stats[p].iters_f32 = cnt.it32;
       stats[p].restarts = rs[p];
       stats[p].residual = std::sqrt(r);
       stats[p].converged = stats[p].residual <= o->tol;
+      stats[p].thick_restarts = cnt.thick;
+      stats[p].pad = 0;
       failed = failed || rs[np + p] != 0;
     }
     if (failed) throw Error{BSDMRG_ESOLVER, "eigensolve: reorthogonalisation failed after 3 restarts"};

@@ -4,6 +4,7 @@
 #include <array>
 #include <cstdint>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -85,6 +86,15 @@ struct MixItem {
 struct Chunk {
   int64_t start;
   int32_t len, prob;
+};
+
+// Diagonal of H_eff over one row range of one psi block (preconditioner):
+// L block (a, w0, a) with nl flux-0 channels, R block (c, w0'', c) with nr,
+// W1 block (w0, s1, s1, w0') nl x nm, W2 block (w0', s2, s2, w0'') nm x nr.
+constexpr int kMaxDiagChannels = 64;
+struct DiagTask {
+  int64_t psi_off, l_off, r_off, w1_off, w2_off;
+  int32_t rows, cols, nl, nm, nr, row0, nrow, pad;
 };
 
 // Per-problem descriptor of the Davidson kernels.
@@ -222,12 +232,16 @@ struct bsdmrg_plan_s {
   std::vector<int64_t> blk_off;      // per psi block: (offset in problem, size)
   std::vector<int32_t> blk_ptr;      // per problem: first block (n_probs + 1)
   bsd::DavProb* d_dav_probs = nullptr;
+  std::vector<bsd::DiagTask> diag_tasks;   // diagonal of H_eff (preconditioner)
+  bsd::DiagTask* d_diag_tasks = nullptr;
   int64_t* d_blk_off = nullptr;
   int32_t* d_blk_ptr = nullptr;
   // backward-pass tables (built lazily)
   bsd::Backward* bwd = nullptr;
-  // cached hipGraph of a fixed-iteration eigensolve
+  // cached hipGraphs of fixed-iteration eigensolves (under mu)
   struct GraphCache* graph = nullptr;
+  // guards the lazily built parts of a plan (graph cache, adjoint tables)
+  std::mutex mu;
 };
 
 // Auxiliary operations (environment extension, two-site merge): one or two

@@ -56,12 +56,16 @@ struct DavBufs {
   double* q;
   double* part_a;   // (B + 1) * nchunk partial sums
   double* part_b;
-  double* part_n0;  // nchunk: ||q||^2 before orthogonalisation
-  double* part_n1;  // nchunk: ||q||^2 after
+  double* part_n0;  // nchunk: ||t||^2 before orthogonalisation (t = q, or the preconditioned q)
+  double* part_n1;  // nchunk: ||t||^2 after
+  double* part_res; // nchunk: ||q||^2 (the residual)
   double* nq0;      // n_probs: ||q||^2 before orthogonalisation (total)
   double* red;      // n_probs * 64 per-problem sums of partials
   double* M;        // n_probs * B * B projected matrices
   double* svec;     // n_probs * B Ritz vectors of M
+  double* svec_prev;// n_probs * B the previous step's Ritz vector (thick restart)
+  double* Srot;     // n_probs * 2 * B restart coefficients
+  double* D;        // n (diagonal of H_eff) or null
   double* lam;      // n_probs
   double* scale;    // n_probs
   int32_t* restarts;  // n_probs
@@ -71,18 +75,30 @@ struct DavBufs {
 };
 
 hipError_t dav_fill_zero(double* x, int64_t n, hipStream_t s);
+// part[j] (j < J) = chunk partials of X_j^T y; with norm_col also ||y||^2 as column J
 hipError_t dav_dots(const bsdmrg_plan_s* P, int J, const double* X, int64_t xstride, const double* y,
-                    double* part, hipStream_t s);
+                    double* part, hipStream_t s, bool norm_col = false);
+// thick restart coefficients (nkeep 1 or 2 vectors out of j) and the new projected matrix
+hipError_t dav_restart(const bsdmrg_plan_s* P, const DavBufs& b, int j, int nkeep, hipStream_t s);
+// V (and VA) <- V S in place, nout output vectors from J inputs
+hipError_t dav_rotate(const bsdmrg_plan_s* P, const DavBufs& b, int J, int nout, bool with_products,
+                      hipStream_t s);
+// D = diagonal of H_eff (padding 0)
+hipError_t dav_diag(const bsdmrg_plan_s* P, const double* L, const double* W1, const double* W2, const double* R,
+                    double* D, hipStream_t s);
 hipError_t dav_psum(const bsdmrg_plan_s* P, int J, const double* part, double* red, int ldr, hipStream_t s);
 hipError_t dav_normalize(const bsdmrg_plan_s* P, const double* part, double* red, const double* x, double* y,
                          hipStream_t s);
 hipError_t dav_gram_eig(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStream_t s);
-// q (and x when want_x); with part_d also the partial dots v_j^T q, j <= i
+// q and the new direction t (q, or q / (D - lambda) when D is non-null) into
+// b.q, x when want_x; with part_d also the partial dots v_j^T t, j <= i, and
+// ||t||^2 as column i + 1
 hipError_t dav_ritz(const bsdmrg_plan_s* P, const DavBufs& b, int i, bool want_x, double* part_d,
-                    hipStream_t s);
+                    const double* D, hipStream_t s);
 hipError_t dav_update(const bsdmrg_plan_s* P, const DavBufs& b, int J, const double* part_in,
                       double* part_out, int mode, hipStream_t s);
-hipError_t dav_finalize(const bsdmrg_plan_s* P, const DavBufs& b, int i, uint64_t seed, double rtol,
+// J: basis size; step: product index of the random-restart key
+hipError_t dav_finalize(const bsdmrg_plan_s* P, const DavBufs& b, int J, int step, uint64_t seed, double rtol,
                         const int64_t* blk_off, const int32_t* blk_ptr, hipStream_t s);
 hipError_t dav_scale_into(const bsdmrg_plan_s* P, const DavBufs& b, double* dst, hipStream_t s);
 

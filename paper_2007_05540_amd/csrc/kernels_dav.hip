@@ -103,8 +103,9 @@ __global__ __launch_bounds__(DT) void psum_kernel(const DavProb* __restrict__ pr
 // per j, one barrier, the four wave sums added in order).
 __global__ __launch_bounds__(DT) void dots_kernel(const Chunk* __restrict__ chunks, int nct, int J,
                                                   const double* __restrict__ X, int64_t xstride,
-                                                  const double* __restrict__ y, double* __restrict__ part) {
-  __shared__ double ws[kMaxBasisD][4];
+                                                  const double* __restrict__ y, double* __restrict__ part,
+                                                  int norm_col) {
+  __shared__ double ws[kMaxBasisD + 1][4];
   const Chunk ch = chunks[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double yv[PER];
@@ -125,8 +126,16 @@ __global__ __launch_bounds__(DT) void dots_kernel(const Chunk* __restrict__ chun
     s = wave_sum(s);
     if (lane == 0) ws[j][wave] = s;
   }
+  // column J: ||y||^2 (the norm column read by the first Gram-Schmidt pass)
+  if (norm_col) {
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) s += yv[u] * yv[u];
+    s = wave_sum(s);
+    if (lane == 0) ws[J][wave] = s;
+  }
   __syncthreads();
-  if ((int)threadIdx.x < J) {
+  if ((int)threadIdx.x < J + (norm_col ? 1 : 0)) {
     const int j = threadIdx.x;
     part[(int64_t)j * nct + blockIdx.x] = ((ws[j][0] + ws[j][1]) + ws[j][2]) + ws[j][3];
   }
@@ -160,13 +169,16 @@ constexpr int GT = 64;   // one wave
 constexpr int kRegRows = 16;   // register path of the tridiagonalisation
 __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, const double* __restrict__ red,
                                                       double* __restrict__ M, double* __restrict__ svec,
-                                                      double* __restrict__ lam) {
+                                                      double* __restrict__ lam, double* __restrict__ svec_prev) {
   __shared__ double A[kMaxBasis][kMaxBasis + 1];
   __shared__ double Vh[kMaxBasis][kMaxBasis];
   __shared__ double d[kMaxBasis], e[kMaxBasis], vb[kMaxBasis], wb[kMaxBasis];
   const int p = blockIdx.x, lane = threadIdx.x, n = i + 1;
   double* Mp = M + (int64_t)p * B * B;
   const double* rp = red + (int64_t)p * ldr;
+  // the previous step's Ritz vector in the coordinates of the grown basis
+  // (its new last coordinate is 0); read before svec is overwritten below
+  if (svec_prev && lane <= i) svec_prev[(int64_t)p * B + lane] = lane < i ? svec[(int64_t)p * B + lane] : 0.0;
   // the new row and column come from red; the rest from the stored matrix
   for (int e2 = lane; e2 < n * n; e2 += GT) {
     const int r = e2 / n, c = e2 % n;
@@ -431,16 +443,21 @@ __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chun
                                                   int64_t stride, const double* __restrict__ svec,
                                                   const double* __restrict__ lam, double* __restrict__ x,
                                                   double* __restrict__ q, double* __restrict__ part,
-                                                  double* __restrict__ part_d) {
-  __shared__ double ws[kMaxBasisD + 1][4];
+                                                  double* __restrict__ part_d, double* __restrict__ part_res,
+                                                  const double* __restrict__ D) {
+  __shared__ double ws[kMaxBasisD + 2][4];
   __shared__ double sv[kMaxBasis];
   const Chunk ch = chunks[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if ((int)threadIdx.x < J) sv[threadIdx.x] = svec[(int64_t)ch.prob * B + threadIdx.x];
   __syncthreads();
   const double l = lam[ch.prob];
+  // positive preconditioner max(D - lambda, floor): amplification bounded by
+  // 1 / floor (the plain D - lambda meets near-zero denominators while the
+  // Ritz value is above some diagonal entries)
+  const double floor_p = 1e-3 * fmax(fabs(l), 1.0);
   double qv[PER];
-  double nrm = 0.0;
+  double nrm = 0.0, res = 0.0;
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int e = threadIdx.x + u * DT;
@@ -452,7 +469,10 @@ __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chun
       xv += sv[j] * ld_at(V + j * stride + ch.start, e);
       av += sv[j] * ld_at(VA + j * stride + ch.start, e);
     }
-    const double v = av - l * xv;
+    const double r = av - l * xv;
+    res += r * r;
+    double v = r;
+    if (D) v = r / fmax(ld_at(D + ch.start, e) - l, floor_p);
     if (x) st_at(x + ch.start, e, xv);
     st_at(q + ch.start, e, v);
     qv[u] = v;
@@ -460,6 +480,8 @@ __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chun
   }
   nrm = wave_sum(nrm);
   if (lane == 0) ws[kMaxBasisD][wave] = nrm;
+  res = wave_sum(res);
+  if (lane == 0) ws[kMaxBasisD + 1][wave] = res;
   if (part_d) {
 #pragma unroll 4
     for (int j = 0; j < J; ++j) {
@@ -476,6 +498,9 @@ __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chun
   __syncthreads();
   if (threadIdx.x == 0)
     part[blockIdx.x] = ((ws[kMaxBasisD][0] + ws[kMaxBasisD][1]) + ws[kMaxBasisD][2]) + ws[kMaxBasisD][3];
+  if (threadIdx.x == 0)
+    part_res[blockIdx.x] =
+        ((ws[kMaxBasisD + 1][0] + ws[kMaxBasisD + 1][1]) + ws[kMaxBasisD + 1][2]) + ws[kMaxBasisD + 1][3];
   if (part_d && (int)threadIdx.x < J) {
     const int j = threadIdx.x;
     part_d[(int64_t)j * nct + blockIdx.x] = ((ws[j][0] + ws[j][1]) + ws[j][2]) + ws[j][3];
@@ -571,7 +596,7 @@ __device__ __forceinline__ double gauss_at(uint64_t key, uint64_t idx) {
 // Decide per problem: accept q (scale = 1/||q||) or, when orthogonalisation
 // failed, restart from seeded Gaussian vectors orthogonalised twice against
 // the basis (single workgroup per problem; a rare path).
-__global__ __launch_bounds__(DT) void finalize_kernel(const DavProb* __restrict__ probs, int i, int B,
+__global__ __launch_bounds__(DT) void finalize_kernel(const DavProb* __restrict__ probs, int J, int step, int B,
                                                       int64_t stride, const double* __restrict__ V,
                                                       double* __restrict__ q,
                                                       const double* __restrict__ part_n0,
@@ -594,7 +619,7 @@ __global__ __launch_bounds__(DT) void finalize_kernel(const DavProb* __restrict_
     return;
   }
   for (int attempt = 0; attempt < 3; ++attempt) {
-    const uint64_t key = seed + 0x632BE59BD9B4E019ull * (uint64_t)(1 + 65536ll * i + attempt);
+    const uint64_t key = seed + 0x632BE59BD9B4E019ull * (uint64_t)(1 + 65536ll * step + attempt);
     // fill the allowed elements (padding stays zero)
     for (int b = blk_ptr[p]; b < blk_ptr[p + 1]; ++b) {
       const int64_t o = blk_off[2 * b], sz = blk_off[2 * b + 1];
@@ -605,7 +630,7 @@ __global__ __launch_bounds__(DT) void finalize_kernel(const DavProb* __restrict_
     for (int64_t e = threadIdx.x; e < pr.len; e += DT) s += q[pr.base + e] * q[pr.base + e];
     const double before = block_sum(s, sh);
     for (int pass = 0; pass < 2; ++pass) {
-      for (int j = 0; j <= i; ++j) {
+      for (int j = 0; j < J; ++j) {
         double d = 0.0;
         for (int64_t e = threadIdx.x; e < pr.len; e += DT) d += V[j * stride + pr.base + e] * q[pr.base + e];
         d = block_sum(d, sh);
@@ -614,7 +639,7 @@ __global__ __launch_bounds__(DT) void finalize_kernel(const DavProb* __restrict_
       __syncthreads();
       for (int64_t e = threadIdx.x; e < pr.len; e += DT) {
         double v = q[pr.base + e];
-        for (int j = 0; j <= i; ++j) v -= cj[j] * V[j * stride + pr.base + e];
+        for (int j = 0; j < J; ++j) v -= cj[j] * V[j * stride + pr.base + e];
         q[pr.base + e] = v;
       }
       __syncthreads();
@@ -647,6 +672,133 @@ __global__ void fill_zero_kernel(double* x, int64_t n) {
     x[i] = 0.0;
 }
 
+// Thick restart of one problem's basis (one wave per problem).  s is the
+// current Ritz vector (coordinates of the j-vector basis) and sp the previous
+// step's Ritz vector padded with 0; the new basis is s and, when nkeep = 2,
+// e = sp orthogonalised twice against s (or, if less than 1e-8 of it remains,
+// the newest basis vector e_{j-1} orthogonalised the same way), normalised.
+// Writes the coefficients S (column t of problem p at S[(p * 2 + t) * B]),
+// the projected matrix S^T M S into rows and columns 0..nkeep-1 of M, and
+// s = e_0 (the current Ritz vector is the first kept vector).
+__global__ __launch_bounds__(GT) void restart_kernel(int j, int B, int nkeep, double* __restrict__ M,
+                                                     double* __restrict__ svec,
+                                                     const double* __restrict__ svec_prev,
+                                                     double* __restrict__ S) {
+  __shared__ double A[kMaxBasis][kMaxBasis + 1];
+  const int p = blockIdx.x, lane = threadIdx.x;
+  double* Mp = M + (int64_t)p * B * B;
+  for (int e2 = lane; e2 < j * j; e2 += GT) A[e2 / j][e2 % j] = Mp[(e2 / j) * B + (e2 % j)];
+  const double sv = lane < j ? svec[(int64_t)p * B + lane] : 0.0;
+  double ev = 0.0;
+  if (nkeep == 2) {
+    double pv = lane < j ? svec_prev[(int64_t)p * B + lane] : 0.0;
+    for (int pass = 0; pass < 2; ++pass) pv -= sv * wave_total(sv * pv);
+    double nn = sqrt(wave_total(pv * pv));
+    if (!(nn > 1e-8)) {
+      pv = lane == j - 1 ? 1.0 : 0.0;
+      for (int pass = 0; pass < 2; ++pass) pv -= sv * wave_total(sv * pv);
+      nn = sqrt(wave_total(pv * pv));
+    }
+    ev = pv / nn;
+  }
+  __syncthreads();
+  // u = M s, w = M e (lane r: row r)
+  double u = 0.0, w = 0.0;
+  if (lane < j)
+    for (int c = 0; c < j; ++c) {
+      const double sc = readlane_d(sv, c), ec = readlane_d(ev, c);
+      u += A[lane][c] * sc;
+      w += A[lane][c] * ec;
+    }
+  else
+    for (int c = 0; c < j; ++c) {   // keep every lane in the lane reads
+      (void)readlane_d(sv, c);
+      (void)readlane_d(ev, c);
+    }
+  const double m00 = wave_total(sv * u), m01 = wave_total(sv * w), m11 = wave_total(ev * w);
+  if (lane < B) {
+    S[((int64_t)p * 2 + 0) * B + lane] = sv;
+    S[((int64_t)p * 2 + 1) * B + lane] = ev;
+    svec[(int64_t)p * B + lane] = lane == 0 ? 1.0 : 0.0;
+  }
+  if (lane == 0) {
+    Mp[0] = m00;
+    if (nkeep == 2) {
+      Mp[1] = m01;
+      Mp[B] = m01;
+      Mp[B + 1] = m11;
+    }
+  }
+}
+
+// In-place rotation of the basis (and, when VA is non-null, of its
+// products): X_t <- sum_c S_ct X_c for t < nout, every input of an element
+// read before its outputs are written (each element belongs to one thread).
+__global__ __launch_bounds__(DT) void rotate_kernel(const Chunk* __restrict__ chunks, int J, int B, int nout,
+                                                    const double* __restrict__ S, double* __restrict__ V,
+                                                    double* __restrict__ VA, int64_t stride) {
+  __shared__ double sc[2][kMaxBasis];
+  const Chunk ch = chunks[blockIdx.x];
+  if ((int)threadIdx.x < J) {
+    sc[0][threadIdx.x] = S[((int64_t)ch.prob * 2 + 0) * B + threadIdx.x];
+    sc[1][threadIdx.x] = S[((int64_t)ch.prob * 2 + 1) * B + threadIdx.x];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * DT;
+    if (e >= ch.len) continue;
+    double o0 = 0.0, o1 = 0.0, a0 = 0.0, a1 = 0.0;
+    for (int c = 0; c < J; ++c) {
+      const double v = ld_at(V + c * stride + ch.start, e);
+      o0 += sc[0][c] * v;
+      o1 += sc[1][c] * v;
+      if (VA) {
+        const double a = ld_at(VA + c * stride + ch.start, e);
+        a0 += sc[0][c] * a;
+        a1 += sc[1][c] * a;
+      }
+    }
+    st_at(V + ch.start, e, o0);
+    if (nout == 2) st_at(V + stride + ch.start, e, o1);
+    if (VA) {
+      st_at(VA + ch.start, e, a0);
+      if (nout == 2) st_at(VA + stride + ch.start, e, a1);
+    }
+  }
+}
+
+// Diagonal of H_eff (Davidson's preconditioner): for every psi block
+// (a, s1, s2, c), D[i, j] = sum over flux-0 channels w of a, w'' of c of
+// L(a, w, a)[i, i] C(w, w'') R(c, w'', c)[j, j] with
+// C(w, w'') = sum_w' W1(w, s1, s1, w') W2(w', s2, s2, w'').  One workgroup
+// per task (a row range of one block); C is formed in LDS first.
+__global__ __launch_bounds__(DT) void diag_kernel(const DiagTask* __restrict__ tasks, const double* __restrict__ L,
+                                                  const double* __restrict__ W1, const double* __restrict__ W2,
+                                                  const double* __restrict__ R, double* __restrict__ D) {
+  __shared__ double C[kMaxDiagChannels * kMaxDiagChannels];
+  const DiagTask t = tasks[blockIdx.x];
+  for (int idx = threadIdx.x; idx < t.nl * t.nr; idx += DT) {
+    const int w = idx / t.nr, z = idx % t.nr;
+    double c = 0.0;
+    for (int v = 0; v < t.nm; ++v) c += W1[t.w1_off + (int64_t)w * t.nm + v] * W2[t.w2_off + (int64_t)v * t.nr + z];
+    C[idx] = c;
+  }
+  __syncthreads();
+  const int n = t.nrow * t.cols;
+  for (int e = threadIdx.x; e < n; e += DT) {
+    const int i = t.row0 + e / t.cols, jj = e % t.cols;
+    double sum = 0.0;
+    for (int w = 0; w < t.nl; ++w) {
+      const double lw = L[t.l_off + ((int64_t)i * t.nl + w) * t.rows + i];
+      double inner = 0.0;
+      for (int z = 0; z < t.nr; ++z) inner += C[w * t.nr + z] * R[t.r_off + ((int64_t)jj * t.nr + z) * t.cols + jj];
+      sum += lw * inner;
+    }
+    D[t.psi_off + (int64_t)i * t.cols + jj] = sum;
+  }
+}
+
 // ---------------------------------------------------------------- launches --
 static unsigned nchunks(const bsdmrg_plan_s* P) { return (unsigned)P->chunks.size(); }
 static const DavProb* dav_probs(const bsdmrg_plan_s* P) { return P->d_dav_probs; }
@@ -659,9 +811,34 @@ hipError_t dav_fill_zero(double* x, int64_t n, hipStream_t s) {
 }
 
 hipError_t dav_dots(const bsdmrg_plan_s* P, int J, const double* X, int64_t xstride, const double* y,
-                    double* part, hipStream_t s) {
+                    double* part, hipStream_t s, bool norm_col) {
+  if (J < 0 || J > kMaxBasisD || (norm_col && J >= kMaxBasisD + 1)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(dots_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), J, X,
-                     xstride, y, part);
+                     xstride, y, part, norm_col ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t dav_restart(const bsdmrg_plan_s* P, const DavBufs& b, int j, int nkeep, hipStream_t s) {
+  if (j < 1 || j > b.B || nkeep < 1 || nkeep > 2 || (nkeep == 2 && j < 2)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(restart_kernel, dim3((unsigned)P->probs.size()), dim3(GT), 0, s, j, b.B, nkeep, b.M, b.svec,
+                     b.svec_prev, b.Srot);
+  return hipGetLastError();
+}
+
+hipError_t dav_rotate(const bsdmrg_plan_s* P, const DavBufs& b, int J, int nout, bool with_products,
+                      hipStream_t s) {
+  if (J < 1 || J > b.B || nout < 1 || nout > 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(rotate_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, J, b.B, nout, b.Srot, b.V,
+                     with_products ? b.VA : nullptr, b.n);
+  return hipGetLastError();
+}
+
+hipError_t dav_diag(const bsdmrg_plan_s* P, const double* L, const double* W1, const double* W2, const double* R,
+                    double* D, hipStream_t s) {
+  hipError_t e = dav_fill_zero(D, P->psi_elems, s);
+  if (e != hipSuccess || P->diag_tasks.empty()) return e;
+  hipLaunchKernelGGL(diag_kernel, dim3((unsigned)P->diag_tasks.size()), dim3(DT), 0, s, P->d_diag_tasks, L, W1,
+                     W2, R, D);
   return hipGetLastError();
 }
 
@@ -683,14 +860,14 @@ hipError_t dav_gram_eig(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStre
   hipError_t e = dav_psum(P, i + 1, b.part_a, b.red, kMaxBasis, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(gram_eig_kernel, dim3((unsigned)P->probs.size()), dim3(GT), 0, s, kMaxBasis, i, b.B,
-                     b.red, b.M, b.svec, b.lam);
+                     b.red, b.M, b.svec, b.lam, b.svec_prev);
   return hipGetLastError();
 }
 
 hipError_t dav_ritz(const bsdmrg_plan_s* P, const DavBufs& b, int i, bool want_x, double* part_d,
-                    hipStream_t s) {
+                    const double* D, hipStream_t s) {
   hipLaunchKernelGGL(ritz_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), i + 1, b.B,
-                     b.V, b.VA, b.n, b.svec, b.lam, want_x ? b.x : nullptr, b.q, b.part_n0, part_d);
+                     b.V, b.VA, b.n, b.svec, b.lam, want_x ? b.x : nullptr, b.q, b.part_n0, part_d, b.part_res, D);
   return hipGetLastError();
 }
 
@@ -704,9 +881,9 @@ hipError_t dav_update(const bsdmrg_plan_s* P, const DavBufs& b, int J, const dou
   return hipGetLastError();
 }
 
-hipError_t dav_finalize(const bsdmrg_plan_s* P, const DavBufs& b, int i, uint64_t seed, double rtol,
+hipError_t dav_finalize(const bsdmrg_plan_s* P, const DavBufs& b, int J, int step, uint64_t seed, double rtol,
                         const int64_t* blk_off, const int32_t* blk_ptr, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)P->probs.size()), dim3(DT), 0, s, dav_probs(P), i, b.B,
+  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)P->probs.size()), dim3(DT), 0, s, dav_probs(P), J, step, b.B,
                      b.n, b.V, b.q, b.part_n0, b.part_n1, blk_off, blk_ptr, seed, rtol, b.scale, b.restarts,
                      b.status);
   return hipGetLastError();

@@ -265,6 +265,30 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
     }
     P->s3.tasks.push_back(t);
   }
+  // ---- diagonal of H_eff: flux-0 channels of L, W1, W2, R per psi block ----
+  {
+    const Charge zero{0, 0};
+    const int f0 = p.wl.find(zero), m0 = p.wm.find(zero), g0 = p.wr.find(zero);
+    if (f0 >= 0 && m0 >= 0 && g0 >= 0) {
+      const int64_t nl = p.wl.d[f0], nm = p.wm.d[m0], nr = p.wr.d[g0];
+      if (nl > kMaxDiagChannels || nr > kMaxDiagChannels)
+        throw Error{BSDMRG_EINVAL, "plan: more than 64 channels in the flux-0 sector"};
+      for (size_t pb = 0; pb < p.psi.keys.size(); ++pb) {
+        const Key& k = p.psi.keys[pb];
+        const int ia = k[0], i1 = k[1], i2 = k[2], ic = k[3];
+        const int lb = p.L.lookup(key3(ia, f0, ia)), rb = p.R.lookup(key3(ic, g0, ic));
+        const int b1 = p.W1.lookup(key4(f0, i1, i1, m0)), b2 = p.W2.lookup(key4(m0, i2, i2, g0));
+        if (lb < 0 || rb < 0 || b1 < 0 || b2 < 0 || !nz1[b1] || !nz2[b2]) continue;   // diagonal 0
+        const int32_t rows = (int32_t)p.a.d[ia], cols = (int32_t)p.c.d[ic];
+        const int32_t per = std::max<int32_t>(1, kMixItemElems / cols);
+        for (int32_t r0 = 0; r0 < rows; r0 += per)
+          P->diag_tasks.push_back(DiagTask{p.psi_base + p.psi.offs[pb], p.L_base + p.L.offs[lb],
+                                           p.R_base + p.R.offs[rb], p.W1_base + p.W1.offs[b1],
+                                           p.W2_base + p.W2.offs[b2], rows, cols, (int32_t)nl, (int32_t)nm,
+                                           (int32_t)nr, r0, std::min(per, rows - r0), 0});
+      }
+    }
+  }
   P->t1_elems += p.t1_elems;
   P->t2_elems += p.t2_elems;
   P->n_coefs += p.n_coefs;

@@ -119,6 +119,18 @@ void validate_heff_plan(const bsdmrg_plan_s* P) {
     for (int32_t b = P->blk_ptr[p]; b < P->blk_ptr[p + 1]; ++b)
       if (P->blk_off[2 * b] < 0 || P->blk_off[2 * b] + P->blk_off[2 * b + 1] > d.len) fail("psi block table");
   }
+  // diagonal tasks: every element read or written stays inside its buffer
+  for (const DiagTask& t : P->diag_tasks) {
+    if (t.rows < 1 || t.cols < 1 || t.nl < 1 || t.nm < 1 || t.nr < 1 || t.nl > kMaxDiagChannels ||
+        t.nr > kMaxDiagChannels || t.row0 < 0 || t.nrow < 1 || t.row0 + t.nrow > t.rows ||
+        (int64_t)t.nrow * t.cols > 4096)
+      fail("diagonal task shape");
+    if (t.psi_off < 0 || t.psi_off + (int64_t)t.rows * t.cols > P->psi_elems) fail("diagonal task psi range");
+    if (t.l_off < 0 || t.l_off + (int64_t)t.rows * t.nl * t.rows > P->L_elems) fail("diagonal task L range");
+    if (t.r_off < 0 || t.r_off + (int64_t)t.cols * t.nr * t.cols > P->R_elems) fail("diagonal task R range");
+    if (t.w1_off < 0 || t.w1_off + (int64_t)t.nl * t.nm > P->W1_elems) fail("diagonal task W1 range");
+    if (t.w2_off < 0 || t.w2_off + (int64_t)t.nm * t.nr > P->W2_elems) fail("diagonal task W2 range");
+  }
 }
 
 }  // namespace bsd

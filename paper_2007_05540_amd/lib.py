@@ -52,13 +52,15 @@ class PlanInfo(ctypes.Structure):
 class EigOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("refine_max_iter", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("tol", ctypes.c_double), ("tol_f32", ctypes.c_double), ("restart_rtol", ctypes.c_double)]
+                ("use_graph", ctypes.c_int32), ("restart_keep", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("tol", ctypes.c_double), ("tol_f32", ctypes.c_double), ("restart_rtol", ctypes.c_double),
+                ("basis", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class EigStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("iters_f32", ctypes.c_int32), ("restarts", ctypes.c_int32),
-                ("converged", ctypes.c_int32), ("residual", ctypes.c_double)]
+                ("converged", ctypes.c_int32), ("residual", ctypes.c_double), ("thick_restarts", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class TruncOpts(ctypes.Structure):
@@ -75,7 +77,7 @@ _lib = None
 
 EXPORTS = ["bsdmrg_layout", "bsdmrg_plan", "bsdmrg_plan_query", "bsdmrg_plan_offsets", "bsdmrg_plan_tasks",
            "bsdmrg_plan_destroy", "bsdmrg_heff_apply", "bsdmrg_heff_apply_noalloc", "bsdmrg_eig_workspace",
-           "bsdmrg_eigensolve",
+           "bsdmrg_eigensolve", "bsdmrg_heff_diagonal",
            "bsdmrg_heff_backward", "bsdmrg_heff_backward_workspace", "bsdmrg_heff_energy", "bsdmrg_stage_timing",
            "bsdmrg_plan_autotune", "bsdmrg_plan_set_tiles", "bsdmrg_truncate_workspace", "bsdmrg_truncate",
            "bsdmrg_env_plan", "bsdmrg_merge_plan", "bsdmrg_op_query", "bsdmrg_op_destroy", "bsdmrg_env_update",
@@ -105,6 +107,7 @@ def load():
     lib.bsdmrg_heff_apply.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, i64, vp]
     lib.bsdmrg_heff_apply_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.bsdmrg_eig_workspace.argtypes = [vp, ctypes.POINTER(EigOpts), ctypes.POINTER(i64)]
+    lib.bsdmrg_heff_diagonal.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.bsdmrg_eigensolve.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(EigOpts),
                                       ctypes.POINTER(dp), ctypes.POINTER(EigStats), vp, i64, vp]
     lib.bsdmrg_heff_backward.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(dp), vp, vp, vp, vp, vp, vp,
@@ -252,9 +255,18 @@ def heff_apply_noalloc(plan, precision, L, W1, W2, R, psi, out, stream=None):
 
 
 def eig_opts(max_iter=10, precision=F64, refine_max_iter=4, fixed_iters=0, use_graph=0, seed=0, tol=1e-12,
-             tol_f32=1e-5, restart_rtol=1e-10):
-    return EigOpts(max_iter, precision, refine_max_iter, fixed_iters, use_graph, 0, seed, tol, tol_f32,
-                   restart_rtol)
+             tol_f32=1e-5, restart_rtol=1e-10, restart_keep=0, basis=0, precond=0):
+    """Options of eigensolve (bsdmrg_eig_opts): max_iter products in the first
+    phase; with restart_keep = 1 the basis holds at most `basis` vectors
+    (0: 64) and is restarted when full; precond = 1 uses the diagonal."""
+    return EigOpts(max_iter, precision, refine_max_iter, fixed_iters, use_graph, restart_keep, seed, tol, tol_f32,
+                   restart_rtol, basis, precond)
+
+
+def heff_diagonal(plan, L, W1, W2, R, D, stream=None):
+    """D = diagonal of H_eff in psi's layout (padding 0)."""
+    check(load().bsdmrg_heff_diagonal(plan.handle, _ptr(L), _ptr(W1), _ptr(W2), _ptr(R), _ptr(D),
+                                      _stream(stream)))
 
 
 def eig_workspace(plan, opts):

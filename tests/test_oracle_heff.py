@@ -262,10 +262,11 @@ def test_restarted_davidson_converges_to_dense_lowest():
     assert st_wide["iters"] <= st["iters"]
 
 
-def test_restart_without_previous_vector_takes_next_ritz_vector():
-    """keep + 2 == basis on a 3-dimensional diagonal operator started from a
-    vector with weight on all three states: the solve reaches the exact
-    lowest value with restarts (the rule's fallback path is well defined)."""
+def test_restart_with_smallest_basis_reaches_lowest_value():
+    """keep + 2 == basis (a restart after every product) on a diagonal
+    operator started from a vector with weight on every state: the solve
+    still reaches the exact lowest value (the kept pair spans the current and
+    the previous Ritz vector, or the newest direction when they coincide)."""
     D = np.diag([1.0, 2.0, 3.0, 10.0])
     x0 = np.array([1.0, 1.0, 1.0, 1.0])
     lam, x, st = davidson(lambda v: D @ v, x0, max_iter=40, tol=1e-12, basis=3, keep=1)
