@@ -6,26 +6,28 @@ m = 1024 on both bond legs (21 spin sectors, largest block 270, sector model of
 the paper's Table 2), MPO k = 14, random Hermitian-structured environments,
 random start vector; synthetic seeded inputs.
 
-One step = one bsdmrg_eigensolve call with a fixed number of Davidson steps
-(captured once as a hipGraph and replayed):
-  mixed path (the reported value): N_F32 products in FP32 MFMA + N_F64
-      products in FP64 after restarting from the FP32 Ritz vector; all
-      orthogonalisation, Rayleigh quotients and the energy in FP64;
-  f64 path: N_F32 + N_F64 products all in FP64, same schedule.
-value = useful GFLOP/s = (products per step x useful flops per product) /
-time per step, where useful flops are the block-pair flops of the two GEMM
-stages (the flop definition of the paper's list method).
+One step = one converged bsdmrg_eigensolve call (bounded basis with thick
+restart), from the same start vector, until the FP64 residual ||q|| <= --tol:
+  mixed path (the reported value): FP32-MFMA products until the FP32 phase's
+      residual reaches --tol-f32, then FP64 products from the two kept basis
+      vectors; all orthogonalisation, Rayleigh quotients and the energy FP64;
+  f64 path: FP64 products throughout.
+Both reach the same accuracy (their energies agree to ~1e-11 here; the line
+reports the difference and the eigenvector error between them).
+value = useful GFLOP/s = (products per solve x useful flops per product) /
+time per solve, useful flops being the block-pair flops of the two GEMM
+stages (the flop definition of the paper's list method), Davidson overhead
+included in the time.
 
-The JSON line also carries the per-stage times of one product, the roofline
-of the dominant grouped GEMM, the same product in the sparse-dense format
-(dense operands, one library GEMM per stage: the work the blocks avoid), the 64-bond batch (one launch per stage for all
-bonds), the m = 4096 Hubbard-type bond (U(1)xU(1), k = 22), sweeps of the
-6x6 J1-J2 cylinder at m = 256 with one sweep per path from the converged
-state (s/sweep of the FP64 and the mixed path at equal accuracy), four
-sweeps of the 16-site Heisenberg chain at m = 64 per path, and the oracle's
-CPU rate (cpu_baseline).  Other workloads: --workload j1j2-6x6
-(adds dE/dJ2 by the adjoint and by finite differences), chain16,
-hubbard-4x16.
+The JSON line also carries the per-stage times and MFMA rooflines of one
+product in both precisions (m = 1024 and m = 2048, k = 18), the roofline of the
+dominant FP32 grouped GEMM, the same product in the sparse-dense format (the
+work the blocks avoid), the 64-bond batch (one launch per stage for all
+bonds, fixed 10-step solves), the m = 4096 Hubbard-type bond (U(1)xU(1),
+k = 22), sweeps of the 6x6 J1-J2 cylinder at m = 256 (s/sweep of the FP64 and
+the mixed path at equal accuracy) and of the 16-site chain, and the oracle's
+CPU rate (cpu_baseline).  Other workloads: --workload j1j2-6x6 (adds dE/dJ2 by
+the adjoint and by finite differences), chain16, hubbard-4x16.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -52,8 +54,8 @@ HBM_TRAFFIC = {"s1": 72457089, "s3": 93191677}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n-f32", type=int, default=10)
     ap.add_argument("--n-f64", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -69,6 +71,13 @@ def parse():
                          "sweeps of the 16-site Heisenberg chain; hubbard-4x16: sweeps of the 4x16 Hubbard "
                          "cylinder at half filling")
     ap.add_argument("--m-max", type=int, default=512)
+    ap.add_argument("--tol", type=float, default=1e-5, help="FP64 residual of a converged solve")
+    ap.add_argument("--tol-f32", type=float, default=1e-5, help="residual that ends the FP32 phase")
+    ap.add_argument("--basis", type=int, default=16, help="Davidson basis (thick restart to 2 vectors)")
+    ap.add_argument("--max-products", type=int, default=1000)
+    ap.add_argument("--check-every", type=int, default=4,
+                    help="read the residual back after every this many products (tol-driven solves)")
+    ap.add_argument("--no-large", action="store_true", help="skip the m=2048, k=18 bond stage rooflines")
     return ap.parse_args()
 
 
@@ -406,6 +415,64 @@ def hubbard_bond_bench(args):
     return out
 
 
+def converged_solves(plan, info, dev, args, stream):
+    """Time-to-solution of the FP64 path and of the mixed path on one bond,
+    both run until the FP64 residual ||q|| <= args.tol (the mixed path: FP32
+    products until its own residual reaches args.tol_f32, then FP64 products
+    from the kept basis), from the same start vector.  Returns per path the
+    ms per converged solve (mean of --steps solves after --warmup), the
+    products of each precision, the energy and the residual."""
+    import torch
+    from paper_2007_05540_amd import lib
+    flops = info["flops_s1"] + info["flops_s3"]
+    common = dict(restart_keep=1, basis=args.basis, tol=args.tol, max_iter=args.max_products,
+                  check_every=args.check_every)
+    opts = {"f64": lib.eig_opts(**common),
+            "mixed": lib.eig_opts(precision=lib.F32_REFINE, refine_max_iter=args.max_products, tol_f32=args.tol_f32,
+                                  **common)}
+    out = {}
+    for path, o in opts.items():
+        ws = torch.empty(lib.eig_workspace(plan, o), dtype=torch.uint8, device="cuda")
+        psi = torch.empty_like(dev["psi"])
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                psi.copy_(dev["psi"])
+                lib.eigensolve(plan, dev["L"], dev["W1"], dev["W2"], dev["R"], psi, o, ws, stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                psi.copy_(dev["psi"])
+                e, st = lib.eigensolve(plan, dev["L"], dev["W1"], dev["W2"], dev["R"], psi, o, ws, stream=stream)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+        products = st[0]["iters"] + st[0]["iters_f32"]
+        out[path] = {"ms_per_solve": dt * 1e3, "products_f32": st[0]["iters_f32"], "products_f64": st[0]["iters"],
+                     "energy": e[0], "residual": st[0]["residual"], "converged": bool(st[0]["converged"]),
+                     "thick_restarts": st[0]["thick_restarts"], "gflops": products * flops / dt / 1e9,
+                     "psi": psi.clone()}
+        del ws
+    return out
+
+
+def stage_roofline(plan, info, dev, stream, reps=20):
+    """Per-stage ms of one product in both precisions (HIP events on the
+    launch stream) and the MFMA roofline of the two grouped-GEMM stages."""
+    import torch
+    from paper_2007_05540_amd import lib
+    out = torch.zeros_like(dev["psi"])
+    wsa = torch.empty(info["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    stage, roof = {}, {}
+    for prec, name in ((lib.F32, "f32"), (lib.F64, "f64")):
+        ms = lib.stage_timing(plan, prec, dev["L"], dev["W1"], dev["W2"], dev["R"], dev["psi"], out, wsa, reps=reps,
+                              stream=stream)
+        stage[name] = {k: round(v, 5) for k, v in ms.items()}
+        for st in ("s1", "s3"):
+            tf = info["flops_" + st] / (ms[st] * 1e-3) / 1e12
+            roof[f"{st}_{name}"] = {"tflops": round(tf, 2), "frac": round(tf / PEAK[name], 4)}
+    del out, wsa
+    return stage, roof
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -423,17 +490,21 @@ def main():
     from paper_2007_05540_amd import lib, problems
 
     spec = synth.c2_bond(m=1024, k=14, seed=1)
-    plan, info, flops, dev, results = bond_measure(spec, args)
+    prob, ops = problems.bond_problem(spec)
+    plan = lib.Plan([prob])
+    info = plan.info()
+    flops = info["flops_s1"] + info["flops_s3"]
+    dev = {k: torch.from_numpy(v).to("cuda") for k, v in ops.items()}
+    del ops
     stream = torch.cuda.Stream()
-    psi0 = dev["psi"]
+    tiles = autotune(plan, info, dev, stream)
+    solves = converged_solves(plan, info, dev, args, stream)
+    mixed, f64 = solves["mixed"], solves["f64"]
+    overlap = abs(float(torch.dot(mixed.pop("psi"), f64.pop("psi"))))
+    rel_de = abs(mixed["energy"] - f64["energy"]) / abs(f64["energy"])
 
     # live per-kernel timing of one product (HIP events on the launch stream)
-    out = torch.zeros_like(psi0)
-    wsa = torch.empty(info["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
-    stage = {}
-    for prec, name in ((lib.F32, "f32"), (lib.F64, "f64")):
-        stage[name] = lib.stage_timing(plan, prec, dev["L"], dev["W1"], dev["W2"], dev["R"], psi0, out, wsa,
-                                       reps=20, stream=stream)
+    stage, roofs = stage_roofline(plan, info, dev, stream)
     s32 = stage["f32"]
     dom = "s1" if s32["s1"] >= s32["s3"] else "s3"
     dom_flops = info["flops_" + dom]
@@ -442,30 +513,42 @@ def main():
                 "peak": PEAK["f32"], "unit": "TFLOP/s", "frac": round(achieved / PEAK["f32"], 4),
                 "traffic": HBM_TRAFFIC[dom], "traffic_unit": "bytes per launch",
                 "ms_per_launch": round(s32[dom], 5), "flops_per_launch": dom_flops}
+    s64 = stage["f64"]
+    dom64 = "s1" if s64["s1"] >= s64["s3"] else "s3"
+    a64 = info["flops_" + dom64] / (s64[dom64] * 1e-3) / 1e12
+    roofline_f64 = {"bound": "mfma", "kernel": f"ggemm {dom64.upper()} FP64", "achieved": round(a64, 3),
+                    "peak": PEAK["f64"], "unit": "TFLOP/s", "frac": round(a64 / PEAK["f64"], 4),
+                    "ms_per_launch": round(s64[dom64], 5), "flops_per_launch": info["flops_" + dom64]}
 
     ablation = dense_ablation(spec, plan, dev)
-    mixed, f64 = results["mixed"], results["f64"]
     line = {
         "metric": "block-sparse H_eff·ψ useful GFLOP/s & s/sweep: FP64 vs mixed+batched at 1e-9 dE",
         "value": round(mixed["gflops"], 3), "unit": "useful GFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(mixed["ms_per_step"], 4), "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": round(mixed["ms_per_solve"], 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32-mfma products + f64 refinement",
         "data": "synthetic (seeded Heisenberg-type bond, Hermitian-structured random environments)",
         "config": {"workload": "isolated mid-chain two-site bond, 6x6 Heisenberg cylinder, m=1024, k=14, "
-                               "21 U(1) sectors", "davidson_steps": f"{args.n_f32} FP32 + {args.n_f64} FP64",
-                   "useful_gflop_per_product": round(flops / 1e9, 4), "graph": True,
-                   "tiles": results["tiles"]},
-        "f64_path": {"value": round(f64["gflops"], 3), "ms_per_step": round(f64["ms_per_step"], 4),
-                     "energy": f64["energy"], "residual": f64["residual"]},
-        "mixed_energy": mixed["energy"], "mixed_residual": mixed["residual"],
-        "speedup_mixed_vs_f64": round(f64["ms_per_step"] / mixed["ms_per_step"], 3),
-        "stage_ms": {k: {s: round(v, 5) for s, v in d.items()} for k, d in stage.items()},
+                               "21 U(1) sectors; one step = one Davidson solve to ||q|| <= %g" % args.tol,
+                   "davidson": f"basis {args.basis}, thick restart to 2, FP32 phase to ||q|| <= {args.tol_f32:g}, "
+                               f"residual checked every {args.check_every} products",
+                   "useful_gflop_per_product": round(flops / 1e9, 4), "tiles": tiles},
+        "f64_path": {"value": round(f64["gflops"], 3), "ms_per_step": round(f64["ms_per_solve"], 4),
+                     "products": f64["products_f64"], "energy": f64["energy"], "residual": f64["residual"],
+                     "converged": f64["converged"]},
+        "mixed_path": {"products_f32": mixed["products_f32"], "products_f64": mixed["products_f64"],
+                       "energy": mixed["energy"], "residual": mixed["residual"], "converged": mixed["converged"]},
+        "equal_accuracy": {"energy_rel_diff": rel_de, "within_1e-9": bool(rel_de <= 1e-9),
+                           "psi_error": 1.0 - overlap},
+        "speedup_mixed_vs_f64": round(f64["ms_per_solve"] / mixed["ms_per_solve"], 3),
+        "stage_ms": stage, "stage_roofline": roofs,
         "dense_format_ablation": ablation,
-        "roofline": roofline,
+        "roofline": roofline, "roofline_f64": roofline_f64,
     }
-    del dev, out, wsa
+    del dev
     plan.destroy()
     torch.cuda.empty_cache()
+    if not args.no_large:
+        line["bond_m2048_k18"] = large_bond_bench(args)
     if not args.no_batch:
         line["batch_64_bonds"] = batch_bench(args)
     if not args.no_hubbard:
@@ -480,6 +563,29 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, flops, args.cpu_seconds)
     print(json.dumps(line))
+
+
+def large_bond_bench(args):
+    """The m = 2048, k = 18 bond (25 spin sectors, the largest of the batch):
+    per-stage times and MFMA rooflines of one product in both precisions."""
+    import torch
+    import synth
+    from paper_2007_05540_amd import lib, problems
+    spec = synth.c2_bond(m=2048, k=18, seed=1)
+    prob, ops = problems.bond_problem(spec)
+    plan = lib.Plan([prob])
+    info = plan.info()
+    dev = {k: torch.from_numpy(v).to("cuda") for k, v in ops.items()}
+    del ops
+    stream = torch.cuda.Stream()
+    stage, roofs = stage_roofline(plan, info, dev, stream)
+    out = {"workload": "isolated two-site bond, m=2048, k=18, 25 U(1) sectors",
+           "useful_gflop_per_product": round((info["flops_s1"] + info["flops_s3"]) / 1e9, 3),
+           "s3_split_k": info["s3_split_k"], "stage_ms": stage, "stage_roofline": roofs}
+    del dev
+    plan.destroy()
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

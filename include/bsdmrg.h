@@ -197,6 +197,12 @@ typedef struct {
   int32_t basis;           /* basis size with thick restart (3..64; 0: 64)   */
   int32_t precond;         /* 0: none (Alg. 1); 1: Davidson's diagonal
                               preconditioner (see bsdmrg_eigensolve)        */
+  int32_t check_every;     /* tol mode: ||q|| is read back (one host sync)
+                              after every check_every-th product only, and
+                              at the end of a phase (0 or 1: every product);
+                              the solve then stops at the first check with
+                              ||q|| <= tol                                    */
+  int32_t reserved;
 } bsdmrg_eig_opts;
 
 typedef struct {

@@ -301,6 +301,7 @@ static void validate_opts(const bsdmrg_plan_s* P, const bsdmrg_eig_opts* o) {
     throw Error{BSDMRG_EINVAL, "eigensolve precision must be F64 or F32_REFINE"};
   if (o->restart_keep != 0 && o->restart_keep != 1) throw Error{BSDMRG_EINVAL, "restart_keep must be 0 or 1"};
   if (o->precond != 0 && o->precond != 1) throw Error{BSDMRG_EINVAL, "precond must be 0 or 1"};
+  if (o->check_every < 0 || o->check_every > 4096) throw Error{BSDMRG_EINVAL, "check_every must be in 0..4096"};
   const bool mixed = o->precision == BSDMRG_F32_REFINE;
   if (o->restart_keep == 0) {
     if (o->max_iter < 1 || o->max_iter > 64) throw Error{BSDMRG_EINVAL, "max_iter must be in 1..64"};
@@ -436,7 +437,8 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
       const bool last = products >= f.budget || j >= dim;
       // q, t and (unless this is the last step) the first Gram-Schmidt dots v_c^T t
       HIPCHK(dav_ritz(P, d, i, false, last ? nullptr : d.part_a, d.D, s));
-      if (!o->fixed_iters) {
+      const int every = std::max(1, o->check_every);
+      if (!o->fixed_iters && (last || products % every == 0)) {
         HIPCHK(hipMemcpyAsync(hpart.data(), d.part_res, hpart.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         bool all = true;

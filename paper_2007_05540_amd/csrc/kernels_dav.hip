@@ -151,6 +151,88 @@ __global__ __launch_bounds__(DT) void normalize_kernel(const Chunk* __restrict__
   for (int e = threadIdx.x; e < ch.len; e += DT) y[ch.start + e] = x[ch.start + e] * inv;
 }
 
+constexpr int kMaxBasis = 64;
+constexpr int GT = 64;   // one wave
+
+// A[r][c] = Mp[r * B + c] for r, c < n (lane r loads row r; the loads of a
+// group of eight are issued before any of them is stored).
+__device__ __forceinline__ void load_rows(double (*A)[kMaxBasis + 1], const double* __restrict__ Mp, int B, int n,
+                                          int lane) {
+  if (lane >= n) return;
+  const double* row = Mp + (int64_t)lane * B;
+  for (int c0 = 0; c0 < n; c0 += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = c0 + u < n ? row[c0 + u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (c0 + u < n) A[lane][c0 + u] = t[u];
+  }
+}
+
+// Householder tridiagonalisation of the leading n x n block of A (n <= R)
+// with row r held in the registers of lane r; the Householder vectors go to
+// Vh, the diagonal and off-diagonal of T to d and e.  The vector and its
+// image are broadcast with lane reads.
+template <int R>
+__device__ __forceinline__ void tridiag_in_registers(const double (*A)[kMaxBasis + 1], double (*Vh)[kMaxBasis],
+                                                     double* d, double* e, int n, int lane) {
+  double ar[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) ar[c] = (lane < n && c < n) ? A[lane][c] : 0.0;
+#pragma unroll
+  for (int k = 0; k + 2 < R; ++k) {
+    if (k + 2 < n) {
+      const bool mine = lane > k && lane < n;
+      const double xr = mine ? ar[k] : 0.0;
+      const double nrm2 = wave_total(xr * xr);
+      const double x0 = readlane_d(ar[k], k + 1);
+      const double alpha = nrm2 > 0.0 ? -copysign(sqrt(nrm2), x0) : 0.0;
+      const double vn2 = 2.0 * (nrm2 - alpha * x0);   // ||x - alpha e_{k+1}||^2
+      const double vr = vn2 > 0.0 ? (xr - (lane == k + 1 ? alpha : 0.0)) / sqrt(vn2) : 0.0;
+      Vh[k][lane] = vr;
+      const double dk = readlane_d(ar[k], k);
+      if (lane == 0) {
+        d[k] = dk;
+        e[k] = alpha;
+      }
+      if (vn2 > 0.0) {
+        // p = A v over the trailing columns (zero past n on both sides)
+        double vc[R];
+        double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+        for (int c = k + 1; c < R; ++c) {
+          vc[c] = readlane_d(vr, c);
+          if ((c - k) & 1) p0 += ar[c] * vc[c];
+          else p1 += ar[c] * vc[c];
+        }
+        const double pr = mine ? p0 + p1 : 0.0;
+        const double beta = wave_total(vr * pr);
+        const double wr = pr - beta * vr;
+#pragma unroll
+        for (int c = k + 1; c < R; ++c) ar[c] -= 2.0 * (vr * readlane_d(wr, c) + wr * vc[c]);
+      }
+    }
+  }
+  // the last 2 x 2 block
+  double dl = 0.0, dm = 0.0, el = 0.0;
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    if (c == n - 2) {
+      dl = readlane_d(ar[c], c);
+      el = readlane_d(ar[c], c + 1);
+    }
+    if (c == n - 1) dm = readlane_d(ar[c], c);
+  }
+  if (lane == 0) {
+    if (n >= 2) {
+      d[n - 2] = dl;
+      e[n - 2] = el;
+    }
+    d[n - 1] = dm;
+  }
+}
+
 // Gram row m_ij = m_ji = (v^A_j)^T v_i (j <= i) from the chunk partials, then
 // the lowest eigenpair of the (i+1) x (i+1) projected matrix M, in one wave
 // (lane r owns row r, so no step needs more than a wave-level reduction):
@@ -164,9 +246,6 @@ __global__ __launch_bounds__(DT) void normalize_kernel(const Chunk* __restrict__
 //     (T - lambda I) / ||T|| (tridiagonal Gaussian elimination with partial
 //     pivoting, a pivot below eps replaced by eps);
 //  4. back-transformation x = Q y.
-constexpr int kMaxBasis = 64;
-constexpr int GT = 64;   // one wave
-constexpr int kRegRows = 16;   // register path of the tridiagonalisation
 __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, const double* __restrict__ red,
                                                       double* __restrict__ M, double* __restrict__ svec,
                                                       double* __restrict__ lam, double* __restrict__ svec_prev) {
@@ -179,11 +258,15 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
   // the previous step's Ritz vector in the coordinates of the grown basis
   // (its new last coordinate is 0); read before svec is overwritten below
   if (svec_prev && lane <= i) svec_prev[(int64_t)p * B + lane] = lane < i ? svec[(int64_t)p * B + lane] : 0.0;
-  // the new row and column come from red; the rest from the stored matrix
-  for (int e2 = lane; e2 < n * n; e2 += GT) {
-    const int r = e2 / n, c = e2 % n;
-    A[r][c] = (r == i) ? rp[c] : (c == i) ? rp[r] : Mp[r * B + c];
+  // the new row and column come from red, the rest from the stored matrix:
+  // lane r reads row r, eight independent loads in flight at a time
+  load_rows(A, Mp, B, i, lane);
+  if (lane < i) {
+    const double v = rp[lane];
+    A[i][lane] = v;
+    A[lane][i] = v;
   }
+  if (lane == i) A[i][i] = rp[i];
   if (lane <= i) {
     const double v = rp[lane];
     Mp[i * B + lane] = v;
@@ -191,63 +274,12 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
   }
   __syncthreads();
   // 1. tridiagonalisation (lane r owns row r of the trailing block).  Up to
-  // kRegRows rows the row is held in registers and the Householder vector
-  // and its image are broadcast with lane reads; larger matrices stay in LDS.
-  if (n <= kRegRows) {
-    double ar[kRegRows];
-#pragma unroll
-    for (int c = 0; c < kRegRows; ++c) ar[c] = (lane < n && c < n) ? A[lane][c] : 0.0;
-#pragma unroll
-    for (int k = 0; k + 2 < kRegRows; ++k) {
-      if (k + 2 < n) {
-        const bool mine = lane > k && lane < n;
-        const double xr = mine ? ar[k] : 0.0;
-        const double nrm2 = wave_total(xr * xr);
-        const double x0 = readlane_d(ar[k], k + 1);
-        const double alpha = nrm2 > 0.0 ? -copysign(sqrt(nrm2), x0) : 0.0;
-        const double vn2 = 2.0 * (nrm2 - alpha * x0);   // ||x - alpha e_{k+1}||^2
-        const double vr = vn2 > 0.0 ? (xr - (lane == k + 1 ? alpha : 0.0)) / sqrt(vn2) : 0.0;
-        Vh[k][lane] = vr;
-        const double dk = readlane_d(ar[k], k);
-        if (lane == 0) {
-          d[k] = dk;
-          e[k] = alpha;
-        }
-        if (vn2 > 0.0) {
-          // p = A v over the trailing columns (zero past n on both sides)
-          double vc[kRegRows];
-          double p0 = 0.0, p1 = 0.0;
-#pragma unroll
-          for (int c = k + 1; c < kRegRows; ++c) {
-            vc[c] = readlane_d(vr, c);
-            if ((c - k) & 1) p0 += ar[c] * vc[c];
-            else p1 += ar[c] * vc[c];
-          }
-          const double pr = mine ? p0 + p1 : 0.0;
-          const double beta = wave_total(vr * pr);
-          const double wr = pr - beta * vr;
-#pragma unroll
-          for (int c = k + 1; c < kRegRows; ++c) ar[c] -= 2.0 * (vr * readlane_d(wr, c) + wr * vc[c]);
-        }
-      }
-    }
-    // the last 2 x 2 block
-    double dl = 0.0, dm = 0.0, el = 0.0;
-#pragma unroll
-    for (int c = 0; c < kRegRows; ++c) {
-      if (c == n - 2) {
-        dl = readlane_d(ar[c], c);
-        el = readlane_d(ar[c], c + 1);
-      }
-      if (c == n - 1) dm = readlane_d(ar[c], c);
-    }
-    if (lane == 0) {
-      if (n >= 2) {
-        d[n - 2] = dl;
-        e[n - 2] = el;
-      }
-      d[n - 1] = dm;
-    }
+  // 16 or 32 rows the row is held in registers (tridiag_in_registers);
+  // larger matrices stay in LDS.
+  if (n <= 16) {
+    tridiag_in_registers<16>(A, Vh, d, e, n, lane);
+  } else if (n <= 32) {
+    tridiag_in_registers<32>(A, Vh, d, e, n, lane);
   } else {
     for (int k = 0; k + 2 < n; ++k) {
       const bool mine = lane > k && lane < n;
@@ -532,6 +564,9 @@ __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ ch
   if (mode == 1 && threadIdx.x == 0) nq0[ch.prob] = nred;   // same value from every block
   __syncthreads();
   const bool pass = mode == 1 || !(nred >= 0.5 * nq0[ch.prob]);
+  // a second pass that is not needed writes nothing: the finalize step takes
+  // ||q||^2 after the first pass from red (the same test decides there)
+  if (!pass) return;
   double qv[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
@@ -601,6 +636,8 @@ __global__ __launch_bounds__(DT) void finalize_kernel(const DavProb* __restrict_
                                                       double* __restrict__ q,
                                                       const double* __restrict__ part_n0,
                                                       const double* __restrict__ part_n1,
+                                                      const double* __restrict__ red, int ldr,
+                                                      const double* __restrict__ nq0,
                                                       const int64_t* __restrict__ blk_off,
                                                       const int32_t* __restrict__ blk_ptr, uint64_t seed,
                                                       double rtol, double* __restrict__ scale,
@@ -612,7 +649,15 @@ __global__ __launch_bounds__(DT) void finalize_kernel(const DavProb* __restrict_
   const int p = blockIdx.x;
   const DavProb pr = probs[p];
   sum_partials(part_n0, 0, pr, 1, nn, sh);
-  sum_partials(part_n1, 0, pr, 1, nn + 1, sh);
+  // ||q||^2 after orthogonalisation: after the second pass if it was made
+  // (same test as the update kernel), else after the first (in red)
+  const double n1 = red[(int64_t)p * ldr + J];
+  if (!(n1 >= 0.5 * nq0[p])) {
+    sum_partials(part_n1, 0, pr, 1, nn + 1, sh);
+  } else if (threadIdx.x == 0) {
+    nn[1] = n1;
+  }
+  __syncthreads();
   const double nb = nn[0], na = nn[1];
   if (na >= rtol * rtol * nb && na > 0.0) {
     if (threadIdx.x == 0) scale[p] = 1.0 / sqrt(na);
@@ -687,7 +732,7 @@ __global__ __launch_bounds__(GT) void restart_kernel(int j, int B, int nkeep, do
   __shared__ double A[kMaxBasis][kMaxBasis + 1];
   const int p = blockIdx.x, lane = threadIdx.x;
   double* Mp = M + (int64_t)p * B * B;
-  for (int e2 = lane; e2 < j * j; e2 += GT) A[e2 / j][e2 % j] = Mp[(e2 / j) * B + (e2 % j)];
+  load_rows(A, Mp, B, j, lane);
   const double sv = lane < j ? svec[(int64_t)p * B + lane] : 0.0;
   double ev = 0.0;
   if (nkeep == 2) {
@@ -884,7 +929,7 @@ hipError_t dav_update(const bsdmrg_plan_s* P, const DavBufs& b, int J, const dou
 hipError_t dav_finalize(const bsdmrg_plan_s* P, const DavBufs& b, int J, int step, uint64_t seed, double rtol,
                         const int64_t* blk_off, const int32_t* blk_ptr, hipStream_t s) {
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)P->probs.size()), dim3(DT), 0, s, dav_probs(P), J, step, b.B,
-                     b.n, b.V, b.q, b.part_n0, b.part_n1, blk_off, blk_ptr, seed, rtol, b.scale, b.restarts,
+                     b.n, b.V, b.q, b.part_n0, b.part_n1, b.red, kMaxBasis, b.nq0, blk_off, blk_ptr, seed, rtol, b.scale, b.restarts,
                      b.status);
   return hipGetLastError();
 }

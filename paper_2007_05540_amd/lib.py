@@ -54,7 +54,8 @@ class EigOpts(ctypes.Structure):
                 ("refine_max_iter", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("restart_keep", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("tol", ctypes.c_double), ("tol_f32", ctypes.c_double), ("restart_rtol", ctypes.c_double),
-                ("basis", ctypes.c_int32), ("precond", ctypes.c_int32)]
+                ("basis", ctypes.c_int32), ("precond", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class EigStats(ctypes.Structure):
@@ -255,12 +256,13 @@ def heff_apply_noalloc(plan, precision, L, W1, W2, R, psi, out, stream=None):
 
 
 def eig_opts(max_iter=10, precision=F64, refine_max_iter=4, fixed_iters=0, use_graph=0, seed=0, tol=1e-12,
-             tol_f32=1e-5, restart_rtol=1e-10, restart_keep=0, basis=0, precond=0):
+             tol_f32=1e-5, restart_rtol=1e-10, restart_keep=0, basis=0, precond=0, check_every=1):
     """Options of eigensolve (bsdmrg_eig_opts): max_iter products in the first
     phase; with restart_keep = 1 the basis holds at most `basis` vectors
-    (0: 64) and is restarted when full; precond = 1 uses the diagonal."""
+    (0: 64) and is restarted when full; precond = 1 uses the diagonal; in tol
+    mode the residual is checked after every check_every-th product."""
     return EigOpts(max_iter, precision, refine_max_iter, fixed_iters, use_graph, restart_keep, seed, tol, tol_f32,
-                   restart_rtol, basis, precond)
+                   restart_rtol, basis, precond, check_every, 0)
 
 
 def heff_diagonal(plan, L, W1, W2, R, D, stream=None):

@@ -76,8 +76,9 @@ def compare(lib, spec, got, ref, scale=1.0, ops=None):
         assert np.all(np.isfinite(got[k])), k
 
 
-@pytest.mark.parametrize("m,k,seed", [(64, 5, 1), (96, 14, 2), (160, 10, 3)])
+@pytest.mark.parametrize("m,k,seed", [(64, 5, 1), (96, 14, 2), (160, 10, 3), (512, 20, 5)])
 def test_backward_matches_oracle(mods, m, k, seed):
+    """Up to the m = 512, k = 20 bond of the differentiable J1-J2 workload."""
     lib, problems, _ = mods
     spec = synth.c2_bond(m=m, k=k, seed=seed)
     plan, ops, d = setup([spec], lib, problems)

@@ -40,6 +40,20 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def blockwise_max_rel(lib, got, ref, legs):
+    """Largest ||got_b - ref_b|| / ||ref_b|| over the blocks of the canonical
+    layout with a non-zero reference block (the small edge sectors count as
+    much as the large ones)."""
+    keys, offs = lib.layout(legs, PSI_SIGNS)
+    worst = 0.0
+    for b in range(len(keys)):
+        r = ref[offs[b]:offs[b + 1]]
+        nr = np.linalg.norm(r)
+        if nr > 0.0:
+            worst = max(worst, float(np.linalg.norm(got[offs[b]:offs[b + 1]] - r) / nr))
+    return worst
+
+
 def oracle_apply(spec, psi_flat=None):
     L, W1, W2, R, psi = bond_operands(spec)
     if psi_flat is not None:
@@ -101,7 +115,9 @@ def test_apply_f64_full_size_mid_chain_bond(mods):
     ws = torch.empty(plan.info()["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
     lib.heff_apply(plan, lib.F64, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
     torch.cuda.synchronize()
-    assert rel(out.cpu().numpy(), oracle_apply(spec)) < 1e-12
+    got, ref = out.cpu().numpy(), oracle_apply(spec)
+    assert rel(got, ref) < 1e-12
+    assert blockwise_max_rel(lib, got, ref, [spec.a_leg, spec.s_leg, spec.s_leg, spec.c_leg]) < 1e-12
 
 
 ELECTRON_CASES = [(96, 10, 1), (256, 22, 2), (1024, 22, 3)]
@@ -141,6 +157,7 @@ def test_apply_hubbard_bond_full_size(mods):
     del ws, d
     ref = oracle_apply(spec)
     assert rel(outs[lib.F64], ref) < 1e-12
+    assert blockwise_max_rel(lib, outs[lib.F64], ref, [spec.a_leg, spec.s_leg, spec.s_leg, spec.c_leg]) < 1e-12
     assert 1e-9 < rel(outs[lib.F32], ref) < 5e-5
 
 
@@ -436,3 +453,33 @@ def test_eigensolve_restart_on_breakdown(mods):
     opts = lib.eig_opts(max_iter=3, fixed_iters=1, seed=5)
     e, st, out = run_eig(lib, plan, d, opts)
     assert st[0]["restarts"] >= 1 and abs(e[0] - 1.0) < 1e-14
+
+
+def test_batch_c3_shape_with_the_largest_bond(mods):
+    """A batch of the shape of the 64-bond workload including its largest
+    bond (m = 2048, k = 18, 25 sectors) beside an m = 1024, k = 10 and an
+    m = 256, k = 14 bond: the batched FP64 product of every problem against
+    the oracle (norm-wise and block by block), and a batched fixed 6-step
+    eigensolve against the oracle's Davidson per problem."""
+    lib, problems = mods
+    specs = [synth.c2_bond(m=2048, k=18, seed=101), synth.c2_bond(m=1024, k=10, seed=102),
+             synth.c2_bond(m=256, k=14, seed=103)]
+    plan, ops, d = setup(specs, lib, problems)
+    out = torch.zeros_like(d["psi"])
+    ws = torch.empty(plan.info()["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    lib.heff_apply(plan, lib.F64, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    del ws, out
+    for p, spec in enumerate(specs):
+        o = plan.offsets(p)["psi"]
+        ref = oracle_apply(spec)
+        piece = got[o:o + ref.size]
+        print(f"batch problem {p}: rel {rel(piece, ref):.2e}", flush=True)
+        assert rel(piece, ref) < 1e-12
+        assert blockwise_max_rel(lib, piece, ref, [spec.a_leg, spec.s_leg, spec.s_leg, spec.c_leg]) < 1e-12
+    opts = lib.eig_opts(max_iter=6, fixed_iters=1)
+    e, st, _ = run_eig(lib, plan, d, opts)
+    for p, spec in enumerate(specs):
+        lam, _, _, _ = oracle_davidson(spec, 6)
+        assert abs(e[p] - lam) < 1e-11 * abs(lam)
