@@ -119,9 +119,10 @@ typedef struct {
   double flops_s1, flops_s2, flops_s3;  /* per product, all problems       */
   int64_t n_s1_tasks, n_s3_tasks, n_s1_tiles, n_s3_tiles;
   int64_t n_mix_terms, n_coefs;
-  int64_t s1_big_min, s3_big_min;       /* tile shape classes: tasks with M and N >=
-                                           this use 128 x 128 tiles, the others
-                                           64 x 64 (2^30: 64 x 64 only) */
+  int64_t s1_big_min, s3_big_min;       /* launch form of the stage: 0 = persistent,
+                                           else one workgroup per tile, tasks with
+                                           M and N >= this in 128 x 128 tiles, the
+                                           others 64 x 64 (2^30: 64 x 64 only) */
   int64_t s3_split_k;                   /* S3 split-K width chosen by the plan: tasks
                                            whose K-list is longer are cut into pieces
                                            of at most this width and summed in a fixed
@@ -423,7 +424,8 @@ bsdmrg_status bsdmrg_stage_timing(bsdmrg_plan_t plan, int32_t precision, const d
  * path: one launch per stage over every block pair of every problem).  For
  * each of the two GEMM stages S1 and S3 it tries the shape classes
  * "64 x 64 tiles only" and "128 x 128 tiles for tasks with M and N >= T"
- * (T = 384, 256, 160, 96), times `reps` launches of each distinct tile
+ * (T = 384, 256, 160, 96) and the persistent launch (big_min 0, see
+ * bsdmrg_plan_set_tiles), times `reps` launches of each distinct tile
  * schedule with HIP events on `stream` in the given precision (operands as
  * for bsdmrg_heff_apply; out receives one product), and keeps the fastest
  * (a larger tile must win by 2% to replace a smaller one).  The chosen
@@ -438,10 +440,15 @@ bsdmrg_status bsdmrg_plan_autotune(bsdmrg_plan_t plan, int32_t precision, const 
                                    int64_t workspace_bytes, int32_t reps, int32_t* big_min,
                                    hipStream_t stream);
 
-/* Install the tile shape classes of the two GEMM stages directly
- * (big_min as returned by bsdmrg_plan_autotune; 2^30 or more: 64 x 64 tiles
- * only, at least 1).  Drops the plan's captured graph.  No work using the plan
- * may be in flight.  Errors: EINVAL, EHIP. */
+/* Install the launch form of the two GEMM stages directly (big_min as
+ * returned by bsdmrg_plan_autotune): 0 = persistent launch (64 x 64 tiles
+ * dealt on the host, XCD-aware longest first, to one workgroup per resident
+ * slot, 128 per XCD; each workgroup fetches the first slice of its next tile
+ * while it finishes the current one); 2^30 or more: one workgroup per 64 x 64
+ * tile; otherwise one workgroup per tile with 128 x 128 tiles for tasks with
+ * M and N >= big_min.  Every form gives the same products bit for bit.  Drops
+ * the plan's captured graphs.  No work using the plan may be in flight.
+ * Errors: EINVAL, EHIP. */
 bsdmrg_status bsdmrg_plan_set_tiles(bsdmrg_plan_t plan, int32_t s1_big_min, int32_t s3_big_min);
 
 const char* bsdmrg_last_error(void);

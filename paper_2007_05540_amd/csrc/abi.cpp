@@ -159,6 +159,10 @@ static void upload(bsdmrg_plan_s* P) {
       {P->blk_off.data(), P->blk_off.size() * sizeof(int64_t), (void**)&P->d_blk_off},
       {P->blk_ptr.data(), P->blk_ptr.size() * sizeof(int32_t), (void**)&P->d_blk_ptr},
       {P->diag_tasks.data(), P->diag_tasks.size() * sizeof(DiagTask), (void**)&P->d_diag_tasks},
+      {P->s1.ptiles.data(), P->s1.ptiles.size() * sizeof(PTile), (void**)&P->s1.d_ptiles},
+      {P->s1.wg_ptr.data(), P->s1.wg_ptr.size() * sizeof(int32_t), (void**)&P->s1.d_wg_ptr},
+      {P->s3.ptiles.data(), P->s3.ptiles.size() * sizeof(PTile), (void**)&P->s3.d_ptiles},
+      {P->s3.wg_ptr.data(), P->s3.wg_ptr.size() * sizeof(int32_t), (void**)&P->s3.d_wg_ptr},
   };
   size_t total = 0;
   for (auto& p : parts) total += al256(std::max<size_t>(p.bytes, 1));
@@ -178,6 +182,15 @@ static void upload(bsdmrg_plan_s* P) {
 // uploaded to a buffer of its own; a captured graph holds the old table and
 // is dropped.
 static void reschedule_stage(bsdmrg_plan_s* P, Stage& st, int32_t big_min, const char* name) {
+  if (big_min == 0) {
+    // the persistent tables were built, checked and uploaded with the plan
+    schedule_tiles(st, kNoBigTiles);
+    st.big_min = 0;
+    destroy_graph(P);
+    st.persistent = true;
+    return;
+  }
+  st.persistent = false;
   schedule_tiles(st, big_min);
   validate_tiles(st, name);
   destroy_graph(P);
@@ -586,8 +599,8 @@ bsdmrg_status bsdmrg_plan_destroy(bsdmrg_plan_t P) {
     if (!P) return;
     destroy_graph(P);
     destroy_backward(P);
-    if (P->s1.d_tiles_own) (void)hipFree(P->s1.d_tiles_own);
-    if (P->s3.d_tiles_own) (void)hipFree(P->s3.d_tiles_own);
+    for (Stage* st : {&P->s1, &P->s3})
+      if (st->d_tiles_own) (void)hipFree(st->d_tiles_own);
     if (P->d_blob) (void)hipFree(P->d_blob);
     delete P;
   });
@@ -799,7 +812,7 @@ bsdmrg_status bsdmrg_stage_timing(bsdmrg_plan_t P, int32_t precision, const doub
 bsdmrg_status bsdmrg_plan_set_tiles(bsdmrg_plan_t P, int32_t s1_big_min, int32_t s3_big_min) {
   return guarded([&] {
     need_device(P);
-    if (s1_big_min < 1 || s3_big_min < 1) throw Error{BSDMRG_EINVAL, "plan_set_tiles: big_min must be >= 1"};
+    if (s1_big_min < 0 || s3_big_min < 0) throw Error{BSDMRG_EINVAL, "plan_set_tiles: big_min must be >= 0"};
     reschedule_stage(P, P->s1, std::min(s1_big_min, kNoBigTiles), "S1 tiles");
     reschedule_stage(P, P->s3, std::min(s3_big_min, kNoBigTiles), "S3 tiles");
   });
@@ -823,7 +836,7 @@ bsdmrg_status bsdmrg_plan_autotune(bsdmrg_plan_t P, int32_t precision, const dou
     HIPCHK(hipEventCreate(&ev[1]));
     prepare(P, precision, L, W1, W2, R, w, s);
     matvec(P, precision, L, R, w, psi, out, s);   // T1 and T2 hold the values the stages see
-    static const int32_t kCand[] = {kNoBigTiles, 384, 256, 160, 96};
+    static const int32_t kCand[] = {kNoBigTiles, 0, 384, 256, 160, 96};
     for (int which = 0; which < 2; ++which) {
       Stage& sg = which == 0 ? P->s1 : P->s3;
       const char* name = which == 0 ? "S1 tiles" : "S3 tiles";
@@ -838,17 +851,20 @@ bsdmrg_status bsdmrg_plan_autotune(bsdmrg_plan_t P, int32_t precision, const dou
       };
       int32_t best = kNoBigTiles;
       float best_t = 0.f;
+      bool first = true;
       std::vector<std::vector<GemmTile>> seen;
       for (int32_t cand : kCand) {
-        Stage probe;
-        probe.tasks = sg.tasks;
-        schedule_tiles(probe, cand);
-        bool dup = false;
-        for (const auto& t : seen)
-          dup = dup || (t.size() == probe.tiles.size() &&
-                        std::memcmp(t.data(), probe.tiles.data(), t.size() * sizeof(GemmTile)) == 0);
-        if (dup) continue;
-        seen.push_back(probe.tiles);
+        if (cand != 0) {   // tile classes that give the same one-workgroup-per-tile schedule are timed once
+          Stage probe;
+          probe.tasks = sg.tasks;
+          schedule_tiles(probe, cand);
+          bool dup = false;
+          for (const auto& t : seen)
+            dup = dup || (t.size() == probe.tiles.size() &&
+                          std::memcmp(t.data(), probe.tiles.data(), t.size() * sizeof(GemmTile)) == 0);
+          if (dup) continue;
+          seen.push_back(probe.tiles);
+        }
         reschedule_stage(P, sg, cand, name);
         launch();   // warm-up
         HIPCHK(hipEventRecord(ev[0], s));
@@ -857,7 +873,8 @@ bsdmrg_status bsdmrg_plan_autotune(bsdmrg_plan_t P, int32_t precision, const dou
         HIPCHK(hipEventSynchronize(ev[1]));
         float t = 0.f;
         HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
-        if (seen.size() == 1 || t < 0.98f * best_t) {
+        if (first || t < 0.98f * best_t) {
+          first = false;
           best = cand;
           best_t = t;
         }

@@ -68,6 +68,17 @@ struct GemmTile {
 };
 constexpr int32_t kNoBigTiles = 1 << 30;   // big_min of a stage with 64 x 64 tiles only
 
+// One 64 x 64 tile of the persistent grouped GEMM with everything its
+// workgroup needs to start it: the task's output geometry and its first
+// K segment inline (further segments come from the segment table).
+struct PTile {
+  int64_t c_off;
+  int32_t m0, n0, M, N, ldc, cbuf;
+  int32_t seg0, nseg, pad0, pad1;
+  GemmSeg first;
+};
+static_assert(sizeof(PTile) == 80, "PTile layout");
+
 // MPO mixing: dst rows x cols sub-matrix (row stride ld_dst) = sum over terms
 // coef[c] * src sub-matrix (row stride ld_src).
 struct MixTask {
@@ -160,7 +171,17 @@ struct Stage {
   int32_t big_min = kNoBigTiles;   // tasks with M and N >= big_min use 128 x 128 tiles
   bool big = false;                // the tile table holds 128 x 128 tiles
   void* d_tiles_own = nullptr;     // device tile table allocated by a re-schedule (else inside the plan blob)
+  // persistent launch: one workgroup per slot, its 64 x 64 tiles in
+  // ptiles[wg_ptr[w] .. wg_ptr[w + 1])
+  bool persistent = false;
+  std::vector<PTile> ptiles;
+  std::vector<int32_t> wg_ptr;
+  PTile* d_ptiles = nullptr;       // device copies (inside the plan blob)
+  int32_t* d_wg_ptr = nullptr;
 };
+// resident workgroup slots of a persistent launch per XCD: 4 workgroups of
+// 64 x 64 tiles per CU (LDS and registers allow 4), 32 CUs per XCD
+constexpr int kPersistentSlotsPerXcd = 128;
 
 // Forward intermediate blocks kept for the adjoint.
 struct T1Block {

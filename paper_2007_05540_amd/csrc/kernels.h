@@ -115,6 +115,10 @@ hipError_t launch_seg_scale(int64_t n, const int64_t* base, int np, const double
 // XCD-aware tile schedule of a GEMM stage (schedule.cpp)
 void schedule_tiles(Stage& st, int32_t big_min = kNoBigTiles);
 void validate_tiles(const Stage& st, const char* name);
+// persistent launch of a stage: 64 x 64 tiles dealt to slots_per_xcd
+// workgroups per XCD (schedule.cpp), and its table check (validate.cpp)
+void schedule_persistent(Stage& st, int slots_per_xcd);
+void validate_ptiles(const Stage& st, const char* name);
 
 // host-side table checks (validate.cpp)
 void validate_gemm(const Stage& st, int layout, int64_t a_elems, int64_t b_elems, int64_t c_elems,

@@ -310,6 +310,244 @@ __global__ __launch_bounds__(NTHR) void ggemm_kernel(const GemmTile* __restrict_
     ggemm_wave<TC, TA, TB, TO, BT, AT, 64, 0, 0>(tile, task, segs, A, B, C, Cpart, As, Bs, 0, 0);
 }
 
+// MFMA work of one k-slice for a wave whose 32 x 32 quarter of the tile has
+// NI x NJ valid 16 x 16 sub-tiles (the same lane / LDS layout as ggemm_wave).
+template <typename TC, bool BT, bool AT, int NI, int NJ>
+__device__ __forceinline__ void pslice_mfma(const TC* as, const TC* bs, typename Mfma<TC>::v4 (&acc)[2][2], int wm,
+                                            int wn, int l16, int g4) {
+  using SA = Slice<TC, !AT, 64>;
+  using SB = Slice<TC, BT, 64>;
+  constexpr int QN = SA::BKT / 4;
+  TC a[NI][QN], b[NJ][QN];
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int q = 0; q < QN; ++q) a[i][q] = as[SA::at(wm * 32 + i * 16 + l16, g4 * QN + q)];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j)
+#pragma unroll
+    for (int q = 0; q < QN; ++q) b[j][q] = bs[SB::at(wn * 32 + j * 16 + l16, g4 * QN + q)];
+#pragma unroll
+  for (int q = 0; q < QN; ++q)
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) acc[i][j] = Mfma<TC>::op(a[i][q], b[j][q], acc[i][j]);
+}
+
+// Persistent grouped block GEMM: one workgroup per resident slot works
+// through its own list of 64 x 64 tiles (assigned on the host: a task's
+// tiles on one XCD, longest first over the slots of that XCD).  The k-slice
+// after the current one is fetched into registers while the current one is
+// multiplied, also across a tile change: the first slice of the next tile
+// is in flight during the last MFMAs and the result stores of the current
+// tile, and the record of the tile after that is prefetched one tile ahead,
+// so a tile change exposes no load latency.  Per tile the K-list segments
+// are accumulated in the same registers in segment order, as in
+// ggemm_kernel (the outputs are bit-identical).  Tasks without segments
+// have their output block written as zeros.
+template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT>
+__global__ __launch_bounds__(NTHR) void pgemm_kernel(const int32_t* __restrict__ wg_ptr,
+                                                     const PTile* __restrict__ ptiles,
+                                                     const GemmSeg* __restrict__ segs, const TA* __restrict__ A,
+                                                     const TB* __restrict__ B, TO* __restrict__ C,
+                                                     TO* __restrict__ Cpart) {
+  constexpr int TM = 64;
+  using SA = Slice<TC, !AT, TM>;
+  using SB = Slice<TC, BT, TM>;
+  constexpr int BKT = SA::BKT;
+  constexpr int EPT = TM * BKT / NTHR;
+  constexpr int RSTEP = NTHR / BKT;
+  constexpr int KSTEP = NTHR / TM;
+  __shared__ TC As[2 * SA::SIZE];
+  __shared__ TC Bs[2 * SB::SIZE];
+  const int t_begin = wg_ptr[blockIdx.x], t_end = wg_ptr[blockIdx.x + 1];
+  if (t_begin >= t_end) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l16 = lane & 15, g4 = lane >> 4;
+  const int kc_k = tid % BKT, kc_r = tid / BKT;
+  const int mc_c = tid % TM, mc_k = tid / TM;
+  using V4 = typename Mfma<TC>::v4;
+
+  // ---- load side: the tile, segment and k of the slice being fetched ----
+  int lt = t_begin;          // index of the load tile
+  PTile lrec;                // its record
+  PTile nrec;                // record of tile lt + 1 (prefetched)
+  int lseg = 0;              // segment index within the load tile (0 = inline first)
+  GemmSeg ls;                // current segment of the load tile
+  int lk0 = 0;
+  unsigned a_v = 0, b_v = 0;
+  TA la[EPT];
+  TB lb[EPT];
+  unsigned va = 0, vb = 0;
+  const TA* a_seg = nullptr;
+  const TB* b_seg = nullptr;
+  int64_t a_ext = 0, b_ext = 0;
+  unsigned ao[EPT], bo[EPT];
+
+  auto tile_masks = [&](const PTile& r) {
+    a_v = 0;
+    b_v = 0;
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      a_v |= (unsigned)(r.m0 + (AT ? mc_c : kc_r + RSTEP * u) < r.M) << u;
+      b_v |= (unsigned)(r.n0 + (BT ? kc_r + RSTEP * u : mc_c) < r.N) << u;
+    }
+  };
+  auto setup = [&](const GemmSeg& sg) {
+    a_seg = A + sg.a_off;
+    b_seg = B + sg.b_off;
+    a_ext = AT ? (int64_t)(sg.K - 1) * sg.lda + lrec.M : (int64_t)(lrec.M - 1) * sg.lda + sg.K;
+    b_ext = BT ? (int64_t)(lrec.N - 1) * sg.ldb + sg.K : (int64_t)(sg.K - 1) * sg.ldb + lrec.N;
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const unsigned ar = lrec.m0 + (AT ? mc_c : kc_r + RSTEP * u);
+      const unsigned br = lrec.n0 + (BT ? kc_r + RSTEP * u : mc_c);
+      ao[u] = (AT ? (unsigned)(mc_k + KSTEP * u) * sg.lda + ar : ar * sg.lda + kc_k) * sizeof(TA);
+      bo[u] = (BT ? br * sg.ldb + kc_k : (unsigned)(mc_k + KSTEP * u) * sg.ldb + br) * sizeof(TB);
+    }
+  };
+  auto load = [&](int kk0) {
+    const int64_t ash = (int64_t)kk0 * (AT ? ls.lda : 1);
+    const int64_t bsh = (int64_t)kk0 * (BT ? 1 : ls.ldb);
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(a_seg + ash, (a_ext - ash) * (int64_t)sizeof(TA));
+    const __amdgpu_buffer_rsrc_t rb = make_rsrc(b_seg + bsh, (b_ext - bsh) * (int64_t)sizeof(TB));
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      la[u] = buf_load<TA>(ra, ao[u]);
+      lb[u] = buf_load<TB>(rb, bo[u]);
+    }
+    const bool kin = kk0 + kc_k < ls.K;
+    va = (AT || kin) ? a_v : 0u;
+    vb = (!BT || kin) ? b_v : 0u;
+  };
+  auto store = [&](int buf) {
+    TC* as = As + buf * SA::SIZE;
+    TC* bs = Bs + buf * SB::SIZE;
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const TC x = ((va >> u) & 1) ? (TC)la[u] : (TC)0;
+      const TC y = ((vb >> u) & 1) ? (TC)lb[u] : (TC)0;
+      as[AT ? SA::at(mc_c, mc_k + KSTEP * u) : SA::at(kc_r + RSTEP * u, kc_k)] = x;
+      bs[BT ? SB::at(kc_r + RSTEP * u, kc_k) : SB::at(mc_c, mc_k + KSTEP * u)] = y;
+    }
+  };
+  // output block of a tile written as zeros (a task without K segments)
+  auto zero_tile = [&](const PTile& r) {
+    TO* Cp = (r.cbuf ? Cpart : C) + r.c_off;
+    for (int e = tid; e < TM * TM; e += NTHR) {
+      const int row = r.m0 + e / TM, col = r.n0 + e % TM;
+      if (row < r.M && col < r.N) Cp[(int64_t)row * r.ldc + col] = (TO)0;
+    }
+  };
+  // make tile index idx the load tile (record from nrec, which then
+  // prefetches the following one); false when it has no segment
+  auto enter_tile = [&](int idx) {
+    lrec = nrec;
+    if (idx + 1 < t_end) nrec = ptiles[idx + 1];
+    lt = idx;
+    lseg = 0;
+    lk0 = 0;
+    if (lrec.nseg == 0) return false;
+    ls = lrec.first;
+    tile_masks(lrec);
+    setup(ls);
+    return true;
+  };
+  // move the load position to the next slice (maybe in a later tile) and
+  // fetch it; false when the workgroup's list is done
+  auto advance = [&]() {
+    lk0 += BKT;
+    if (lk0 >= ls.K) {
+      lk0 = 0;
+      ++lseg;
+      if (lseg < lrec.nseg) {
+        ls = segs[lrec.seg0 + lseg];
+        setup(ls);
+      } else {
+        bool found = false;
+        for (int idx = lt + 1; idx < t_end && !found; ++idx) {
+          found = enter_tile(idx);
+          if (!found) zero_tile(lrec);
+        }
+        if (!found) return false;
+      }
+    }
+    load(lk0);
+    return true;
+  };
+
+  // ---- compute side: the tile whose slice is in LDS ----
+  V4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = V4{0, 0, 0, 0};
+  PTile crec;
+  int ct = -1;
+  int ni = 0, nj = 0;
+  auto start_compute = [&]() {
+    crec = lrec;
+    ct = lt;
+    const int r0 = crec.m0 + wm * 32, c0 = crec.n0 + wn * 32;
+    ni = r0 >= crec.M ? 0 : (r0 + 16 < crec.M ? 2 : 1);
+    nj = c0 >= crec.N ? 0 : (c0 + 16 < crec.N ? 2 : 1);
+  };
+  auto compute = [&](int buf) {
+    const TC* as = As + buf * SA::SIZE;
+    const TC* bs = Bs + buf * SB::SIZE;
+    if (ni == 2 && nj == 2) pslice_mfma<TC, BT, AT, 2, 2>(as, bs, acc, wm, wn, l16, g4);
+    else if (ni == 2 && nj == 1) pslice_mfma<TC, BT, AT, 2, 1>(as, bs, acc, wm, wn, l16, g4);
+    else if (ni == 1 && nj == 2) pslice_mfma<TC, BT, AT, 1, 2>(as, bs, acc, wm, wn, l16, g4);
+    else if (ni == 1 && nj == 1) pslice_mfma<TC, BT, AT, 1, 1>(as, bs, acc, wm, wn, l16, g4);
+  };
+  auto epilogue = [&]() {
+    TO* Cp = (crec.cbuf ? Cpart : C) + crec.c_off;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if (i < ni && j < nj) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = crec.m0 + wm * 32 + i * 16 + Mfma<TC>::row(lane, r);
+            const int col = crec.n0 + wn * 32 + j * 16 + l16;
+            if (row < crec.M && col < crec.N) Cp[(int64_t)row * crec.ldc + col] = (TO)acc[i][j][r];
+          }
+        }
+        acc[i][j] = V4{0, 0, 0, 0};
+      }
+  };
+
+  // first tile with a segment (the ones before it are written as zeros)
+  nrec = ptiles[t_begin];
+  bool have = false;
+  for (int idx = t_begin; idx < t_end && !have; ++idx) {
+    have = enter_tile(idx);
+    if (!have) zero_tile(lrec);
+  }
+  if (!have) return;
+  load(0);
+  store(0);
+  start_compute();
+  __syncthreads();
+  int buf = 0;
+  for (;;) {
+    const bool more = advance();
+    compute(buf);
+    if (!more || lt != ct) {
+      epilogue();
+      if (!more) break;
+      start_compute();
+    }
+    store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
 // MPO mixing (S2): each workgroup handles one row range of one task; every
 // thread owns up to 16 elements and issues the 16 loads of a term together,
 // from the term's block base (scalar registers) plus a 32-bit byte offset
@@ -390,6 +628,23 @@ static hipError_t launch_gemm(const Stage& st, const TA* A, const TB* B, TO* C, 
   return hipGetLastError();
 }
 
+// Persistent variant (64 x 64 tiles, one workgroup per slot with tiles).
+template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT = false>
+static hipError_t launch_pgemm(const Stage& st, const TA* A, const TB* B, TO* C, TO* Cpart, hipStream_t s) {
+  const int n_wg = (int)st.wg_ptr.size() - 1;
+  if (n_wg <= 0) return hipSuccess;
+  hipLaunchKernelGGL((pgemm_kernel<TC, TA, TB, TO, BT, AT>), dim3((unsigned)n_wg), dim3(NTHR), 0, s, st.d_wg_ptr,
+                     st.d_ptiles, st.d_segs, A, B, C, Cpart);
+  return hipGetLastError();
+}
+
+// The stage's launch: persistent or one workgroup per tile.
+template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT = false>
+static hipError_t launch_stage(const Stage& st, const TA* A, const TB* B, TO* C, TO* Cpart, hipStream_t s) {
+  if (st.persistent) return launch_pgemm<TC, TA, TB, TO, BT, AT>(st, A, B, C, Cpart, s);
+  return launch_gemm<TC, TA, TB, TO, BT, AT>(st, A, B, C, Cpart, s);
+}
+
 // FP64 grouped GEMM of any stage in one of the layouts NN, NT (B stored
 // N x K) or TN (A stored K x M).
 hipError_t launch_gemm_f64(const Stage& st, int layout, const double* A, const double* B, double* C,
@@ -416,7 +671,7 @@ hipError_t launch_s3_reduce(const bsdmrg_plan_s* P, const double* part, double* 
 
 hipError_t launch_s1_f64(const bsdmrg_plan_s* P, const double* L, const double* psi, double* T1,
                          hipStream_t s) {
-  return launch_gemm<double, double, double, double, false>(P->s1, L, psi, T1, T1, s);
+  return launch_stage<double, double, double, double, false>(P->s1, L, psi, T1, T1, s);
 }
 hipError_t launch_s3_f64(const bsdmrg_plan_s* P, const double* T2, const double* R, double* out,
                          double* part, hipStream_t s) {
@@ -426,11 +681,11 @@ hipError_t launch_s3_f64(const bsdmrg_plan_s* P, const double* T2, const double*
 }
 hipError_t launch_s3_gemm_f64(const bsdmrg_plan_s* P, const double* T2, const double* R, double* out,
                               double* part, hipStream_t s) {
-  return launch_gemm<double, double, double, double, true>(P->s3, T2, R, out, part, s);
+  return launch_stage<double, double, double, double, true>(P->s3, T2, R, out, part, s);
 }
 hipError_t launch_s1_f32(const bsdmrg_plan_s* P, const float* L, const double* psi, float* T1,
                          hipStream_t s) {
-  return launch_gemm<float, float, double, float, false>(P->s1, L, psi, T1, T1, s);
+  return launch_stage<float, float, double, float, false>(P->s1, L, psi, T1, T1, s);
 }
 hipError_t launch_s3_f32(const bsdmrg_plan_s* P, const float* T2, const float* R, double* out,
                          double* part, hipStream_t s) {
@@ -440,7 +695,7 @@ hipError_t launch_s3_f32(const bsdmrg_plan_s* P, const float* T2, const float* R
 }
 hipError_t launch_s3_gemm_f32(const bsdmrg_plan_s* P, const float* T2, const float* R, double* out,
                               double* part, hipStream_t s) {
-  return launch_gemm<float, float, float, double, true>(P->s3, T2, R, out, part, s);
+  return launch_stage<float, float, float, double, true>(P->s3, T2, R, out, part, s);
 }
 
 hipError_t launch_mix_f64(const bsdmrg_plan_s* P, const double* coef, const double* T1, double* T2,

@@ -379,6 +379,10 @@ bsdmrg_plan_s* build_plan(const bsdmrg_problem* probs, int n_probs) {
     split_k(P);
     schedule_tiles(P->s1);
     schedule_tiles(P->s3);
+    schedule_persistent(P->s1, kPersistentSlotsPerXcd);
+    schedule_persistent(P->s3, kPersistentSlotsPerXcd);
+    validate_ptiles(P->s1, "S1 persistent tiles");
+    validate_ptiles(P->s3, "S3 persistent tiles");
     // Davidson reduction chunks
     for (int i = 0; i < n_probs; ++i) {
       ProblemPlan& p = P->probs[i];

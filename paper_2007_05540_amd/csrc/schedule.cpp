@@ -90,4 +90,56 @@ void schedule_tiles(Stage& st, int32_t big_min) {
   while (!st.tiles.empty() && st.tiles.back().task < 0) st.tiles.pop_back();
 }
 
+// Persistent schedule of a stage (64 x 64 tiles): slots_per_xcd workgroups
+// per XCD, workgroup w on XCD w mod 8.  The tasks are spread over the XCDs
+// as above (a task's tiles stay on one XCD: one L2 holds its panels); on each
+// XCD the tiles are dealt longest first to the least loaded slot (LPT on
+// k-slices plus a fixed per-tile cost), so the tiles of one task run at the
+// same time on different slots and every slot ends at about the same time.
+void schedule_persistent(Stage& st, int slots_per_xcd) {
+  Stage flat;
+  flat.tasks = st.tasks;
+  schedule_tiles(flat, kNoBigTiles);   // the XCD binning, 64 x 64 tiles only
+  std::vector<std::vector<GemmTile>> per_xcd(kXcd);
+  for (size_t i = 0; i < flat.tiles.size(); ++i)
+    if (flat.tiles[i].task >= 0) per_xcd[i % kXcd].push_back(flat.tiles[i]);
+  const int S = std::max(1, slots_per_xcd);
+  std::vector<std::vector<GemmTile>> slot_tiles((size_t)S * kXcd);
+  for (int x = 0; x < kXcd; ++x) {
+    auto& lst = per_xcd[x];
+    auto cost = [&](const GemmTile& t) { return (double)st.tasks[t.task].ksum + 64.0; };
+    std::stable_sort(lst.begin(), lst.end(), [&](const GemmTile& a, const GemmTile& b) { return cost(a) > cost(b); });
+    std::vector<double> load(S, 0.0);
+    for (const GemmTile& t : lst) {
+      const int sl = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[sl] += cost(t);
+      slot_tiles[(size_t)sl * kXcd + x].push_back(t);
+    }
+  }
+  // drop trailing workgroups without tiles
+  size_t n_wg = slot_tiles.size();
+  while (n_wg > 0 && slot_tiles[n_wg - 1].empty()) --n_wg;
+  st.ptiles.clear();
+  st.wg_ptr.assign(1, 0);
+  for (size_t w = 0; w < n_wg; ++w) {
+    for (const GemmTile& t : slot_tiles[w]) {
+      const GemmTask& k = st.tasks[t.task];
+      PTile r{};
+      r.c_off = k.c_off;
+      r.m0 = t.m0;
+      r.n0 = t.n0;
+      r.M = k.M;
+      r.N = k.N;
+      r.ldc = k.ldc;
+      r.cbuf = k.cbuf;
+      r.seg0 = k.seg0;
+      r.nseg = k.nseg;
+      r.pad0 = t.task;   // for the table check
+      if (k.nseg > 0) r.first = st.segs[k.seg0];
+      st.ptiles.push_back(r);
+    }
+    st.wg_ptr.push_back((int32_t)st.ptiles.size());
+  }
+}
+
 }  // namespace bsd

@@ -2,6 +2,7 @@
 // when a plan is built (and on the truncation tables before upload); a
 // violation raises an error instead of launching a kernel that would read
 // or write out of bounds.
+#include <cstring>
 #include <string>
 
 #include "bsdmrg_internal.h"
@@ -60,6 +61,35 @@ void validate_tiles(const Stage& st, const char* name) {
     const GemmTask& k = st.tasks[tl.task];
     if (tl.m0 < 0 || tl.m0 >= k.M || tl.n0 < 0 || tl.n0 >= k.N) fail(std::string(name) + ": tile origin");
     if (tl.shape != 0 && !(tl.shape == 1 && st.big)) fail(std::string(name) + ": tile shape");
+  }
+}
+
+// The persistent schedule covers every 64 x 64 tile of every task exactly
+// once, and every record repeats its task's fields and first segment.
+void validate_ptiles(const Stage& st, const char* name) {
+  if (st.wg_ptr.empty() || st.wg_ptr.front() != 0 || st.wg_ptr.back() != (int32_t)st.ptiles.size())
+    fail(std::string(name) + ": persistent workgroup table");
+  for (size_t w = 0; w + 1 < st.wg_ptr.size(); ++w)
+    if (st.wg_ptr[w] > st.wg_ptr[w + 1]) fail(std::string(name) + ": persistent workgroup order");
+  int64_t expect = 0;
+  for (const GemmTask& k : st.tasks) expect += (int64_t)((k.M + 63) / 64) * ((k.N + 63) / 64);
+  if ((int64_t)st.ptiles.size() != expect) fail(std::string(name) + ": persistent tile count");
+  std::vector<std::vector<char>> seen(st.tasks.size());
+  for (size_t t = 0; t < st.tasks.size(); ++t)
+    seen[t].assign((size_t)((st.tasks[t].M + 63) / 64) * ((st.tasks[t].N + 63) / 64), 0);
+  for (const PTile& r : st.ptiles) {
+    if (r.pad0 < 0 || r.pad0 >= (int32_t)st.tasks.size()) fail(std::string(name) + ": persistent tile task");
+    const GemmTask& k = st.tasks[r.pad0];
+    if (r.c_off != k.c_off || r.M != k.M || r.N != k.N || r.ldc != k.ldc || r.cbuf != k.cbuf || r.seg0 != k.seg0 ||
+        r.nseg != k.nseg)
+      fail(std::string(name) + ": persistent tile record");
+    if (r.m0 < 0 || r.m0 >= k.M || r.n0 < 0 || r.n0 >= k.N || r.m0 % 64 || r.n0 % 64)
+      fail(std::string(name) + ": persistent tile origin");
+    if (k.nseg > 0 && std::memcmp(&r.first, &st.segs[k.seg0], sizeof(GemmSeg)) != 0)
+      fail(std::string(name) + ": persistent tile first segment");
+    char& f = seen[r.pad0][(size_t)(r.m0 / 64) * ((k.N + 63) / 64) + r.n0 / 64];
+    if (f) fail(std::string(name) + ": persistent tile repeated");
+    f = 1;
   }
 }
 

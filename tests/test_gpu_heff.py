@@ -259,17 +259,22 @@ def test_tile_shape_classes_bit_identical_and_autotune(mods, spec_fn):
         return res
     assert plan.info()["s1_big_min"] == lib.NO_BIG_TILES
     base = products()
+    lib.plan_set_tiles(plan, 0, 0)                 # persistent launch of both stages
+    assert plan.info()["s1_big_min"] == 0 and plan.info()["s3_big_min"] == 0
+    persistent = products()
     lib.plan_set_tiles(plan, 64, 64)
     info = plan.info()
     assert info["s1_big_min"] == 64 and info["s3_big_min"] == 64
     forced = products()
     out = torch.zeros_like(d["psi"])
     got = lib.plan_autotune(plan, lib.F32, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws, reps=3)
-    assert got["s1"] in (lib.NO_BIG_TILES, 384, 256, 160, 96) and got["s3"] in (lib.NO_BIG_TILES, 384, 256, 160, 96)
+    classes = (lib.NO_BIG_TILES, 0, 384, 256, 160, 96)
+    assert got["s1"] in classes and got["s3"] in classes
     assert plan.info()["s3_big_min"] == got["s3"]
     assert np.array_equal(out.cpu().numpy(), base[lib.F32])
     tuned = products()
     for prec in (lib.F64, lib.F32):
+        assert np.array_equal(persistent[prec], base[prec])
         assert np.array_equal(forced[prec], base[prec])
         assert np.array_equal(tuned[prec], base[prec])
     assert rel(base[lib.F64], oracle_apply(spec)) < 1e-12
@@ -483,3 +488,27 @@ def test_batch_c3_shape_with_the_largest_bond(mods):
     for p, spec in enumerate(specs):
         lam, _, _, _ = oracle_davidson(spec, 6)
         assert abs(e[p] - lam) < 1e-11 * abs(lam)
+
+
+@pytest.mark.parametrize("spec_fn", [lambda: synth.c2_bond(m=1024, k=14, seed=1),
+                                     lambda: synth.c2_bond(m=2048, k=18, seed=2),
+                                     lambda: synth.c4_bond(m=4096, k=22, seed=1)])
+def test_persistent_launch_bit_identical_at_full_size(mods, spec_fn):
+    """The persistent launch of both GEMM stages (one workgroup per resident
+    slot, tiles dealt on the host) gives the same products bit for bit as one
+    workgroup per tile, in both precisions, on the full-size bonds (split-K
+    S3 at m = 1024 and 2048, 313 electron sectors at m = 4096)."""
+    lib, problems = mods
+    spec = spec_fn()
+    plan, ops, d = setup([spec], lib, problems)
+    ws = torch.empty(plan.info()["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    res = {}
+    for mode in (lib.NO_BIG_TILES, 0):
+        lib.plan_set_tiles(plan, mode, mode)
+        for prec in (lib.F64, lib.F32):
+            out = torch.full_like(d["psi"], 0.0)
+            lib.heff_apply(plan, prec, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
+            torch.cuda.synchronize()
+            res[(mode, prec)] = out.cpu().numpy()
+    for prec in (lib.F64, lib.F32):
+        assert np.array_equal(res[(0, prec)], res[(lib.NO_BIG_TILES, prec)])
