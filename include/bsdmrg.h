@@ -26,7 +26,10 @@
  *   lexicographic order of their sector-index tuples; each block dense and
  *   row-major over its legs; offsets[0] = 0,
  *   offsets[b+1] = offsets[b] + round_up(size_b, 32) elements; padding is 0.
- * Physical legs must have sectors of dimension 1 (spin-1/2, electrons).
+ * Physical legs of bsdmrg_plan and bsdmrg_env_plan must have sectors of
+ *   dimension 1 (spin-1/2, electrons); bsdmrg_merge_plan and bsdmrg_truncate
+ *   take physical sectors of any dimension up to 64 (e.g. the fused (s', s)
+ *   leg of an MPO site compressed as a chain).
  * Memory: every device buffer (operands, outputs, workspace) is allocated and
  *   owned by the caller; the library owns only plan tables, which
  *   bsdmrg_plan_destroy frees.  Device pointers are FP64 in canonical layout.

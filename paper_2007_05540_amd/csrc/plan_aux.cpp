@@ -183,7 +183,9 @@ bsdmrg_op_s* build_merge(const Leg& a, const Leg& s1, const Leg& b, const Leg& s
     O->out_elems = T.elems();
     for (size_t tb = 0; tb < T.keys.size(); ++tb) {
       const int ia = T.keys[tb][0], i1 = T.keys[tb][1], i2 = T.keys[tb][2], ic = T.keys[tb][3];
-      const int32_t M = (int32_t)a.d[ia], N = (int32_t)c.d[ic];
+      // theta block (a, s1, s2, c) = A block (a, s1, b) as an (a s1) x b matrix
+      // times B block (b, s2, c) as b x (s2 c) (physical sectors of any size)
+      const int32_t M = (int32_t)(a.d[ia] * s1.d[i1]), N = (int32_t)(s2.d[i2] * c.d[ic]);
       GemmTask t{T.offs[tb], N, M, N, (int32_t)O->g1.segs.size(), 0, 0, 0, 0};
       const int ib = b.find(cadd(a.q[ia], s1.q[i1]));
       if (ib >= 0) {

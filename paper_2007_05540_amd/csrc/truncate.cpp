@@ -2,11 +2,15 @@
 // theta(a,s1,s2,c) is wrapped into one matrix per charge q of the new bond
 // (rows: the (a, s1) pairs with q_a + q_s1 = q; columns: the (s2, c) pairs
 // with q_c - q_s2 = q; both in lexicographic order of their sector indices),
-// each matrix is decomposed with a one-sided Jacobi SVD kernel (FP64, high
-// relative accuracy for small singular values), the singular values
-// of all charges are pooled and truncated on the host, and U, S, V^T are
-// scattered into A(a,s1,b) and B(b,s2,c) with S absorbed in the direction of
-// the sweep.  Readings of the silent points: see bsdmrg_truncate in the
+// each matrix is decomposed in FP64 on the device: QR with column pivoting
+// (one workgroup per matrix up to 256 columns, else one launch per step over
+// many workgroups) cut at the numerical rank, then block one-sided Jacobi on
+// R^T (block pairs of a step in parallel workgroups, columns in LDS) until a
+// sweep rotates nothing; the singular values of all charges are pooled and
+// truncated on the host, and U, S, V^T are scattered into A(a,s1,b) and
+// B(b,s2,c) with S absorbed in the direction of the sweep.  Physical sectors
+// may have any dimension up to 64 (rows (a, s1) and columns (s2, c) of a
+// charge matrix are then fused a-major and s2-major).  Readings of the silent points: see bsdmrg_truncate in the
 // header (cutoff modes, degenerate groups, sign gauge).
 #include <hip/hip_runtime.h>
 
@@ -37,6 +41,7 @@ struct TPlan {
   Layout theta;
   std::vector<TSector> sec;
   int64_t n_mat = 0, n_u = 0, n_s = 0, n_v = 0, n_work = 0, n_pairs = 0, n_cols = 0, n_big = 0, n_bigcols = 0;
+  int64_t n_gather = 0;
   size_t bytes = 0;
 };
 
@@ -51,7 +56,7 @@ static TPlan make_tplan(const bsdmrg_leg* legs) {
   T.a = leg_from(legs[0]); T.s1 = leg_from(legs[1]); T.s2 = leg_from(legs[2]); T.c = leg_from(legs[3]);
   for (const Leg* l : {&T.s1, &T.s2})
     for (auto d : l->d)
-      if (d != 1) throw Error{BSDMRG_EINVAL, "truncate: physical sectors must have dimension 1"};
+      if (d > 64) throw Error{BSDMRG_EINVAL, "truncate: physical sectors above dimension 64"};
   T.theta = make_layout({&T.a, &T.s1, &T.s2, &T.c}, kPsiS);
   std::map<Charge, std::vector<std::pair<int, int>>> rows, cols;
   for (int ia = 0; ia < T.a.size(); ++ia)
@@ -97,10 +102,17 @@ static TPlan make_tplan(const bsdmrg_leg* legs) {
     T.sec.push_back(s);
   }
   T.n_mat = T.n_work;
+  // scatter copies: one per (row pair, i_1) into A and per (column pair, i_2) into B
   int64_t n_rk = 0, n_ck = 0;
-  for (auto& s : T.sec) { n_rk += (int64_t)s.rk.size(); n_ck += (int64_t)s.ck.size(); }
+  for (auto& s : T.sec) {
+    for (auto& r : s.rk) n_rk += T.s1.d[r.second];
+    for (auto& c : s.ck) n_ck += T.s2.d[c.first];
+  }
+  // gather copies: one per (theta block, i_1, i_2)
+  T.n_gather = 0;
+  for (const Key& k : T.theta.keys) T.n_gather += T.s1.d[k[1]] * T.s2.d[k[2]];
   T.bytes = al(T.n_work * 8) + al(T.n_u * 8) + al(T.n_s * 8) + al(T.n_v * 8) + al(T.n_s * 8) * 2 +
-            al(T.theta.keys.size() * sizeof(CopyTask) + 1) + al(T.sec.size() * sizeof(SvdTask) + 1) +
+            al(T.n_gather * sizeof(CopyTask) + 1) + al(T.sec.size() * sizeof(SvdTask) + 1) +
             al(T.n_pairs * sizeof(SvdPair) + 1) + al(T.n_cols * sizeof(SvdCols) + 1) + al(T.sec.size() * 8) * 2 +
             al(T.n_big * sizeof(int32_t) + 1) + al(T.n_bigcols * sizeof(SvdCols) + 1) +
             al(T.n_s * sizeof(GaugeTask) + 1) + al((n_rk + n_ck) * sizeof(CopyTask) + 1);
@@ -184,7 +196,7 @@ void truncate_run(const bsdmrg_leg* legs, const double* theta, const bsdmrg_trun
   double* V = (double*)take(T.n_v * 8);
   double* sign = (double*)take(T.n_s * 8);
   double* sgn_s = (double*)take(T.n_s * 8);
-  char* gather_tab = take(T.theta.keys.size() * sizeof(CopyTask) + 1);
+  char* gather_tab = take(T.n_gather * sizeof(CopyTask) + 1);
   char* svd_tab = take(T.sec.size() * sizeof(SvdTask) + 1);
   char* pair_tab = take(T.n_pairs * sizeof(SvdPair) + 1);
   char* cols_tab = take(T.n_cols * sizeof(SvdCols) + 1);
@@ -205,13 +217,21 @@ void truncate_run(const bsdmrg_leg* legs, const double* theta, const bsdmrg_trun
         k[0] = s.rk[r].first; k[1] = s.rk[r].second; k[2] = s.ck[c].first; k[3] = s.ck[c].second;
         const int b = T.theta.lookup(k);
         if (b < 0) throw Error{BSDMRG_EQN, "truncate: theta block missing"};
+        // block (a, s1, s2, c) row-major; matrix row r0 + i_a d1 + i_1, column
+        // c0 + i_2 dc + i_c: one strided copy of an a x c sub-block per (i_1, i_2)
         const int32_t rows = (int32_t)T.a.d[k[0]], cols = (int32_t)T.c.d[k[3]];
-        if (s.rows >= s.cols)   // X = M, column-major (ld rows)
-          gt.push_back(CopyTask{T.theta.offs[b], s.mat + s.r0[r] + s.c0[c] * s.rows, rows, cols, cols, 1, 1,
-                                (int32_t)s.rows, -1, 0});
-        else                    // X = M^T, column-major (ld cols)
-          gt.push_back(CopyTask{T.theta.offs[b], s.mat + s.c0[c] + s.r0[r] * s.cols, rows, cols, cols, 1,
-                                (int32_t)s.cols, 1, -1, 0});
+        const int32_t d1 = (int32_t)T.s1.d[k[1]], d2 = (int32_t)T.s2.d[k[2]];
+        for (int32_t i1 = 0; i1 < d1; ++i1)
+          for (int32_t i2 = 0; i2 < d2; ++i2) {
+            const int64_t src = T.theta.offs[b] + (int64_t)(i1 * d2 + i2) * cols;
+            const int64_t mr = s.r0[r] + i1, mc = s.c0[c] + (int64_t)i2 * cols;
+            if (s.rows >= s.cols)   // X = M, column-major (ld rows)
+              gt.push_back(CopyTask{src, s.mat + mr + mc * s.rows, rows, cols, d1 * d2 * cols, 1, d1,
+                                    (int32_t)s.rows, -1, 0});
+            else                    // X = M^T, column-major (ld cols)
+              gt.push_back(CopyTask{src, s.mat + mc + mr * s.cols, rows, cols, d1 * d2 * cols, 1,
+                                    (int32_t)s.cols * d1, 1, -1, 0});
+          }
       }
   }
   validate_copy(gt, T.theta.elems(), T.n_work, 0, "truncate gather");
@@ -348,22 +368,27 @@ void truncate_run(const bsdmrg_leg* legs, const double* theta, const bsdmrg_trun
     const TSector& s = T.sec[si];
     const int ib = new_of[si];
     const int32_t nq = (int32_t)counts[si];
+    // A block (a, s1, b) row-major [i_a][i_1][j] from U rows r0 + i_a d1 + i_1
     for (size_t r = 0; r < s.rk.size(); ++r) {
       Key k{};
       k[0] = s.rk[r].first; k[1] = s.rk[r].second; k[2] = ib;
       const int blk = LA.lookup(k);
       if (blk < 0) throw Error{BSDMRG_EQN, "truncate: A block missing"};
-      ta.push_back(CopyTask{s.u + s.r0[r], LA.offs[blk], (int32_t)T.a.d[k[0]], nq, 1, (int32_t)s.rows, nq, 1,
-                            (int32_t)gbase[si], 0});
+      const int32_t d1 = (int32_t)T.s1.d[k[1]];
+      for (int32_t i1 = 0; i1 < d1; ++i1)
+        ta.push_back(CopyTask{s.u + s.r0[r] + i1, LA.offs[blk] + (int64_t)i1 * nq, (int32_t)T.a.d[k[0]], nq, d1,
+                              (int32_t)s.rows, d1 * nq, 1, (int32_t)gbase[si], 0});
     }
+    // B block (b, s2, c) row-major [j][i_2][i_c] from V^T columns c0 + i_2 dc + i_c
     for (size_t c = 0; c < s.ck.size(); ++c) {
       Key k{};
       k[0] = ib; k[1] = s.ck[c].first; k[2] = s.ck[c].second;
       const int blk = LB.lookup(k);
       if (blk < 0) throw Error{BSDMRG_EQN, "truncate: B block missing"};
-      const int32_t bc = (int32_t)T.c.d[k[2]];
-      tb.push_back(CopyTask{s.v + s.c0[c] * s.kmin, LB.offs[blk], nq, bc, 1, (int32_t)s.kmin, bc, 1,
-                            (int32_t)gbase[si], 1});
+      const int32_t bc = (int32_t)T.c.d[k[2]], d2 = (int32_t)T.s2.d[k[1]];
+      for (int32_t i2 = 0; i2 < d2; ++i2)
+        tb.push_back(CopyTask{s.v + (s.c0[c] + (int64_t)i2 * bc) * s.kmin, LB.offs[blk] + (int64_t)i2 * bc, nq, bc, 1,
+                              (int32_t)s.kmin, d2 * bc, 1, (int32_t)gbase[si], 1});
     }
   }
   validate_copy(ta, T.n_u, LA.elems(), (int64_t)gg.size(), "truncate scatter A");

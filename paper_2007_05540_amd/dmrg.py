@@ -24,18 +24,22 @@ class Tensor:
 class GpuDMRG:
     def __init__(self, mpo, mps_host, target, device="cuda", precision=lib.F64, refine_max_iter=8,
                  tol_f32=1e-6):
-        """mpo: uniform-channel MPO (W[j] dense (k, d, d, k), channels
-        sector-major); mps_host: list of (legs, packed FP64 array);
-        target: total charge of the state."""
+        """mpo: a uniform-channel MPO (W[j] dense (k, d, d, k), channels
+        sector-major) or a BondMPO (a leg per bond, e.g. after compression);
+        mps_host: list of (legs, packed FP64 array); target: total charge of
+        the state."""
         import torch
+        from .mpo import BondMPO
         self.torch = torch
         self.device = device
         self.mpo = mpo
-        self.N = len(mpo.W)
-        self.wl = mpo.w_leg()
-        s = mpo.phys
+        bm = mpo if isinstance(mpo, BondMPO) else BondMPO.uniform(mpo)
+        self.N = len(bm.W)
+        self.legs = bm.legs            # channel leg of every bond (N + 1)
+        s = bm.phys
         self.s = s
-        self.W_host = [problems.pack_dense(W, [self.wl, s, s, self.wl], lib.W_SIGNS) for W in mpo.W]
+        self.W_host = [problems.pack_dense(W, [self.legs[j], s, s, self.legs[j + 1]], lib.W_SIGNS)
+                       for j, W in enumerate(bm.W)]
         self.W = [torch.from_numpy(w).to(device) for w in self.W_host]
         self.T = [Tensor(l, torch.from_numpy(np.ascontiguousarray(a)).to(device)) for l, a in mps_host]
         self.target = tuple(target)
@@ -46,18 +50,18 @@ class GpuDMRG:
         zero = tuple([0] * r)
         self.L = [None] * (self.N + 1)
         self.R = [None] * (self.N + 1)
-        self.L[0] = self._boundary(zero, mpo.start)
-        self.R[self.N] = self._boundary(self.target, mpo.done)
+        self.L[0] = self._boundary(zero, bm.start, self.legs[0])
+        self.R[self.N] = self._boundary(self.target, bm.done, self.legs[self.N])
         self.log = []
 
     # -- helpers -------------------------------------------------------------
-    def _boundary(self, q, channel):
+    def _boundary(self, q, channel, wleg):
         leg = [(tuple(q), 1)]
-        k = sum(n for _, n in self.wl)
+        k = sum(n for _, n in wleg)
         dense = np.zeros((1, k, 1))
         dense[0, channel, 0] = 1.0
-        data = problems.pack_dense(dense, [leg, self.wl, leg], lib.ENV_SIGNS)
-        return Tensor([leg, self.wl, leg], self.torch.from_numpy(data).to(self.device))
+        data = problems.pack_dense(dense, [leg, wleg, leg], lib.ENV_SIGNS)
+        return Tensor([leg, wleg, leg], self.torch.from_numpy(data).to(self.device))
 
     def _merge(self, A, B):
         a, s1, b = A.legs
@@ -78,12 +82,12 @@ class GpuDMRG:
             x, s, y = site.legs
         else:
             y, s, x = site.legs
-        op = lib.env_plan(x, s, y, self.wl, self.wl, self.W_host[j], side)
+        op = lib.env_plan(x, s, y, self.legs[j], self.legs[j + 1], self.W_host[j], side)
         info = op.query()
         out = self.torch.zeros(max(1, info["out_elems"]), dtype=self.torch.float64, device=self.device)
         ws = self.torch.empty(max(1, info["workspace_bytes"]), dtype=self.torch.uint8, device=self.device)
         lib.env_update(op, env.data, site.data, self.W[j], out, ws)
-        return Tensor([y, self.wl, y], out)
+        return Tensor([y, self.legs[j + 1] if side == 0 else self.legs[j], y], out)
 
     # -- algorithm -----------------------------------------------------------
     def right_canonicalize(self, cutoff=1e-14, progress=False):
@@ -100,8 +104,8 @@ class GpuDMRG:
 
     def solve_bond(self, j, theta, max_iter, tol, seed):
         a, s1, s2, c = theta.legs
-        prob = {"a": a, "s1": s1, "s2": s2, "c": c, "wl": self.wl, "wm": self.wl, "wr": self.wl,
-                "w1": self.W_host[j], "w2": self.W_host[j + 1]}
+        prob = {"a": a, "s1": s1, "s2": s2, "c": c, "wl": self.legs[j], "wm": self.legs[j + 1],
+                "wr": self.legs[j + 2], "w1": self.W_host[j], "w2": self.W_host[j + 1]}
         plan = lib.Plan([prob])
         if self.precision == lib.F64:
             opts = lib.eig_opts(max_iter=max_iter, tol=tol, seed=seed)
@@ -123,27 +127,27 @@ class GpuDMRG:
         Returns (E, [dE/dW_s device tensors in canonical W layout])."""
         from . import autograd
         torch = self.torch
-        N, wl = self.N, self.wl
+        N, lg = self.N, self.legs
         Wg = [w.detach().clone().requires_grad_(True) for w in self.W]
         keep = []
         L = self.L[0].data
         for j in range(bond):
             x, s, y = self.T[j].legs
-            op = lib.env_plan(x, s, y, wl, wl, self.W_host[j], 0)
-            adj = lib.env_plan(y, s, x, wl, wl, self.W_host[j], 1)
+            op = lib.env_plan(x, s, y, lg[j], lg[j + 1], self.W_host[j], 0)
+            adj = lib.env_plan(y, s, x, lg[j], lg[j + 1], self.W_host[j], 1)
             keep += [op, adj]
             L = autograd.EnvUpdate.apply(op, adj, L, self.T[j].data, Wg[j])
         R = self.R[N].data
         for j in range(N - 1, bond + 1, -1):
             y, s, x = self.T[j].legs
-            op = lib.env_plan(x, s, y, wl, wl, self.W_host[j], 1)
-            adj = lib.env_plan(y, s, x, wl, wl, self.W_host[j], 0)
+            op = lib.env_plan(x, s, y, lg[j], lg[j + 1], self.W_host[j], 1)
+            adj = lib.env_plan(y, s, x, lg[j], lg[j + 1], self.W_host[j], 0)
             keep += [op, adj]
             R = autograd.EnvUpdate.apply(op, adj, R, self.T[j].data, Wg[j])
         theta = self._merge(self.T[bond], self.T[bond + 1])
         a, s1, s2, c = theta.legs
-        plan = lib.Plan([{"a": a, "s1": s1, "s2": s2, "c": c, "wl": wl, "wm": wl, "wr": wl,
-                          "w1": self.W_host[bond], "w2": self.W_host[bond + 1]}])
+        plan = lib.Plan([{"a": a, "s1": s1, "s2": s2, "c": c, "wl": lg[bond], "wm": lg[bond + 1],
+                          "wr": lg[bond + 2], "w1": self.W_host[bond], "w2": self.W_host[bond + 1]}])
         E = autograd.HeffEnergy.apply(plan, L, Wg[bond], Wg[bond + 1], R, theta.data)
         E.sum().backward()
         torch.cuda.synchronize()
@@ -159,8 +163,8 @@ class GpuDMRG:
         the MPO builder.  This contraction over the O(k^2 d^2) MPO entries of
         each site belongs to the model builder and runs on the host."""
         total = 0.0
-        for g, d in zip(grads, dW_dp):
-            dp = problems.pack_dense(d, [self.wl, self.s, self.s, self.wl], lib.W_SIGNS)
+        for j, (g, d) in enumerate(zip(grads, dW_dp)):
+            dp = problems.pack_dense(d, [self.legs[j], self.s, self.s, self.legs[j + 1]], lib.W_SIGNS)
             total += float(np.dot(g.detach().cpu().numpy(), dp))
         return total
 
