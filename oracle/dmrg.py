@@ -17,7 +17,7 @@ from .blocks import BlockTensor, canonical_layout, block_shape
 from .eig import davidson
 from .env import (left_boundary, right_boundary, left_update_dense, right_update_dense,
                   left_update_blocks, right_update_blocks, merge)
-from .heff import MPS_SIGNS, PSI_SIGNS, DenseHeff, heff_blocks, w_tensor
+from .heff import MPS_SIGNS, PSI_SIGNS, DenseHeff, heff1_dense, heff_blocks, w_tensor
 from .truncate import truncate
 
 
@@ -115,3 +115,84 @@ def dmrg(mpo, mps, n_sweeps, m_max, cutoff=1e-10, cutoff_mode="sv", dav=None,
             step += 1
         sweep_e.append(energies[-1])
     return energies, mps, sweep_e, disc
+
+
+def _with_dummy(t, pos):
+    """The one-site tensor (a, s, c) as a two-site tensor with a one-state
+    zero-charge leg inserted at position pos (2: (a, s, 1, c); 1: (a, 1, s, c));
+    blocks and their order are unchanged."""
+    a, s, c = t.legs
+    zero = tuple([0] * len(a[0][0]))
+    one = [(zero, 1)]
+    legs = [a, s, one, c] if pos == 2 else [a, one, s, c]
+    out = BlockTensor(legs, PSI_SIGNS)
+    for (ia, i_s, ic), v in t.blocks.items():
+        key = (ia, i_s, 0, ic) if pos == 2 else (ia, 0, i_s, ic)
+        out.blocks[key] = v.reshape(v.shape[0], v.shape[1], 1, v.shape[2]) if pos == 2 else \
+            v.reshape(v.shape[0], 1, v.shape[1], v.shape[2])
+    return out
+
+
+def _drop_dummy(t, pos):
+    legs = [l for i, l in enumerate(t.legs) if i != pos]
+    out = BlockTensor(legs, MPS_SIGNS)
+    for k, v in t.blocks.items():
+        key = tuple(x for i, x in enumerate(k) if i != pos)
+        out.blocks[key] = v.reshape([n for i, n in enumerate(v.shape) if i != pos])
+    return out
+
+
+def dmrg1(mpo, mps, n_sweeps, dav=None, target=None, log=None):
+    """Single-site sweeps (the single-site form of Sec. II-C: the projected
+    operator L W_j R acts on one site tensor).  From the given MPS (any
+    gauge; it is right-canonicalised first), a sweep solves site j for
+    j = 0 .. N-2 moving right (the solution split by SVD into a
+    left-orthonormal site and S V^T carried into site j+1) and j = N-1 .. 1
+    moving left (U S carried into site j-1).  The bond dimensions never grow;
+    the split drops only numerically zero singular values.  Returns (energy
+    of every solve, MPS, last energy of every sweep)."""
+    dav = dav or {"max_iter": 40, "tol": 1e-12}
+    N = len(mps)
+    r = len(mpo.phys[0][0])
+    target = target if target is not None else mps[-1].legs[2][0][0]
+    wl = mpo.w_leg()
+    Ws = [w_tensor(W, wl, mpo.phys, wl) for W in mpo.W]
+    mps = right_canonicalize(mps)
+    Lenv = [None] * (N + 1)
+    Renv = [None] * (N + 1)
+    Lenv[0] = left_boundary(wl, mpo.start, r)
+    Renv[N] = right_boundary(wl, mpo.done, target)
+    for j in range(N - 1, 0, -1):
+        Renv[j] = right_update_dense(Renv[j + 1], mps[j], Ws[j])
+    energies, sweep_e = [], []
+    step = 0
+    for sw in range(n_sweeps):
+        order = [(j, "right") for j in range(N - 1)] + [(j, "left") for j in range(N - 1, 0, -1)]
+        for j, d in order:
+            psi = mps[j]
+            legs = psi.legs
+
+            def mv(v, j=j, legs=legs):
+                return heff1_dense(Lenv[j], Ws[j], Renv[j + 1], BlockTensor.unpack(v, legs, MPS_SIGNS)).pack()
+            lam, xv, st = davidson(mv, psi.pack(), dav.get("max_iter", 40), dav.get("tol", 1e-12),
+                                   restart_mask=mask_of(legs, MPS_SIGNS), seed=step)
+            x = BlockTensor.unpack(xv, legs, MPS_SIGNS)
+            if d == "right":
+                # x(a, s, 1, c) = A(a, s, b) [S V^T](b, 1, c); S V^T goes into site j+1
+                A, SV, _, _, _ = truncate(_with_dummy(x, 2), "right", cutoff=CANON_CUTOFF, m_max=1 << 60)
+                mps[j] = A
+                mps[j + 1] = _drop_dummy(merge(SV, mps[j + 1]), 1)
+                Lenv[j + 1] = left_update_dense(Lenv[j], mps[j], Ws[j])
+            else:
+                # x(a, 1, s, c) = [U S](a, 1, b) B(b, s, c); U S goes into site j-1
+                US, B, _, _, _ = truncate(_with_dummy(x, 1), "left", cutoff=CANON_CUTOFF, m_max=1 << 60)
+                mps[j] = B
+                mps[j - 1] = _drop_dummy(merge(mps[j - 1], US), 2)
+                Renv[j] = right_update_dense(Renv[j + 1], mps[j], Ws[j])
+            energies.append(lam)
+            if log is not None:
+                log.append({"sweep": sw, "site": j, "dir": d, "E": lam, "iters": st["iters"]})
+            step += 1
+        sweep_e.append(energies[-1])
+    return energies, mps, sweep_e
+

@@ -100,6 +100,18 @@ def useful_flops(L, W1, W2, R, psi):
     return f["s1"] + f["s3"]
 
 
+def heff1_dense(L, W, R, psi):
+    """Single-site projected operator of Sec. II-C applied to the one-site
+    tensor psi(a, s, c) (bond, physical, bond; MPS signs):
+      out(a',s',c') = sum L(a',w,a) W(w,s',s,w') R(c',w',c) psi(a,s,c),
+    on the dense embeddings, read back on the allowed blocks."""
+    Ld, Wd, Rd, pd = (t.to_dense() for t in (L, W, R, psi))
+    t = np.einsum("xwa,asc->xwsc", Ld, pd)            # sum over a
+    t = np.einsum("xwsc,wpsv->xpvc", t, Wd)           # sum over w, s
+    out = np.einsum("xpvc,yvc->xpy", t, Rd)           # sum over v (w'), c
+    return BlockTensor.from_dense(out, psi.legs, MPS_SIGNS, check_zero=True)
+
+
 def heff_diagonal(L, W1, W2, R, psi_legs):
     """Diagonal of H_eff on the packed canonical vector: the matrix element
     <e|H_eff|e> of every basis tensor e, i.e. the two-site formula with the

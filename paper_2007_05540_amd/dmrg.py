@@ -209,6 +209,95 @@ class GpuDMRG:
                 on_sweep(sw, sweep_e[-1], self.sweep_seconds[-1])
         return energies, sweep_e
 
+    # -- single-site sweeps -----------------------------------------------
+    def _identity_site(self, j):
+        """W(w, 1, 1, w') = delta on the channel leg of bond j with a one-state
+        zero-charge physical leg: the second site of the two-site plan that
+        turns it into the single-site operator L W_j R."""
+        if not hasattr(self, "_ids"):
+            self._ids = {}
+        if j not in self._ids:
+            leg = self.legs[j]
+            k = sum(n for _, n in leg)
+            one = self._one_leg()
+            dense = np.eye(k).reshape(k, 1, 1, k)
+            host = problems.pack_dense(dense, [leg, one, one, leg], lib.W_SIGNS)
+            self._ids[j] = (host, self.torch.from_numpy(host).to(self.device))
+        return self._ids[j]
+
+    def _one_leg(self):
+        return [(tuple([0] * len(self.s[0][0])), 1)]
+
+    def solve_site(self, j, max_iter, tol, seed):
+        """Lowest eigenpair of the single-site operator L_j W_j R_{j+1} (Sec.
+        II-C) on site tensor j, through a two-site plan whose second site is
+        the identity on a one-state leg (the site tensor (a, s, c) is the
+        two-site tensor (a, s, 1, c): same blocks, same layout).  The solution
+        overwrites the site tensor."""
+        a, s, c = self.T[j].legs
+        one = self._one_leg()
+        wid_host, wid = self._identity_site(j + 1)
+        prob = {"a": a, "s1": s, "s2": one, "c": c, "wl": self.legs[j], "wm": self.legs[j + 1],
+                "wr": self.legs[j + 1], "w1": self.W_host[j], "w2": wid_host}
+        plan = lib.Plan([prob])
+        if self.precision == lib.F64:
+            opts = lib.eig_opts(max_iter=max_iter, tol=tol, seed=seed)
+        else:
+            opts = lib.eig_opts(max_iter=max_iter, precision=lib.F32_REFINE, refine_max_iter=self.refine_max_iter,
+                                tol=tol, tol_f32=self.tol_f32, seed=seed)
+        ws = self.torch.empty(lib.eig_workspace(plan, opts), dtype=self.torch.uint8, device=self.device)
+        e, st = lib.eigensolve(plan, self.L[j].data, self.W[j], wid, self.R[j + 1].data, self.T[j].data, opts, ws)
+        plan.destroy()
+        return e[0], st[0]
+
+    def run_single_site(self, n_sweeps, max_iter=40, tol=1e-12, on_sweep=None):
+        """Single-site sweeps from the current MPS (the bond dimensions stay
+        fixed: start from a two-site result or an MPS of the wanted size).  A
+        sweep solves site j = 0 .. N-2 moving right (the solution split by the
+        library's SVD into a left-orthonormal site and S V^T merged into site
+        j+1, dropping only singular values below 1e-14 of the norm) and
+        j = N-1 .. 1 moving left (U S merged into site j-1).  Returns (energy
+        of every solve, last energy of every sweep)."""
+        import time
+        N = self.N
+        one = self._one_leg()
+        self.right_canonicalize()
+        self.R[1] = self._env(self.R[2], self.T[1], 1, 1)
+        energies, sweep_e = [], []
+        self.sweep_seconds = []
+        step = 0
+        for sw in range(n_sweeps):
+            self.torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            order = [(j, 0) for j in range(N - 1)] + [(j, 1) for j in range(N - 1, 0, -1)]
+            for j, d in order:
+                E, st = self.solve_site(j, max_iter, tol, step)
+                a, s, c = self.T[j].legs
+                if d == 0:
+                    theta = Tensor([a, s, one, c], self.T[j].data)
+                    A, SV, _ = self._split(theta, 0, 1e-14, 0, 1 << 62)
+                    self.T[j] = A
+                    nxt = self._merge(SV, self.T[j + 1])      # (b, 1, s', d)
+                    self.T[j + 1] = Tensor([nxt.legs[0], nxt.legs[2], nxt.legs[3]], nxt.data)
+                    self.L[j + 1] = self._env(self.L[j], self.T[j], j, 0)
+                else:
+                    theta = Tensor([a, one, s, c], self.T[j].data)
+                    US, B, _ = self._split(theta, 1, 1e-14, 0, 1 << 62)
+                    self.T[j] = B
+                    prv = self._merge(self.T[j - 1], US)      # (x, s', 1, b)
+                    self.T[j - 1] = Tensor([prv.legs[0], prv.legs[1], prv.legs[3]], prv.data)
+                    self.R[j] = self._env(self.R[j + 1], self.T[j], j, 1)
+                energies.append(E)
+                self.log.append({"sweep": sw, "site": j, "dir": d, "E": E, "iters": st["iters"],
+                                 "iters_f32": st["iters_f32"], "res": st["residual"]})
+                step += 1
+            sweep_e.append(energies[-1])
+            self.torch.cuda.synchronize()
+            self.sweep_seconds.append(time.perf_counter() - t0)
+            if on_sweep is not None:
+                on_sweep(sw, sweep_e[-1], self.sweep_seconds[-1])
+        return energies, sweep_e
+
     def host_mps(self):
         """The current MPS as (legs, packed FP64 array) pairs (a warm start)."""
         return [(t.legs, t.data.detach().cpu().numpy()) for t in self.T]

@@ -8,7 +8,7 @@ import synth
 from synth.blocks import mps_block
 from oracle import ed
 from oracle.blocks import BlockTensor
-from oracle.dmrg import random_mps, dmrg
+from oracle.dmrg import random_mps, dmrg, dmrg1
 from oracle.env import left_update_blocks, right_update_blocks, merge
 from oracle.heff import w_tensor, MPS_SIGNS, ENV_SIGNS, PSI_SIGNS
 from oracle.truncate import truncate as o_truncate
@@ -198,3 +198,52 @@ def test_hubbard_cylinder_sweeps_against_ed(mods):
     E, swe = g.run(3, 64, cutoff=1e-10, max_iter=40, tol=1e-12)
     e0 = ed.lowest(ed.hubbard_sector(n, hops, U, n // 2, n // 2))
     assert abs(swe[-1] - e0) < 1e-9 * abs(e0)
+
+
+def test_single_site_operator_matches_oracle(mods):
+    """The single-site operator L W R through the two-site plan with an
+    identity second site on a one-state leg, against the oracle's direct
+    single-site contraction."""
+    lib, problems, _ = mods
+    from oracle.blocks import block_shape
+    from oracle.heff import heff1_dense
+    base = synth.c2_bond(m=256, k=14, seed=8)
+    # a single site adds one spin: the right bond leg has odd charges
+    spec = synth.BondSpec(base.a_leg, synth.spin_bond_leg(256, center=1), base.mpo, 8)
+    wl, s = spec.w_leg(), spec.s_leg
+    a, c = spec.a_leg, spec.c_leg
+    one = [((0,), 1)]
+    k = sum(n for _, n in wl)
+    W = problems.pack_dense(spec.W1, [wl, s, s, wl], lib.W_SIGNS)
+    Wid = problems.pack_dense(np.eye(k).reshape(k, 1, 1, k), [wl, one, one, wl], lib.W_SIGNS)
+    prob = {"a": a, "s1": s, "s2": one, "c": c, "wl": wl, "wm": wl, "wr": wl, "w1": W, "w2": Wid}
+    plan = lib.Plan([prob])
+    L = problems.pack_fn([a, wl, a], lib.ENV_SIGNS, spec.L_block)
+    R = problems.pack_fn([c, wl, c], lib.ENV_SIGNS, spec.R_block)
+    psi = BlockTensor.from_fn([a, s, c], MPS_SIGNS, lambda kk: synth.gaussian_block(2, 7, kk, block_shape([a, s, c], kk)))
+    out = torch.zeros(plan.info()["psi_elems"], dtype=torch.float64, device="cuda")
+    ws = torch.empty(plan.info()["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    lib.heff_apply(plan, lib.F64, dev(L), dev(W), dev(Wid), dev(R), dev(psi.pack()), out, ws)
+    torch.cuda.synchronize()
+    Lo = BlockTensor.unpack(L, [a, wl, a], ENV_SIGNS)
+    Ro = BlockTensor.unpack(R, [c, wl, c], ENV_SIGNS)
+    ref = heff1_dense(Lo, w_tensor(spec.W1, wl, s, wl), Ro, psi).pack()
+    assert rel(out.cpu().numpy(), ref) < 1e-12
+
+
+def test_single_site_sweeps_match_oracle_and_ed(mods):
+    """Single-site sweeps of the 12-site chain from the same random MPS with
+    every bond sector at its full size: the energy of every solve equals the
+    oracle's single-site sweeps, and the last one exact diagonalisation."""
+    lib, problems, gdmrg = mods
+    n = 12
+    b = synth.chain_bonds(n)
+    mpo = synth.heisenberg_mpo(n, b)
+    mps = random_mps(mpo, n, (0,), 4096, 4, mps_block)
+    g = gdmrg.GpuDMRG(mpo, host_mps(problems, lib, mps), (0,))
+    E, swe = g.run_single_site(3, max_iter=40, tol=1e-12)
+    oE, _, oswe = dmrg1(mpo, mps, 3)
+    e0 = ed.lowest(ed.heisenberg_sector(n, b, n // 2))
+    assert len(E) == len(oE)
+    assert max(abs(x - y) for x, y in zip(E, oE)) < 1e-9 * abs(e0)
+    assert abs(swe[-1] - e0) < 1e-10 * abs(e0)

@@ -5,7 +5,7 @@ import numpy as np
 import synth
 from synth.blocks import mps_block
 from oracle import ed
-from oracle.dmrg import random_mps, dmrg
+from oracle.dmrg import random_mps, dmrg, dmrg1
 
 DAV = {"max_iter": 40, "tol": 1e-12}
 
@@ -89,3 +89,45 @@ def test_j1_j2_cylinder_against_ed():
     e0 = ed.lowest(ed.heisenberg_sector(n, bonds, (n + 1) // 2))
     _, swe, _, _ = run(synth.heisenberg_mpo(n, bonds), n, (1,), 32, 3)
     assert abs(swe[-1] - e0) < 1e-9 * abs(e0)
+
+
+def test_single_site_operator_equals_two_site_with_identity_site():
+    """The single-site operator L W R (Sec. II-C) equals the two-site operator
+    whose second site is the identity on a one-state zero-charge leg, acting
+    on the site tensor with that leg inserted (the two-site form is pinned to
+    Q^T H Q by exact diagonalisation)."""
+    from oracle.blocks import BlockTensor, block_shape
+    from oracle.heff import heff1_dense, heff_blocks, w_tensor, MPS_SIGNS, ENV_SIGNS, PSI_SIGNS
+    base = synth.c2_bond(m=40, k=14, seed=4)
+    # a single site adds one spin: the right bond leg has odd charges
+    spec = synth.BondSpec(base.a_leg, synth.spin_bond_leg(40, center=1), base.mpo, 4)
+    wl, s = spec.w_leg(), spec.s_leg
+    a, c = spec.a_leg, spec.c_leg
+    L = BlockTensor.from_fn([a, wl, a], ENV_SIGNS, spec.L_block)
+    R = BlockTensor.from_fn([c, wl, c], ENV_SIGNS, spec.R_block)
+    W = w_tensor(spec.W1, wl, s, wl)
+    psi = BlockTensor.from_fn([a, s, c], MPS_SIGNS, lambda k: synth.gaussian_block(2, 7, k, block_shape([a, s, c], k)))
+    one = [((0,), 1)]
+    k = sum(n for _, n in wl)
+    Wid = w_tensor(np.eye(k).reshape(k, 1, 1, k), wl, one, wl)
+    psi2 = BlockTensor([a, s, one, c], PSI_SIGNS,
+                       {(ia, i_s, 0, ic): v.reshape(v.shape[0], v.shape[1], 1, v.shape[2])
+                        for (ia, i_s, ic), v in psi.blocks.items()})
+    got = heff1_dense(L, W, R, psi).pack()
+    ref = heff_blocks(L, W, Wid, R, psi2).pack()
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_single_site_sweeps_reach_ed_and_never_rise():
+    """Single-site sweeps from a random MPS whose bonds already hold the whole
+    space (L = 8, every sector of every bond at its full size): the energy of
+    every solve is non-increasing and the last equals exact diagonalisation."""
+    n = 8
+    b = synth.chain_bonds(n)
+    mpo = synth.heisenberg_mpo(n, b)
+    mps = random_mps(mpo, n, (0,), 256, 2, mps_block)
+    E, _, swe = dmrg1(mpo, mps, 3)
+    e0 = ed.lowest(ed.heisenberg_sector(n, b, n // 2))
+    assert abs(swe[-1] - e0) < 1e-10 * abs(e0)
+    for x, y in zip(E, E[1:]):
+        assert y <= x + 1e-11 * abs(x)
