@@ -310,22 +310,25 @@ def dense_ablation(spec, plan, dev, reps=5):
     lib.heff_apply(plan, lib.F64, dev["L"], dev["W1"], dev["W2"], dev["R"], dev["psi"], ref, ws)
     ref = ref.cpu().numpy()
     del ws
-    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
-        t = {kk: torch.from_numpy(v).to("cuda", dt) for kk, v in host.items()}
-        y = dense.heff_dense(t["L"], t["W1"], t["W2"], t["R"], t["psi"])
+    t = {kk: torch.from_numpy(np.ascontiguousarray(v)).to("cuda") for kk, v in host.items()}
+    dp = dense.DenseProduct(ma, mc, k, d)
+    y = torch.zeros_like(t["psi"])
+    for name, prec in (("f64", lib.F64), ("f32", lib.F32)):
+        dp.apply(prec, t["L"], t["W1"], t["W2"], t["R"], t["psi"], y)
         torch.cuda.synchronize()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         ev[0].record()
         for _ in range(reps):
-            y = dense.heff_dense(t["L"], t["W1"], t["W2"], t["R"], t["psi"])
+            dp.apply(prec, t["L"], t["W1"], t["W2"], t["R"], t["psi"], y)
         ev[1].record()
         torch.cuda.synchronize()
         ms = ev[0].elapsed_time(ev[1]) / reps
-        got = problems.pack_dense(y.double().cpu().numpy(), legs_psi, lib.PSI_SIGNS)
+        got = problems.pack_dense(y.cpu().numpy(), legs_psi, lib.PSI_SIGNS)
         out[name] = {"ms_per_product": round(ms, 3), "dense_tflops": round((f1 + f2 + f3) / ms / 1e9, 1),
                      "rel_diff_vs_block_sparse_f64": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
-        del t, y
-        torch.cuda.empty_cache()
+    dp.destroy()
+    del t, y
+    torch.cuda.empty_cache()
     return out
 
 

@@ -37,9 +37,16 @@
  *   buffers; bsdmrg_plan_offsets gives each problem's element offsets.
  * Errors: every call returns a status; no exception crosses the ABI;
  *   bsdmrg_last_error() gives a thread-local message for the last failure.
- * Streams: work is enqueued on the given stream (0 = default).  Calls are
- *   asynchronous unless stated; a plan is immutable after creation and may be
- *   used on several streams if each call has its own workspace.
+ * Streams and threads: work is enqueued on the given stream (0 = default).
+ *   Calls are asynchronous unless stated.  A plan or op may be used from
+ *   several threads and streams at once if each call has its own workspace
+ *   and outputs: its tables are fixed at creation except for the parts built
+ *   on first use (the adjoint tables of bsdmrg_heff_backward, bsdmrg_heff_energy
+ *   and bsdmrg_env_backward, and the captured graphs of bsdmrg_eigensolve),
+ *   which are built, looked up and launched under a lock held by the plan or
+ *   op.  bsdmrg_plan_set_tiles and bsdmrg_plan_autotune change the plan and
+ *   must not overlap any other call on it; bsdmrg_heff_apply_noalloc shares
+ *   one scratch array per GPU (see there).
  */
 #ifndef BSDMRG_H
 #define BSDMRG_H
@@ -343,7 +350,8 @@ bsdmrg_status bsdmrg_truncate_workspace(const bsdmrg_leg* theta_legs, int64_t* b
  * sv_capacity is too small, returns BSDMRG_ECAPACITY with new_n_sectors,
  * A_elems, B_elems and n_kept set.  Synchronises the stream.
  * Errors: EINVAL (also a charge matrix above 4096 columns), EQN, EHIP,
- * ESOLVER (theta not finite, or theta == 0). */
+ * ESOLVER (theta not finite, theta == 0, or a sector's block-Jacobi SVD
+ * still rotating after its sweep limit of 60). */
 bsdmrg_status bsdmrg_truncate(const bsdmrg_leg* theta_legs, const double* theta,
                               const bsdmrg_trunc_opts* opts, int32_t* new_n_sectors,
                               int32_t* new_charges, int64_t* new_dims, int32_t leg_capacity,
@@ -406,9 +414,59 @@ bsdmrg_status bsdmrg_env_backward(bsdmrg_op_t op, const double* env, const doubl
                                   const double* d_out, double* d_W, void* workspace,
                                   int64_t workspace_bytes, hipStream_t stream);
 
+/* Chain rule for a parameter p of the MPO (e.g. J2 of the J1-J2 model,
+ * on which every site tensor depends affinely):
+ *   dE/dp = sum_s <dE/dW_s, dW_s/dp>,
+ * the inner product of each site's energy gradient (bsdmrg_heff_backward,
+ * bsdmrg_env_backward; canonical W layout) with that site's derivative
+ * tensor dW_s/dp packed in the same layout by the model builder.
+ * dE_dW, dW_dp: host arrays of n_sites device pointers (FP64); n_elems: host
+ * array of n_sites element counts (0 allowed).  terms: device, n_sites + 1
+ * doubles; receives the per-site inner products and, last, their sum taken
+ * in site order (each inner product in a fixed order: repeated calls are
+ * bit-identical).  *result (host) receives the sum.  Synchronises the
+ * stream.  Errors: EINVAL (NULL argument, n_sites < 1, negative count),
+ * EHIP. */
+bsdmrg_status bsdmrg_param_derivative(int32_t n_sites, const double* const* dE_dW,
+                                      const double* const* dW_dp, const int64_t* n_elems,
+                                      double* terms, double* result, hipStream_t stream);
+
 /* Run a merge op (no workspace).  Errors: EINVAL, EHIP. */
 bsdmrg_status bsdmrg_merge(bsdmrg_op_t op, const double* A, const double* B, double* theta,
                            hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Sparse-dense format (Sec. IV-A): the two-site product with every operand
+ * one dense array, the blocks that the charge rules forbid stored as zeros
+ * and multiplied like any other entry.  It computes the same product as
+ * bsdmrg_heff_apply with all the work the block structure avoids, on the
+ * same grouped GEMM kernels; its use is to measure that work (ablation).
+ * ------------------------------------------------------------------------ */
+
+/* Plan of the dense product for bond dimensions ma (left) and mc (right),
+ * k MPO channels and physical dimension d (1..8): three GEMM stages,
+ *   T1(a' w, s1 s2 c) = L(a' w, a) psi(a, s1 s2 c),
+ *   T2[a'](s1' s2' w'', c) = WW(s1' s2' w'', w s1 s2) T1[a'](w s1 s2, c)
+ *     with WW the two sites contracted over their shared channel,
+ *   out(a' s1' s2', c') = sum_{w'' c} T2(a' s1' s2', w'' c) R(c', w'', c).
+ * bsdmrg_op_query gives the workspace (the larger of the FP64 and FP32
+ * needs), out_elems = ma d^2 mc and the flops of the three stages.  flags:
+ * BSDMRG_PLAN_HOST_ONLY as for bsdmrg_plan.  Free with bsdmrg_op_destroy.
+ * Errors: EINVAL (a dimension out of range, or an operand of 2 GiB or more),
+ * EHIP, ENOMEM. */
+bsdmrg_status bsdmrg_dense_plan(int64_t ma, int64_t mc, int32_t k, int32_t d, int32_t flags,
+                                bsdmrg_op_t* op);
+
+/* out = H_eff psi in the dense format.  Device operands, FP64, dense
+ * row-major: L (ma, k, ma) as (bra, channel, ket), W1 and W2 (k, d, d, k) as
+ * (w, s', s, w'), R (mc, k, mc), psi and out (ma, d, d, mc).  precision
+ * BSDMRG_F64, or BSDMRG_F32 (FP32 MFMA, FP32 intermediates and FP32 copies
+ * of L, R, WW in the workspace; out in FP64).  Every output element is
+ * summed in a fixed order.  Errors: EINVAL (wrong op kind, NULL operand,
+ * out == psi, workspace too small), EHIP. */
+bsdmrg_status bsdmrg_dense_apply(bsdmrg_op_t op, int32_t precision, const double* L, const double* W1,
+                                 const double* W2, const double* R, const double* psi, double* out,
+                                 void* workspace, int64_t workspace_bytes, hipStream_t stream);
 
 /* Measurement helper: runs each stage of one product `reps` times on
  * `stream`, bracketed by HIP events recorded on that stream, and writes the

@@ -1,4 +1,4 @@
-"""Two-site DMRG sweeps (Sec. II-C, Fig. 1; Sec. III for the eigensolver).
+"""Two-site DMRG sweeps (Sec. II-C, Fig. 1; Alg. 1 of Sec. II-C for the eigensolver).
 
 Bond j sits to the left of site j (j = 0 .. N); MPS tensor T_j has legs
 (bond j, s_j, bond j+1).  Starting from a right-canonical MPS, a sweep visits

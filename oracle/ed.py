@@ -1,8 +1,8 @@
 """Exact diagonalisation references (textbook constructions, independent of the
 MPO builders).
 
-Spin-1/2 Heisenberg H = sum J_ij S_i . S_j (Sec. IV) and the Hubbard model
-H = -sum t_ij (c+_is c_js + h.c.) + U sum n_iu n_id (Sec. IV).
+Spin-1/2 Heisenberg H = sum J_ij S_i . S_j (Sec. V) and the Hubbard model
+H = -sum t_ij (c+_is c_js + h.c.) + U sum n_iu n_id (Sec. V).
 
 Full-space matrices use the product basis with site 0 most significant and
 the local orders: spin 0 = down, 1 = up; electron local index 2 n_up + n_dn.

@@ -1,6 +1,6 @@
 """Eigensolvers for the lowest eigenpair of the implicit effective Hamiltonian.
 
-``davidson`` follows Alg. 1 (Sec. III): no preconditioning, Gram row from the
+``davidson`` follows Alg. 1 (Sec. II-C): no preconditioning, Gram row from the
 stored products, smallest Ritz pair of the projected matrix, residual, modified
 Gram-Schmidt, randomisation when reorthogonalisation fails.  Readings where the
 listing is silent or slightly off:

@@ -94,7 +94,7 @@ def heff_blocks(L, W1, W2, R, psi, return_flops=False):
 
 def useful_flops(L, W1, W2, R, psi):
     """Useful flop count (S1 + S3) of one application, from the block-pair
-    structure alone (the same definition as the flop counts of Sec. V, which
+    structure alone (the same definition as the flop counts of Sec. VI, which
     are measured on the list method)."""
     _, f = heff_blocks(L, W1, W2, R, psi, return_flops=True)
     return f["s1"] + f["s3"]

@@ -1,4 +1,4 @@
-"""Counter-based Gaussian stream for the Davidson restart (Sec. III: the
+"""Counter-based Gaussian stream for the Davidson restart (Sec. II-C: the
 routine uses randomization when reorthogonalization fails).
 
 SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number

@@ -549,7 +549,12 @@ bsdmrg_status bsdmrg_plan_query(bsdmrg_plan_t P, bsdmrg_plan_info* info) {
     info->t1_elems = P->t1_elems;
     info->t2_elems = P->t2_elems;
     info->apply_workspace_bytes = (int64_t)apply_bytes(P);
-    info->backward_workspace_bytes = P->bwd ? heff_backward_bytes(P) : 0;
+    bool bwd_built = false;
+    {
+      std::lock_guard<std::mutex> lk(P->mu);
+      bwd_built = P->bwd != nullptr;
+    }
+    info->backward_workspace_bytes = bwd_built ? heff_backward_bytes(P) : 0;
     info->flops_s1 = P->s1.flops;
     info->flops_s2 = P->flops_s2;
     info->flops_s3 = P->s3.flops;

@@ -13,6 +13,7 @@
 namespace bsd {
 bsdmrg_op_s* build_env(const bsdmrg_env_problem& in, int side);
 bsdmrg_op_s* build_merge(const Leg& a, const Leg& s1, const Leg& b, const Leg& s2, const Leg& c);
+bsdmrg_op_s* build_dense(int64_t ma, int64_t mc, int32_t k, int32_t d);
 void truncate_workspace(const bsdmrg_leg* legs, int64_t* bytes);
 void truncate_run(const bsdmrg_leg* legs, const double* theta, const bsdmrg_trunc_opts* o, int32_t* new_n,
                   int32_t* new_q, int64_t* new_d, int32_t leg_cap, double* A, int64_t A_cap, int64_t* A_elems,
@@ -66,6 +67,9 @@ static void upload_op(bsdmrg_op_s* O) {
       {O->mix_tasks.data(), O->mix_tasks.size() * sizeof(MixTask), (void**)&O->d_mix_tasks},
       {O->mix_terms.data(), O->mix_terms.size() * sizeof(MixTerm), (void**)&O->d_mix_terms},
       {O->mix_items.data(), O->mix_items.size() * sizeof(MixItem), (void**)&O->d_mix_items},
+      {O->g3.tasks.data(), O->g3.tasks.size() * sizeof(GemmTask), (void**)&O->g3.d_tasks},
+      {O->g3.segs.data(), O->g3.segs.size() * sizeof(GemmSeg), (void**)&O->g3.d_segs},
+      {O->g3.tiles.data(), O->g3.tiles.size() * sizeof(GemmTile), (void**)&O->g3.d_tiles},
   };
   size_t total = 0;
   for (auto& p : parts) total += al(std::max<size_t>(p.bytes, 1));
@@ -80,7 +84,18 @@ static void upload_op(bsdmrg_op_s* O) {
   HIPCHK(hipMemcpy(O->d_blob, host.data(), total, hipMemcpyHostToDevice));
 }
 
-static int64_t op_ws_bytes(const bsdmrg_op_s* O) { return (int64_t)(al(O->x1_elems * 8) + al(O->x2_elems * 8)); }
+// dense product workspace: T1, T2, WW in FP64, or T1, T2, WW, L and R in FP32
+static int64_t dense_ws_bytes(const bsdmrg_op_s* O, int precision) {
+  const int64_t dk = (int64_t)O->dn_d * O->dn_d * O->dn_k;
+  if (precision == BSDMRG_F64) return (int64_t)(al(O->x1_elems * 8) + al(O->x2_elems * 8) + al(dk * dk * 8));
+  return (int64_t)(al(O->x1_elems * 4) + al(O->x2_elems * 4) + al(dk * dk * 4) +
+                   al(O->dn_ma * O->dn_k * O->dn_ma * 4) + al(O->dn_mc * O->dn_k * O->dn_mc * 4));
+}
+
+static int64_t op_ws_bytes(const bsdmrg_op_s* O) {
+  if (O->kind == 4) return std::max(dense_ws_bytes(O, BSDMRG_F64), dense_ws_bytes(O, BSDMRG_F32));
+  return (int64_t)(al(O->x1_elems * 8) + al(O->x2_elems * 8));
+}
 
 extern "C" {
 
@@ -115,6 +130,51 @@ bsdmrg_status bsdmrg_merge_plan(const bsdmrg_leg* legs, int32_t flags, bsdmrg_op
       throw;
     }
     *out = O;
+  });
+}
+
+bsdmrg_status bsdmrg_dense_plan(int64_t ma, int64_t mc, int32_t k, int32_t d, int32_t flags, bsdmrg_op_t* out) {
+  return guarded([&] {
+    if (!out) throw Error{BSDMRG_EINVAL, "dense_plan: NULL output"};
+    *out = nullptr;
+    bsdmrg_op_s* O = build_dense(ma, mc, k, d);
+    try {
+      if (!(flags & BSDMRG_PLAN_HOST_ONLY)) upload_op(O);
+    } catch (...) {
+      if (O->d_blob) (void)hipFree(O->d_blob);
+      delete O;
+      throw;
+    }
+    *out = O;
+  });
+}
+
+bsdmrg_status bsdmrg_dense_apply(bsdmrg_op_t O, int32_t precision, const double* L, const double* W1,
+                                 const double* W2, const double* R, const double* psi, double* out,
+                                 void* workspace, int64_t workspace_bytes, hipStream_t s) {
+  return guarded([&] {
+    if (!O || O->kind != 4) throw Error{BSDMRG_EINVAL, "dense_apply: not a dense product op"};
+    if (!O->d_blob) throw Error{BSDMRG_EINVAL, "dense_apply: op was built host-only"};
+    if (precision != BSDMRG_F64 && precision != BSDMRG_F32)
+      throw Error{BSDMRG_EINVAL, "dense_apply: precision must be BSDMRG_F64 or BSDMRG_F32"};
+    if (!L || !W1 || !W2 || !R || !psi || !out) throw Error{BSDMRG_EINVAL, "dense_apply: NULL operand"};
+    if (out == psi) throw Error{BSDMRG_EINVAL, "dense_apply: out aliases psi"};
+    const int64_t need = dense_ws_bytes(O, precision);
+    if (!workspace || workspace_bytes < need)
+      throw Error{BSDMRG_EINVAL, "dense_apply: workspace too small: need " + std::to_string(need) + " bytes"};
+    const size_t es = precision == BSDMRG_F64 ? 8 : 4;
+    const int64_t dk = (int64_t)O->dn_d * O->dn_d * O->dn_k;
+    char* p = (char*)workspace;
+    void* T1 = p;
+    p += al(O->x1_elems * es);
+    void* T2 = p;
+    p += al(O->x2_elems * es);
+    void* WW = p;
+    p += al(dk * dk * es);
+    float* Lf = precision == BSDMRG_F32 ? (float*)p : nullptr;
+    if (Lf) p += al(O->dn_ma * O->dn_k * O->dn_ma * 4);
+    float* Rf = precision == BSDMRG_F32 ? (float*)p : nullptr;
+    HIPCHK(launch_dense_product(O, precision, L, W1, W2, R, psi, out, T1, T2, WW, Lf, Rf, s));
   });
 }
 
@@ -169,6 +229,31 @@ bsdmrg_status bsdmrg_env_backward(bsdmrg_op_t O, const double* env, const double
     if (!env || !mps || !d_out || !d_W) throw Error{BSDMRG_EINVAL, "env_backward: NULL operand"};
     if (d_W == env || d_W == mps || d_W == d_out) throw Error{BSDMRG_EINVAL, "env_backward: d_W aliases an input"};
     env_backward_run(O, env, mps, d_out, d_W, workspace, workspace_bytes, s);
+  });
+}
+
+bsdmrg_status bsdmrg_param_derivative(int32_t n_sites, const double* const* dE_dW, const double* const* dW_dp,
+                                      const int64_t* n_elems, double* terms, double* result, hipStream_t s) {
+  return guarded([&] {
+    if (n_sites < 1 || !dE_dW || !dW_dp || !n_elems || !terms || !result)
+      throw Error{BSDMRG_EINVAL, "param_derivative: NULL argument or n_sites < 1"};
+    for (int i = 0; i < n_sites; ++i) {
+      if (n_elems[i] < 0) throw Error{BSDMRG_EINVAL, "param_derivative: negative element count"};
+      if (n_elems[i] > 0 && (!dE_dW[i] || !dW_dp[i])) throw Error{BSDMRG_EINVAL, "param_derivative: NULL site"};
+    }
+    for (int base = 0; base < n_sites; base += kSiteDotGroup) {
+      SiteDotGroup g{};
+      const int count = std::min(kSiteDotGroup, n_sites - base);
+      for (int b = 0; b < count; ++b) {
+        g.x[b] = dE_dW[base + b];
+        g.y[b] = dW_dp[base + b];
+        g.n[b] = n_elems[base + b];
+      }
+      HIPCHK(launch_site_dots(g, count, base, terms, s));
+    }
+    HIPCHK(launch_ordered_sum(n_sites, terms, s));
+    HIPCHK(hipMemcpyAsync(result, terms + n_sites, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
   });
 }
 

@@ -388,7 +388,10 @@ static BwdWS carve_bwd(const bsdmrg_plan_s* P, const Backward* B, void* ws) {
   return w;
 }
 
+// The adjoint tables are built on first use; the plan's mutex makes the
+// build and upload happen once when several threads share the plan.
 static void ensure_tables(bsdmrg_plan_s* P) {
+  std::lock_guard<std::mutex> lk(P->mu);
   if (!P->bwd) build_backward(P);
   if (!P->bwd->d_blob) upload_backward(P->bwd);
 }
@@ -460,6 +463,7 @@ void heff_energy_run(bsdmrg_plan_s* P, const double* L, const double* W1, const 
 }
 
 int64_t heff_backward_bytes(bsdmrg_plan_s* P) {
+  std::lock_guard<std::mutex> lk(P->mu);
   if (!P->bwd) build_backward(P);
   return carve_bwd(P, P->bwd, nullptr).bytes;
 }

@@ -269,8 +269,11 @@ struct bsdmrg_plan_s {
 // grouped-GEMM stages around an MPO-mixing stage whose coefficients are the
 // entries of W itself.
 struct bsdmrg_op_s {
-  int kind = 0;                       // 1 env left, 2 env right, 3 merge
+  int kind = 0;                       // 1 env left, 2 env right, 3 merge, 4 dense two-site product
   bsd::Stage g1, g2;                  // first and last GEMM stage
+  bsd::Stage g3;                      // dense product: the MPO mixing as a GEMM
+  int64_t dn_ma = 0, dn_mc = 0;       // dense product: bond dimensions,
+  int32_t dn_k = 0, dn_d = 0;         //   channels and physical dimension
   int layout1 = 0, layout2 = 0;       // kNN / kNT / kTN
   std::vector<bsd::MixTask> mix_tasks;
   std::vector<bsd::MixTerm> mix_terms;
@@ -286,4 +289,5 @@ struct bsdmrg_op_s {
   std::vector<bsd::Leg> legs;
   std::vector<bsd::X1Block> x1_blocks;
   bsd::EnvBackward* ebwd = nullptr;
+  std::mutex mu;                      // guards the lazy build of ebwd
 };

@@ -174,9 +174,17 @@ static void upload_env_backward(EnvBackward* B) {
   }
 }
 
-int64_t env_backward_bytes(bsdmrg_op_s* O) {
+// The adjoint tables are built (and uploaded) on first use, under the op's
+// mutex so that threads sharing the op build them once.
+static EnvBackward* ensure_env_tables(bsdmrg_op_s* O, bool upload) {
+  std::lock_guard<std::mutex> lk(O->mu);
   if (!O->ebwd) build_env_backward(O);
-  const EnvBackward* B = O->ebwd;
+  if (upload && !O->ebwd->d_blob) upload_env_backward(O->ebwd);
+  return O->ebwd;
+}
+
+int64_t env_backward_bytes(bsdmrg_op_s* O) {
+  const EnvBackward* B = ensure_env_tables(O, false);
   return (int64_t)(al(std::max<int64_t>(O->x1_elems, 1) * 8) + al(std::max<int64_t>(B->y_elems, 1) * 8) +
                    al(std::max<size_t>(B->dots.size(), 1) * 8));
 }
@@ -187,8 +195,7 @@ void env_backward_run(bsdmrg_op_s* O, const double* env, const double* site, con
   const int64_t need = env_backward_bytes(O);
   if (!ws || ws_bytes < need)
     throw Error{BSDMRG_EINVAL, "env_backward: workspace too small: need " + std::to_string(need) + " bytes"};
-  EnvBackward* B = O->ebwd;
-  if (!B->d_blob) upload_env_backward(B);
+  EnvBackward* B = ensure_env_tables(O, true);
   double* X1 = (double*)ws;
   double* Y = (double*)((char*)ws + al(std::max<int64_t>(O->x1_elems, 1) * 8));
   double* part = (double*)((char*)Y + al(std::max<int64_t>(B->y_elems, 1) * 8));

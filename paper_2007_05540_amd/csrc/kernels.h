@@ -29,6 +29,11 @@ hipError_t launch_mix_f32(const bsdmrg_plan_s* P, const double* coef, const floa
 hipError_t launch_coef(const bsdmrg_plan_s* P, const double* W1, const double* W2, double* coef,
                        hipStream_t s);
 hipError_t launch_cast(int64_t n, const double* x, float* y, hipStream_t s);
+// sparse-dense product of a dense op (precision 0: FP64, 1: FP32 MFMA with
+// FP32 T1, T2, WW and L, R cast into Lf, Rf)
+hipError_t launch_dense_product(const bsdmrg_op_s* O, int precision, const double* L, const double* W1,
+                                const double* W2, const double* R, const double* psi, double* out, void* T1,
+                                void* T2, void* WW, float* Lf, float* Rf, hipStream_t s);
 
 enum { kNN = 0, kNT = 1, kTN = 2 };
 hipError_t launch_copy(const void* d_tasks, int n, const double* src, double* dst, const double* fac,
@@ -103,6 +108,14 @@ hipError_t dav_finalize(const bsdmrg_plan_s* P, const DavBufs& b, int J, int ste
 hipError_t dav_scale_into(const bsdmrg_plan_s* P, const DavBufs& b, double* dst, hipStream_t s);
 
 // adjoint kernels (kernels_bwd.hip)
+constexpr int kSiteDotGroup = 32;   // sites per launch of the chain-rule dots
+struct SiteDotGroup {
+  const double* x[kSiteDotGroup];
+  const double* y[kSiteDotGroup];
+  int64_t n[kSiteDotGroup];
+};
+hipError_t launch_site_dots(const SiteDotGroup& g, int count, int base, double* terms, hipStream_t s);
+hipError_t launch_ordered_sum(int n, double* terms, hipStream_t s);
 hipError_t launch_bwd_dots(const BwdDot* items, int n, const double* G, const double* T1, double* part,
                            hipStream_t s);
 hipError_t launch_bwd_coef(int n, const int32_t* ptr, const double* part, const int64_t* idx, double* out,

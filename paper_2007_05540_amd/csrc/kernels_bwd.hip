@@ -61,6 +61,31 @@ __global__ void seg_scale_kernel(int64_t n, const int64_t* __restrict__ base, in
   }
 }
 
+// One workgroup per site of a group: terms[base + b] = <x_b, y_b>, each
+// thread summing a fixed stride, then the wave and workgroup sums in a fixed
+// order (bit-identical on every call).
+__global__ __launch_bounds__(256) void site_dot_kernel(SiteDotGroup g, int base, double* __restrict__ terms) {
+  __shared__ double sh[4];
+  const int b = blockIdx.x;
+  const double* __restrict__ x = g.x[b];
+  const double* __restrict__ y = g.y[b];
+  const int64_t n = g.n[b];
+  double s = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) s += x[e] * y[e];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) terms[base + b] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// terms[n] = terms[0] + terms[1] + ... + terms[n - 1], left to right.
+__global__ void ordered_sum_kernel(int n, double* __restrict__ terms) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += terms[i];
+  terms[n] = s;
+}
+
 static unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
 
 hipError_t launch_bwd_dots(const BwdDot* items, int n, const double* G, const double* T1, double* part,
@@ -86,6 +111,15 @@ hipError_t launch_seg_scale(int64_t n, const int64_t* base, int np, const double
                             const double* y, double* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(seg_scale_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, base, np, g, x, y, out);
+  return hipGetLastError();
+}
+hipError_t launch_site_dots(const SiteDotGroup& g, int count, int base, double* terms, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(site_dot_kernel, dim3((unsigned)count), dim3(256), 0, s, g, base, terms);
+  return hipGetLastError();
+}
+hipError_t launch_ordered_sum(int n, double* terms, hipStream_t s) {
+  hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(64), 0, s, n, terms);
   return hipGetLastError();
 }
 }  // namespace bsd

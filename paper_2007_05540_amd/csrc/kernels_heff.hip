@@ -722,6 +722,58 @@ hipError_t launch_coef(const bsdmrg_plan_s* P, const double* W1, const double* W
   return hipGetLastError();
 }
 
+// Sparse-dense format (every operand one dense array, Sec. IV-A): the two
+// MPO sites contracted over their shared channel, laid out as the A operand
+// of the mixing GEMM, WW[(s1' s2' w''), (w s1 s2)] = sum_v W1(w, s1', s1, v)
+// W2(v, s2', s2, w'') with W dense (k, d, d, k).
+template <typename TO>
+__global__ void dense_ww_kernel(int k, int d, const double* __restrict__ W1, const double* __restrict__ W2,
+                                TO* __restrict__ WW) {
+  const int n = d * d * k;
+  const int64_t total = (int64_t)n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / n), c = (int)(e % n);
+    const int s1p = r / (d * k), s2p = (r / k) % d, wpp = r % k;
+    const int w = c / (d * d), s1 = (c / d) % d, s2 = c % d;
+    double acc = 0.0;
+    for (int v = 0; v < k; ++v)
+      acc += W1[(((int64_t)w * d + s1p) * d + s1) * k + v] * W2[(((int64_t)v * d + s2p) * d + s2) * k + wpp];
+    WW[e] = (TO)acc;
+  }
+}
+
+hipError_t launch_dense_product(const bsdmrg_op_s* O, int precision, const double* L, const double* W1,
+                                const double* W2, const double* R, const double* psi, double* out, void* T1,
+                                void* T2, void* WW, float* Lf, float* Rf, hipStream_t s) {
+  const int k = O->dn_k, d = O->dn_d;
+  const int64_t n_ww = (int64_t)d * d * k * d * d * k;
+  const unsigned ww_blocks = (unsigned)std::min<int64_t>((n_ww + 255) / 256, 1024);
+  if (precision == 0) {
+    hipLaunchKernelGGL(dense_ww_kernel<double>, dim3(ww_blocks), dim3(256), 0, s, k, d, W1, W2, (double*)WW);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_stage<double, double, double, double, false>(O->g1, L, psi, (double*)T1,
+                                                                                 (double*)T1, s);
+    if (e == hipSuccess)
+      e = launch_stage<double, double, double, double, false>(O->g3, (const double*)WW, (const double*)T1,
+                                                              (double*)T2, (double*)T2, s);
+    if (e == hipSuccess)
+      e = launch_stage<double, double, double, double, true>(O->g2, (const double*)T2, R, out, out, s);
+    return e;
+  }
+  const int64_t l_elems = O->dn_ma * k * O->dn_ma, r_elems = O->dn_mc * k * O->dn_mc;
+  hipLaunchKernelGGL(dense_ww_kernel<float>, dim3(ww_blocks), dim3(256), 0, s, k, d, W1, W2, (float*)WW);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = launch_cast(l_elems, L, Lf, s);
+  if (e == hipSuccess) e = launch_cast(r_elems, R, Rf, s);
+  if (e == hipSuccess)
+    e = launch_stage<float, float, double, float, false>(O->g1, Lf, psi, (float*)T1, (float*)T1, s);
+  if (e == hipSuccess)
+    e = launch_stage<float, float, float, float, false>(O->g3, (const float*)WW, (const float*)T1, (float*)T2,
+                                                        (float*)T2, s);
+  if (e == hipSuccess) e = launch_stage<float, float, float, double, true>(O->g2, (const float*)T2, Rf, out, out, s);
+  return e;
+}
+
 hipError_t launch_cast(int64_t n, const double* x, float* y, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);

@@ -210,4 +210,55 @@ bsdmrg_op_s* build_merge(const Leg& a, const Leg& s1, const Leg& b, const Leg& s
   return O;
 }
 
+// Sparse-dense two-site product (Sec. IV-A: every operand embedded in one
+// dense array, the forbidden blocks stored as zeros) as three GEMM stages:
+//   T1(a' w, s1 s2 c)       = L(a' w, a) psi(a, s1 s2 c)              NN, one task
+//   T2[a'](s1' s2' w'', c)  = WW(s1' s2' w'', w s1 s2) T1[a'](w s1 s2, c)  NN, one task per a'
+//   out(a' s1' s2', c')     = T2(a' s1' s2', w'' c) R(c', w'' c)^T      NT, one task
+bsdmrg_op_s* build_dense(int64_t ma, int64_t mc, int32_t k, int32_t d) {
+  if (ma < 1 || mc < 1 || k < 1 || d < 1 || d > 8)
+    throw Error{BSDMRG_EINVAL, "dense_plan: need ma, mc, k >= 1 and 1 <= d <= 8"};
+  const int64_t dd = (int64_t)d * d;
+  const int64_t lim = (int64_t)1 << 30;
+  if (ma * k >= lim || dd * mc >= lim || k * mc >= lim || ma * dd >= lim || dd * k >= lim)
+    throw Error{BSDMRG_EINVAL, "dense_plan: a GEMM dimension reaches 2^30"};
+  if ((ma * k) * ma >= ((int64_t)1 << 31) / 8 || ma * dd * k * mc >= ((int64_t)1 << 31) / 8 ||
+      (mc * k) * mc >= ((int64_t)1 << 31) / 8)
+    throw Error{BSDMRG_EINVAL, "dense_plan: an operand reaches 2 GiB (32-bit buffer offsets)"};
+  auto* O = new bsdmrg_op_s();
+  try {
+    O->kind = 4;
+    O->dn_ma = ma;
+    O->dn_mc = mc;
+    O->dn_k = k;
+    O->dn_d = d;
+    const int32_t kdd = (int32_t)(k * dd);
+    O->g1.segs.push_back(GemmSeg{0, 0, (int32_t)ma, (int32_t)(dd * mc), (int32_t)ma, 0});
+    O->g1.tasks.push_back(GemmTask{0, (int32_t)(dd * mc), (int32_t)(ma * k), (int32_t)(dd * mc), 0, 1, (int32_t)ma, 0, 0});
+    for (int64_t ap = 0; ap < ma; ++ap) {
+      O->g3.segs.push_back(GemmSeg{0, ap * kdd * mc, kdd, (int32_t)mc, kdd, 0});
+      O->g3.tasks.push_back(GemmTask{ap * kdd * mc, (int32_t)mc, kdd, (int32_t)mc, (int32_t)ap, 1, kdd, 0, 0});
+    }
+    O->g2.segs.push_back(GemmSeg{0, 0, (int32_t)(k * mc), (int32_t)(k * mc), (int32_t)(k * mc), 0});
+    O->g2.tasks.push_back(GemmTask{0, (int32_t)mc, (int32_t)(ma * dd), (int32_t)mc, 0, 1, (int32_t)(k * mc), 0, 0});
+    O->x1_elems = ma * kdd * mc;   // T1
+    O->x2_elems = ma * kdd * mc;   // T2
+    O->out_elems = ma * dd * mc;
+    O->flops = 2.0 * (double)(ma * k) * ma * (dd * mc) + 2.0 * (double)ma * mc * kdd * kdd +
+               2.0 * (double)(ma * dd) * (k * mc) * mc;
+    O->layout1 = kNN;
+    O->layout2 = kNT;
+    schedule_tiles(O->g1);
+    schedule_tiles(O->g3);
+    schedule_tiles(O->g2);
+    validate_gemm(O->g1, kNN, ma * k * ma, ma * dd * mc, O->x1_elems, 0, "dense S1");
+    validate_gemm(O->g3, kNN, (int64_t)kdd * kdd, O->x1_elems, O->x2_elems, 0, "dense mixing");
+    validate_gemm(O->g2, kNT, O->x2_elems, mc * k * mc, O->out_elems, 0, "dense S3");
+  } catch (...) {
+    delete O;
+    throw;
+  }
+  return O;
+}
+
 }  // namespace bsd

@@ -286,6 +286,7 @@ void truncate_run(const bsdmrg_leg* legs, const double* theta, const bsdmrg_trun
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sv[a].nb > sv[b].nb; });
   std::vector<SvdPair> live;
   std::vector<int> prefix(nb_max > 1 ? nb_max - 1 : 0, 0);
+  bool converged = false;
   for (int sweep = 0; sweep < kSvdMaxSweeps; ++sweep) {
     live.clear();
     std::fill(prefix.begin(), prefix.end(), 0);
@@ -294,7 +295,10 @@ void truncate_run(const bsdmrg_leg* legs, const double* theta, const bsdmrg_trun
       for (int q = 0; q < sv[si].nb / 2; ++q) live.push_back(SvdPair{si, q});
       for (int t = 0; t < sv[si].nb - 1; ++t) prefix[t] = (int)live.size();
     }
-    if (live.empty()) break;
+    if (live.empty()) {
+      converged = true;
+      break;
+    }
     HIPCHK(hipMemcpyAsync(pair_tab, live.data(), live.size() * sizeof(SvdPair), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d_active, active.data(), active.size() * 8, hipMemcpyHostToDevice, st));
     HIPCHK(dav_fill_zero(d_rot, (int64_t)T.sec.size(), st));
@@ -308,8 +312,16 @@ void truncate_run(const bsdmrg_leg* legs, const double* theta, const bsdmrg_trun
       active[i] = (active[i] != 0.0 && rot[i] != 0.0) ? 1.0 : 0.0;
       any = any || active[i] != 0.0;
     }
-    if (!any) break;
+    if (!any) {
+      converged = true;
+      break;
+    }
   }
+  // a matrix still rotating after the last sweep has singular values that
+  // are not yet accurate: refuse to truncate with them
+  if (!converged)
+    throw Error{BSDMRG_ESOLVER, "truncate: block-Jacobi SVD still rotating after " + std::to_string(kSvdMaxSweeps) +
+                                    " sweeps"};
   HIPCHK(launch_svd_finish(svd_tab, (int)sv.size(), cols_tab, (int)colblk.size(), work, U, S, V, st));
   std::vector<double> hS(T.n_s);
   HIPCHK(hipMemcpyAsync(hS.data(), S, T.n_s * 8, hipMemcpyDeviceToHost, st));

@@ -1,13 +1,14 @@
 """The sparse-dense format of Sec. IV-A on the GPU, as an ablation of the
 block-sparse list path: every operand of the two-site product embedded in one
-dense tensor (the forbidden blocks are zeros), and each stage one dense
-library GEMM (torch.matmul on the device).  It computes the same product with
-all the work that the block structure avoids; its only use is to measure that
-work.
+dense array (the forbidden blocks are zeros) and the product run by the
+library's grouped GEMM stages on those arrays (bsdmrg_dense_plan /
+bsdmrg_dense_apply).  It computes the same product with all the work that the
+block structure avoids; its only use is to measure that work.
 
 Index names as in the block-sparse path: L (a', w, a), W_i (w, s1', s1, v),
 W_{i+1} (v, s2', s2, w''), R (c', w'', c), psi (a, s1, s2, c).
 """
+from . import lib
 
 
 def dense_flops(m_a, m_c, k, d):
@@ -18,15 +19,27 @@ def dense_flops(m_a, m_c, k, d):
     return s1, s2, s3
 
 
-def heff_dense(L, W1, W2, R, psi):
-    """out = H_eff psi with dense device tensors of one dtype."""
-    ma, k, _ = L.shape
-    mc = R.shape[0]
-    d = psi.shape[1]
-    T1 = (L.reshape(ma * k, ma) @ psi.reshape(ma, d * d * mc)).reshape(ma, k, d, d, mc)
-    WW = (W1.reshape(k * d * d, k) @ W2.reshape(k, d * d * k)).reshape(k, d, d, d, d, k)   # w s1' s1 s2' s2 w''
-    A = T1.permute(0, 4, 1, 2, 3).reshape(ma * mc, k * d * d)                                 # (a' c) (w s1 s2)
-    B = WW.permute(0, 2, 4, 1, 3, 5).reshape(k * d * d, d * d * k)                            # (w s1 s2) (s1' s2' w'')
-    T2 = (A @ B).reshape(ma, mc, d, d, k).permute(0, 2, 3, 4, 1).reshape(ma * d * d, k * mc)  # (a' s1' s2') (w'' c)
-    out = T2 @ R.reshape(mc, k * mc).t().contiguous()
-    return out.reshape(ma, d, d, mc)
+class DenseProduct:
+    """H_eff psi in the dense format for fixed (m_a, m_c, k, d): the op and
+    its workspace are made once; apply() runs the three library stages."""
+
+    def __init__(self, m_a, m_c, k, d, device="cuda"):
+        import torch
+        self.op = lib.dense_plan(m_a, m_c, k, d)
+        q = self.op.query()
+        self.shape = (m_a, d, d, m_c)
+        self.ws = torch.empty(max(1, q["workspace_bytes"]), dtype=torch.uint8, device=device)
+        self.flops = q["flops"]
+
+    def apply(self, precision, L, W1, W2, R, psi, out, stream=None):
+        """out (m_a, d, d, m_c) = H_eff psi; dense FP64 device tensors."""
+        for t in (L, W1, W2, R, psi, out):
+            if not t.is_contiguous() or t.dtype.itemsize != 8:
+                raise ValueError("dense operands must be contiguous FP64 tensors")
+        if tuple(psi.shape) != self.shape or tuple(out.shape) != self.shape:
+            raise ValueError("psi / out shape does not match the plan")
+        lib.dense_apply(self.op, precision, L, W1, W2, R, psi, out, self.ws, stream)
+
+    def destroy(self):
+        self.op.destroy()
+        self.ws = None

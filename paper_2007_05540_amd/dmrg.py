@@ -160,13 +160,14 @@ class GpuDMRG:
     def parameter_derivative(self, grads, dW_dp):
         """Chain rule over the sites, sum_s <dE/dW_s, dW_s/dp>, for an MPO
         parameter p with dense per-site derivatives dW_dp[s] (w, s', s, w') from
-        the MPO builder.  This contraction over the O(k^2 d^2) MPO entries of
-        each site belongs to the model builder and runs on the host."""
-        total = 0.0
-        for j, (g, d) in enumerate(zip(grads, dW_dp)):
-            dp = problems.pack_dense(d, [self.legs[j], self.s, self.s, self.legs[j + 1]], lib.W_SIGNS)
-            total += float(np.dot(g.detach().cpu().numpy(), dp))
-        return total
+        the MPO builder: the derivatives are packed in the canonical W layout
+        and the inner products and their sum run in the library."""
+        torch = self.torch
+        dps = [torch.from_numpy(problems.pack_dense(d, [self.legs[j], self.s, self.s, self.legs[j + 1]],
+                                                    lib.W_SIGNS)).to(self.device)
+               for j, d in enumerate(dW_dp)]
+        terms = torch.empty(len(grads) + 1, dtype=torch.float64, device=self.device)
+        return lib.param_derivative([g.detach().contiguous() for g in grads], dps, terms)
 
     def run(self, n_sweeps, m_max, cutoff=1e-10, cutoff_mode=0, max_iter=40, tol=1e-12, progress=False,
             on_sweep=None):

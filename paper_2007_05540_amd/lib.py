@@ -82,8 +82,8 @@ EXPORTS = ["bsdmrg_layout", "bsdmrg_plan", "bsdmrg_plan_query", "bsdmrg_plan_off
            "bsdmrg_heff_backward", "bsdmrg_heff_backward_workspace", "bsdmrg_heff_energy", "bsdmrg_stage_timing",
            "bsdmrg_plan_autotune", "bsdmrg_plan_set_tiles", "bsdmrg_truncate_workspace", "bsdmrg_truncate",
            "bsdmrg_env_plan", "bsdmrg_merge_plan", "bsdmrg_op_query", "bsdmrg_op_destroy", "bsdmrg_env_update",
-           "bsdmrg_env_backward_workspace", "bsdmrg_env_backward",
-           "bsdmrg_merge", "bsdmrg_last_error"]
+           "bsdmrg_env_backward_workspace", "bsdmrg_env_backward", "bsdmrg_param_derivative",
+           "bsdmrg_merge", "bsdmrg_dense_plan", "bsdmrg_dense_apply", "bsdmrg_last_error"]
 
 
 def load():
@@ -131,6 +131,9 @@ def load():
     lib.bsdmrg_merge.argtypes = [vp, vp, vp, vp, vp]
     lib.bsdmrg_env_backward_workspace.argtypes = [vp, P(i64)]
     lib.bsdmrg_env_backward.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
+    lib.bsdmrg_param_derivative.argtypes = [i32, P(vp), P(vp), P(i64), vp, P(ctypes.c_double), vp]
+    lib.bsdmrg_dense_plan.argtypes = [i64, i64, i32, i32, i32, P(vp)]
+    lib.bsdmrg_dense_apply.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, i64, vp]
     _lib = lib
     return lib
 
@@ -399,10 +402,43 @@ def env_backward_workspace(op):
     return n.value
 
 
+def param_derivative(grads, dW_dp, terms, stream=None):
+    """sum_s <grads[s], dW_dp[s]> on the device (see the header); grads and
+    dW_dp are lists of device tensors in canonical W layout, terms a device
+    tensor of len(grads) + 1 doubles.  Returns the sum."""
+    n = len(grads)
+    if len(dW_dp) != n:
+        raise ValueError("param_derivative: one derivative tensor per site")
+    for g, d in zip(grads, dW_dp):
+        if g.numel() != d.numel():
+            raise ValueError("param_derivative: gradient and derivative sizes differ")
+    x = (ctypes.c_void_p * n)(*[_ptr(g) for g in grads])
+    y = (ctypes.c_void_p * n)(*[_ptr(d) for d in dW_dp])
+    cnt = (ctypes.c_int64 * n)(*[g.numel() for g in grads])
+    out = ctypes.c_double(0.0)
+    check(load().bsdmrg_param_derivative(n, x, y, cnt, _ptr(terms), ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
 def env_backward(op, env, mps, d_out, d_W, workspace, stream=None):
     """d_W = cotangent of W of an environment op (see the header)."""
     check(load().bsdmrg_env_backward(op.handle, _ptr(env), _ptr(mps), _ptr(d_out), _ptr(d_W), _ptr(workspace),
                                      workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def dense_plan(ma, mc, k, d, host_only=False):
+    """Op of the two-site product in the sparse-dense format (see the header)."""
+    h = ctypes.c_void_p()
+    check(load().bsdmrg_dense_plan(int(ma), int(mc), int(k), int(d), PLAN_HOST_ONLY if host_only else 0,
+                                   ctypes.byref(h)))
+    return Op(h)
+
+
+def dense_apply(op, precision, L, W1, W2, R, psi, out, workspace, stream=None):
+    """out = H_eff psi with dense FP64 device operands (see the header)."""
+    check(load().bsdmrg_dense_apply(op.handle, precision, _ptr(L), _ptr(W1), _ptr(W2), _ptr(R), _ptr(psi), _ptr(out),
+                                    _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                    _stream(stream)))
 
 
 def merge(op, A, B, theta, stream=None):

@@ -109,7 +109,7 @@ _SPIN_COMP = {"S+": ("S-", 0.5), "S-": ("S+", 0.5), "Sz": ("Sz", 1.0)}
 
 
 def heisenberg_mpo(n_sites, bonds):
-    """H = sum_{(i,j)} J_ij S_i . S_j (Sec. IV, J1-J2 model) as a distance FSM.
+    """H = sum_{(i,j)} J_ij S_i . S_j (Sec. V, J1-J2 model) as a distance FSM.
 
     Channel (op, r) means: ``op`` was placed r sites to the left and waits for
     its partner.  k = 2 + 3 R with R the largest |i - j| in ``bonds``.
@@ -160,7 +160,7 @@ _HUB_FLUX = {"cu+": (1, 1), "cu": (-1, -1), "cd+": (1, -1), "cd": (-1, 1)}
 
 
 def hubbard_mpo(n_sites, hops, U):
-    """H = -sum_{(i,j),s} t_ij (c+_is c_js + h.c.) + U sum_i n_iu n_id (Sec. IV).
+    """H = -sum_{(i,j),s} t_ij (c+_is c_js + h.c.) + U sum_i n_iu n_id (Sec. V).
 
     For i < j:  c+_is c_js = (c~+_s F)_i F_{i+1..j-1} (c~_s)_j  and
                 c+_js c_is = (F c~_s)_i  F_{i+1..j-1} (c~+_s)_j,

@@ -178,3 +178,21 @@ def test_s3_split_width_rule(lib, name, spec_fn, expect):
     assert info["s3_split_k"] == expect, name
     if info["s3_split_k"] != 512:
         assert info["n_s3_tiles"] >= 3072
+
+
+def test_dense_plan_host_only(lib):
+    """The sparse-dense op: flops of its three stages equal the dense GEMM
+    counts, out_elems = ma d^2 mc, and the workspace covers T1, T2 (ma k d^2
+    mc each) and WW in FP64; out-of-range shapes are rejected."""
+    from paper_2007_05540_amd import dense
+    ma, mc, k, d = 150, 130, 14, 2
+    op = lib.dense_plan(ma, mc, k, d, host_only=True)
+    q = op.query()
+    f1, f2, f3 = dense.dense_flops(ma, mc, k, d)
+    assert q["flops"] == pytest.approx(f1 + f2 + f3, rel=1e-12)
+    assert q["out_elems"] == ma * d * d * mc
+    assert q["workspace_bytes"] >= 8 * (2 * ma * k * d * d * mc + (d * d * k) ** 2)
+    op.destroy()
+    for bad in ((0, 4, 2, 2), (4, 4, 0, 2), (4, 4, 2, 9), (1 << 20, 1 << 20, 14, 2)):
+        with pytest.raises(lib.BsdmrgError):
+            lib.dense_plan(*bad, host_only=True)

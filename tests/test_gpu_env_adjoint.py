@@ -138,3 +138,30 @@ def test_de_dj2_matches_exact_hellmann_feynman(mods):
     assert abs(E - w[0]) < 1e-10 * abs(w[0])
     dE = g.parameter_derivative(grads, dWs)
     assert abs(dE - hf) < 1e-9 * abs(hf)
+
+
+def test_param_derivative_entry_point(gpu_lib):
+    """bsdmrg_param_derivative against a host dot product of the same
+    vectors: 70 sites (three launch groups), one of them empty, sizes up to
+    a few 10^4; per-site terms to 1e-14 relative, the ordered sum to
+    1e-13, bit-identical on a second call."""
+    lib = gpu_lib
+    rng = np.random.default_rng(5)
+    sizes = [int(x) for x in rng.integers(1, 40000, size=70)]
+    sizes[17] = 0
+    xs = [rng.standard_normal(n) for n in sizes]
+    ys = [rng.standard_normal(n) for n in sizes]
+    gx = [torch.from_numpy(x).to("cuda") for x in xs]
+    gy = [torch.from_numpy(y).to("cuda") for y in ys]
+    terms = torch.full((len(sizes) + 1,), float("nan"), dtype=torch.float64, device="cuda")
+    total = lib.param_derivative(gx, gy, terms)
+    want = np.array([float(np.dot(x, y)) for x, y in zip(xs, ys)])
+    got = terms.cpu().numpy()
+    scale = np.array([np.linalg.norm(x) * np.linalg.norm(y) for x, y in zip(xs, ys)])
+    assert np.all(np.abs(got[:-1] - want) <= 1e-14 * np.maximum(scale, 1e-300))
+    assert got[17] == 0.0
+    assert abs(total - want.sum()) <= 1e-13 * scale.sum()
+    assert got[-1] == total
+    assert lib.param_derivative(gx, gy, terms) == total
+    with pytest.raises(ValueError):
+        lib.param_derivative(gx[:3], gy[:2], terms)

@@ -286,23 +286,37 @@ def test_tile_shape_classes_bit_identical_and_autotune(mods, spec_fn):
     assert e1[0] == e2[0]
 
 
-def test_dense_format_ablation_matches_oracle(mods):
-    """The sparse-dense format (every operand one dense tensor, each stage
-    one library GEMM on the device) computes the same product: FP64 within
-    1e-12 of the oracle and exactly zero outside the allowed blocks."""
+@pytest.mark.parametrize("m", [96, 150])
+def test_dense_format_ablation_matches_oracle(mods, m):
+    """The sparse-dense format (every operand one dense array, the product
+    run by the library's three grouped-GEMM stages on them) computes the
+    same product: FP64 within 1e-12 of the oracle, FP32 within 1e-5 (FP32
+    MFMA sums over up to k m terms), and exactly zero outside the allowed
+    blocks in FP64.  m = 150 leaves ragged 64 x 64 tiles in every stage."""
     lib, problems = mods
     from paper_2007_05540_amd import dense
-    spec = synth.c2_bond(m=96, k=14, seed=41)
+    spec = synth.c2_bond(m=m, k=14, seed=41)
     prob, ops = problems.bond_problem(spec)
     wl, s = spec.w_leg(), spec.s_leg
     legs_psi = [spec.a_leg, s, s, spec.c_leg]
     Ld = dev(problems.unpack_dense(ops["L"], [spec.a_leg, wl, spec.a_leg], lib.ENV_SIGNS))
     Rd = dev(problems.unpack_dense(ops["R"], [spec.c_leg, wl, spec.c_leg], lib.ENV_SIGNS))
     pd = dev(problems.unpack_dense(ops["psi"], legs_psi, lib.PSI_SIGNS))
-    out = dense.heff_dense(Ld, dev(spec.W1), dev(spec.W2), Rd, pd).cpu().numpy()
-    got = problems.pack_dense(out, legs_psi, lib.PSI_SIGNS)
-    assert rel(got, oracle_apply(spec)) < 1e-12
-    assert np.array_equal(problems.unpack_dense(got, legs_psi, lib.PSI_SIGNS), out)
+    ma, k, _ = Ld.shape
+    dp = dense.DenseProduct(ma, Rd.shape[0], k, pd.shape[1])
+    ref = oracle_apply(spec)
+    for precision, tol in ((lib.F64, 1e-12), (lib.F32, 1e-5)):
+        out = torch.full_like(pd, float("nan"))
+        dp.apply(precision, Ld, dev(spec.W1), dev(spec.W2), Rd, pd, out)
+        torch.cuda.synchronize()
+        out = out.cpu().numpy()
+        got = problems.pack_dense(out, legs_psi, lib.PSI_SIGNS)
+        assert rel(got, ref) < tol
+        if precision == lib.F64:
+            assert np.array_equal(problems.unpack_dense(got, legs_psi, lib.PSI_SIGNS), out)
+    f1, f2, f3 = dense.dense_flops(ma, Rd.shape[0], k, pd.shape[1])
+    assert dp.flops == pytest.approx(f1 + f2 + f3, rel=1e-12)
+    dp.destroy()
 
 
 # ------------------------------------------------------------ eigensolver ---
