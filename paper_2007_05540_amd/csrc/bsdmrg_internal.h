@@ -236,6 +236,8 @@ struct bsdmrg_plan_s {
   std::vector<bsd::MixTask> mix_tasks;
   std::vector<bsd::MixTerm> mix_terms;
   std::vector<bsd::MixItem> mix_items;
+  std::vector<int32_t> mix_item_group;   // per item: the (problem, a', c) group whose T1 blocks it reads (host)
+  int32_t n_mix_groups = 0;
   std::vector<int32_t> coef_ptr;     // CSR over coefficient pairs
   std::vector<int64_t> coef_e1, coef_e2;
   std::vector<bsd::Chunk> chunks;

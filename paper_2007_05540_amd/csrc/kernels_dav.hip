@@ -77,8 +77,17 @@ __device__ __forceinline__ double wave_sum(double v) { return wave_total(v); }
 __device__ __forceinline__ void sum_partials(const double* __restrict__ part, int nct, const DavProb& pr,
                                              int J, double* out, double* sh) {
   for (int j = 0; j < J; ++j) {
+    const double* col = part + (int64_t)j * nct + pr.chunk0;
     double v = 0.0;
-    for (int c = threadIdx.x; c < pr.nchunk; c += blockDim.x) v += part[(int64_t)j * nct + pr.chunk0 + c];
+    int c = threadIdx.x;
+    for (; c + 7 * (int)blockDim.x < pr.nchunk; c += 8 * blockDim.x) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = col[c + u * blockDim.x];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v += t[u];
+    }
+    for (; c < pr.nchunk; c += blockDim.x) v += col[c];
     v = block_sum(v, sh);
     if (threadIdx.x == 0) out[j] = v;
   }
@@ -93,8 +102,19 @@ __global__ __launch_bounds__(DT) void psum_kernel(const DavProb* __restrict__ pr
   __shared__ double sh[16];
   const int p = blockIdx.x, j = blockIdx.y;
   const DavProb pr = probs[p];
+  const double* col = part + (int64_t)j * nct + pr.chunk0;
+  // the loads of a thread are issued together (they are independent), then
+  // added in chunk order
   double v = 0.0;
-  for (int c = threadIdx.x; c < pr.nchunk; c += DT) v += part[(int64_t)j * nct + pr.chunk0 + c];
+  int c = threadIdx.x;
+  for (; c + 7 * DT < pr.nchunk; c += 8 * DT) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = col[c + u * DT];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += t[u];
+  }
+  for (; c < pr.nchunk; c += DT) v += col[c];
   v = block_sum(v, sh);
   if (threadIdx.x == 0) red[(int64_t)p * ldr + j] = v;
 }

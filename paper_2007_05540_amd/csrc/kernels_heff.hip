@@ -572,24 +572,38 @@ __global__ __launch_bounds__(NTHR) void mix_kernel(const MixItem* __restrict__ i
     cc[q] = e % t.cols;
     acc[q] = 0;
   }
-  // terms read with a uniform index (scalar registers), the next one fetched
-  // while the current one is applied; element offsets within a source block
-  // are 32-bit
-  MixTerm m = t.nterm > 0 ? terms[t.term0] : MixTerm{0, 0, 0};
-  for (int j = 0; j < t.nterm; ++j) {
-    const MixTerm cur = m;
-    if (j + 1 < t.nterm) m = terms[t.term0 + j + 1];
-    const T* sp = src + cur.src_off;
-    const TACC cj = coef ? (TACC)coef[cur.coef] : (TACC)1;
-    T v[PER];
+  // terms read with a uniform index (scalar registers), two at a time: the
+  // loads of both are in flight together, then they are added in term order;
+  // element offsets within a source block are 32-bit
+  auto load = [&](const MixTerm& m, T* v) {
+    const T* sp = src + m.src_off;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = threadIdx.x + q * NTHR;
-      v[q] = e < n ? *(const T*)((const char*)sp + (unsigned)(rr[q] * cur.ld_src + cc[q]) * (unsigned)sizeof(T))
+      v[q] = e < n ? *(const T*)((const char*)sp + (unsigned)(rr[q] * m.ld_src + cc[q]) * (unsigned)sizeof(T))
                    : (T)0;
     }
+  };
+  int j = 0;
+  for (; j + 1 < t.nterm; j += 2) {
+    const MixTerm m0 = terms[t.term0 + j], m1 = terms[t.term0 + j + 1];
+    T v0[PER], v1[PER];
+    load(m0, v0);
+    load(m1, v1);
+    const TACC c0 = coef ? (TACC)coef[m0.coef] : (TACC)1;
+    const TACC c1 = coef ? (TACC)coef[m1.coef] : (TACC)1;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) acc[q] += cj * (TACC)v[q];
+    for (int q = 0; q < PER; ++q) acc[q] += c0 * (TACC)v0[q];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) acc[q] += c1 * (TACC)v1[q];
+  }
+  if (j < t.nterm) {
+    const MixTerm m0 = terms[t.term0 + j];
+    T v0[PER];
+    load(m0, v0);
+    const TACC c0 = coef ? (TACC)coef[m0.coef] : (TACC)1;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) acc[q] += c0 * (TACC)v0[q];
   }
 #pragma unroll
   for (int q = 0; q < PER; ++q) {

@@ -199,6 +199,9 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
 
   std::map<Key, std::pair<int64_t, int>> t2;   // (a', s1', s2', g) -> (offset, c)
   int64_t t2_cursor = 0;
+  // mixing items that read the T1 blocks of one (a', c) sector pair form a
+  // group (placed on one XCD so that the blocks are re-read from its L2)
+  std::map<std::pair<int, int>, int32_t> group_of;
   for (int iap = 0; iap < p.a.size(); ++iap)
     for (int s1p = 0; s1p < p.s1.size(); ++s1p)
       for (int s2p = 0; s2p < p.s2.size(); ++s2p) {
@@ -236,14 +239,22 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
             P->flops_s2 += 2.0 * mt.nterm * (double)ba * bc;
             const int task = (int)P->mix_tasks.size();
             P->mix_tasks.push_back(mt);
-            int rows_per = std::max<int64_t>(1, kMixItemElems / std::max<int64_t>(1, bc));
-            for (int r0 = 0; r0 < ba; r0 += rows_per)
+            // item size: up to kMixItemElems outputs, fewer for tasks with many
+            // terms (their loads come in rounds of two terms), so that no
+            // workgroup runs much longer than the others
+            const int64_t rounds = std::max<int64_t>(1, (mt.nterm + 1) / 2);
+            int rows_per = std::max<int64_t>(1, kMixItemElems / std::max<int64_t>(1, bc * rounds));
+            auto gi = group_of.emplace(std::make_pair(iap, ic), (int32_t)(P->n_mix_groups + group_of.size())).first;
+            for (int r0 = 0; r0 < ba; r0 += rows_per) {
               P->mix_items.push_back(MixItem{task, r0, (int32_t)std::min<int64_t>(rows_per, ba - r0), 0});
+              P->mix_item_group.push_back(gi->second);
+            }
           }
           t2_cursor += round_up(ba * ng * bc);
         }
       }
   p.t2_elems = t2_cursor;
+  P->n_mix_groups += (int32_t)group_of.size();
 
   // ---- S3: one task per output block, K-list over the w'' flux sectors ------
   for (size_t ob = 0; ob < p.psi.keys.size(); ++ob) {
@@ -355,7 +366,11 @@ static void split_k(bsdmrg_plan_s* P) {
   // reduction workgroups of whole rows, up to kMixItemElems outputs each, or
   // up to kRedItemSmall when the larger ones would number fewer than one per
   // CU (kMinRedItems)
-  auto rows_per = [](const MixTask& r, int item) { return std::max(1, item / std::max(1, r.cols)); };
+  // (items of tasks with many pieces are smaller: the pieces are loaded in
+  // rounds of two)
+  auto rows_per = [](const MixTask& r, int item) {
+    return std::max(1, item / std::max(1, r.cols * std::max(1, (r.nterm + 1) / 2)));
+  };
   int64_t n_big = 0;
   for (const MixTask& r : P->red_tasks) n_big += (r.rows + rows_per(r, kMixItemElems) - 1) / rows_per(r, kMixItemElems);
   const int item = n_big < kMinRedItems ? kRedItemSmall : kMixItemElems;
@@ -370,6 +385,60 @@ static void split_k(bsdmrg_plan_s* P) {
 
 using namespace bsd;
 
+// Order the mixing items so that the items of one group (they read the
+// same T1 blocks) run on one XCD: workgroup i of a launch runs on XCD
+// i mod 8, so the groups are dealt to 8 bins longest-first by work (rows x
+// columns x terms) and slot i takes the next item of bin i mod 8 (of the
+// fullest bin once its own is empty).  Every item computes the same values
+// in any order.
+static void order_mix_items(bsdmrg_plan_s* P) {
+  constexpr int kXcd = 8;
+  const size_t n = P->mix_items.size();
+  if (n == 0) return;
+  const int ng = P->n_mix_groups;
+  std::vector<double> work(ng, 0.0);
+  std::vector<std::vector<int>> items(ng);
+  for (size_t i = 0; i < n; ++i) {
+    const MixItem& it = P->mix_items[i];
+    const MixTask& t = P->mix_tasks[it.task];
+    const int g = P->mix_item_group[i];
+    work[g] += (double)it.nrows * t.cols * std::max(1, t.nterm);
+    items[g].push_back((int)i);
+  }
+  std::vector<int> gorder(ng);
+  for (int g = 0; g < ng; ++g) gorder[g] = g;
+  std::stable_sort(gorder.begin(), gorder.end(), [&](int a, int b) { return work[a] > work[b]; });
+  std::vector<double> load(kXcd, 0.0);
+  std::vector<std::vector<int>> bin(kXcd);
+  for (int g : gorder) {
+    if (items[g].empty()) continue;
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[x] += work[g];
+    bin[x].insert(bin[x].end(), items[g].begin(), items[g].end());
+  }
+  std::vector<size_t> next(kXcd, 0);
+  std::vector<MixItem> out;
+  std::vector<int32_t> out_group;
+  out.reserve(n);
+  out_group.reserve(n);
+  for (size_t i = 0; i < n; ++i) {
+    int x = (int)(i % kXcd);
+    if (next[x] == bin[x].size()) {
+      size_t best = 0;
+      for (int y = 0; y < kXcd; ++y)
+        if (bin[y].size() - next[y] > best) {
+          best = bin[y].size() - next[y];
+          x = y;
+        }
+    }
+    const int src = bin[x][next[x]++];
+    out.push_back(P->mix_items[src]);
+    out_group.push_back(P->mix_item_group[src]);
+  }
+  P->mix_items.swap(out);
+  P->mix_item_group.swap(out_group);
+}
+
 bsdmrg_plan_s* build_plan(const bsdmrg_problem* probs, int n_probs) {
   auto* P = new bsdmrg_plan_s();
   try {
@@ -377,6 +446,7 @@ bsdmrg_plan_s* build_plan(const bsdmrg_problem* probs, int n_probs) {
     P->coef_ptr.push_back(0);
     for (int i = 0; i < n_probs; ++i) plan_problem(P, i, probs[i]);
     split_k(P);
+    order_mix_items(P);
     schedule_tiles(P->s1);
     schedule_tiles(P->s3);
     schedule_persistent(P->s1, kPersistentSlotsPerXcd);
