@@ -63,13 +63,13 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-bond batch measurement")
     ap.add_argument("--no-hubbard", action="store_true", help="skip the m=4096 Hubbard bond measurement")
     ap.add_argument("--no-sweeps", action="store_true",
-                    help="skip the sweeps of the 6x6 J1-J2 cylinder and of the 16-site chain (FP64 vs mixed "
-                         "s/sweep at equal accuracy)")
-    ap.add_argument("--workload", default="bond", choices=["bond", "j1j2-6x6", "chain16", "hubbard-4x16"],
+                    help="skip the 6x6 J1-J2 cylinder at m=512 (sweeps, dE/dJ2 by the adjoint and by finite "
+                         "differences, FP64 vs mixed s/sweep) and the 16-site chain sweeps")
+    ap.add_argument("--workload", default="bond", choices=["bond", "j1j2-6x6", "chain16", "hubbard-4x16", "bond-m2048"],
                     help="bond: the isolated-bond product bench (default); j1j2-6x6: DMRG sweeps on the "
                          "6x6 J1-J2 cylinder, dE/dJ2 by the adjoint and by finite differences; chain16: "
                          "sweeps of the 16-site Heisenberg chain; hubbard-4x16: sweeps of the 4x16 Hubbard "
-                         "cylinder at half filling")
+                         "cylinder at half filling; bond-m2048: per-stage rooflines of the m=2048, k=18 bond")
     ap.add_argument("--m-max", type=int, default=512)
     ap.add_argument("--tol", type=float, default=1e-5, help="FP64 residual of a converged solve")
     ap.add_argument("--tol-f32", type=float, default=1e-5, help="residual that ends the FP32 phase")
@@ -135,7 +135,8 @@ def batch_bench(args):
     t0 = time.perf_counter()
     specs = synth.c3_batch()
     pairs = [problems.bond_problem(s) for s in specs]
-    plan = lib.Plan([p for p, _ in pairs])
+    probs = [p for p, _ in pairs]
+    plan = lib.Plan(probs)
     ops = problems.concat(plan, [o for _, o in pairs])
     del pairs
     info = plan.info()
@@ -146,6 +147,7 @@ def batch_bench(args):
     stream = torch.cuda.Stream()
     out = {"problems": len(specs), "useful_gflop_per_batched_product": round(flops / 1e9, 3),
            "setup_s": round(setup_s, 1), "tiles": autotune(plan, info, dev, stream)}
+    energies = {}
     for path in ("f64", "mixed"):
         if path == "mixed":
             o = lib.eig_opts(max_iter=args.n_f32, precision=lib.F32_REFINE, refine_max_iter=args.n_f64,
@@ -168,10 +170,57 @@ def batch_bench(args):
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t1) / reps
         products = args.n_f32 + args.n_f64
+        energies[path] = list(e)
         out[path] = {"ms_per_davidson_step": round(dt * 1e3, 3),
                      "useful_gflops": round(products * flops / dt / 1e9, 1)}
         del ws, psi
     out["speedup_mixed_vs_f64"] = round(out["f64"]["ms_per_davidson_step"] / out["mixed"]["ms_per_davidson_step"], 3)
+
+    # the plain FP64 path: one plan and one FP64 solve per bond (the same
+    # fixed schedule), called one after another, on views of the same operands
+    plans = [lib.Plan([p]) for p in probs]
+    o = lib.eig_opts(max_iter=args.n_f32 + args.n_f64, fixed_iters=1, use_graph=1)
+    ws = torch.empty(max(lib.eig_workspace(pl, o) for pl in plans), dtype=torch.uint8, device="cuda")
+    psi = torch.empty_like(dev["psi"])
+    views = []
+    for i, pl in enumerate(plans):
+        off, pi = plan.offsets(i), pl.info()
+        size = {"psi": pi["psi_elems"], "L": pi["L_elems"], "R": pi["R_elems"], "W1": pi["W1_elems"],
+                "W2": pi["W2_elems"]}
+        views.append({k: (dev[k] if k != "psi" else psi)[off[k]:off[k] + size[k]] for k in size})
+
+    def plain_pass():
+        e_all = []
+        for pl, v in zip(plans, views):
+            e, _ = lib.eigensolve(pl, v["L"], v["W1"], v["W2"], v["R"], v["psi"], o, ws, stream=stream)
+            e_all.append(e[0])
+        return e_all
+
+    with torch.cuda.stream(stream):
+        psi.copy_(dev["psi"])
+        plain_pass()
+        torch.cuda.synchronize()
+        reps = max(2, args.steps // 4)
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            psi.copy_(dev["psi"])
+            e_plain = plain_pass()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / reps
+    products = args.n_f32 + args.n_f64
+    out["plain_f64"] = {"ms_per_davidson_step": round(dt * 1e3, 3),
+                        "useful_gflops": round(products * flops / dt / 1e9, 1),
+                        "max_energy_diff_vs_batched_f64": float(max(abs(a - b) for a, b in
+                                                                    zip(e_plain, energies["f64"])))}
+    out["speedup_mixed_batched_vs_plain_f64"] = round(dt * 1e3 / out["mixed"]["ms_per_davidson_step"], 3)
+    out["speedup_f64_batched_vs_plain_f64"] = round(dt * 1e3 / out["f64"]["ms_per_davidson_step"], 3)
+    # the fixed schedule is not a converged solve: the mixed energies differ
+    # from the FP64 ones by the FP32 error of an unconverged Krylov space
+    out["max_rel_energy_diff_mixed_vs_f64"] = float(max(abs(a - b) / abs(b) for a, b in
+                                                        zip(energies["mixed"], energies["f64"])))
+    for pl in plans:
+        pl.destroy()
+    del ws, psi, views
     plan.destroy()
     return out
 
@@ -186,13 +235,18 @@ def j1j2_bench(args, with_fd=True):
     equal accuracy)."""
     import torch
     import synth
-    from paper_2007_05540_amd import lib, problems, dmrg as gdmrg
+    from paper_2007_05540_amd import lib, problems, dmrg as gdmrg, mpo as gmpo
 
     Wd, Lx, J2, h = 6, 6, 0.5, 1e-4
     n = Wd * Lx
     j1, j2 = synth.cylinder_j1_bonds(Wd, Lx), synth.cylinder_j2_bonds(Wd, Lx)
-    mpo, dWs = synth.heisenberg_j2_derivative(n, j1, j2, J2)
-    k = sum(d for _, d in mpo.w_leg())
+    # the sweeps run with the SVD-compressed operator (cutoff 1e-13 of its
+    # norm); the adjoint differentiates the builder's own operator, whose
+    # site tensors are affine in J2, at the same converged state
+    full, dWs = synth.heisenberg_j2_derivative(n, j1, j2, J2)
+    k_full = sum(d for _, d in full.w_leg())
+    mpo = gmpo.compress(full)
+    k = max(mpo.bond_dims())
     m = args.m_max
     sched = [min(m, x) for x in (64, 128, 256)] + [m] * 3
     opts = dict(cutoff=1e-10, max_iter=30, tol=1e-10)
@@ -211,21 +265,24 @@ def j1j2_bench(args, with_fd=True):
     sweep["speedup_mixed_vs_f64"] = round(sweep["f64"]["s_per_sweep"] / sweep["mixed"]["s_per_sweep"], 3)
     if not with_fd:
         return {"workload": f"6x6 J1-J2 Heisenberg cylinder, J2/J1=0.5, U(1) Sz, m={m}", "mpo_k": k,
+                "mpo_k_uncompressed": k_full,
                 "m_schedule": sched, "sweep_energies": swe, "sweep_seconds": [round(t, 3) for t in g.sweep_seconds],
                 "one_sweep_from_converged": sweep}
     t0 = time.perf_counter()
-    E_bond, grads = g.energy_and_mpo_gradients(0)
-    dE_adj = g.parameter_derivative(grads, dWs)
+    ga = gdmrg.GpuDMRG(full, warm, (0,))
+    E_bond, grads = ga.energy_and_mpo_gradients(0)
+    dE_adj = ga.parameter_derivative(grads, dWs)
     t_adj = time.perf_counter() - t0
     ef = {}
     for sgn in (1, -1):
         mp, _ = synth.heisenberg_j2_derivative(n, j1, j2, J2 + sgn * h)
-        gg = gdmrg.GpuDMRG(mp, warm, (0,))
+        gg = gdmrg.GpuDMRG(gmpo.compress(mp), warm, (0,))
         _, e = gg.run(2, m, on_sweep=log(f"J2{sgn * h:+g}"), **opts)
         ef[sgn] = e[-1]
     dE_fd = (ef[1] - ef[-1]) / (2 * h)
     return {"metric": "6x6 J1-J2 cylinder: DMRG energy and dE/dJ2 (adjoint vs finite differences)",
             "config": {"workload": "6x6 J1-J2 Heisenberg cylinder, J2/J1=0.5, U(1) Sz", "mpo_k": k,
+                       "mpo_k_uncompressed": k_full,
                        "m_schedule": sched, "cutoff": opts["cutoff"], "davidson_tol": opts["tol"]},
             "sweep_energies": swe, "sweep_seconds": [round(t, 3) for t in g.sweep_seconds],
             "energy_per_site": swe[-1] / n, "bond_energy": E_bond,
@@ -488,6 +545,9 @@ def main():
     if args.workload in ("chain16", "hubbard-4x16"):
         print(json.dumps(sweeps_bench(args)))
         return
+    if args.workload == "bond-m2048":
+        print(json.dumps(large_bond_bench(args)))
+        return
     import torch
     import synth
     from paper_2007_05540_amd import lib, problems
@@ -558,8 +618,8 @@ def main():
         line["hubbard_bond_m4096"] = hubbard_bond_bench(args)
     if not args.no_sweeps:
         a2 = argparse.Namespace(**vars(args))
-        a2.m_max = 256
-        line["sweeps_j1j2_6x6"] = j1j2_bench(a2, with_fd=False)
+        a2.m_max = 512
+        line["j1j2_6x6_m512_dE_dJ2"] = j1j2_bench(a2, with_fd=True)
         a3 = argparse.Namespace(**vars(args))
         a3.workload = "chain16"
         line["sweeps_chain16"] = sweeps_bench(a3)
