@@ -72,6 +72,14 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 __device__ __forceinline__ double wave_sum(double v) { return wave_total(v); }
 
+// Ordering of LDS traffic between the lanes of one wave (code run by a
+// single wave): LDS operations of a wave complete in order; the fence makes
+// the compiler wait for them and keeps it from moving accesses across.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // out[j] = sum over the problem's chunks of part[j * nct + chunk] for j < J
 // (thread-strided sums, then the deterministic block tree); result in LDS.
 __device__ __forceinline__ void sum_partials(const double* __restrict__ part, int nct, const DavProb& pr,
@@ -292,7 +300,7 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
     Mp[i * B + lane] = v;
     Mp[lane * B + i] = v;
   }
-  __syncthreads();
+  wave_sync();
   // 1. tridiagonalisation (lane r owns row r of the trailing block).  Up to
   // 16 or 32 rows the row is held in registers (tridiag_in_registers);
   // larger matrices stay in LDS.
@@ -315,7 +323,7 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
         d[k] = A[k][k];
         e[k] = alpha;
       }
-      __syncthreads();
+      wave_sync();
       if (vn2 > 0.0) {
         // four partial sums so that the LDS loads of a row are in flight together
         double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
@@ -333,12 +341,12 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
         const double beta = wave_total(vr * pr);
         const double wr = pr - beta * vr;
         wb[lane] = wr;
-        __syncthreads();
+        wave_sync();
         if (mine) {
 #pragma unroll 4
           for (int c = k + 1; c < n; ++c) A[lane][c] -= 2.0 * (vr * wb[c] + wr * vb[c]);
         }
-        __syncthreads();
+        wave_sync();
       }
     }
     if (lane == 0) {
@@ -349,7 +357,7 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
       d[n - 1] = A[n - 1][n - 1];
     }
   }
-  __syncthreads();
+  wave_sync();
   // 2. multisection for the lowest eigenvalue of T
   double glo = 1e308, ghi = -1e308, tn = 0.0, emax2 = 0.0;
   if (lane < n) {
@@ -370,7 +378,7 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
   double lo = glo - 2.0 * eps * tn - pivmin, hi = ghi + 2.0 * eps * tn + pivmin;
   // squared off-diagonal in LDS once (the Sturm recurrence reads it every round)
   if (lane + 1 < n) wb[lane] = e[lane] * e[lane];
-  __syncthreads();
+  wave_sync();
   for (int round = 0; round < 24; ++round) {
     const double width = hi - lo;
     if (!(width > 4.0 * eps * fmax(fabs(lo), fabs(hi))) || width <= pivmin) break;
@@ -402,78 +410,72 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
     }
   }
   const double lambda = 0.5 * (lo + hi);
-  // 3. inverse iteration.  The elimination is sequential: every lane runs it
-  // on the same (uniform) values, and each array is one register spread over
-  // the lanes (element j in lane j), read and written with lane operations.
-  const double dv = lane < n ? d[lane] : 0.0, ev = lane + 1 < n ? e[lane] : 0.0;
+  // 3. the eigenvector of T for lambda by the twisted factorisation
+  // (Dhillon and Parlett's "getvec"): the pivots of T - lambda I = L+ D+ L+^T
+  // (forward) and = U- D- U-^T (backward), the twist index r where
+  // |gamma_r| = |D+_r + D-_r - (d_r - lambda)| is smallest, z_r = 1 and the
+  // other entries by the two recurrences outward from r.  The recurrences
+  // are sequential: every lane runs them on the same (uniform) values, with
+  // the arrays held one element per lane (read and written with lane
+  // operations).  A pivot of magnitude below pivmin is replaced by -pivmin
+  // (as in the Sturm counts); the reciprocals use the hardware reciprocal
+  // refined by one Newton step.
+  const double dv = lane < n ? d[lane] - lambda : 0.0;           // d_k - lambda
+  const double e2v = lane + 1 < n ? wb[lane] : 0.0;              // e_k^2
+  const double ev = lane + 1 < n ? e[lane] : 0.0;                // e_k
+  auto recip = [](double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    return fma(r, fma(-q, r, 1.0), r);
+  };
   double yv;
-  if (!(tn > 0.0)) {   // T = 0: every vector is an eigenvector
+  if (!(tn > 0.0) || n == 1) {   // T = 0 or 1 x 1: a unit vector is an eigenvector
     yv = lane == 0 ? 1.0 : 0.0;
   } else {
-    // work with (T - lambda I) / ||T|| so that the iterates cannot overflow
-    const double sc = 1.0 / tn, tiny = eps;
-    // factor = P L U; row j of U is (U0, U1, U2) at columns j, j+1, j+2
-    double u0v = 0.0, u1v = 0.0, u2v = 0.0, mlv = 0.0;
-    int swv = 0;
-    double a = (readlane_d(dv, 0) - lambda) * sc, b = n > 1 ? readlane_d(ev, 0) * sc : 0.0, c = 0.0;
-    for (int j = 0; j + 1 < n; ++j) {
-      const double sub = readlane_d(ev, j) * sc, dn = (readlane_d(dv, j + 1) - lambda) * sc;
-      const double en = j + 2 < n ? readlane_d(ev, j + 1) * sc : 0.0;
-      double r0, r1, r2, m;
-      int swj;
-      if (fabs(a) >= fabs(sub)) {
-        m = a != 0.0 ? sub / a : 0.0;
-        r0 = a; r1 = b; r2 = c; swj = 0;
-        a = dn - m * b;
-        b = en - m * c;
-      } else {
-        m = a / sub;
-        r0 = sub; r1 = dn; r2 = en; swj = 1;
-        a = b - m * dn;
-        b = c - m * en;
-      }
-      c = 0.0;
-      u0v = writelane(r0, j, u0v);
-      u1v = writelane(r1, j, u1v);
-      u2v = writelane(r2, j, u2v);
-      mlv = writelane(m, j, mlv);
-      swv = writelane(swj, j, swv);
+    double dpv = 0.0, dmv = 0.0;   // D+_k and D-_k in lane k
+    double cur = readlane_d(dv, 0);
+    if (fabs(cur) < pivmin) cur = -pivmin;
+    dpv = writelane(cur, 0, dpv);
+    for (int k = 0; k + 1 < n; ++k) {
+      cur = readlane_d(dv, k + 1) - readlane_d(e2v, k) * recip(cur);
+      if (fabs(cur) < pivmin) cur = -pivmin;
+      dpv = writelane(cur, k + 1, dpv);
     }
-    u0v = writelane(a, n - 1, u0v);
-    u1v = writelane(0.0, n - 1, u1v);
-    u2v = writelane(0.0, n - 1, u2v);
-    // pivots below eps replaced by eps; their reciprocals kept (all lanes at once)
-    {
-      const double u = fabs(u0v) < tiny ? (u0v < 0.0 ? -tiny : tiny) : u0v;
-      u0v = lane < n ? 1.0 / u : 0.0;
+    cur = readlane_d(dv, n - 1);
+    if (fabs(cur) < pivmin) cur = -pivmin;
+    dmv = writelane(cur, n - 1, dmv);
+    for (int k = n - 2; k >= 0; --k) {
+      cur = readlane_d(dv, k) - readlane_d(e2v, k) * recip(cur);
+      if (fabs(cur) < pivmin) cur = -pivmin;
+      dmv = writelane(cur, k, dmv);
     }
-    yv = lane < n ? 1.0 / sqrt((double)n) : 0.0;
-    for (int it = 0; it < 2; ++it) {
-      // y <- L^-1 P y, the running entry carried in a register
-      double cur = readlane_d(yv, 0);
-      for (int j = 0; j + 1 < n; ++j) {
-        const double nxt = readlane_d(yv, j + 1), m = readlane_d(mlv, j);
-        if (__builtin_amdgcn_readlane(swv, j)) {
-          yv = writelane(nxt, j, yv);
-          cur = cur - m * nxt;
-        } else {
-          yv = writelane(cur, j, yv);
-          cur = nxt - m * cur;
-        }
+    // twist index: the smallest |gamma_k| (the lowest k among equal ones)
+    double g = lane < n ? fabs(dpv + dmv - dv) : 1e308;
+    int r = lane;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double go = __shfl_xor(g, o, 64);
+      const int ro = __shfl_xor(r, o, 64);
+      if (go < g || (go == g && ro < r)) {
+        g = go;
+        r = ro;
       }
-      yv = writelane(cur, n - 1, yv);
-      // y <- U^-1 y, the two entries below carried in registers
-      double y1 = 0.0, y2 = 0.0, s2 = 0.0;
-      for (int j = n - 1; j >= 0; --j) {
-        const double t = (readlane_d(yv, j) - readlane_d(u1v, j) * y1 - readlane_d(u2v, j) * y2) *
-                         readlane_d(u0v, j);
-        yv = writelane(t, j, yv);
-        s2 += t * t;
-        y2 = y1;
-        y1 = t;
-      }
-      yv *= 1.0 / sqrt(s2);
     }
+    // z_r = 1; z_k = -(e_k / D+_k) z_{k+1} below r; z_{k+1} = -(e_k / D-_{k+1}) z_k above r
+    yv = lane == r ? 1.0 : 0.0;
+    double z = 1.0;
+    for (int k = r - 1; k >= 0; --k) {
+      z = -readlane_d(ev, k) * recip(readlane_d(dpv, k)) * z;
+      yv = writelane(z, k, yv);
+    }
+    z = 1.0;
+    for (int k = r; k + 1 < n; ++k) {
+      z = -readlane_d(ev, k) * recip(readlane_d(dmv, k + 1)) * z;
+      yv = writelane(z, k + 1, yv);
+    }
+    // unit length; the sign that makes the entries sum to a positive value
+    // (the sign inverse iteration from the constant vector would give)
+    const double nrm = sqrt(wave_total(yv * yv));
+    const double sum = wave_total(yv);
+    yv *= (sum < 0.0 ? -1.0 : 1.0) / nrm;
   }
   // 4. x = H_0 (H_1 (... (H_{n-3} y)))
   double xr = lane < n ? yv : 0.0;
@@ -490,6 +492,11 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
 // non-null the Ritz vector x = sum s_j v_j is stored too, and when part_d is
 // non-null the partial dots v_j^T q (the first Gram-Schmidt pass, columns
 // j < J) and the partial ||q||^2 again (column J) as well.
+//
+// JR > 0 (J <= JR): the loop over the basis is unrolled JR times and the
+// chunk's basis values stay in registers for the Gram-Schmidt dots (the
+// same arithmetic in the same order as JR = 0).
+template <int JR>
 __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chunks, int nct, int J, int B,
                                                   const double* __restrict__ V, const double* __restrict__ VA,
                                                   int64_t stride, const double* __restrict__ svec,
@@ -509,17 +516,31 @@ __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chun
   // Ritz value is above some diagonal entries)
   const double floor_p = 1e-3 * fmax(fabs(l), 1.0);
   double qv[PER];
+  double vr[JR > 0 ? JR : 1][PER];
   double nrm = 0.0, res = 0.0;
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int e = threadIdx.x + u * DT;
     qv[u] = 0.0;
+#pragma unroll
+    for (int j = 0; j < (JR > 0 ? JR : 1); ++j) vr[j][u] = 0.0;
     if (e >= ch.len) continue;
     double xv = 0.0, av = 0.0;
+    if (JR > 0) {
+#pragma unroll
+      for (int j = 0; j < (JR > 0 ? JR : 1); ++j)
+        if (j < J) {
+          const double vv = ld_at(V + j * stride + ch.start, e);
+          vr[j][u] = vv;
+          xv += sv[j] * vv;
+          av += sv[j] * ld_at(VA + j * stride + ch.start, e);
+        }
+    } else {
 #pragma unroll 4
-    for (int j = 0; j < J; ++j) {
-      xv += sv[j] * ld_at(V + j * stride + ch.start, e);
-      av += sv[j] * ld_at(VA + j * stride + ch.start, e);
+      for (int j = 0; j < J; ++j) {
+        xv += sv[j] * ld_at(V + j * stride + ch.start, e);
+        av += sv[j] * ld_at(VA + j * stride + ch.start, e);
+      }
     }
     const double r = av - l * xv;
     res += r * r;
@@ -535,16 +556,31 @@ __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chun
   res = wave_sum(res);
   if (lane == 0) ws[kMaxBasisD + 1][wave] = res;
   if (part_d) {
-#pragma unroll 4
-    for (int j = 0; j < J; ++j) {
-      double d = 0.0;
+    if (JR > 0) {
 #pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int e = threadIdx.x + u * DT;
-        if (e < ch.len) d += ld_at(V + j * stride + ch.start, e) * qv[u];
+      for (int j = 0; j < (JR > 0 ? JR : 1); ++j)
+        if (j < J) {
+          double d = 0.0;
+#pragma unroll
+          for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * DT;
+            if (e < ch.len) d += vr[j][u] * qv[u];
+          }
+          d = wave_sum(d);
+          if (lane == 0) ws[j][wave] = d;
+        }
+    } else {
+#pragma unroll 4
+      for (int j = 0; j < J; ++j) {
+        double d = 0.0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int e = threadIdx.x + u * DT;
+          if (e < ch.len) d += ld_at(V + j * stride + ch.start, e) * qv[u];
+        }
+        d = wave_sum(d);
+        if (lane == 0) ws[j][wave] = d;
       }
-      d = wave_sum(d);
-      if (lane == 0) ws[j][wave] = d;
     }
   }
   __syncthreads();
@@ -570,6 +606,9 @@ __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chun
 // holds ||q||^2 after the first pass; the pass is made only when the first
 // one lost more than half of ||q||^2 ("twice is enough": otherwise q is
 // already orthogonal to working accuracy), and the partial ||q||^2 is written.
+// JR > 0 (J <= JR): the basis loop unrolled JR times and the chunk's basis
+// values kept in registers for the dots of mode 1 (same arithmetic and order).
+template <int JR>
 __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ chunks, int nct, int J,
                                                     const double* __restrict__ V, int64_t stride, int ldr,
                                                     const double* __restrict__ red,
@@ -588,14 +627,27 @@ __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ ch
   // ||q||^2 after the first pass from red (the same test decides there)
   if (!pass) return;
   double qv[PER];
+  double vr[JR > 0 ? JR : 1][PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int e = threadIdx.x + u * DT;
+#pragma unroll
+    for (int j = 0; j < (JR > 0 ? JR : 1); ++j) vr[j][u] = 0.0;
     if (e < ch.len) {
       double v = ld_at(q + ch.start, e);
       if (pass) {
+        if (JR > 0) {
+#pragma unroll
+          for (int j = 0; j < (JR > 0 ? JR : 1); ++j)
+            if (j < J) {
+              const double vv = ld_at(V + j * stride + ch.start, e);
+              vr[j][u] = vv;
+              v -= cj[j] * vv;
+            }
+        } else {
 #pragma unroll 4
-        for (int j = 0; j < J; ++j) v -= cj[j] * ld_at(V + j * stride + ch.start, e);
+          for (int j = 0; j < J; ++j) v -= cj[j] * ld_at(V + j * stride + ch.start, e);
+        }
         st_at(q + ch.start, e, v);
       }
       qv[u] = v;
@@ -605,16 +657,31 @@ __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ ch
   }
   if (mode == 1) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll 4
-    for (int j = 0; j < J; ++j) {
-      double s = 0.0;
+    if (JR > 0) {
 #pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int e = threadIdx.x + u * DT;
-        if (e < ch.len) s += ld_at(V + j * stride + ch.start, e) * qv[u];
+      for (int j = 0; j < (JR > 0 ? JR : 1); ++j)
+        if (j < J) {
+          double s = 0.0;
+#pragma unroll
+          for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * DT;
+            if (e < ch.len) s += vr[j][u] * qv[u];
+          }
+          s = wave_sum(s);
+          if (lane == 0) wsum[j][wave] = s;
+        }
+    } else {
+#pragma unroll 4
+      for (int j = 0; j < J; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int e = threadIdx.x + u * DT;
+          if (e < ch.len) s += ld_at(V + j * stride + ch.start, e) * qv[u];
+        }
+        s = wave_sum(s);
+        if (lane == 0) wsum[j][wave] = s;
       }
-      s = wave_sum(s);
-      if (lane == 0) wsum[j][wave] = s;
     }
     double s = 0.0;
 #pragma unroll
@@ -922,6 +989,9 @@ hipError_t dav_normalize(const bsdmrg_plan_s* P, const double* part, double* red
 }
 
 hipError_t dav_gram_eig(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStream_t s) {
+  if (i < 0 || i >= kMaxBasis) return hipErrorInvalidValue;
+  // the Gram row's sums in parallel over its columns (one workgroup each),
+  // then the one-wave eigensolve
   hipError_t e = dav_psum(P, i + 1, b.part_a, b.red, kMaxBasis, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(gram_eig_kernel, dim3((unsigned)P->probs.size()), dim3(GT), 0, s, kMaxBasis, i, b.B,
@@ -931,8 +1001,14 @@ hipError_t dav_gram_eig(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStre
 
 hipError_t dav_ritz(const bsdmrg_plan_s* P, const DavBufs& b, int i, bool want_x, double* part_d,
                     const double* D, hipStream_t s) {
-  hipLaunchKernelGGL(ritz_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), i + 1, b.B,
-                     b.V, b.VA, b.n, b.svec, b.lam, want_x ? b.x : nullptr, b.q, b.part_n0, part_d, b.part_res, D);
+  if (i + 1 <= 16)
+    hipLaunchKernelGGL(ritz_kernel<16>, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), i + 1,
+                       b.B, b.V, b.VA, b.n, b.svec, b.lam, want_x ? b.x : nullptr, b.q, b.part_n0, part_d,
+                       b.part_res, D);
+  else
+    hipLaunchKernelGGL(ritz_kernel<0>, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), i + 1,
+                       b.B, b.V, b.VA, b.n, b.svec, b.lam, want_x ? b.x : nullptr, b.q, b.part_n0, part_d,
+                       b.part_res, D);
   return hipGetLastError();
 }
 
@@ -941,8 +1017,12 @@ hipError_t dav_update(const bsdmrg_plan_s* P, const DavBufs& b, int J, const dou
   if (J < 1 || J >= kMaxBasisD) return hipErrorInvalidValue;   // column J holds a norm
   hipError_t e = dav_psum(P, J + 1, part_in, b.red, kMaxBasis, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(update_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), J, b.V,
-                     b.n, kMaxBasis, b.red, b.q, part_out, b.nq0, mode);
+  if (J <= 16)
+    hipLaunchKernelGGL(update_kernel<16>, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), J, b.V,
+                       b.n, kMaxBasis, b.red, b.q, part_out, b.nq0, mode);
+  else
+    hipLaunchKernelGGL(update_kernel<0>, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), J, b.V,
+                       b.n, kMaxBasis, b.red, b.q, part_out, b.nq0, mode);
   return hipGetLastError();
 }
 
