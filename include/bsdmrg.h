@@ -208,11 +208,15 @@ typedef struct {
   int32_t basis;           /* basis size with thick restart (3..64; 0: 64)   */
   int32_t precond;         /* 0: none (Alg. 1); 1: Davidson's diagonal
                               preconditioner (see bsdmrg_eigensolve)        */
-  int32_t check_every;     /* tol mode: ||q|| is read back (one host sync)
-                              after every check_every-th product only, and
-                              at the end of a phase (0 or 1: every product);
-                              the solve then stops at the first check with
-                              ||q|| <= tol                                    */
+  int32_t check_every;     /* tol mode: ||q|| is copied back after every
+                              check_every-th product (0 or 1: every product)
+                              without waiting, and examined at the next such
+                              check; when that lagged value is <= tol, the
+                              current ||q|| is read (one host sync) and the
+                              phase stops if it is <= tol too (so a phase
+                              ends at most 2 check_every products after
+                              ||q|| first fell to tol); the end of a phase's
+                              budget also reads ||q|| synchronously          */
   int32_t reserved;
 } bsdmrg_eig_opts;
 

@@ -411,7 +411,44 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
   } else {
     phases.push_back({BSDMRG_F64, o->max_iter, o->tol});
   }
-  std::vector<double> hpart(P->chunks.size());
+  // tol mode: the residual partials of a check are copied to pinned host
+  // memory without waiting for them and examined at the next check, so the
+  // device never idles for a host round trip between checks; when a lagged
+  // check is converged, the current residual is read synchronously and the
+  // solve stops if it is converged too.  The end of a phase reads the
+  // current residual synchronously.
+  const size_t nch = P->chunks.size();
+  struct Lagged {
+    double* h = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ~Lagged() {
+      for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+      if (h) (void)hipHostFree(h);
+    }
+  } lag;
+  std::vector<double> hpart(nch);
+  if (!o->fixed_iters) {
+    HIPCHK(hipHostMalloc((void**)&lag.h, 2 * nch * sizeof(double), hipHostMallocDefault));
+    for (hipEvent_t& e : lag.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  auto converged_from = [&](const double* hp, double tol) {
+    bool all = true;
+    for (int p = 0; p < np; ++p) {
+      const DavProb& pr = P->dav_probs[p];
+      double r = 0.0;
+      for (int c = 0; c < pr.nchunk; ++c) r += hp[pr.chunk0 + c];
+      res[p] = std::sqrt(r);
+      conv[p] = res[p] <= tol;
+      all = all && conv[p];
+    }
+    return all;
+  };
+  auto read_now = [&](double tol) {
+    HIPCHK(hipMemcpyAsync(hpart.data(), d.part_res, nch * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return converged_from(hpart.data(), tol);
+  };
   const int64_t dim = solve_dim(P);
   const bool thick = o->restart_keep > 0;
   int j = 1;          // basis size
@@ -420,6 +457,7 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
   for (size_t ph = 0; ph < phases.size(); ++ph) {
     const Phase& f = phases[ph];
     int products = 0;
+    int pend = -1, nextb = 0;   // buffer of the check in flight, next buffer
     int& counter = f.prec == BSDMRG_F64 ? cnt.it64 : cnt.it32;
     if (ph == 0) {
       matvec(P, f.prec, L, R, w.a, d.V, d.VA, s);
@@ -451,24 +489,25 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
       // q, t and (unless this is the last step) the first Gram-Schmidt dots v_c^T t
       HIPCHK(dav_ritz(P, d, i, false, last ? nullptr : d.part_a, d.D, s));
       const int every = std::max(1, o->check_every);
-      if (!o->fixed_iters && (last || products % every == 0)) {
-        HIPCHK(hipMemcpyAsync(hpart.data(), d.part_res, hpart.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        bool all = true;
-        for (int p = 0; p < np; ++p) {
-          const DavProb& pr = P->dav_probs[p];
-          double r = 0.0;
-          for (int c = 0; c < pr.nchunk; ++c) r += hpart[pr.chunk0 + c];
-          res[p] = std::sqrt(r);
-          conv[p] = res[p] <= f.tol;
-          all = all && conv[p];
+      if (!o->fixed_iters && !last && products % every == 0) {
+        bool stop = false;
+        if (pend >= 0) {
+          HIPCHK(hipEventSynchronize(lag.ev[pend]));
+          if (converged_from(lag.h + (size_t)pend * nch, f.tol)) stop = read_now(f.tol);
+          pend = -1;
         }
-        if (all) {
+        if (stop) {
           HIPCHK(dav_ritz(P, d, i, true, nullptr, d.D, s));
           break;
         }
+        HIPCHK(hipMemcpyAsync(lag.h + (size_t)nextb * nch, d.part_res, nch * sizeof(double), hipMemcpyDeviceToHost,
+                              s));
+        HIPCHK(hipEventRecord(lag.ev[nextb], s));
+        pend = nextb;
+        nextb ^= 1;
       }
       if (last) {
+        if (!o->fixed_iters) (void)read_now(f.tol);   // also completes a check in flight
         HIPCHK(dav_ritz(P, d, i, true, nullptr, d.D, s));
         break;
       }
