@@ -9,6 +9,8 @@ the sweep direction) and extend the environment.  This module only orders the
 calls and keeps leg tables; every contraction, eigensolve and SVD runs in the
 library through its C ABI.
 """
+from collections import OrderedDict
+
 import numpy as np
 
 from . import lib, problems
@@ -19,6 +21,11 @@ class Tensor:
 
     def __init__(self, legs, data):
         self.legs, self.data = legs, data
+
+
+def _lk(leg):
+    """Hashable form of a leg [(charge, dim), ...]."""
+    return tuple((tuple(q), int(d)) for q, d in leg)
 
 
 class GpuDMRG:
@@ -53,6 +60,26 @@ class GpuDMRG:
         self.L[0] = self._boundary(zero, bm.start, self.legs[0])
         self.R[self.N] = self._boundary(self.target, bm.done, self.legs[self.N])
         self.log = []
+        # plans and ops keyed by what they are built from (site, side and the
+        # legs of the operands): sweeps at a saturated bond dimension meet the
+        # same sector structure again and reuse them
+        self._cache = OrderedDict()
+        self._cache_max = 6 * self.N + 8
+        self.cache_hits = self.cache_misses = 0
+
+    def _cached(self, key, build):
+        obj = self._cache.get(key)
+        if obj is not None:
+            self._cache.move_to_end(key)
+            self.cache_hits += 1
+            return obj
+        self.cache_misses += 1
+        obj = build()
+        self._cache[key] = obj
+        if len(self._cache) > self._cache_max:
+            _, old = self._cache.popitem(last=False)
+            old.destroy()
+        return obj
 
     # -- helpers -------------------------------------------------------------
     def _boundary(self, q, channel, wleg):
@@ -66,7 +93,8 @@ class GpuDMRG:
     def _merge(self, A, B):
         a, s1, b = A.legs
         _, s2, c = B.legs
-        op = lib.merge_plan(a, s1, b, s2, c)
+        op = self._cached(("merge", _lk(a), _lk(s1), _lk(b), _lk(s2), _lk(c)),
+                          lambda: lib.merge_plan(a, s1, b, s2, c))
         theta = self.torch.zeros(max(1, op.query()["out_elems"]), dtype=self.torch.float64, device=self.device)
         lib.merge(op, A.data, B.data, theta)
         return Tensor([a, s1, s2, c], theta)
@@ -82,7 +110,8 @@ class GpuDMRG:
             x, s, y = site.legs
         else:
             y, s, x = site.legs
-        op = lib.env_plan(x, s, y, self.legs[j], self.legs[j + 1], self.W_host[j], side)
+        op = self._cached(("env", j, side, _lk(x), _lk(s), _lk(y)),
+                          lambda: lib.env_plan(x, s, y, self.legs[j], self.legs[j + 1], self.W_host[j], side))
         info = op.query()
         out = self.torch.zeros(max(1, info["out_elems"]), dtype=self.torch.float64, device=self.device)
         ws = self.torch.empty(max(1, info["workspace_bytes"]), dtype=self.torch.uint8, device=self.device)
@@ -106,7 +135,7 @@ class GpuDMRG:
         a, s1, s2, c = theta.legs
         prob = {"a": a, "s1": s1, "s2": s2, "c": c, "wl": self.legs[j], "wm": self.legs[j + 1],
                 "wr": self.legs[j + 2], "w1": self.W_host[j], "w2": self.W_host[j + 1]}
-        plan = lib.Plan([prob])
+        plan = self._cached(("heff", j, _lk(a), _lk(s1), _lk(s2), _lk(c)), lambda: lib.Plan([prob]))
         if self.precision == lib.F64:
             opts = lib.eig_opts(max_iter=max_iter, tol=tol, seed=seed)
         else:
@@ -116,7 +145,6 @@ class GpuDMRG:
         e, st = lib.eigensolve(plan, self.L[j].data, self.W[j], self.W[j + 1], self.R[j + 2].data, theta.data,
                                opts, ws)
         info = plan.info()
-        plan.destroy()
         return e[0], st[0], info["flops_s1"] + info["flops_s3"]
 
     def energy_and_mpo_gradients(self, bond=0):
@@ -240,7 +268,7 @@ class GpuDMRG:
         wid_host, wid = self._identity_site(j + 1)
         prob = {"a": a, "s1": s, "s2": one, "c": c, "wl": self.legs[j], "wm": self.legs[j + 1],
                 "wr": self.legs[j + 1], "w1": self.W_host[j], "w2": wid_host}
-        plan = lib.Plan([prob])
+        plan = self._cached(("site", j, _lk(a), _lk(s), _lk(c)), lambda: lib.Plan([prob]))
         if self.precision == lib.F64:
             opts = lib.eig_opts(max_iter=max_iter, tol=tol, seed=seed)
         else:
@@ -248,7 +276,6 @@ class GpuDMRG:
                                 tol=tol, tol_f32=self.tol_f32, seed=seed)
         ws = self.torch.empty(lib.eig_workspace(plan, opts), dtype=self.torch.uint8, device=self.device)
         e, st = lib.eigensolve(plan, self.L[j].data, self.W[j], wid, self.R[j + 1].data, self.T[j].data, opts, ws)
-        plan.destroy()
         return e[0], st[0]
 
     def run_single_site(self, n_sweeps, max_iter=40, tol=1e-12, on_sweep=None):

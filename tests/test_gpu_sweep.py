@@ -200,6 +200,53 @@ def test_hubbard_cylinder_sweeps_against_ed(mods):
     assert abs(swe[-1] - e0) < 1e-9 * abs(e0)
 
 
+def test_hubbard_4x16_sweep_products_match_oracle_on_sampled_bonds(mods):
+    """Two-site sweeps of the 4x16 Hubbard cylinder (U(1)xU(1), k = 18, m up
+    to 256, the plan and op cache in use), then at two mid-chain bonds the
+    environments are rebuilt from the current site tensors on the device and
+    the library's FP64 product on those operands is compared with the
+    oracle's block loop (Alg. 2) on the same operands: 1e-12 norm-wise and
+    1e-10 per block."""
+    lib, problems, gdmrg = mods
+    from oracle.heff import heff_blocks, W_SIGNS
+    Wd, Lx = 4, 16
+    n = Wd * Lx
+    mpo = synth.hubbard_mpo(n, synth.cylinder_j1_bonds(Wd, Lx), 8.0)
+    target = (n, 0)
+    g = gdmrg.GpuDMRG(mpo, problems.initial_mps(mpo, target, 16, 0), target)
+    g.run(3, [64, 128, 256], cutoff=1e-10, max_iter=20, tol=1e-8)
+    assert g.cache_hits > 0
+    for j in (21, 40):
+        L = g.L[0]
+        for i in range(j):
+            L = g._env(L, g.T[i], i, 0)
+        R = g.R[n]
+        for i in range(n - 1, j + 1, -1):
+            R = g._env(R, g.T[i], i, 1)
+        theta = g._merge(g.T[j], g.T[j + 1])
+        a, s1, s2, c = theta.legs
+        plan = lib.Plan([{"a": a, "s1": s1, "s2": s2, "c": c, "wl": g.legs[j], "wm": g.legs[j + 1],
+                          "wr": g.legs[j + 2], "w1": g.W_host[j], "w2": g.W_host[j + 1]}])
+        out = torch.full_like(theta.data, float("nan"))
+        ws = torch.empty(plan.info()["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+        lib.heff_apply(plan, lib.F64, L.data, g.W[j], g.W[j + 1], R.data, theta.data, out, ws)
+        torch.cuda.synchronize()
+        s = g.s
+        oL = BlockTensor.unpack(L.data.cpu().numpy(), L.legs, ENV_SIGNS)
+        oR = BlockTensor.unpack(R.data.cpu().numpy(), R.legs, ENV_SIGNS)
+        oW1 = BlockTensor.unpack(g.W_host[j], [g.legs[j], s, s, g.legs[j + 1]], W_SIGNS)
+        oW2 = BlockTensor.unpack(g.W_host[j + 1], [g.legs[j + 1], s, s, g.legs[j + 2]], W_SIGNS)
+        opsi = BlockTensor.unpack(theta.data.cpu().numpy(), theta.legs, PSI_SIGNS)
+        ref = heff_blocks(oL, oW1, oW2, oR, opsi)
+        got = BlockTensor.unpack(out.cpu().numpy(), theta.legs, PSI_SIGNS)
+        print(f"bond {j}: m = {sum(d for _, d in a)} x {sum(d for _, d in c)}, {len(ref.blocks)} blocks", flush=True)
+        assert rel(got.pack(), ref.pack()) < 1e-12
+        scale = max(np.abs(v).max() for v in ref.blocks.values())
+        for k, v in ref.blocks.items():
+            assert np.abs(got.blocks[k] - v).max() <= 1e-10 * max(np.abs(v).max(), 1e-3 * scale)
+        plan.destroy()
+
+
 def test_single_site_operator_matches_oracle(mods):
     """The single-site operator L W R through the two-site plan with an
     identity second site on a one-state leg, against the oracle's direct
