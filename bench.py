@@ -48,7 +48,7 @@ HBM_PEAK = 8000.0                       # GB/s
 # bond, from rocprofv3 FETCH_SIZE and WRITE_SIZE counters of the current
 # kernel (FETCH_SIZE scaled by 1.989 and WRITE_SIZE by 1.000, the ratios of
 # the known size of a plain device copy to what the counters read for it)
-HBM_TRAFFIC = {"s1": 72457089, "s3": 93191677}
+HBM_TRAFFIC = {"s1": 73475326, "s3": 92500940}
 
 
 def parse():
@@ -65,11 +65,12 @@ def parse():
     ap.add_argument("--no-sweeps", action="store_true",
                     help="skip the 6x6 J1-J2 cylinder at m=512 (sweeps, dE/dJ2 by the adjoint and by finite "
                          "differences, FP64 vs mixed s/sweep) and the 16-site chain sweeps")
-    ap.add_argument("--workload", default="bond", choices=["bond", "j1j2-6x6", "chain16", "hubbard-4x16", "bond-m2048"],
+    ap.add_argument("--workload", default="bond", choices=["bond", "j1j2-6x6", "chain16", "hubbard-4x16", "bond-m2048", "bond-m1024-stages"],
                     help="bond: the isolated-bond product bench (default); j1j2-6x6: DMRG sweeps on the "
                          "6x6 J1-J2 cylinder, dE/dJ2 by the adjoint and by finite differences; chain16: "
                          "sweeps of the 16-site Heisenberg chain; hubbard-4x16: sweeps of the 4x16 Hubbard "
-                         "cylinder at half filling; bond-m2048: per-stage rooflines of the m=2048, k=18 bond")
+                         "cylinder at half filling; bond-m2048 / bond-m1024-stages: per-stage rooflines of the "
+                         "m=2048, k=18 bond / of the headline m=1024, k=14 bond only")
     ap.add_argument("--m-max", type=int, default=512)
     ap.add_argument("--tol", type=float, default=1e-5, help="FP64 residual of a converged solve")
     ap.add_argument("--tol-f32", type=float, default=1e-5, help="residual that ends the FP32 phase")
@@ -548,6 +549,9 @@ def main():
     if args.workload == "bond-m2048":
         print(json.dumps(large_bond_bench(args)))
         return
+    if args.workload == "bond-m1024-stages":
+        print(json.dumps(large_bond_bench(args, m=1024, k=14)))
+        return
     import torch
     import synth
     from paper_2007_05540_amd import lib, problems
@@ -628,21 +632,22 @@ def main():
     print(json.dumps(line))
 
 
-def large_bond_bench(args):
-    """The m = 2048, k = 18 bond (25 spin sectors, the largest of the batch):
-    per-stage times and MFMA rooflines of one product in both precisions."""
+def large_bond_bench(args, m=2048, k=18):
+    """An isolated spin bond (by default m = 2048, k = 18: 25 sectors, the
+    largest of the batch): per-stage times and MFMA rooflines of one product
+    in both precisions."""
     import torch
     import synth
     from paper_2007_05540_amd import lib, problems
-    spec = synth.c2_bond(m=2048, k=18, seed=1)
+    spec = synth.c2_bond(m=m, k=k, seed=1)
     prob, ops = problems.bond_problem(spec)
     plan = lib.Plan([prob])
     info = plan.info()
-    dev = {k: torch.from_numpy(v).to("cuda") for k, v in ops.items()}
+    dev = {kk: torch.from_numpy(v).to("cuda") for kk, v in ops.items()}
     del ops
     stream = torch.cuda.Stream()
     stage, roofs = stage_roofline(plan, info, dev, stream)
-    out = {"workload": "isolated two-site bond, m=2048, k=18, 25 U(1) sectors",
+    out = {"workload": f"isolated two-site bond, m={m}, k={k}, {len(spec.a_leg)} U(1) sectors",
            "useful_gflop_per_product": round((info["flops_s1"] + info["flops_s3"]) / 1e9, 3),
            "s3_split_k": info["s3_split_k"], "stage_ms": stage, "stage_roofline": roofs}
     del dev

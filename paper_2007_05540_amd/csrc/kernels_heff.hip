@@ -95,7 +95,10 @@ struct Slice {
 // segment, so a load costs no vector address arithmetic and a read past the
 // block returns zero.  Loads keep their storage type until they are written
 // to LDS, so they stay in flight across the MFMAs of the current slice.  LDS
-// holds two slices (double buffer) and each iteration has one barrier.
+// holds one slice, written after a barrier that follows the slice's MFMAs
+// (two barriers per iteration): with the half-slice operand fragments this
+// leaves room for five workgroups of 64 x 64 FP32 tiles per CU instead of
+// four, and the next slice's loads still overlap the current MFMAs.
 template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT, int TM, int NI, int NJ>
 __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask& task,
                                            const GemmSeg* __restrict__ segs, const TA* __restrict__ A,
@@ -195,25 +198,31 @@ __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask&
     constexpr int QN = BKT / 4;
     const TC* as = As + buf * SA::SIZE;
     const TC* bs = Bs + buf * SB::SIZE;
-    TC a[MI > 0 ? MI : 1][QN], b[MJ > 0 ? MJ : 1][QN];
+    // the operands of a half slice at a time (fewer registers, so five
+    // workgroups fit on a CU in FP32), the MFMAs in the same k order
+    constexpr int QH = QN / 2;
 #pragma unroll
-    for (int i = 0; i < MI; ++i)
-      if (NI >= 0 || i < ni_rt)
-#pragma unroll
-        for (int q = 0; q < QN; ++q) a[i][q] = as[SA::at(wm * WQ + i * 16 + l16, g4 * QN + q)];
-#pragma unroll
-    for (int j = 0; j < MJ; ++j)
-      if (NJ >= 0 || j < nj_rt)
-#pragma unroll
-        for (int q = 0; q < QN; ++q) b[j][q] = bs[SB::at(wn * WQ + j * 16 + l16, g4 * QN + q)];
-#pragma unroll
-    for (int q = 0; q < QN; ++q)
+    for (int q0 = 0; q0 < QN; q0 += QH) {
+      TC a[MI > 0 ? MI : 1][QH], b[MJ > 0 ? MJ : 1][QH];
 #pragma unroll
       for (int i = 0; i < MI; ++i)
+        if (NI >= 0 || i < ni_rt)
 #pragma unroll
-        for (int j = 0; j < MJ; ++j)
-          if ((NI >= 0 || i < ni_rt) && (NJ >= 0 || j < nj_rt))
-            acc[i][j] = Mfma<TC>::op(a[i][q], b[j][q], acc[i][j]);
+          for (int q = 0; q < QH; ++q) a[i][q] = as[SA::at(wm * WQ + i * 16 + l16, g4 * QN + q0 + q)];
+#pragma unroll
+      for (int j = 0; j < MJ; ++j)
+        if (NJ >= 0 || j < nj_rt)
+#pragma unroll
+          for (int q = 0; q < QH; ++q) b[j][q] = bs[SB::at(wn * WQ + j * 16 + l16, g4 * QN + q0 + q)];
+#pragma unroll
+      for (int q = 0; q < QH; ++q)
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < MJ; ++j)
+            if ((NI >= 0 || i < ni_rt) && (NJ >= 0 || j < nj_rt))
+              acc[i][j] = Mfma<TC>::op(a[i][q], b[j][q], acc[i][j]);
+    }
   };
 
   int seg = task.seg0;
@@ -244,9 +253,10 @@ __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask&
     if (have) load(s, k0);
     compute(buf);
     if (have) {
-      store(buf ^ 1);
+      // one LDS slice: every wave has read it before the next is stored
       __syncthreads();
-      buf ^= 1;
+      store(buf);
+      __syncthreads();
     }
   }
 
@@ -277,8 +287,8 @@ __global__ __launch_bounds__(NTHR) void ggemm_kernel(const GemmTile* __restrict_
                                                      const TB* __restrict__ B,
                                                      TO* __restrict__ C, TO* __restrict__ Cpart) {
   constexpr int TMX = BIG ? 128 : 64;
-  __shared__ TC As[2 * Slice<TC, !AT, TMX>::SIZE];
-  __shared__ TC Bs[2 * Slice<TC, BT, TMX>::SIZE];
+  __shared__ TC As[Slice<TC, !AT, TMX>::SIZE];
+  __shared__ TC Bs[Slice<TC, BT, TMX>::SIZE];
   const GemmTile tile = tiles[blockIdx.x];
   if (tile.task < 0) return;   // padding of the per-XCD schedule
   const GemmTask task = tasks[tile.task];
