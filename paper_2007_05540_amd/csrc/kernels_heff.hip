@@ -280,7 +280,7 @@ __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask&
 // with BIG, 128 x 128 (shape 1, each wave a 64 x 64 quarter: half the LDS
 // and global traffic per flop, for large blocks).
 template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT, bool BIG>
-__global__ __launch_bounds__(NTHR) void ggemm_kernel(const GemmTile* __restrict__ tiles,
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(BIG || sizeof(TC) == 4 ? 1 : 5))) void ggemm_kernel(const GemmTile* __restrict__ tiles,
                                                      const GemmTask* __restrict__ tasks,
                                                      const GemmSeg* __restrict__ segs,
                                                      const TA* __restrict__ A,
