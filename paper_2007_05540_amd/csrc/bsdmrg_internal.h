@@ -237,6 +237,7 @@ struct bsdmrg_plan_s {
   std::vector<bsd::MixTerm> mix_terms;
   std::vector<bsd::MixItem> mix_items;
   std::vector<int32_t> mix_item_group;   // per item: the (problem, a', c) group whose T1 blocks it reads (host)
+  int32_t mix_per = 16;                  // outputs per thread of the S2 and split-K-sum launches (8 or 16)
   int32_t n_mix_groups = 0;
   std::vector<int32_t> coef_ptr;     // CSR over coefficient pairs
   std::vector<int64_t> coef_e1, coef_e2;

@@ -138,7 +138,7 @@ void validate_gemm(const Stage& st, int layout, int64_t a_elems, int64_t b_elems
                    int64_t cpart_elems, const char* name);
 void validate_mix(const std::vector<MixTask>& tasks, const std::vector<MixTerm>& terms,
                   const std::vector<MixItem>& items, int64_t src_elems, int64_t dst_elems, int64_t coef_elems,
-                  const char* name);
+                  const char* name, int64_t item_max = 4096);
 void validate_copy(const std::vector<CopyTask>& tasks, int64_t src_elems, int64_t dst_elems, int64_t fac_elems,
                    const char* name);
 void validate_heff_plan(const bsdmrg_plan_s* P);

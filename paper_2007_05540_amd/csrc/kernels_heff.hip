@@ -563,13 +563,12 @@ __global__ __launch_bounds__(NTHR) void pgemm_kernel(const int32_t* __restrict__
 // from the term's block base (scalar registers) plus a 32-bit byte offset
 // (source blocks below 2^29 elements: checked on the host).
 // coef == nullptr means unit coefficients (the split-K reduction).
-template <typename T, typename TACC>
+template <typename T, typename TACC, int PER>
 __global__ __launch_bounds__(NTHR) void mix_kernel(const MixItem* __restrict__ items,
                                                    const MixTask* __restrict__ tasks,
                                                    const MixTerm* __restrict__ terms,
                                                    const double* __restrict__ coef,
                                                    const T* __restrict__ src, T* __restrict__ dst) {
-  constexpr int PER = 16;   // kMixItemElems = 4096 = 16 * 256
   const MixItem it = items[blockIdx.x];
   const MixTask t = tasks[it.task];
   const int n = it.nrows * t.cols;
@@ -681,15 +680,19 @@ hipError_t launch_gemm_f64(const Stage& st, int layout, const double* A, const d
 hipError_t launch_mix_tables(const MixItem* items, size_t n_items, const MixTask* tasks, const MixTerm* terms,
                              const double* coef, const double* src, double* dst, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL((mix_kernel<double, double>), dim3((unsigned)n_items), dim3(NTHR), 0, s, items, tasks,
+  hipLaunchKernelGGL((mix_kernel<double, double, 16>), dim3((unsigned)n_items), dim3(NTHR), 0, s, items, tasks,
                      terms, coef, src, dst);
   return hipGetLastError();
 }
 
 hipError_t launch_s3_reduce(const bsdmrg_plan_s* P, const double* part, double* out, hipStream_t s) {
   if (P->red_items.empty()) return hipSuccess;
-  hipLaunchKernelGGL((mix_kernel<double, double>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
-                     P->d_red_items, P->d_red_tasks, P->d_red_terms, (const double*)nullptr, part, out);
+  if (P->mix_per == 8)
+    hipLaunchKernelGGL((mix_kernel<double, double, 8>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
+                       P->d_red_items, P->d_red_tasks, P->d_red_terms, (const double*)nullptr, part, out);
+  else
+    hipLaunchKernelGGL((mix_kernel<double, double, 16>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
+                       P->d_red_items, P->d_red_tasks, P->d_red_terms, (const double*)nullptr, part, out);
   return hipGetLastError();
 }
 
@@ -725,15 +728,23 @@ hipError_t launch_s3_gemm_f32(const bsdmrg_plan_s* P, const float* T2, const flo
 hipError_t launch_mix_f64(const bsdmrg_plan_s* P, const double* coef, const double* T1, double* T2,
                           hipStream_t s) {
   if (P->mix_items.empty()) return hipSuccess;
-  hipLaunchKernelGGL((mix_kernel<double, double>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
-                     P->d_mix_items, P->d_mix_tasks, P->d_mix_terms, coef, T1, T2);
+  if (P->mix_per == 8)
+    hipLaunchKernelGGL((mix_kernel<double, double, 8>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
+                       P->d_mix_items, P->d_mix_tasks, P->d_mix_terms, coef, T1, T2);
+  else
+    hipLaunchKernelGGL((mix_kernel<double, double, 16>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
+                       P->d_mix_items, P->d_mix_tasks, P->d_mix_terms, coef, T1, T2);
   return hipGetLastError();
 }
 hipError_t launch_mix_f32(const bsdmrg_plan_s* P, const double* coef, const float* T1, float* T2,
                           hipStream_t s) {
   if (P->mix_items.empty()) return hipSuccess;
-  hipLaunchKernelGGL((mix_kernel<float, float>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
-                     P->d_mix_items, P->d_mix_tasks, P->d_mix_terms, coef, T1, T2);
+  if (P->mix_per == 8)
+    hipLaunchKernelGGL((mix_kernel<float, float, 8>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
+                       P->d_mix_items, P->d_mix_tasks, P->d_mix_terms, coef, T1, T2);
+  else
+    hipLaunchKernelGGL((mix_kernel<float, float, 16>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
+                       P->d_mix_items, P->d_mix_tasks, P->d_mix_terms, coef, T1, T2);
   return hipGetLastError();
 }
 

@@ -243,7 +243,8 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
             // terms (their loads come in rounds of two terms), so that no
             // workgroup runs much longer than the others
             const int64_t rounds = std::max<int64_t>(1, (mt.nterm + 1) / 2);
-            int rows_per = std::max<int64_t>(1, kMixItemElems / std::max<int64_t>(1, bc * rounds));
+            const int64_t item_elems = (int64_t)P->mix_per * 256;
+            int rows_per = std::max<int64_t>(1, item_elems / std::max<int64_t>(1, bc * rounds));
             auto gi = group_of.emplace(std::make_pair(iap, ic), (int32_t)(P->n_mix_groups + group_of.size())).first;
             for (int r0 = 0; r0 < ba; r0 += rows_per) {
               P->mix_items.push_back(MixItem{task, r0, (int32_t)std::min<int64_t>(rows_per, ba - r0), 0});
@@ -372,8 +373,9 @@ static void split_k(bsdmrg_plan_s* P) {
     return std::max(1, item / std::max(1, r.cols * std::max(1, (r.nterm + 1) / 2)));
   };
   int64_t n_big = 0;
-  for (const MixTask& r : P->red_tasks) n_big += (r.rows + rows_per(r, kMixItemElems) - 1) / rows_per(r, kMixItemElems);
-  const int item = n_big < kMinRedItems ? kRedItemSmall : kMixItemElems;
+  const int big = P->mix_per * 256;
+  for (const MixTask& r : P->red_tasks) n_big += (r.rows + rows_per(r, big) - 1) / rows_per(r, big);
+  const int item = n_big < kMinRedItems ? std::min(kRedItemSmall, big) : big;
   for (int task = 0; task < (int)P->red_tasks.size(); ++task) {
     const MixTask& r = P->red_tasks[task];
     const int rp = rows_per(r, item);
@@ -444,6 +446,12 @@ bsdmrg_plan_s* build_plan(const bsdmrg_problem* probs, int n_probs) {
   try {
     P->probs.resize(n_probs);
     P->coef_ptr.push_back(0);
+    // S2 and the split-K sums work on rows of c-sector width: eight outputs
+    // per thread (items of up to 2048) when every row fits, else sixteen
+    int64_t widest = 0;
+    for (int i = 0; i < n_probs; ++i)
+      for (auto d : leg_from(probs[i].c).d) widest = std::max<int64_t>(widest, d);
+    P->mix_per = widest <= 2048 ? 8 : 16;
     for (int i = 0; i < n_probs; ++i) plan_problem(P, i, probs[i]);
     split_k(P);
     order_mix_items(P);

@@ -95,7 +95,7 @@ void validate_ptiles(const Stage& st, const char* name) {
 
 void validate_mix(const std::vector<MixTask>& tasks, const std::vector<MixTerm>& terms,
                   const std::vector<MixItem>& items, int64_t src_elems, int64_t dst_elems, int64_t coef_elems,
-                  const char* name) {
+                  const char* name, int64_t item_max) {
   for (const MixTask& t : tasks) {
     if (t.rows < 1 || t.cols < 1 || t.cols > t.ld_dst || t.dst_off < 0 ||
         t.dst_off + (int64_t)(t.rows - 1) * t.ld_dst + t.cols > dst_elems)
@@ -114,7 +114,7 @@ void validate_mix(const std::vector<MixTask>& tasks, const std::vector<MixTerm>&
   for (const MixItem& it : items) {
     if (it.task < 0 || it.task >= (int64_t)tasks.size()) fail(std::string(name) + ": item task");
     const MixTask& t = tasks[it.task];
-    if (it.row0 < 0 || it.nrows < 1 || it.row0 + it.nrows > t.rows || (int64_t)it.nrows * t.cols > 4096)
+    if (it.row0 < 0 || it.nrows < 1 || it.row0 + it.nrows > t.rows || (int64_t)it.nrows * t.cols > item_max)
       fail(std::string(name) + ": item rows");
   }
 }
@@ -135,8 +135,11 @@ void validate_copy(const std::vector<CopyTask>& tasks, int64_t src_elems, int64_
 void validate_heff_plan(const bsdmrg_plan_s* P) {
   validate_gemm(P->s1, kNN, P->L_elems, P->psi_elems, P->t1_elems, 0, "S1");
   validate_gemm(P->s3, kNT, P->t2_elems, P->R_elems, P->psi_elems, P->s3_part_elems, "S3");
-  validate_mix(P->mix_tasks, P->mix_terms, P->mix_items, P->t1_elems, P->t2_elems, P->n_coefs, "S2");
-  validate_mix(P->red_tasks, P->red_terms, P->red_items, P->s3_part_elems, P->psi_elems, -1, "S3 reduce");
+  // the launches of S2 and of the split-K sums process 256 * mix_per outputs per workgroup
+  validate_mix(P->mix_tasks, P->mix_terms, P->mix_items, P->t1_elems, P->t2_elems, P->n_coefs, "S2",
+               256 * P->mix_per);
+  validate_mix(P->red_tasks, P->red_terms, P->red_items, P->s3_part_elems, P->psi_elems, -1, "S3 reduce",
+               256 * P->mix_per);
   for (size_t i = 0; i + 1 < P->coef_ptr.size(); ++i)
     for (int32_t k = P->coef_ptr[i]; k < P->coef_ptr[i + 1]; ++k)
       if (P->coef_e1[k] < 0 || P->coef_e1[k] >= P->W1_elems || P->coef_e2[k] < 0 || P->coef_e2[k] >= P->W2_elems)

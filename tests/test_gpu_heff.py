@@ -286,6 +286,28 @@ def test_tile_shape_classes_bit_identical_and_autotune(mods, spec_fn):
     assert e1[0] == e2[0]
 
 
+def test_sector_wider_than_2048_matches_oracle(mods):
+    """A right bond leg with one 2100-wide sector: the S2 and split-K-sum
+    launches then take 16 outputs per thread (items of up to 4096) instead of
+    8; the product equals the oracle in FP64 (1e-12) and FP32 (1e-5)."""
+    lib, problems = mods
+    from synth.blocks import BondSpec, synthetic_heisenberg_bond
+    a = [((-2,), 5), ((0,), 6), ((2,), 5)]
+    c = [((0,), 2100)]
+    spec = BondSpec(a, c, synthetic_heisenberg_bond(14, 5), 5, name="wide sector")
+    prob, ops = problems.bond_problem(spec)
+    plan = lib.Plan([prob])
+    d = {k: dev(v) for k, v in ops.items()}
+    ws = torch.empty(plan.info()["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    ref = oracle_apply(spec)
+    for precision, tol in ((lib.F64, 1e-12), (lib.F32, 1e-5)):
+        out = torch.zeros_like(d["psi"])   # the product does not write the padding
+        lib.heff_apply(plan, precision, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws)
+        torch.cuda.synchronize()
+        assert rel(out.cpu().numpy(), ref) < tol
+    plan.destroy()
+
+
 @pytest.mark.parametrize("m", [96, 150])
 def test_dense_format_ablation_matches_oracle(mods, m):
     """The sparse-dense format (every operand one dense array, the product
