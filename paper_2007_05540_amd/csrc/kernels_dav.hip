@@ -201,10 +201,11 @@ __device__ __forceinline__ void load_rows(double (*A)[kMaxBasis + 1], const doub
 // Householder tridiagonalisation of the leading n x n block of A (n <= R)
 // with row r held in the registers of lane r; the Householder vectors go to
 // Vh, the diagonal and off-diagonal of T to d and e.  The vector and its
-// image are broadcast with lane reads.
+// image are broadcast through LDS (Vh and the scratch row ws): every lane
+// reads all entries, the reads of a step issued together.  Run by one wave.
 template <int R>
 __device__ __forceinline__ void tridiag_in_registers(const double (*A)[kMaxBasis + 1], double (*Vh)[kMaxBasis],
-                                                     double* d, double* e, int n, int lane) {
+                                                     double* d, double* e, double* ws, int n, int lane) {
   double ar[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) ar[c] = (lane < n && c < n) ? A[lane][c] : 0.0;
@@ -225,20 +226,28 @@ __device__ __forceinline__ void tridiag_in_registers(const double (*A)[kMaxBasis
         e[k] = alpha;
       }
       if (vn2 > 0.0) {
+        wave_sync();   // Vh[k] complete before it is read back
         // p = A v over the trailing columns (zero past n on both sides)
         double vc[R];
         double p0 = 0.0, p1 = 0.0;
 #pragma unroll
+        for (int c = k + 1; c < R; ++c) vc[c] = Vh[k][c];
+#pragma unroll
         for (int c = k + 1; c < R; ++c) {
-          vc[c] = readlane_d(vr, c);
           if ((c - k) & 1) p0 += ar[c] * vc[c];
           else p1 += ar[c] * vc[c];
         }
         const double pr = mine ? p0 + p1 : 0.0;
         const double beta = wave_total(vr * pr);
         const double wr = pr - beta * vr;
+        ws[lane] = wr;
+        wave_sync();
+        double wc[R];
 #pragma unroll
-        for (int c = k + 1; c < R; ++c) ar[c] -= 2.0 * (vr * readlane_d(wr, c) + wr * vc[c]);
+        for (int c = k + 1; c < R; ++c) wc[c] = ws[c];
+#pragma unroll
+        for (int c = k + 1; c < R; ++c) ar[c] -= 2.0 * (vr * wc[c] + wr * vc[c]);
+        wave_sync();   // ws read by every lane before the next step writes it
       }
     }
   }
@@ -266,13 +275,13 @@ __device__ __forceinline__ void tridiag_in_registers(const double (*A)[kMaxBasis
 // (lane r owns row r, so no step needs more than a wave-level reduction):
 //  1. Householder tridiagonalisation T = Q^T M Q, Q = H_0 ... H_{n-3},
 //     H_k = I - 2 v_k v_k^T;
-//  2. the lowest eigenvalue of T by multisection on Sturm counts: each round
-//     the 64 lanes test 64 equally spaced shifts inside the current bracket
-//     (initially the Gershgorin interval) and the bracket shrinks 65-fold,
-//     until its width is 4 eps of the eigenvalue's magnitude;
-//  3. its eigenvector by two steps of inverse iteration with
-//     (T - lambda I) / ||T|| (tridiagonal Gaussian elimination with partial
-//     pivoting, a pivot below eps replaced by eps);
+//  2. the lowest eigenvalue of T by multisection on Sturm counts: the
+//     bracket starts as the Gershgorin interval, one round of 64 shifts
+//     spaced geometrically around the previous step's eigenvalue narrows it
+//     (from the second step of a solve on), then each round the 64 lanes
+//     test 64 equally spaced shifts inside it and it shrinks 65-fold, until
+//     its width is 4 eps of the eigenvalue's magnitude;
+//  3. its eigenvector by the twisted factorisation of T - lambda I;
 //  4. back-transformation x = Q y.
 __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, const double* __restrict__ red,
                                                       double* __restrict__ M, double* __restrict__ svec,
@@ -283,6 +292,9 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
   const int p = blockIdx.x, lane = threadIdx.x, n = i + 1;
   double* Mp = M + (int64_t)p * B * B;
   const double* rp = red + (int64_t)p * ldr;
+  // the previous step's eigenvalue (written by this kernel's previous call in
+  // the same solve; the first call of a solve has i = 0)
+  const double lam_prev = i > 0 ? lam[p] : 0.0;
   // the previous step's Ritz vector in the coordinates of the grown basis
   // (its new last coordinate is 0); read before svec is overwritten below
   if (svec_prev && lane <= i) svec_prev[(int64_t)p * B + lane] = lane < i ? svec[(int64_t)p * B + lane] : 0.0;
@@ -305,9 +317,9 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
   // 16 or 32 rows the row is held in registers (tridiag_in_registers);
   // larger matrices stay in LDS.
   if (n <= 16) {
-    tridiag_in_registers<16>(A, Vh, d, e, n, lane);
+    tridiag_in_registers<16>(A, Vh, d, e, vb, n, lane);
   } else if (n <= 32) {
-    tridiag_in_registers<32>(A, Vh, d, e, n, lane);
+    tridiag_in_registers<32>(A, Vh, d, e, vb, n, lane);
   } else {
     for (int k = 0; k + 2 < n; ++k) {
       const bool mine = lane > k && lane < n;
@@ -379,10 +391,8 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
   // squared off-diagonal in LDS once (the Sturm recurrence reads it every round)
   if (lane + 1 < n) wb[lane] = e[lane] * e[lane];
   wave_sync();
-  for (int round = 0; round < 24; ++round) {
-    const double width = hi - lo;
-    if (!(width > 4.0 * eps * fmax(fabs(lo), fabs(hi))) || width <= pivmin) break;
-    const double sigma = lo + width * (double)(lane + 1) / (double)(GT + 1);
+  // number of eigenvalues of T below sigma (Sturm count of the LDL^T pivots)
+  auto count_below = [&](double sigma) {
     int cnt = 0;
     double q = d[0] - sigma;
     if (fabs(q) < pivmin) q = -pivmin;
@@ -398,6 +408,31 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
       if (fabs(q) < pivmin) q = -pivmin;
       cnt += q < 0.0;
     }
+    return cnt;
+  };
+  // a first round of 64 shifts spaced geometrically on both sides of the
+  // previous step's eigenvalue (distances 4^-24 .. 4^7 of its magnitude):
+  // the lowest eigenvalue moves little from step to step, so the bracket
+  // usually shrinks to a few times that move at once.  Only a guess: the
+  // bracket keeps count(lo) = 0 and count(hi) >= 1 whatever it finds.
+  if (i > 0 && isfinite(lam_prev)) {
+    const double scale = fmax(fabs(lam_prev), 1e-3 * tn);
+    const double off = scale * exp2(2.0 * (double)(lane < 32 ? 7 - lane : lane - 56));
+    const double sigma = lane < 32 ? lam_prev - off : lam_prev + off;   // ascending in the lane
+    const unsigned long long below = __ballot(count_below(sigma) >= 1);
+    if (below) {
+      const int first = __ffsll((long long)below) - 1;
+      hi = fmin(hi, readlane_d(sigma, first));
+      if (first > 0) lo = fmax(lo, readlane_d(sigma, first - 1));
+    } else {
+      lo = fmax(lo, readlane_d(sigma, GT - 1));
+    }
+  }
+  for (int round = 0; round < 24; ++round) {
+    const double width = hi - lo;
+    if (!(width > 4.0 * eps * fmax(fabs(lo), fabs(hi))) || width <= pivmin) break;
+    const double sigma = lo + width * (double)(lane + 1) / (double)(GT + 1);
+    const int cnt = count_below(sigma);
     const unsigned long long below = __ballot(cnt >= 1);   // shifts with an eigenvalue below them
     if (below) {
       const int first = __ffsll((long long)below) - 1;
@@ -415,41 +450,44 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
   // (forward) and = U- D- U-^T (backward), the twist index r where
   // |gamma_r| = |D+_r + D-_r - (d_r - lambda)| is smallest, z_r = 1 and the
   // other entries by the two recurrences outward from r.  The recurrences
-  // are sequential: every lane runs them on the same (uniform) values, with
-  // the arrays held one element per lane (read and written with lane
-  // operations).  A pivot of magnitude below pivmin is replaced by -pivmin
-  // (as in the Sturm counts); the reciprocals use the hardware reciprocal
-  // refined by one Newton step.
-  const double dv = lane < n ? d[lane] - lambda : 0.0;           // d_k - lambda
-  const double e2v = lane + 1 < n ? wb[lane] : 0.0;              // e_k^2
-  const double ev = lane + 1 < n ? e[lane] : 0.0;                // e_k
+  // are sequential: every lane runs them on the same (uniform) values read
+  // from LDS (d, e, and e^2 in wb), and lane 0 stores the pivots and the
+  // entries to scratch rows of A (free after the tridiagonalisation).  A
+  // pivot of magnitude below pivmin is replaced by -pivmin (as in the Sturm
+  // counts); the reciprocals use the hardware reciprocal refined by one
+  // Newton step.
   auto recip = [](double q) {
     double r = __builtin_amdgcn_rcp(q);
     return fma(r, fma(-q, r, 1.0), r);
   };
+  double* Dp = A[0];
+  double* Dm = A[1];
+  double* Y = A[2];
   double yv;
   if (!(tn > 0.0) || n == 1) {   // T = 0 or 1 x 1: a unit vector is an eigenvector
     yv = lane == 0 ? 1.0 : 0.0;
   } else {
-    double dpv = 0.0, dmv = 0.0;   // D+_k and D-_k in lane k
-    double cur = readlane_d(dv, 0);
+    double cur = d[0] - lambda;
     if (fabs(cur) < pivmin) cur = -pivmin;
-    dpv = writelane(cur, 0, dpv);
+    if (lane == 0) Dp[0] = cur;
+#pragma unroll 4
     for (int k = 0; k + 1 < n; ++k) {
-      cur = readlane_d(dv, k + 1) - readlane_d(e2v, k) * recip(cur);
+      cur = (d[k + 1] - lambda) - wb[k] * recip(cur);
       if (fabs(cur) < pivmin) cur = -pivmin;
-      dpv = writelane(cur, k + 1, dpv);
+      if (lane == 0) Dp[k + 1] = cur;
     }
-    cur = readlane_d(dv, n - 1);
+    cur = d[n - 1] - lambda;
     if (fabs(cur) < pivmin) cur = -pivmin;
-    dmv = writelane(cur, n - 1, dmv);
+    if (lane == 0) Dm[n - 1] = cur;
+#pragma unroll 4
     for (int k = n - 2; k >= 0; --k) {
-      cur = readlane_d(dv, k) - readlane_d(e2v, k) * recip(cur);
+      cur = (d[k] - lambda) - wb[k] * recip(cur);
       if (fabs(cur) < pivmin) cur = -pivmin;
-      dmv = writelane(cur, k, dmv);
+      if (lane == 0) Dm[k] = cur;
     }
+    wave_sync();
     // twist index: the smallest |gamma_k| (the lowest k among equal ones)
-    double g = lane < n ? fabs(dpv + dmv - dv) : 1e308;
+    double g = lane < n ? fabs(Dp[lane] + Dm[lane] - (d[lane] - lambda)) : 1e308;
     int r = lane;
     for (int o = 32; o > 0; o >>= 1) {
       const double go = __shfl_xor(g, o, 64);
@@ -460,17 +498,19 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
       }
     }
     // z_r = 1; z_k = -(e_k / D+_k) z_{k+1} below r; z_{k+1} = -(e_k / D-_{k+1}) z_k above r
-    yv = lane == r ? 1.0 : 0.0;
+    if (lane == 0) Y[r] = 1.0;
     double z = 1.0;
     for (int k = r - 1; k >= 0; --k) {
-      z = -readlane_d(ev, k) * recip(readlane_d(dpv, k)) * z;
-      yv = writelane(z, k, yv);
+      z = -e[k] * recip(Dp[k]) * z;
+      if (lane == 0) Y[k] = z;
     }
     z = 1.0;
     for (int k = r; k + 1 < n; ++k) {
-      z = -readlane_d(ev, k) * recip(readlane_d(dmv, k + 1)) * z;
-      yv = writelane(z, k + 1, yv);
+      z = -e[k] * recip(Dm[k + 1]) * z;
+      if (lane == 0) Y[k + 1] = z;
     }
+    wave_sync();
+    yv = lane < n ? Y[lane] : 0.0;
     // unit length; the sign that makes the entries sum to a positive value
     // (the sign inverse iteration from the constant vector would give)
     const double nrm = sqrt(wave_total(yv * yv));
