@@ -183,83 +183,108 @@ constexpr int kMaxBasis = 64;
 constexpr int GT = 64;   // one wave
 
 // A[r][c] = Mp[r * B + c] for r, c < n (lane r loads row r; the loads of a
-// group of eight are issued before any of them is stored).
+// group of G are issued before any of them is stored).
+template <int G>
 __device__ __forceinline__ void load_rows(double (*A)[kMaxBasis + 1], const double* __restrict__ Mp, int B, int n,
                                           int lane) {
   if (lane >= n) return;
   const double* row = Mp + (int64_t)lane * B;
-  for (int c0 = 0; c0 < n; c0 += 8) {
-    double t[8];
+  for (int c0 = 0; c0 < n; c0 += G) {
+    double t[G];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) t[u] = c0 + u < n ? row[c0 + u] : 0.0;
+    for (int u = 0; u < G; ++u) t[u] = c0 + u < n ? row[c0 + u] : 0.0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < G; ++u)
       if (c0 + u < n) A[lane][c0 + u] = t[u];
   }
 }
 
-// Householder tridiagonalisation of the leading n x n block of A (n <= R)
-// with row r held in the registers of lane r; the Householder vectors go to
-// Vh, the diagonal and off-diagonal of T to d and e.  The vector and its
-// image are broadcast through LDS (Vh and the scratch row ws): every lane
-// reads all entries, the reads of a step issued together.  Run by one wave.
+// Householder tridiagonalisation of the leading n x n block of A (n <= R,
+// R = 16 or 32) held in registers: row r is split over LPR = 64 / R lanes
+// (lanes r * LPR .. r * LPR + LPR - 1), lane r * LPR + q holding columns
+// q * C .. q * C + C - 1 (C = R / LPR), so all 64 lanes share the products.
+// Step k: the reflector v (zero in entries 0..k) from column k below the
+// diagonal, p = A v (partial sums over a lane's columns, added across the
+// row's lanes in one fixed order), beta = v^T p, w = p - beta v and the
+// rank-2 update A -= 2 (v w^T + w v^T); v and w reach every lane through LDS
+// (Vh and the scratch row ws).  The Householder vectors go to Vh (entries of
+// rows R..63 are not written), the diagonal and off-diagonal of T to d and e.
+// Run by one wave.
 template <int R>
 __device__ __forceinline__ void tridiag_in_registers(const double (*A)[kMaxBasis + 1], double (*Vh)[kMaxBasis],
                                                      double* d, double* e, double* ws, int n, int lane) {
-  double ar[R];
+  constexpr int LPR = 64 / R, C = R / LPR;
+  static_assert(LPR == 2 || LPR == 4, "rows split over two or four lanes");
+  const int row = lane / LPR, q = lane % LPR;
+  double ar[C];
 #pragma unroll
-  for (int c = 0; c < R; ++c) ar[c] = (lane < n && c < n) ? A[lane][c] : 0.0;
+  for (int t = 0; t < C; ++t) {
+    const int c = q * C + t;
+    ar[t] = (row < n && c < n) ? A[row][c] : 0.0;
+  }
 #pragma unroll
   for (int k = 0; k + 2 < R; ++k) {
     if (k + 2 < n) {
-      const bool mine = lane > k && lane < n;
-      const double xr = mine ? ar[k] : 0.0;
-      const double nrm2 = wave_total(xr * xr);
-      const double x0 = readlane_d(ar[k], k + 1);
+      const int qk = k / C, tk = k % C;   // owner lane (within the row) and register of column k
+      // x_row = A[row][k] on every lane of the row
+      double xk = ar[tk];
+      if (LPR == 4) {
+        if (qk == 0) xk = mov_dpp_d<0x00>(xk);
+        else if (qk == 1) xk = mov_dpp_d<0x55>(xk);
+        else if (qk == 2) xk = mov_dpp_d<0xAA>(xk);
+        else xk = mov_dpp_d<0xFF>(xk);
+      } else {
+        if (qk == 0) xk = mov_dpp_d<0xA0>(xk);   // quad_perm [0,0,2,2]
+        else xk = mov_dpp_d<0xF5>(xk);           // quad_perm [1,1,3,3]
+      }
+      const bool mine = row > k && row < n;
+      const double xr = mine ? xk : 0.0;
+      const double nrm2 = wave_total(q == 0 ? xr * xr : 0.0);
+      const double x0 = readlane_d(xk, (k + 1) * LPR);
       const double alpha = nrm2 > 0.0 ? -copysign(sqrt(nrm2), x0) : 0.0;
       const double vn2 = 2.0 * (nrm2 - alpha * x0);   // ||x - alpha e_{k+1}||^2
-      const double vr = vn2 > 0.0 ? (xr - (lane == k + 1 ? alpha : 0.0)) / sqrt(vn2) : 0.0;
-      Vh[k][lane] = vr;
-      const double dk = readlane_d(ar[k], k);
+      const double vr = vn2 > 0.0 ? (xr - (row == k + 1 ? alpha : 0.0)) / sqrt(vn2) : 0.0;
+      if (q == 0) Vh[k][row] = vr;
+      const double dk = readlane_d(ar[tk], k * LPR + qk);
       if (lane == 0) {
         d[k] = dk;
         e[k] = alpha;
       }
       if (vn2 > 0.0) {
         wave_sync();   // Vh[k] complete before it is read back
-        // p = A v over the trailing columns (zero past n on both sides)
-        double vc[R];
-        double p0 = 0.0, p1 = 0.0;
+        // v is zero in entries 0..k, so columns up to k add nothing
+        double vc[C];
+        double pp = 0.0;
 #pragma unroll
-        for (int c = k + 1; c < R; ++c) vc[c] = Vh[k][c];
+        for (int t = 0; t < C; ++t) vc[t] = Vh[k][q * C + t];
 #pragma unroll
-        for (int c = k + 1; c < R; ++c) {
-          if ((c - k) & 1) p0 += ar[c] * vc[c];
-          else p1 += ar[c] * vc[c];
-        }
-        const double pr = mine ? p0 + p1 : 0.0;
-        const double beta = wave_total(vr * pr);
+        for (int t = 0; t < C; ++t) pp += ar[t] * vc[t];
+        pp += mov_dpp_d<0xB1>(pp);                  // lane ^ 1
+        if (LPR == 4) pp += mov_dpp_d<0x4E>(pp);    // lane ^ 2
+        const double pr = mine ? pp : 0.0;
+        const double beta = wave_total(q == 0 ? vr * pr : 0.0);
         const double wr = pr - beta * vr;
-        ws[lane] = wr;
+        if (q == 0) ws[row] = wr;
         wave_sync();
-        double wc[R];
+        double wc[C];
 #pragma unroll
-        for (int c = k + 1; c < R; ++c) wc[c] = ws[c];
+        for (int t = 0; t < C; ++t) wc[t] = ws[q * C + t];
 #pragma unroll
-        for (int c = k + 1; c < R; ++c) ar[c] -= 2.0 * (vr * wc[c] + wr * vc[c]);
+        for (int t = 0; t < C; ++t) ar[t] -= 2.0 * (vr * wc[t] + wr * vc[t]);
         wave_sync();   // ws read by every lane before the next step writes it
       }
     }
   }
-  // the last 2 x 2 block
+  // the last 2 x 2 block: element (r, c) is register c % C of lane r * LPR + c / C
   double dl = 0.0, dm = 0.0, el = 0.0;
+  const int c0 = n - 2, c1 = n - 1;
 #pragma unroll
-  for (int c = 0; c < R; ++c) {
-    if (c == n - 2) {
-      dl = readlane_d(ar[c], c);
-      el = readlane_d(ar[c], c + 1);
+  for (int t = 0; t < C; ++t) {
+    if (c0 >= 0 && c0 % C == t) {
+      dl = readlane_d(ar[t], c0 * LPR + c0 / C);
+      el = readlane_d(ar[t], c1 * LPR + c0 / C);
     }
-    if (c == n - 1) dm = readlane_d(ar[c], c);
+    if (c1 % C == t) dm = readlane_d(ar[t], c1 * LPR + c1 / C);
   }
   if (lane == 0) {
     if (n >= 2) {
@@ -270,9 +295,11 @@ __device__ __forceinline__ void tridiag_in_registers(const double (*A)[kMaxBasis
   }
 }
 
-// Gram row m_ij = m_ji = (v^A_j)^T v_i (j <= i) from the chunk partials, then
-// the lowest eigenpair of the (i+1) x (i+1) projected matrix M, in one wave
-// (lane r owns row r, so no step needs more than a wave-level reduction):
+// Gram row m_ij = m_ji = (v^A_j)^T v_i (j <= i) from the chunk partials (all
+// GE_T threads: wave w sums columns w, w + 16, ... over the problem's chunks,
+// each lane a chunk stride of 64 in chunk order, then the wave sum), then
+// the lowest eigenpair of the (i+1) x (i+1) projected matrix M in the first
+// wave (no step needs more than a wave-level reduction):
 //  1. Householder tridiagonalisation T = Q^T M Q, Q = H_0 ... H_{n-3},
 //     H_k = I - 2 v_k v_k^T;
 //  2. the lowest eigenvalue of T by multisection on Sturm counts: the
@@ -283,34 +310,68 @@ __device__ __forceinline__ void tridiag_in_registers(const double (*A)[kMaxBasis
 //     its width is 4 eps of the eigenvalue's magnitude;
 //  3. its eigenvector by the twisted factorisation of T - lambda I;
 //  4. back-transformation x = Q y.
-__global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, const double* __restrict__ red,
-                                                      double* __restrict__ M, double* __restrict__ svec,
-                                                      double* __restrict__ lam, double* __restrict__ svec_prev) {
+constexpr int GE_T = 1024;
+__global__ __launch_bounds__(GE_T) void gram_eig_kernel(const DavProb* __restrict__ probs, int nct,
+                                                        const double* __restrict__ part, int i, int B,
+                                                        double* __restrict__ M, double* __restrict__ svec,
+                                                        double* __restrict__ lam, double* __restrict__ svec_prev) {
   __shared__ double A[kMaxBasis][kMaxBasis + 1];
   __shared__ double Vh[kMaxBasis][kMaxBasis];
-  __shared__ double d[kMaxBasis], e[kMaxBasis], vb[kMaxBasis], wb[kMaxBasis];
-  const int p = blockIdx.x, lane = threadIdx.x, n = i + 1;
+  __shared__ double d[kMaxBasis], e[kMaxBasis], vb[kMaxBasis], wb[kMaxBasis], rowsum[kMaxBasis];
+  const int p = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = i + 1;
   double* Mp = M + (int64_t)p * B * B;
-  const double* rp = red + (int64_t)p * ldr;
-  // the previous step's eigenvalue (written by this kernel's previous call in
-  // the same solve; the first call of a solve has i = 0)
-  const double lam_prev = i > 0 ? lam[p] : 0.0;
-  // the previous step's Ritz vector in the coordinates of the grown basis
-  // (its new last coordinate is 0); read before svec is overwritten below
-  if (svec_prev && lane <= i) svec_prev[(int64_t)p * B + lane] = lane < i ? svec[(int64_t)p * B + lane] : 0.0;
-  // the new row and column come from red, the rest from the stored matrix:
-  // lane r reads row r, eight independent loads in flight at a time
-  load_rows(A, Mp, B, i, lane);
-  if (lane < i) {
-    const double v = rp[lane];
-    A[i][lane] = v;
-    A[lane][i] = v;
+  // the first wave's loads go out first and complete during the sums: the
+  // previous step's eigenvalue (written by this kernel's previous call in
+  // the same solve; the first call of a solve has i = 0), the previous Ritz
+  // vector (read before svec is overwritten below) and, up to order 16, the
+  // stored rows (lane r reads row r)
+  double lam_prev = 0.0, sp = 0.0, mrow[16];
+  if (wave == 0) {
+    lam_prev = i > 0 ? lam[p] : 0.0;
+    sp = svec_prev && lane < i ? svec[(int64_t)p * B + lane] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) mrow[c] = n <= 16 && lane < i && c < i ? Mp[(int64_t)lane * B + c] : 0.0;
   }
-  if (lane == i) A[i][i] = rp[i];
+  {
+    const DavProb pr = probs[p];
+    for (int j = wave; j <= i; j += GE_T / 64) {
+      const double* col = part + (int64_t)j * nct + pr.chunk0;
+      double v = 0.0;
+      int c = lane;
+      for (; c + 15 * 64 < pr.nchunk; c += 16 * 64) {
+        double t[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) t[u] = col[c + u * 64];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v += t[u];
+      }
+      for (; c < pr.nchunk; c += 64) v += col[c];
+      v = wave_total(v);
+      if (lane == 0) rowsum[j] = v;
+    }
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  // the new row and column from the sums, the rest from the stored matrix
+  const double rv = lane <= i ? rowsum[lane] : 0.0;
+  if (n <= 16) {
+    if (lane < i) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c < i) A[lane][c] = mrow[c];
+    }
+  } else {
+    load_rows<8>(A, Mp, B, i, lane);
+  }
+  if (svec_prev && lane <= i) svec_prev[(int64_t)p * B + lane] = sp;
+  if (lane < i) {
+    A[i][lane] = rv;
+    A[lane][i] = rv;
+  }
+  if (lane == i) A[i][i] = rv;
   if (lane <= i) {
-    const double v = rp[lane];
-    Mp[i * B + lane] = v;
-    Mp[lane * B + i] = v;
+    Mp[i * B + lane] = rv;
+    Mp[lane * B + i] = rv;
   }
   wave_sync();
   // 1. tridiagonalisation (lane r owns row r of the trailing block).  Up to
@@ -391,7 +452,10 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
   // squared off-diagonal in LDS once (the Sturm recurrence reads it every round)
   if (lane + 1 < n) wb[lane] = e[lane] * e[lane];
   wave_sync();
-  // number of eigenvalues of T below sigma (Sturm count of the LDL^T pivots)
+  // number of eigenvalues of T below sigma (Sturm count of the LDL^T pivots).
+  // One shift per lane: the recurrence is bound by the issue of its FP64
+  // reciprocal and FMAs, so interleaving several shifts per lane costs about
+  // proportionally more per round than it saves in rounds.
   auto count_below = [&](double sigma) {
     int cnt = 0;
     double q = d[0] - sigma;
@@ -410,15 +474,11 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
     }
     return cnt;
   };
-  // a first round of 64 shifts spaced geometrically on both sides of the
-  // previous step's eigenvalue (distances 4^-24 .. 4^7 of its magnitude):
-  // the lowest eigenvalue moves little from step to step, so the bracket
-  // usually shrinks to a few times that move at once.  Only a guess: the
-  // bracket keeps count(lo) = 0 and count(hi) >= 1 whatever it finds.
-  if (i > 0 && isfinite(lam_prev)) {
-    const double scale = fmax(fabs(lam_prev), 1e-3 * tn);
-    const double off = scale * exp2(2.0 * (double)(lane < 32 ? 7 - lane : lane - 56));
-    const double sigma = lane < 32 ? lam_prev - off : lam_prev + off;   // ascending in the lane
+  // The 64 shifts of a round ascend with the lane.  The bracket becomes
+  // [shift f - 1, shift f] for the first lane f whose count is >= 1 (lo kept
+  // when f = 0), or [last shift, hi] when none is, so count(lo) = 0 and
+  // count(hi) >= 1 hold throughout.
+  auto narrow = [&](double sigma) {
     const unsigned long long below = __ballot(count_below(sigma) >= 1);
     if (below) {
       const int first = __ffsll((long long)below) - 1;
@@ -427,22 +487,23 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
     } else {
       lo = fmax(lo, readlane_d(sigma, GT - 1));
     }
+  };
+  // a first round of shifts spaced geometrically on both sides of the
+  // previous step's eigenvalue (32 a side, distances 2^-50 .. 2^12 of its
+  // magnitude, ratio 4): the lowest eigenvalue moves little from step to
+  // step, so the bracket usually shrinks to a few times the move at once.
+  // Only a guess: the bracket rules above hold whatever it finds.
+  if (i > 0 && isfinite(lam_prev)) {
+    const double scale = fmax(fabs(lam_prev), 1e-3 * tn);
+    const int side = lane < 32 ? 31 - lane : lane - 32;   // 0 nearest .. 31 farthest
+    const double off = scale * exp2(-50.0 + 2.0 * (double)side);
+    narrow(lane < 32 ? lam_prev - off : lam_prev + off);
   }
+  // then rounds of 64 equally spaced shifts inside the bracket
   for (int round = 0; round < 24; ++round) {
     const double width = hi - lo;
     if (!(width > 4.0 * eps * fmax(fabs(lo), fabs(hi))) || width <= pivmin) break;
-    const double sigma = lo + width * (double)(lane + 1) / (double)(GT + 1);
-    const int cnt = count_below(sigma);
-    const unsigned long long below = __ballot(cnt >= 1);   // shifts with an eigenvalue below them
-    if (below) {
-      const int first = __ffsll((long long)below) - 1;
-      const double nhi = lo + width * (double)(first + 1) / (double)(GT + 1);
-      const double nlo = first > 0 ? lo + width * (double)first / (double)(GT + 1) : lo;
-      lo = nlo;
-      hi = nhi;
-    } else {
-      lo = lo + width * (double)GT / (double)(GT + 1);
-    }
+    narrow(lo + width * (double)(lane + 1) / (double)(GT + 1));
   }
   const double lambda = 0.5 * (lo + hi);
   // 3. the eigenvector of T for lambda by the twisted factorisation
@@ -467,23 +528,25 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
   if (!(tn > 0.0) || n == 1) {   // T = 0 or 1 x 1: a unit vector is an eigenvector
     yv = lane == 0 ? 1.0 : 0.0;
   } else {
-    double cur = d[0] - lambda;
-    if (fabs(cur) < pivmin) cur = -pivmin;
-    if (lane == 0) Dp[0] = cur;
-#pragma unroll 4
-    for (int k = 0; k + 1 < n; ++k) {
-      cur = (d[k + 1] - lambda) - wb[k] * recip(cur);
-      if (fabs(cur) < pivmin) cur = -pivmin;
-      if (lane == 0) Dp[k + 1] = cur;
+    // the forward and the backward recurrence side by side (independent)
+    double fw = d[0] - lambda, bw = d[n - 1] - lambda;
+    if (fabs(fw) < pivmin) fw = -pivmin;
+    if (fabs(bw) < pivmin) bw = -pivmin;
+    if (lane == 0) {
+      Dp[0] = fw;
+      Dm[n - 1] = bw;
     }
-    cur = d[n - 1] - lambda;
-    if (fabs(cur) < pivmin) cur = -pivmin;
-    if (lane == 0) Dm[n - 1] = cur;
-#pragma unroll 4
-    for (int k = n - 2; k >= 0; --k) {
-      cur = (d[k] - lambda) - wb[k] * recip(cur);
-      if (fabs(cur) < pivmin) cur = -pivmin;
-      if (lane == 0) Dm[k] = cur;
+#pragma unroll 2
+    for (int k = 0; k + 1 < n; ++k) {
+      const int kb = n - 2 - k;
+      fw = (d[k + 1] - lambda) - wb[k] * recip(fw);
+      bw = (d[kb] - lambda) - wb[kb] * recip(bw);
+      if (fabs(fw) < pivmin) fw = -pivmin;
+      if (fabs(bw) < pivmin) bw = -pivmin;
+      if (lane == 0) {
+        Dp[k + 1] = fw;
+        Dm[kb] = bw;
+      }
     }
     wave_sync();
     // twist index: the smallest |gamma_k| (the lowest k among equal ones)
@@ -517,10 +580,10 @@ __global__ __launch_bounds__(GT) void gram_eig_kernel(int ldr, int i, int B, con
     const double sum = wave_total(yv);
     yv *= (sum < 0.0 ? -1.0 : 1.0) / nrm;
   }
-  // 4. x = H_0 (H_1 (... (H_{n-3} y)))
+  // 4. x = H_0 (H_1 (... (H_{n-3} y))) (entries of Vh past n are not read)
   double xr = lane < n ? yv : 0.0;
   for (int k = n - 3; k >= 0; --k) {
-    const double v = Vh[k][lane];
+    const double v = lane < n ? Vh[k][lane] : 0.0;
     const double dv = wave_total(v * xr);
     xr -= 2.0 * dv * v;
   }
@@ -859,7 +922,7 @@ __global__ __launch_bounds__(GT) void restart_kernel(int j, int B, int nkeep, do
   __shared__ double A[kMaxBasis][kMaxBasis + 1];
   const int p = blockIdx.x, lane = threadIdx.x;
   double* Mp = M + (int64_t)p * B * B;
-  load_rows(A, Mp, B, j, lane);
+  load_rows<8>(A, Mp, B, j, lane);
   const double sv = lane < j ? svec[(int64_t)p * B + lane] : 0.0;
   double ev = 0.0;
   if (nkeep == 2) {
@@ -1030,12 +1093,9 @@ hipError_t dav_normalize(const bsdmrg_plan_s* P, const double* part, double* red
 
 hipError_t dav_gram_eig(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStream_t s) {
   if (i < 0 || i >= kMaxBasis) return hipErrorInvalidValue;
-  // the Gram row's sums in parallel over its columns (one workgroup each),
-  // then the one-wave eigensolve
-  hipError_t e = dav_psum(P, i + 1, b.part_a, b.red, kMaxBasis, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gram_eig_kernel, dim3((unsigned)P->probs.size()), dim3(GT), 0, s, kMaxBasis, i, b.B,
-                     b.red, b.M, b.svec, b.lam, b.svec_prev);
+  // the Gram row's sums and the eigensolve in one workgroup per problem
+  hipLaunchKernelGGL(gram_eig_kernel, dim3((unsigned)P->probs.size()), dim3(GE_T), 0, s, dav_probs(P),
+                     (int)nchunks(P), b.part_a, i, b.B, b.M, b.svec, b.lam, b.svec_prev);
   return hipGetLastError();
 }
 
