@@ -132,25 +132,35 @@ void heff_forward_f64(const bsdmrg_plan_s* P, const double* L, const double* W1,
 }
 }  // namespace bsd
 
+static std::vector<MixWork> work_of(const std::vector<MixItem>& items, const std::vector<MixTask>& tasks) {
+  std::vector<MixWork> w;
+  w.reserve(items.size());
+  for (const MixItem& it : items) {
+    const MixTask& t = tasks[it.task];
+    w.push_back(MixWork{t.dst_off, t.ld_dst, t.cols, it.row0, it.nrows, t.term0, t.nterm});
+  }
+  return w;
+}
+
 static void upload(bsdmrg_plan_s* P) {
   struct Part {
     const void* src;
     size_t bytes;
     void** dst;
   };
+  const std::vector<MixWork> mix_work = work_of(P->mix_items, P->mix_tasks);
+  const std::vector<MixWork> red_work = work_of(P->red_items, P->red_tasks);
   std::vector<Part> parts = {
+      {mix_work.data(), mix_work.size() * sizeof(MixWork), (void**)&P->d_mix_work},
+      {red_work.data(), red_work.size() * sizeof(MixWork), (void**)&P->d_red_work},
       {P->s1.tasks.data(), P->s1.tasks.size() * sizeof(GemmTask), (void**)&P->s1.d_tasks},
       {P->s1.segs.data(), P->s1.segs.size() * sizeof(GemmSeg), (void**)&P->s1.d_segs},
       {P->s1.tiles.data(), P->s1.tiles.size() * sizeof(GemmTile), (void**)&P->s1.d_tiles},
       {P->s3.tasks.data(), P->s3.tasks.size() * sizeof(GemmTask), (void**)&P->s3.d_tasks},
       {P->s3.segs.data(), P->s3.segs.size() * sizeof(GemmSeg), (void**)&P->s3.d_segs},
       {P->s3.tiles.data(), P->s3.tiles.size() * sizeof(GemmTile), (void**)&P->s3.d_tiles},
-      {P->mix_tasks.data(), P->mix_tasks.size() * sizeof(MixTask), (void**)&P->d_mix_tasks},
       {P->mix_terms.data(), P->mix_terms.size() * sizeof(MixTerm), (void**)&P->d_mix_terms},
-      {P->mix_items.data(), P->mix_items.size() * sizeof(MixItem), (void**)&P->d_mix_items},
-      {P->red_tasks.data(), P->red_tasks.size() * sizeof(MixTask), (void**)&P->d_red_tasks},
       {P->red_terms.data(), P->red_terms.size() * sizeof(MixTerm), (void**)&P->d_red_terms},
-      {P->red_items.data(), P->red_items.size() * sizeof(MixItem), (void**)&P->d_red_items},
       {P->coef_ptr.data(), P->coef_ptr.size() * sizeof(int32_t), (void**)&P->d_coef_ptr},
       {P->coef_e1.data(), P->coef_e1.size() * sizeof(int64_t), (void**)&P->d_coef_e1},
       {P->coef_e2.data(), P->coef_e2.size() * sizeof(int64_t), (void**)&P->d_coef_e2},

@@ -92,6 +92,13 @@ struct MixTerm {
 struct MixItem {
   int32_t task, row0, nrows, pad;
 };
+// An item with its task's fields, as the S2 and split-K-sum launches read it
+// (one descriptor load instead of two dependent ones).
+struct MixWork {
+  int64_t dst_off;
+  int32_t ld_dst, cols, row0, nrows, term0, nterm;
+};
+static_assert(sizeof(MixWork) == 32, "MixWork layout");
 
 // Davidson reduction chunks (never straddle two problems).
 struct Chunk {
@@ -230,9 +237,8 @@ struct bsdmrg_plan_s {
   std::vector<bsd::MixTask> red_tasks;
   std::vector<bsd::MixTerm> red_terms;
   std::vector<bsd::MixItem> red_items;
-  bsd::MixTask* d_red_tasks = nullptr;
   bsd::MixTerm* d_red_terms = nullptr;
-  bsd::MixItem* d_red_items = nullptr;
+  bsd::MixWork* d_red_work = nullptr;
   std::vector<bsd::MixTask> mix_tasks;
   std::vector<bsd::MixTerm> mix_terms;
   std::vector<bsd::MixItem> mix_items;
@@ -245,9 +251,8 @@ struct bsdmrg_plan_s {
   double flops_s2 = 0.0;
   bool on_device = false;
   void* d_blob = nullptr;            // one device allocation for all tables
-  bsd::MixTask* d_mix_tasks = nullptr;
   bsd::MixTerm* d_mix_terms = nullptr;
-  bsd::MixItem* d_mix_items = nullptr;
+  bsd::MixWork* d_mix_work = nullptr;
   int32_t* d_coef_ptr = nullptr;
   int64_t* d_coef_e1 = nullptr;
   int64_t* d_coef_e2 = nullptr;

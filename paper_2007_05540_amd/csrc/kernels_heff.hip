@@ -559,26 +559,23 @@ __global__ __launch_bounds__(NTHR) void pgemm_kernel(const int32_t* __restrict__
 }
 
 // MPO mixing (S2): each workgroup handles one row range of one task; every
-// thread owns up to 16 elements and issues the 16 loads of a term together,
+// thread owns up to PER elements and issues the PER loads of a term together,
 // from the term's block base (scalar registers) plus a 32-bit byte offset
 // (source blocks below 2^29 elements: checked on the host).
 // coef == nullptr means unit coefficients (the split-K reduction).
 template <typename T, typename TACC, int PER>
-__global__ __launch_bounds__(NTHR) void mix_kernel(const MixItem* __restrict__ items,
-                                                   const MixTask* __restrict__ tasks,
-                                                   const MixTerm* __restrict__ terms,
-                                                   const double* __restrict__ coef,
-                                                   const T* __restrict__ src, T* __restrict__ dst) {
-  const MixItem it = items[blockIdx.x];
-  const MixTask t = tasks[it.task];
-  const int n = it.nrows * t.cols;
+__device__ __forceinline__ void mix_body(int64_t dst_off, int ld_dst, int cols, int row0, int nrows, int term0,
+                                         int nterm, const MixTerm* __restrict__ terms,
+                                         const double* __restrict__ coef, const T* __restrict__ src,
+                                         T* __restrict__ dst) {
+  const int n = nrows * cols;
   int rr[PER], cc[PER];
   TACC acc[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = threadIdx.x + q * NTHR;
-    rr[q] = it.row0 + e / t.cols;
-    cc[q] = e % t.cols;
+    rr[q] = row0 + e / cols;
+    cc[q] = e % cols;
     acc[q] = 0;
   }
   // terms read with a uniform index (scalar registers), two at a time: the
@@ -594,8 +591,8 @@ __global__ __launch_bounds__(NTHR) void mix_kernel(const MixItem* __restrict__ i
     }
   };
   int j = 0;
-  for (; j + 1 < t.nterm; j += 2) {
-    const MixTerm m0 = terms[t.term0 + j], m1 = terms[t.term0 + j + 1];
+  for (; j + 1 < nterm; j += 2) {
+    const MixTerm m0 = terms[term0 + j], m1 = terms[term0 + j + 1];
     T v0[PER], v1[PER];
     load(m0, v0);
     load(m1, v1);
@@ -606,8 +603,8 @@ __global__ __launch_bounds__(NTHR) void mix_kernel(const MixItem* __restrict__ i
 #pragma unroll
     for (int q = 0; q < PER; ++q) acc[q] += c1 * (TACC)v1[q];
   }
-  if (j < t.nterm) {
-    const MixTerm m0 = terms[t.term0 + j];
+  if (j < nterm) {
+    const MixTerm m0 = terms[term0 + j];
     T v0[PER];
     load(m0, v0);
     const TACC c0 = coef ? (TACC)coef[m0.coef] : (TACC)1;
@@ -617,8 +614,30 @@ __global__ __launch_bounds__(NTHR) void mix_kernel(const MixItem* __restrict__ i
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = threadIdx.x + q * NTHR;
-    if (e < n) dst[t.dst_off + (int64_t)rr[q] * t.ld_dst + cc[q]] = (T)acc[q];
+    if (e < n) dst[dst_off + (int64_t)rr[q] * ld_dst + cc[q]] = (T)acc[q];
   }
+}
+
+// The S2 and split-K-sum launches: one flattened descriptor per workgroup.
+template <typename T, typename TACC, int PER>
+__global__ __launch_bounds__(NTHR) void mix_kernel(const MixWork* __restrict__ work,
+                                                   const MixTerm* __restrict__ terms,
+                                                   const double* __restrict__ coef,
+                                                   const T* __restrict__ src, T* __restrict__ dst) {
+  const MixWork w = work[blockIdx.x];
+  mix_body<T, TACC, PER>(w.dst_off, w.ld_dst, w.cols, w.row0, w.nrows, w.term0, w.nterm, terms, coef, src, dst);
+}
+
+// The adjoint and environment launches: item and task tables.
+__global__ __launch_bounds__(NTHR) void mix_table_kernel(const MixItem* __restrict__ items,
+                                                         const MixTask* __restrict__ tasks,
+                                                         const MixTerm* __restrict__ terms,
+                                                         const double* __restrict__ coef,
+                                                         const double* __restrict__ src, double* __restrict__ dst) {
+  const MixItem it = items[blockIdx.x];
+  const MixTask t = tasks[it.task];
+  mix_body<double, double, 16>(t.dst_off, t.ld_dst, t.cols, it.row0, it.nrows, t.term0, t.nterm, terms, coef, src,
+                               dst);
 }
 
 // WW coefficients: coef[i] = sum over pairs W1[e1] * W2[e2] (fixed order).
@@ -680,8 +699,8 @@ hipError_t launch_gemm_f64(const Stage& st, int layout, const double* A, const d
 hipError_t launch_mix_tables(const MixItem* items, size_t n_items, const MixTask* tasks, const MixTerm* terms,
                              const double* coef, const double* src, double* dst, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL((mix_kernel<double, double, 16>), dim3((unsigned)n_items), dim3(NTHR), 0, s, items, tasks,
-                     terms, coef, src, dst);
+  hipLaunchKernelGGL(mix_table_kernel, dim3((unsigned)n_items), dim3(NTHR), 0, s, items, tasks, terms, coef, src,
+                     dst);
   return hipGetLastError();
 }
 
@@ -689,10 +708,10 @@ hipError_t launch_s3_reduce(const bsdmrg_plan_s* P, const double* part, double* 
   if (P->red_items.empty()) return hipSuccess;
   if (P->mix_per == 8)
     hipLaunchKernelGGL((mix_kernel<double, double, 8>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
-                       P->d_red_items, P->d_red_tasks, P->d_red_terms, (const double*)nullptr, part, out);
+                       P->d_red_work, P->d_red_terms, (const double*)nullptr, part, out);
   else
     hipLaunchKernelGGL((mix_kernel<double, double, 16>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
-                       P->d_red_items, P->d_red_tasks, P->d_red_terms, (const double*)nullptr, part, out);
+                       P->d_red_work, P->d_red_terms, (const double*)nullptr, part, out);
   return hipGetLastError();
 }
 
@@ -730,10 +749,10 @@ hipError_t launch_mix_f64(const bsdmrg_plan_s* P, const double* coef, const doub
   if (P->mix_items.empty()) return hipSuccess;
   if (P->mix_per == 8)
     hipLaunchKernelGGL((mix_kernel<double, double, 8>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
-                       P->d_mix_items, P->d_mix_tasks, P->d_mix_terms, coef, T1, T2);
+                       P->d_mix_work, P->d_mix_terms, coef, T1, T2);
   else
     hipLaunchKernelGGL((mix_kernel<double, double, 16>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
-                       P->d_mix_items, P->d_mix_tasks, P->d_mix_terms, coef, T1, T2);
+                       P->d_mix_work, P->d_mix_terms, coef, T1, T2);
   return hipGetLastError();
 }
 hipError_t launch_mix_f32(const bsdmrg_plan_s* P, const double* coef, const float* T1, float* T2,
@@ -741,10 +760,10 @@ hipError_t launch_mix_f32(const bsdmrg_plan_s* P, const double* coef, const floa
   if (P->mix_items.empty()) return hipSuccess;
   if (P->mix_per == 8)
     hipLaunchKernelGGL((mix_kernel<float, float, 8>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
-                       P->d_mix_items, P->d_mix_tasks, P->d_mix_terms, coef, T1, T2);
+                       P->d_mix_work, P->d_mix_terms, coef, T1, T2);
   else
     hipLaunchKernelGGL((mix_kernel<float, float, 16>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
-                       P->d_mix_items, P->d_mix_tasks, P->d_mix_terms, coef, T1, T2);
+                       P->d_mix_work, P->d_mix_terms, coef, T1, T2);
   return hipGetLastError();
 }
 
