@@ -156,9 +156,11 @@ static void upload(bsdmrg_plan_s* P) {
       {P->s1.tasks.data(), P->s1.tasks.size() * sizeof(GemmTask), (void**)&P->s1.d_tasks},
       {P->s1.segs.data(), P->s1.segs.size() * sizeof(GemmSeg), (void**)&P->s1.d_segs},
       {P->s1.tiles.data(), P->s1.tiles.size() * sizeof(GemmTile), (void**)&P->s1.d_tiles},
+      {P->s1.ftiles.data(), P->s1.ftiles.size() * sizeof(PTile), (void**)&P->s1.d_ftiles},
       {P->s3.tasks.data(), P->s3.tasks.size() * sizeof(GemmTask), (void**)&P->s3.d_tasks},
       {P->s3.segs.data(), P->s3.segs.size() * sizeof(GemmSeg), (void**)&P->s3.d_segs},
       {P->s3.tiles.data(), P->s3.tiles.size() * sizeof(GemmTile), (void**)&P->s3.d_tiles},
+      {P->s3.ftiles.data(), P->s3.ftiles.size() * sizeof(PTile), (void**)&P->s3.d_ftiles},
       {P->mix_terms.data(), P->mix_terms.size() * sizeof(MixTerm), (void**)&P->d_mix_terms},
       {P->red_terms.data(), P->red_terms.size() * sizeof(MixTerm), (void**)&P->d_red_terms},
       {P->coef_ptr.data(), P->coef_ptr.size() * sizeof(int32_t), (void**)&P->d_coef_ptr},
@@ -202,12 +204,17 @@ static void reschedule_stage(bsdmrg_plan_s* P, Stage& st, int32_t big_min, const
   }
   st.persistent = false;
   schedule_tiles(st, big_min);
+  flatten_tiles(st);
   validate_tiles(st, name);
   destroy_graph(P);
-  const size_t bytes = std::max<size_t>(st.tiles.size() * sizeof(GemmTile), 1);
+  // both tile tables in one buffer: tiles, then (256-byte aligned) ftiles
+  const size_t tb = al256(std::max<size_t>(st.tiles.size() * sizeof(GemmTile), 1));
+  const size_t bytes = tb + std::max<size_t>(st.ftiles.size() * sizeof(PTile), 1);
   void* d = nullptr;
   HIPCHK(hipMalloc(&d, bytes));
   hipError_t e = hipMemcpy(d, st.tiles.data(), st.tiles.size() * sizeof(GemmTile), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy((char*)d + tb, st.ftiles.data(), st.ftiles.size() * sizeof(PTile), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(d);
     HIPCHK(e);
@@ -215,6 +222,7 @@ static void reschedule_stage(bsdmrg_plan_s* P, Stage& st, int32_t big_min, const
   if (st.d_tiles_own) (void)hipFree(st.d_tiles_own);
   st.d_tiles_own = d;
   st.d_tiles = (GemmTile*)d;
+  st.d_ftiles = (PTile*)((char*)d + tb);
 }
 
 static void check_ws(void* ws, int64_t have, size_t need) {

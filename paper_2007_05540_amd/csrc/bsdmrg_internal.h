@@ -177,7 +177,12 @@ struct Stage {
   double flops = 0.0;
   int32_t big_min = kNoBigTiles;   // tasks with M and N >= big_min use 128 x 128 tiles
   bool big = false;                // the tile table holds 128 x 128 tiles
-  void* d_tiles_own = nullptr;     // device tile table allocated by a re-schedule (else inside the plan blob)
+  void* d_tiles_own = nullptr;     // device tile tables allocated by a re-schedule (else inside the plan blob)
+  // the tile table with each tile's task fields and first K segment inline
+  // (same order; pad0 = task index or -1 for an empty tile, pad1 = shape);
+  // launches of stages that upload it read one descriptor per workgroup
+  std::vector<PTile> ftiles;
+  PTile* d_ftiles = nullptr;
   // persistent launch: one workgroup per slot, its 64 x 64 tiles in
   // ptiles[wg_ptr[w] .. wg_ptr[w + 1])
   bool persistent = false;

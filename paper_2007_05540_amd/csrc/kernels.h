@@ -127,6 +127,7 @@ hipError_t launch_seg_scale(int64_t n, const int64_t* base, int np, const double
 
 // XCD-aware tile schedule of a GEMM stage (schedule.cpp)
 void schedule_tiles(Stage& st, int32_t big_min = kNoBigTiles);
+void flatten_tiles(Stage& st);   // Stage::ftiles from the tiles, tasks and segments
 void validate_tiles(const Stage& st, const char* name);
 // persistent launch of a stage: 64 x 64 tiles dealt to slots_per_xcd
 // workgroups per XCD (schedule.cpp), and its table check (validate.cpp)

@@ -100,7 +100,7 @@ struct Slice {
 // leaves room for five workgroups of 64 x 64 FP32 tiles per CU instead of
 // four, and the next slice's loads still overlap the current MFMAs.
 template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT, int TM, int NI, int NJ>
-__device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask& task,
+__device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask& task, const GemmSeg& first,
                                            const GemmSeg* __restrict__ segs, const TA* __restrict__ A,
                                            const TB* __restrict__ B, TO* __restrict__ C,
                                            TO* __restrict__ Cpart, TC* As, TC* Bs, int ni_rt, int nj_rt) {
@@ -231,7 +231,7 @@ __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask&
   GemmSeg s;
   bool have = seg < seg_end;
   if (have) {
-    s = segs[seg];
+    s = first;
     setup(s);
     load(s, 0);
     store(0);
@@ -281,6 +281,7 @@ __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask&
 // and global traffic per flop, for large blocks).
 template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT, bool BIG>
 __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(BIG || sizeof(TC) == 4 ? 1 : 5))) void ggemm_kernel(const GemmTile* __restrict__ tiles,
+                                                     const PTile* __restrict__ ftiles,
                                                      const GemmTask* __restrict__ tasks,
                                                      const GemmSeg* __restrict__ segs,
                                                      const TA* __restrict__ A,
@@ -289,9 +290,24 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(BIG || siz
   constexpr int TMX = BIG ? 128 : 64;
   __shared__ TC As[Slice<TC, !AT, TMX>::SIZE];
   __shared__ TC Bs[Slice<TC, BT, TMX>::SIZE];
-  const GemmTile tile = tiles[blockIdx.x];
-  if (tile.task < 0) return;   // padding of the per-XCD schedule
-  const GemmTask task = tasks[tile.task];
+  // the tile, its task's fields and its first K segment: from the flattened
+  // table when the stage has one (one descriptor load), else from the tile,
+  // task and segment tables (three dependent loads)
+  GemmTile tile;
+  GemmTask task;
+  GemmSeg first{};
+  if (ftiles) {
+    const PTile r = ftiles[blockIdx.x];
+    if (r.pad0 < 0) return;   // padding of the per-XCD schedule
+    tile = GemmTile{r.pad0, r.m0, r.n0, r.pad1};
+    task = GemmTask{r.c_off, r.ldc, r.M, r.N, r.seg0, r.nseg, 0, r.cbuf, 0};
+    first = r.first;
+  } else {
+    tile = tiles[blockIdx.x];
+    if (tile.task < 0) return;
+    task = tasks[tile.task];
+    if (task.nseg > 0) first = segs[task.seg0];
+  }
   const int wave = threadIdx.x >> 6;
   if (BIG && tile.shape == 1) {
     // valid 16 x 16 sub-tiles of this wave's 64 x 64 quarter (wave-uniform)
@@ -299,9 +315,9 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(BIG || siz
     const int ni = min(4, max(0, (task.M - r0 + 15) / 16));
     const int nj = min(4, max(0, (task.N - c0 + 15) / 16));
     if (ni == 4 && nj == 4)
-      ggemm_wave<TC, TA, TB, TO, BT, AT, 128, 4, 4>(tile, task, segs, A, B, C, Cpart, As, Bs, 4, 4);
+      ggemm_wave<TC, TA, TB, TO, BT, AT, 128, 4, 4>(tile, task, first, segs, A, B, C, Cpart, As, Bs, 4, 4);
     else
-      ggemm_wave<TC, TA, TB, TO, BT, AT, 128, -1, -1>(tile, task, segs, A, B, C, Cpart, As, Bs, ni, nj);
+      ggemm_wave<TC, TA, TB, TO, BT, AT, 128, -1, -1>(tile, task, first, segs, A, B, C, Cpart, As, Bs, ni, nj);
     return;
   }
   // valid 16 x 16 sub-tiles of this wave's 32 x 32 quarter (wave-uniform)
@@ -309,15 +325,15 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(BIG || siz
   const int ni = r0 >= task.M ? 0 : (r0 + 16 < task.M ? 2 : 1);
   const int nj = c0 >= task.N ? 0 : (c0 + 16 < task.N ? 2 : 1);
   if (ni == 2 && nj == 2)
-    ggemm_wave<TC, TA, TB, TO, BT, AT, 64, 2, 2>(tile, task, segs, A, B, C, Cpart, As, Bs, 2, 2);
+    ggemm_wave<TC, TA, TB, TO, BT, AT, 64, 2, 2>(tile, task, first, segs, A, B, C, Cpart, As, Bs, 2, 2);
   else if (ni == 2 && nj == 1)
-    ggemm_wave<TC, TA, TB, TO, BT, AT, 64, 2, 1>(tile, task, segs, A, B, C, Cpart, As, Bs, 2, 1);
+    ggemm_wave<TC, TA, TB, TO, BT, AT, 64, 2, 1>(tile, task, first, segs, A, B, C, Cpart, As, Bs, 2, 1);
   else if (ni == 1 && nj == 2)
-    ggemm_wave<TC, TA, TB, TO, BT, AT, 64, 1, 2>(tile, task, segs, A, B, C, Cpart, As, Bs, 1, 2);
+    ggemm_wave<TC, TA, TB, TO, BT, AT, 64, 1, 2>(tile, task, first, segs, A, B, C, Cpart, As, Bs, 1, 2);
   else if (ni == 1 && nj == 1)
-    ggemm_wave<TC, TA, TB, TO, BT, AT, 64, 1, 1>(tile, task, segs, A, B, C, Cpart, As, Bs, 1, 1);
+    ggemm_wave<TC, TA, TB, TO, BT, AT, 64, 1, 1>(tile, task, first, segs, A, B, C, Cpart, As, Bs, 1, 1);
   else
-    ggemm_wave<TC, TA, TB, TO, BT, AT, 64, 0, 0>(tile, task, segs, A, B, C, Cpart, As, Bs, 0, 0);
+    ggemm_wave<TC, TA, TB, TO, BT, AT, 64, 0, 0>(tile, task, first, segs, A, B, C, Cpart, As, Bs, 0, 0);
 }
 
 // MFMA work of one k-slice for a wave whose 32 x 32 quarter of the tile has
@@ -663,10 +679,10 @@ static hipError_t launch_gemm(const Stage& st, const TA* A, const TB* B, TO* C, 
   if (st.tiles.empty()) return hipSuccess;
   if (st.big)
     hipLaunchKernelGGL((ggemm_kernel<TC, TA, TB, TO, BT, AT, true>), dim3((unsigned)st.tiles.size()), dim3(NTHR),
-                       0, s, st.d_tiles, st.d_tasks, st.d_segs, A, B, C, Cpart);
+                       0, s, st.d_tiles, st.d_ftiles, st.d_tasks, st.d_segs, A, B, C, Cpart);
   else
     hipLaunchKernelGGL((ggemm_kernel<TC, TA, TB, TO, BT, AT, false>), dim3((unsigned)st.tiles.size()),
-                       dim3(NTHR), 0, s, st.d_tiles, st.d_tasks, st.d_segs, A, B, C, Cpart);
+                       dim3(NTHR), 0, s, st.d_tiles, st.d_ftiles, st.d_tasks, st.d_segs, A, B, C, Cpart);
   return hipGetLastError();
 }
 

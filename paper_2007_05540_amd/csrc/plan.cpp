@@ -457,6 +457,8 @@ bsdmrg_plan_s* build_plan(const bsdmrg_problem* probs, int n_probs) {
     order_mix_items(P);
     schedule_tiles(P->s1);
     schedule_tiles(P->s3);
+    flatten_tiles(P->s1);
+    flatten_tiles(P->s3);
     schedule_persistent(P->s1, kPersistentSlotsPerXcd);
     schedule_persistent(P->s3, kPersistentSlotsPerXcd);
     validate_ptiles(P->s1, "S1 persistent tiles");

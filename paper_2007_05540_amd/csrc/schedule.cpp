@@ -90,6 +90,31 @@ void schedule_tiles(Stage& st, int32_t big_min) {
   while (!st.tiles.empty() && st.tiles.back().task < 0) st.tiles.pop_back();
 }
 
+// The flattened tile table of a stage (its tasks, segments and tiles built).
+void flatten_tiles(Stage& st) {
+  st.ftiles.clear();
+  st.ftiles.reserve(st.tiles.size());
+  for (const GemmTile& t : st.tiles) {
+    PTile r{};
+    r.pad0 = t.task;
+    if (t.task >= 0) {
+      const GemmTask& k = st.tasks[t.task];
+      r.c_off = k.c_off;
+      r.m0 = t.m0;
+      r.n0 = t.n0;
+      r.M = k.M;
+      r.N = k.N;
+      r.ldc = k.ldc;
+      r.cbuf = k.cbuf;
+      r.seg0 = k.seg0;
+      r.nseg = k.nseg;
+      r.pad1 = t.shape;
+      if (k.nseg > 0) r.first = st.segs[k.seg0];
+    }
+    st.ftiles.push_back(r);
+  }
+}
+
 // Persistent schedule of a stage (64 x 64 tiles): slots_per_xcd workgroups
 // per XCD, workgroup w on XCD w mod 8.  The tasks are spread over the XCDs
 // as above (a task's tiles stay on one XCD: one L2 holds its panels); on each

@@ -62,6 +62,22 @@ void validate_tiles(const Stage& st, const char* name) {
     if (tl.m0 < 0 || tl.m0 >= k.M || tl.n0 < 0 || tl.n0 >= k.N) fail(std::string(name) + ": tile origin");
     if (tl.shape != 0 && !(tl.shape == 1 && st.big)) fail(std::string(name) + ": tile shape");
   }
+  // the flattened table (when built) repeats each tile with its task's
+  // fields and first segment
+  if (st.ftiles.empty()) return;
+  if (st.ftiles.size() != st.tiles.size()) fail(std::string(name) + ": flattened tile count");
+  for (size_t i = 0; i < st.tiles.size(); ++i) {
+    const GemmTile& tl = st.tiles[i];
+    const PTile& r = st.ftiles[i];
+    if (r.pad0 != tl.task) fail(std::string(name) + ": flattened tile task");
+    if (tl.task < 0) continue;
+    const GemmTask& k = st.tasks[tl.task];
+    if (r.c_off != k.c_off || r.M != k.M || r.N != k.N || r.ldc != k.ldc || r.cbuf != k.cbuf || r.seg0 != k.seg0 ||
+        r.nseg != k.nseg || r.m0 != tl.m0 || r.n0 != tl.n0 || r.pad1 != tl.shape)
+      fail(std::string(name) + ": flattened tile record");
+    if (k.nseg > 0 && std::memcmp(&r.first, &st.segs[k.seg0], sizeof(GemmSeg)) != 0)
+      fail(std::string(name) + ": flattened tile first segment");
+  }
 }
 
 // The persistent schedule covers every 64 x 64 tile of every task exactly
