@@ -262,7 +262,12 @@ bsdmrg_status bsdmrg_eig_workspace(bsdmrg_plan_t plan, const bsdmrg_eig_opts* op
  * products are the same combinations of the stored products, so the restart
  * costs no product.  t is orthogonalised against the basis by classical
  * Gram-Schmidt, with a second pass only when the first removed more than
- * half of ||t||^2 ("twice is enough"); if ||t|| drops below restart_rtol
+ * half of ||t||^2 ("twice is enough").  The product is taken of t after the
+ * first pass; the second pass and the normalisation are then applied to t
+ * and, H_eff being linear, to its product with the same coefficients, the
+ * norm after the second pass being ||t||^2 - ||V^T t||^2 (a second pass
+ * that would leave less than 1e-4 of ||t||^2 counts as a breakdown).  If
+ * ||t|| drops below restart_rtol
  * times its value before orthogonalisation, t is replaced by a seeded
  * Gaussian vector (SplitMix64 + Box-Muller, key from seed, product index,
  * attempt; at most 3 attempts).  All orthogonalisation, Rayleigh quotients

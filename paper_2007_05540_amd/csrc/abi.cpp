@@ -309,8 +309,9 @@ static EigWS carve_eig(const bsdmrg_plan_s* P, const bsdmrg_eig_opts* o, Carve& 
   d.part_a = c.take<double>((size_t)(B + 1) * nch);
   d.part_b = c.take<double>((size_t)(B + 1) * nch);
   d.part_n0 = c.take<double>(nch);
-  d.part_n1 = c.take<double>(nch);
   d.part_res = c.take<double>(nch);
+  d.cp = c.take<double>((size_t)np * 64);
+  d.p2 = c.take<double>(np);
   d.nq0 = c.take<double>(np);
   d.red = c.take<double>((size_t)np * 65);
   d.M = c.take<double>((size_t)np * B * B);
@@ -499,9 +500,12 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
         }
       }
     }
+    bool fresh = false;   // the newest vector is the raw t of the last step (and VA_i its raw product)
     for (;;) {
       const int i = j - 1;
-      HIPCHK(dav_dots(P, j, d.VA, n, d.V + (int64_t)i * n, d.part_a, s));
+      if (fresh) HIPCHK(dav_fresh_dots(P, d, j, s));
+      else HIPCHK(dav_dots(P, j, d.VA, n, d.V + (int64_t)i * n, d.part_a, s));
+      fresh = false;
       HIPCHK(dav_gram_eig(P, d, i, s));
       const bool last = products >= f.budget || j >= dim;
       // q, t and (unless this is the last step) the first Gram-Schmidt dots v_c^T t
@@ -538,11 +542,13 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
         j = 2;
         HIPCHK(dav_dots(P, j, d.V, n, d.q, d.part_a, s, true));
       }
-      HIPCHK(dav_update(P, d, j, d.part_a, d.part_b, 1, s));
-      HIPCHK(dav_update(P, d, j, d.part_b, d.part_n1, 2, s));
+      // the first Gram-Schmidt pass; the second one (when needed) and the
+      // normalisation are deferred to the Gram row of the next step, which
+      // applies them to t and, H being linear, to the product of t
+      HIPCHK(dav_update(P, d, j, d.part_a, s));
       HIPCHK(dav_finalize(P, d, j, step - 1, o->seed, o->restart_rtol, P->d_blk_off, P->d_blk_ptr, s));
-      HIPCHK(dav_scale_into(P, d, d.V + (int64_t)j * n, s));
-      matvec(P, f.prec, L, R, w.a, d.V + (int64_t)j * n, d.VA + (int64_t)j * n, s);
+      matvec(P, f.prec, L, R, w.a, d.q, d.VA + (int64_t)j * n, s);
+      fresh = true;
       ++j;
       ++products;
       ++step;

@@ -62,8 +62,9 @@ struct DavBufs {
   double* part_a;   // (B + 1) * nchunk partial sums
   double* part_b;
   double* part_n0;  // nchunk: ||t||^2 before orthogonalisation (t = q, or the preconditioned q)
-  double* part_n1;  // nchunk: ||t||^2 after
   double* part_res; // nchunk: ||q||^2 (the residual)
+  double* cp;       // n_probs * 64: coefficients of the deferred second Gram-Schmidt pass
+  double* p2;       // n_probs: 1 when the deferred second pass applies, else 0
   double* nq0;      // n_probs: ||q||^2 before orthogonalisation (total)
   double* red;      // n_probs * 64 per-problem sums of partials
   double* M;        // n_probs * B * B projected matrices
@@ -100,12 +101,17 @@ hipError_t dav_gram_eig(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStre
 // ||t||^2 as column i + 1
 hipError_t dav_ritz(const bsdmrg_plan_s* P, const DavBufs& b, int i, bool want_x, double* part_d,
                     const double* D, hipStream_t s);
-hipError_t dav_update(const bsdmrg_plan_s* P, const DavBufs& b, int J, const double* part_in,
-                      double* part_out, int mode, hipStream_t s);
-// J: basis size; step: product index of the random-restart key
+// first Gram-Schmidt pass t -= V c (c from part_in), the partial dots of the
+// result for the second pass into b.part_b
+hipError_t dav_update(const bsdmrg_plan_s* P, const DavBufs& b, int J, const double* part_in, hipStream_t s);
+// J: basis size; step: product index of the random-restart key.  Decides the
+// second pass and the scale of the new vector (or restarts it at random)
 hipError_t dav_finalize(const bsdmrg_plan_s* P, const DavBufs& b, int J, int step, uint64_t seed, double rtol,
                         const int64_t* blk_off, const int32_t* blk_ptr, hipStream_t s);
-hipError_t dav_scale_into(const bsdmrg_plan_s* P, const DavBufs& b, double* dst, hipStream_t s);
+// basis vector i = J - 1 and its product from t (b.q) and its raw product
+// (in VA_i): the deferred second pass and the scale applied to both, then
+// the Gram row partials VA_c^T v_i (c <= i) into b.part_a
+hipError_t dav_fresh_dots(const bsdmrg_plan_s* P, const DavBufs& b, int J, hipStream_t s);
 
 // adjoint kernels (kernels_bwd.hip)
 constexpr int kSiteDotGroup = 32;   // sites per launch of the chain-rule dots

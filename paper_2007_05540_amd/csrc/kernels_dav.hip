@@ -702,33 +702,24 @@ __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chun
         ((ws[kMaxBasisD][0] + ws[kMaxBasisD][1]) + ws[kMaxBasisD][2]) + ws[kMaxBasisD][3];
 }
 
-// Classical Gram-Schmidt pass q -= sum_j c_j v_j with c_j = red[p * ldr + j].
-// Mode 1 (first pass): red[p * ldr + J] holds ||q||^2 before the pass, kept
-// in nq0[p]; writes the partial dots v_j^T q (columns j < J) and the partial
-// ||q||^2 after the pass (column J).  Mode 2 (second pass): red[p * ldr + J]
-// holds ||q||^2 after the first pass; the pass is made only when the first
-// one lost more than half of ||q||^2 ("twice is enough": otherwise q is
-// already orthogonal to working accuracy), and the partial ||q||^2 is written.
+// First classical Gram-Schmidt pass q -= sum_j c_j v_j with c_j = red[p * ldr + j];
+// red[p * ldr + J] holds ||q||^2 before the pass, kept in nq0[p].  Writes the
+// partial dots v_j^T q of the result (columns j < J: the coefficients of a
+// second pass) and its partial ||q||^2 (column J).
 // JR > 0 (J <= JR): the basis loop unrolled JR times and the chunk's basis
-// values kept in registers for the dots of mode 1 (same arithmetic and order).
+// values kept in registers for the dots (same arithmetic and order).
 template <int JR>
 __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ chunks, int nct, int J,
                                                     const double* __restrict__ V, int64_t stride, int ldr,
                                                     const double* __restrict__ red,
                                                     double* __restrict__ q, double* __restrict__ part_out,
-                                                    double* __restrict__ nq0, int mode) {
-  __shared__ double sh[16];
+                                                    double* __restrict__ nq0) {
   __shared__ double cj[kMaxBasis];
   __shared__ double wsum[kMaxBasisD][4];
   const Chunk ch = chunks[blockIdx.x];
   if ((int)threadIdx.x < J) cj[threadIdx.x] = red[(int64_t)ch.prob * ldr + threadIdx.x];
-  const double nred = red[(int64_t)ch.prob * ldr + J];
-  if (mode == 1 && threadIdx.x == 0) nq0[ch.prob] = nred;   // same value from every block
+  if (threadIdx.x == 0) nq0[ch.prob] = red[(int64_t)ch.prob * ldr + J];   // same value from every block
   __syncthreads();
-  const bool pass = mode == 1 || !(nred >= 0.5 * nq0[ch.prob]);
-  // a second pass that is not needed writes nothing: the finalize step takes
-  // ||q||^2 after the first pass from red (the same test decides there)
-  if (!pass) return;
   double qv[PER];
   double vr[JR > 0 ? JR : 1][PER];
 #pragma unroll
@@ -738,70 +729,129 @@ __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ ch
     for (int j = 0; j < (JR > 0 ? JR : 1); ++j) vr[j][u] = 0.0;
     if (e < ch.len) {
       double v = ld_at(q + ch.start, e);
-      if (pass) {
-        if (JR > 0) {
+      if (JR > 0) {
 #pragma unroll
-          for (int j = 0; j < (JR > 0 ? JR : 1); ++j)
-            if (j < J) {
-              const double vv = ld_at(V + j * stride + ch.start, e);
-              vr[j][u] = vv;
-              v -= cj[j] * vv;
-            }
-        } else {
+        for (int j = 0; j < (JR > 0 ? JR : 1); ++j)
+          if (j < J) {
+            const double vv = ld_at(V + j * stride + ch.start, e);
+            vr[j][u] = vv;
+            v -= cj[j] * vv;
+          }
+      } else {
 #pragma unroll 4
-          for (int j = 0; j < J; ++j) v -= cj[j] * ld_at(V + j * stride + ch.start, e);
-        }
-        st_at(q + ch.start, e, v);
+        for (int j = 0; j < J; ++j) v -= cj[j] * ld_at(V + j * stride + ch.start, e);
       }
+      st_at(q + ch.start, e, v);
       qv[u] = v;
     } else {
       qv[u] = 0.0;
     }
   }
-  if (mode == 1) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (JR > 0) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (JR > 0) {
 #pragma unroll
-      for (int j = 0; j < (JR > 0 ? JR : 1); ++j)
-        if (j < J) {
-          double s = 0.0;
-#pragma unroll
-          for (int u = 0; u < PER; ++u) {
-            const int e = threadIdx.x + u * DT;
-            if (e < ch.len) s += vr[j][u] * qv[u];
-          }
-          s = wave_sum(s);
-          if (lane == 0) wsum[j][wave] = s;
-        }
-    } else {
-#pragma unroll 4
-      for (int j = 0; j < J; ++j) {
+    for (int j = 0; j < (JR > 0 ? JR : 1); ++j)
+      if (j < J) {
         double s = 0.0;
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
           const int e = threadIdx.x + u * DT;
-          if (e < ch.len) s += ld_at(V + j * stride + ch.start, e) * qv[u];
+          if (e < ch.len) s += vr[j][u] * qv[u];
         }
         s = wave_sum(s);
         if (lane == 0) wsum[j][wave] = s;
       }
-    }
-    double s = 0.0;
-#pragma unroll
-    for (int u = 0; u < PER; ++u) s += qv[u] * qv[u];
-    s = wave_sum(s);
-    if (lane == 0) wsum[J][wave] = s;
-    __syncthreads();
-    if ((int)threadIdx.x <= J) {
-      const int j = threadIdx.x;
-      part_out[(int64_t)j * nct + blockIdx.x] = ((wsum[j][0] + wsum[j][1]) + wsum[j][2]) + wsum[j][3];
-    }
   } else {
+#pragma unroll 4
+    for (int j = 0; j < J; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = threadIdx.x + u * DT;
+        if (e < ch.len) s += ld_at(V + j * stride + ch.start, e) * qv[u];
+      }
+      s = wave_sum(s);
+      if (lane == 0) wsum[j][wave] = s;
+    }
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) s += qv[u] * qv[u];
+  s = wave_sum(s);
+  if (lane == 0) wsum[J][wave] = s;
+  __syncthreads();
+  if ((int)threadIdx.x <= J) {
+    const int j = threadIdx.x;
+    part_out[(int64_t)j * nct + blockIdx.x] = ((wsum[j][0] + wsum[j][1]) + wsum[j][2]) + wsum[j][3];
+  }
+}
+
+// The new basis vector v_i (i = J - 1) and its product from t (after the
+// first pass, in q) and the raw product H t (in VA_i): with the deferred
+// second-pass coefficients c (when p2[p] is set)
+//   v_i = s (t - sum_k c_k v_k),   H v_i = s (H t - sum_k c_k H v_k)
+// (H is linear, so the product of the corrected vector is the corrected
+// product), s = scale[p]; both are stored, then the Gram row partials
+// part[c * nct + chunk] = sum over the chunk of (H v_c)[e] v_i[e], c <= i.
+__global__ __launch_bounds__(DT) void fresh_dots_kernel(const Chunk* __restrict__ chunks, int nct, int J,
+                                                        double* __restrict__ V, double* __restrict__ VA,
+                                                        int64_t stride, const double* __restrict__ q,
+                                                        const double* __restrict__ scale,
+                                                        const double* __restrict__ p2,
+                                                        const double* __restrict__ cp, double* __restrict__ part) {
+  __shared__ double ws[kMaxBasisD + 1][4];
+  __shared__ double ck[kMaxBasis];
+  const Chunk ch = chunks[blockIdx.x];
+  const int i = J - 1;
+  const double sc = scale[ch.prob];
+  const bool two = p2[ch.prob] != 0.0;
+  if (two && (int)threadIdx.x < i) ck[threadIdx.x] = cp[(int64_t)ch.prob * kMaxBasis + threadIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* Vi = V + i * stride + ch.start;
+  double* VAi = VA + i * stride + ch.start;
+  double yv[PER], av[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * DT;
+    yv[u] = 0.0;
+    av[u] = 0.0;
+    if (e >= ch.len) continue;
+    double v = ld_at(q + ch.start, e), a = ld_at(VAi, e);
+    if (two) {
+      for (int k = 0; k < i; ++k) {
+        v -= ck[k] * ld_at(V + k * stride + ch.start, e);
+        a -= ck[k] * ld_at(VA + k * stride + ch.start, e);
+      }
+    }
+    v *= sc;
+    a *= sc;
+    st_at(Vi, e, v);
+    st_at(VAi, e, a);
+    yv[u] = v;
+    av[u] = a;
+  }
+#pragma unroll 4
+  for (int c = 0; c < i; ++c) {
+    const double* Xc = VA + c * stride + ch.start;
     double s = 0.0;
 #pragma unroll
-    for (int u = 0; u < PER; ++u) s += qv[u] * qv[u];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) part_out[blockIdx.x] = s;
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * DT;
+      if (e < ch.len) s += ld_at(Xc, e) * yv[u];
+    }
+    s = wave_sum(s);
+    if (lane == 0) ws[c][wave] = s;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) s += av[u] * yv[u];
+  s = wave_sum(s);
+  if (lane == 0) ws[i][wave] = s;
+  __syncthreads();
+  if ((int)threadIdx.x < J) {
+    const int c = threadIdx.x;
+    part[(int64_t)c * nct + blockIdx.x] = ((ws[c][0] + ws[c][1]) + ws[c][2]) + ws[c][3];
   }
 }
 
@@ -818,61 +868,99 @@ __device__ __forceinline__ double gauss_at(uint64_t key, uint64_t idx) {
   return sqrt(-2.0 * log(1.0 - u1)) * cos(6.283185307179586476925286766559 * u2);
 }
 
-// Decide per problem: accept q (scale = 1/||q||) or, when orthogonalisation
-// failed, restart from seeded Gaussian vectors orthogonalised twice against
-// the basis (single workgroup per problem; a rare path).
-__global__ __launch_bounds__(DT) void finalize_kernel(const DavProb* __restrict__ probs, int J, int step, int B,
-                                                      int64_t stride, const double* __restrict__ V,
+// Per problem (one workgroup): the second Gram-Schmidt pass is due when the
+// first one lost more than half of ||t||^2 ("twice is enough": otherwise t
+// is already orthogonal to working accuracy).  Its coefficients c = V^T t
+// (the first pass's partial dots, summed here) go to cp for the next step's
+// Gram row, which applies the pass; ||t||^2 after it is ||t||^2 - ||c||^2
+// (V orthonormal).  A second pass that would leave less than 1e-4 of ||t||^2
+// leaves rounding noise, whose norm that difference does not give
+// accurately: treated as a breakdown.  Then accept t (scale = 1/||t||) or, on
+// breakdown (||t|| below rtol of its value before orthogonalisation), restart
+// from seeded Gaussian vectors orthogonalised twice against the basis (a
+// rare path, done here in full: p2 = 0).
+// out[c] = sum over the problem's chunks of part[c * nct + chunk], c < ncol:
+// wave w of the block sums columns w, w + (waves), ..., each lane a chunk
+// stride of 64 in chunk order, then the wave sum (one fixed order).
+__device__ __forceinline__ void col_sums(const double* __restrict__ part, int nct, const DavProb& pr, int ncol,
+                                         double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int c = wave; c < ncol; c += nw) {
+    const double* col = part + (int64_t)c * nct + pr.chunk0;
+    double v = 0.0;
+    int k = lane;
+    for (; k + 7 * 64 < pr.nchunk; k += 8 * 64) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = col[k + u * 64];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v += t[u];
+    }
+    for (; k < pr.nchunk; k += 64) v += col[k];
+    v = wave_total(v);
+    if (lane == 0) out[c] = v;
+  }
+  __syncthreads();
+}
+
+constexpr int FT = 1024;   // threads of the finalize workgroup
+__global__ __launch_bounds__(FT) void finalize_kernel(const DavProb* __restrict__ probs, int nct, int J, int step,
+                                                      int B, int64_t stride, const double* __restrict__ V,
                                                       double* __restrict__ q,
                                                       const double* __restrict__ part_n0,
-                                                      const double* __restrict__ part_n1,
-                                                      const double* __restrict__ red, int ldr,
+                                                      const double* __restrict__ part_b,
                                                       const double* __restrict__ nq0,
                                                       const int64_t* __restrict__ blk_off,
                                                       const int32_t* __restrict__ blk_ptr, uint64_t seed,
                                                       double rtol, double* __restrict__ scale,
+                                                      double* __restrict__ cp, double* __restrict__ p2,
                                                       int32_t* __restrict__ restarts,
                                                       int32_t* __restrict__ status) {
   __shared__ double sh[16];
-  __shared__ double cj[kMaxBasis];
-  __shared__ double nn[2];
+  __shared__ double cj[kMaxBasis + 1];
+  __shared__ double nn[1];
   const int p = blockIdx.x;
   const DavProb pr = probs[p];
-  sum_partials(part_n0, 0, pr, 1, nn, sh);
-  // ||q||^2 after orthogonalisation: after the second pass if it was made
-  // (same test as the update kernel), else after the first (in red)
-  const double n1 = red[(int64_t)p * ldr + J];
-  if (!(n1 >= 0.5 * nq0[p])) {
-    sum_partials(part_n1, 0, pr, 1, nn + 1, sh);
-  } else if (threadIdx.x == 0) {
-    nn[1] = n1;
+  col_sums(part_n0, 0, pr, 1, nn);
+  col_sums(part_b, nct, pr, J + 1, cj);
+  const double nb = nn[0], n1 = cj[J];
+  const bool two = !(n1 >= 0.5 * nq0[p]);
+  double na = n1;
+  if (two) {
+    double c2 = 0.0;
+    for (int j = 0; j < J; ++j) c2 += cj[j] * cj[j];
+    na = n1 - c2;
+    if (!(na >= 1e-4 * n1)) na = 0.0;
   }
-  __syncthreads();
-  const double nb = nn[0], na = nn[1];
   if (na >= rtol * rtol * nb && na > 0.0) {
-    if (threadIdx.x == 0) scale[p] = 1.0 / sqrt(na);
+    if (threadIdx.x == 0) {
+      scale[p] = 1.0 / sqrt(na);
+      p2[p] = two ? 1.0 : 0.0;
+    }
+    if (two && (int)threadIdx.x < J) cp[(int64_t)p * kMaxBasis + threadIdx.x] = cj[threadIdx.x];
     return;
   }
+  if (threadIdx.x == 0) p2[p] = 0.0;
   for (int attempt = 0; attempt < 3; ++attempt) {
     const uint64_t key = seed + 0x632BE59BD9B4E019ull * (uint64_t)(1 + 65536ll * step + attempt);
     // fill the allowed elements (padding stays zero)
     for (int b = blk_ptr[p]; b < blk_ptr[p + 1]; ++b) {
       const int64_t o = blk_off[2 * b], sz = blk_off[2 * b + 1];
-      for (int64_t e = threadIdx.x; e < sz; e += DT) q[pr.base + o + e] = gauss_at(key, (uint64_t)(o + e));
+      for (int64_t e = threadIdx.x; e < sz; e += FT) q[pr.base + o + e] = gauss_at(key, (uint64_t)(o + e));
     }
     __syncthreads();
     double s = 0.0;
-    for (int64_t e = threadIdx.x; e < pr.len; e += DT) s += q[pr.base + e] * q[pr.base + e];
+    for (int64_t e = threadIdx.x; e < pr.len; e += FT) s += q[pr.base + e] * q[pr.base + e];
     const double before = block_sum(s, sh);
     for (int pass = 0; pass < 2; ++pass) {
       for (int j = 0; j < J; ++j) {
         double d = 0.0;
-        for (int64_t e = threadIdx.x; e < pr.len; e += DT) d += V[j * stride + pr.base + e] * q[pr.base + e];
+        for (int64_t e = threadIdx.x; e < pr.len; e += FT) d += V[j * stride + pr.base + e] * q[pr.base + e];
         d = block_sum(d, sh);
         if (threadIdx.x == 0) cj[j] = d;
       }
       __syncthreads();
-      for (int64_t e = threadIdx.x; e < pr.len; e += DT) {
+      for (int64_t e = threadIdx.x; e < pr.len; e += FT) {
         double v = q[pr.base + e];
         for (int j = 0; j < J; ++j) v -= cj[j] * V[j * stride + pr.base + e];
         q[pr.base + e] = v;
@@ -880,7 +968,7 @@ __global__ __launch_bounds__(DT) void finalize_kernel(const DavProb* __restrict_
       __syncthreads();
     }
     s = 0.0;
-    for (int64_t e = threadIdx.x; e < pr.len; e += DT) s += q[pr.base + e] * q[pr.base + e];
+    for (int64_t e = threadIdx.x; e < pr.len; e += FT) s += q[pr.base + e] * q[pr.base + e];
     const double after = block_sum(s, sh);
     if (threadIdx.x == 0) restarts[p] += 1;
     if (after >= rtol * rtol * before && after > 0.0) {
@@ -892,14 +980,6 @@ __global__ __launch_bounds__(DT) void finalize_kernel(const DavProb* __restrict_
     status[p] = 1;
     scale[p] = 0.0;
   }
-}
-
-__global__ __launch_bounds__(DT) void scale_kernel(const Chunk* __restrict__ chunks,
-                                                   const double* __restrict__ scale,
-                                                   const double* __restrict__ x, double* __restrict__ y) {
-  const Chunk ch = chunks[blockIdx.x];
-  const double s = scale[ch.prob];
-  for (int e = threadIdx.x; e < ch.len; e += DT) st_at(y + ch.start, e, ld_at(x + ch.start, e) * s);
 }
 
 __global__ void fill_zero_kernel(double* x, int64_t n) {
@@ -1112,30 +1192,32 @@ hipError_t dav_ritz(const bsdmrg_plan_s* P, const DavBufs& b, int i, bool want_x
   return hipGetLastError();
 }
 
-hipError_t dav_update(const bsdmrg_plan_s* P, const DavBufs& b, int J, const double* part_in,
-                      double* part_out, int mode, hipStream_t s) {
+hipError_t dav_update(const bsdmrg_plan_s* P, const DavBufs& b, int J, const double* part_in, hipStream_t s) {
   if (J < 1 || J >= kMaxBasisD) return hipErrorInvalidValue;   // column J holds a norm
   hipError_t e = dav_psum(P, J + 1, part_in, b.red, kMaxBasis, s);
   if (e != hipSuccess) return e;
   if (J <= 16)
     hipLaunchKernelGGL(update_kernel<16>, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), J, b.V,
-                       b.n, kMaxBasis, b.red, b.q, part_out, b.nq0, mode);
+                       b.n, kMaxBasis, b.red, b.q, b.part_b, b.nq0);
   else
     hipLaunchKernelGGL(update_kernel<0>, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), J, b.V,
-                       b.n, kMaxBasis, b.red, b.q, part_out, b.nq0, mode);
+                       b.n, kMaxBasis, b.red, b.q, b.part_b, b.nq0);
   return hipGetLastError();
 }
 
 hipError_t dav_finalize(const bsdmrg_plan_s* P, const DavBufs& b, int J, int step, uint64_t seed, double rtol,
                         const int64_t* blk_off, const int32_t* blk_ptr, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)P->probs.size()), dim3(DT), 0, s, dav_probs(P), J, step, b.B,
-                     b.n, b.V, b.q, b.part_n0, b.part_n1, b.red, kMaxBasis, b.nq0, blk_off, blk_ptr, seed, rtol, b.scale, b.restarts,
-                     b.status);
+  if (J < 1 || J >= kMaxBasisD) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)P->probs.size()), dim3(FT), 0, s, dav_probs(P),
+                     (int)nchunks(P), J, step, b.B, b.n, b.V, b.q, b.part_n0, b.part_b, b.nq0, blk_off, blk_ptr,
+                     seed, rtol, b.scale, b.cp, b.p2, b.restarts, b.status);
   return hipGetLastError();
 }
 
-hipError_t dav_scale_into(const bsdmrg_plan_s* P, const DavBufs& b, double* dst, hipStream_t s) {
-  hipLaunchKernelGGL(scale_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, b.scale, b.q, dst);
+hipError_t dav_fresh_dots(const bsdmrg_plan_s* P, const DavBufs& b, int J, hipStream_t s) {
+  if (J < 1 || J > kMaxBasis || J > b.B) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fresh_dots_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), J, b.V,
+                     b.VA, b.n, b.q, b.scale, b.p2, b.cp, b.part_a);
   return hipGetLastError();
 }
 
