@@ -48,7 +48,7 @@ HBM_PEAK = 8000.0                       # GB/s
 # bond, from rocprofv3 FETCH_SIZE and WRITE_SIZE counters of the current
 # kernel (FETCH_SIZE scaled by 1.989 and WRITE_SIZE by 1.000, the ratios of
 # the known size of a plain device copy to what the counters read for it)
-HBM_TRAFFIC = {"s1": 73557338, "s3": 92493562}
+HBM_TRAFFIC = {"s1": 74147896, "s3": 92643283}
 
 
 def parse():
