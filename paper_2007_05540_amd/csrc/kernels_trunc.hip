@@ -115,8 +115,25 @@ __device__ __forceinline__ double svd_block_sum(double v, double* red) {
   return s;
 }
 // sum over an aligned group of gs lanes (gs a power of two <= 64)
+// DPP move of a double (both halves through the same lane pattern).
+template <int CTRL>
+__device__ __forceinline__ double svd_dpp(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+// Sum over a group of gs (a power of two <= 64) consecutive lanes starting at
+// a multiple of gs, the same value on every lane of the group: register
+// exchanges inside rows of 16 (pairs, quads, half rows, rows), then lane
+// shuffles across rows.  Every lane of a group must be active.
 __device__ __forceinline__ double svd_group_sum(double v, int gs) {
-  for (int o = gs / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (gs >= 2) v += svd_dpp<0xB1>(v);    // quad_perm [1,0,3,2]
+  if (gs >= 4) v += svd_dpp<0x4E>(v);    // quad_perm [2,3,0,1]
+  if (gs >= 8) v += svd_dpp<0x141>(v);   // row_half_mirror
+  if (gs >= 16) v += svd_dpp<0x140>(v);  // row_mirror
+  if (gs >= 32) v += __shfl_xor(v, 16, 64);
+  if (gs >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 

@@ -87,9 +87,10 @@ static TPlan make_tplan(const bsdmrg_leg* legs) {
     s.jsig = T.n_work; T.n_work += s.kmin;
     s.jperm = T.n_work; T.n_work += s.kmin;
     // blocks of b columns: a pair of blocks (2b columns of 2 min rows at
-    // most) fills the 16384 doubles of LDS of one workgroup
+    // most) fills the 16384 doubles of LDS of one workgroup; the widest such
+    // b (at most 32): fewer, longer block-Jacobi steps per sweep
     if (s.kmin > 4096) throw Error{BSDMRG_EINVAL, "truncate: a charge sector has more than 4096 columns"};
-    while (s.b < 32 && 4 * (2 * s.b) * s.kmin <= 16384) s.b *= 2;
+    s.b = (int32_t)std::max<int64_t>(1, std::min<int64_t>(32, 16384 / (4 * s.kmin)));
     s.nb = (int32_t)((s.kmin + s.b - 1) / s.b);
     s.nb += s.nb & 1;
     if (s.nb < 2) s.nb = 2;
