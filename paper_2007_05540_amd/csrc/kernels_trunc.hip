@@ -337,6 +337,37 @@ __global__ __launch_bounds__(1024) void svd_qr_finish_kernel(const int32_t* __re
   qr_build_av(q, r);
 }
 
+// The rotation of a column pair with squared norms al, be and inner product
+// ga, or false when the pair is left alone: |ga| <= tol sqrt(al be) (tested
+// squared: no root), or a column at the rank threshold (squared norm <=
+// thr2: rounding noise left by rotations, which would keep rotating against
+// each other).  Rutishauser's formulas: zeta = (be - al) / (2 ga),
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2),
+// s = c t; reciprocals and reciprocal roots from the hardware approximations
+// refined by a Newton step (a few ulp, which the following sweeps absorb like
+// any rounding of the rotation).
+__device__ __forceinline__ bool svd_rotation(double al, double be, double ga, double thr2, double tol, double& cs,
+                                             double& sn) {
+  if (ga == 0.0 || al <= thr2 || be <= thr2 || ga * ga <= (tol * tol) * (al * be)) return false;
+  auto rcp = [](double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+  };
+  auto rsq = [](double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    return y * fma(-0.5 * x * y, y, 1.5);
+  };
+  const double zeta = (be - al) * rcp(2.0 * ga);
+  const double az = fabs(zeta), sg = zeta >= 0.0 ? 1.0 : -1.0;
+  const double z2 = fma(az, az, 1.0);
+  // sqrt(1 + zeta^2) = (1 + zeta^2) rsq(1 + zeta^2); for |zeta| > 1e150 the
+  // square overflows and t = 1 / (2 zeta) to working precision
+  const double tt = az > 1e150 ? sg * 0.5 * rcp(az) : sg * rcp(az + z2 * rsq(z2));
+  cs = rsq(fma(tt, tt, 1.0));
+  sn = cs * tt;
+  return true;
+}
+
 // One step of a block-Jacobi sweep: one workgroup (1024 threads) per block
 // pair of a matrix, the pair's columns of AV held in LDS for one inner
 // cyclic sweep.  rot[sec] is set to 1 when a rotation was applied; matrices
@@ -367,17 +398,28 @@ __global__ __launch_bounds__(1024) void svd_bjac_kernel(const SvdPair* __restric
   double* AV = work + t.av_off;
   auto gcol = [&](int k) { return k < vI ? I * b + k : J * b + (k - vI); };
   const int tid = threadIdx.x, nthr = blockDim.x;
-  for (int e = tid; e < nv * L; e += nthr) {   // nv * L <= kSvdLds: 32-bit index arithmetic
-    const int k = e / L, i = e - k * L;
-    col[e] = AV[(int64_t)gcol(k) * ld + i];
+  // the pair's columns into LDS (nv * L <= kSvdLds: 32-bit index arithmetic),
+  // eight loads of a thread in flight at a time
+  const int ntot = nv * L;
+  for (int e0 = tid; e0 < ntot; e0 += 8 * nthr) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * nthr;
+      v[u] = 0.0;
+      if (e < ntot) {
+        const int k = e / L, i = e - k * L;
+        v[u] = AV[(int64_t)gcol(k) * ld + i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (e0 + u * nthr < ntot) col[e0 + u * nthr] = v[u];
   }
   if (tid == 0) rotated = 0;
   __syncthreads();
   const double eps = 2.220446049250313e-16;
   const double tol = fmax(1e-15, 4.0 * n * eps);
-  // columns at the rank threshold of the QR (squared norm <= thr2) are
-  // rounding noise left by rotations: not rotated, or noise columns would
-  // keep rotating against each other and the sweeps would not stop
   // Step 0 of a sweep runs a full cyclic sweep over all column pairs of the
   // union (this is where the pairs inside a block meet); the later steps
   // only rotate the vI x vJ pairs across the two blocks, in P = max(vI, vJ)
@@ -390,6 +432,7 @@ __global__ __launch_bounds__(1024) void svd_bjac_kernel(const SvdPair* __restric
   int gs = 64;
   while (gs * hp > nthr) gs >>= 1;
   const int gl = tid % gs, grp = tid / gs;
+  double cs = 1.0, sn = 0.0;
   for (int st = 0; st < rounds; ++st) {
     int p = 0, q = nv;                                // q >= nv: no pair for this group
     if (grp < hp) {
@@ -419,11 +462,8 @@ __global__ __launch_bounds__(1024) void svd_bjac_kernel(const SvdPair* __restric
       al = svd_group_sum(al, gs);
       be = svd_group_sum(be, gs);
       ga = svd_group_sum(ga, gs);
-      if (!(ga == 0.0 || al <= thr2 || be <= thr2 || fabs(ga) <= tol * sqrt(al * be))) {
+      if (svd_rotation(al, be, ga, thr2, tol, cs, sn)) {
         if (gl == 0) rotated = 1;
-        const double zeta = (be - al) / (2.0 * ga);
-        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
         for (int i = gl; i < L; i += gs) {
           const double u = ap[i], w = aq[i];
           ap[i] = cs * u - sn * w;
@@ -433,9 +473,18 @@ __global__ __launch_bounds__(1024) void svd_bjac_kernel(const SvdPair* __restric
     }
     __syncthreads();
   }
-  for (int e = tid; e < nv * L; e += nthr) {
-    const int k = e / L, i = e - k * L;
-    AV[(int64_t)gcol(k) * ld + i] = col[e];
+  for (int e0 = tid; e0 < ntot; e0 += 8 * nthr) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = e0 + u * nthr < ntot ? col[e0 + u * nthr] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * nthr;
+      if (e < ntot) {
+        const int k = e / L, i = e - k * L;
+        AV[(int64_t)gcol(k) * ld + i] = v[u];
+      }
+    }
   }
   if (tid == 0 && rotated) rot[pr.sec] = 1.0;
 }
