@@ -579,7 +579,7 @@ __global__ __launch_bounds__(NTHR) void pgemm_kernel(const int32_t* __restrict__
 // from the term's block base (scalar registers) plus a 32-bit byte offset
 // (source blocks below 2^29 elements: checked on the host).
 // coef == nullptr means unit coefficients (the split-K reduction).
-template <typename T, typename TACC, int PER>
+template <typename T, typename TACC, int PER, int TR>
 __device__ __forceinline__ void mix_body(int64_t dst_off, int ld_dst, int cols, int row0, int nrows, int term0,
                                          int nterm, const MixTerm* __restrict__ terms,
                                          const double* __restrict__ coef, const T* __restrict__ src,
@@ -594,9 +594,10 @@ __device__ __forceinline__ void mix_body(int64_t dst_off, int ld_dst, int cols, 
     cc[q] = e % cols;
     acc[q] = 0;
   }
-  // terms read with a uniform index (scalar registers), two at a time: the
-  // loads of both are in flight together, then they are added in term order;
-  // element offsets within a source block are 32-bit
+  // terms read with a uniform index (scalar registers), TR (4 or 2) at a
+  // time, then two, then one: the loads of a round are in flight together,
+  // then they are added in term order; element offsets within a source block
+  // are 32-bit
   auto load = [&](const MixTerm& m, T* v) {
     const T* sp = src + m.src_off;
 #pragma unroll
@@ -607,6 +608,29 @@ __device__ __forceinline__ void mix_body(int64_t dst_off, int ld_dst, int cols, 
     }
   };
   int j = 0;
+  if (TR == 4) {
+    for (; j + 3 < nterm; j += 4) {
+      const MixTerm m0 = terms[term0 + j], m1 = terms[term0 + j + 1];
+      const MixTerm m2 = terms[term0 + j + 2], m3 = terms[term0 + j + 3];
+      T v0[PER], v1[PER], v2[PER], v3[PER];
+      load(m0, v0);
+      load(m1, v1);
+      load(m2, v2);
+      load(m3, v3);
+      const TACC c0 = coef ? (TACC)coef[m0.coef] : (TACC)1;
+      const TACC c1 = coef ? (TACC)coef[m1.coef] : (TACC)1;
+      const TACC c2 = coef ? (TACC)coef[m2.coef] : (TACC)1;
+      const TACC c3 = coef ? (TACC)coef[m3.coef] : (TACC)1;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) acc[q] += c0 * (TACC)v0[q];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) acc[q] += c1 * (TACC)v1[q];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) acc[q] += c2 * (TACC)v2[q];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) acc[q] += c3 * (TACC)v3[q];
+    }
+  }
   for (; j + 1 < nterm; j += 2) {
     const MixTerm m0 = terms[term0 + j], m1 = terms[term0 + j + 1];
     T v0[PER], v1[PER];
@@ -634,14 +658,16 @@ __device__ __forceinline__ void mix_body(int64_t dst_off, int ld_dst, int cols, 
   }
 }
 
-// The S2 and split-K-sum launches: one flattened descriptor per workgroup.
-template <typename T, typename TACC, int PER>
+// The S2 (TR = 4: MPOs with many terms per output keep four terms' loads in
+// flight) and split-K-sum (TR = 2: a few pieces) launches: one flattened
+// descriptor per workgroup.
+template <typename T, typename TACC, int PER, int TR>
 __global__ __launch_bounds__(NTHR) void mix_kernel(const MixWork* __restrict__ work,
                                                    const MixTerm* __restrict__ terms,
                                                    const double* __restrict__ coef,
                                                    const T* __restrict__ src, T* __restrict__ dst) {
   const MixWork w = work[blockIdx.x];
-  mix_body<T, TACC, PER>(w.dst_off, w.ld_dst, w.cols, w.row0, w.nrows, w.term0, w.nterm, terms, coef, src, dst);
+  mix_body<T, TACC, PER, TR>(w.dst_off, w.ld_dst, w.cols, w.row0, w.nrows, w.term0, w.nterm, terms, coef, src, dst);
 }
 
 // The adjoint and environment launches: item and task tables.
@@ -652,8 +678,8 @@ __global__ __launch_bounds__(NTHR) void mix_table_kernel(const MixItem* __restri
                                                          const double* __restrict__ src, double* __restrict__ dst) {
   const MixItem it = items[blockIdx.x];
   const MixTask t = tasks[it.task];
-  mix_body<double, double, 16>(t.dst_off, t.ld_dst, t.cols, it.row0, it.nrows, t.term0, t.nterm, terms, coef, src,
-                               dst);
+  mix_body<double, double, 16, 2>(t.dst_off, t.ld_dst, t.cols, it.row0, it.nrows, t.term0, t.nterm, terms, coef,
+                                  src, dst);
 }
 
 // WW coefficients: coef[i] = sum over pairs W1[e1] * W2[e2] (fixed order).
@@ -723,10 +749,10 @@ hipError_t launch_mix_tables(const MixItem* items, size_t n_items, const MixTask
 hipError_t launch_s3_reduce(const bsdmrg_plan_s* P, const double* part, double* out, hipStream_t s) {
   if (P->red_items.empty()) return hipSuccess;
   if (P->mix_per == 8)
-    hipLaunchKernelGGL((mix_kernel<double, double, 8>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
+    hipLaunchKernelGGL((mix_kernel<double, double, 8, 2>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
                        P->d_red_work, P->d_red_terms, (const double*)nullptr, part, out);
   else
-    hipLaunchKernelGGL((mix_kernel<double, double, 16>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
+    hipLaunchKernelGGL((mix_kernel<double, double, 16, 2>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
                        P->d_red_work, P->d_red_terms, (const double*)nullptr, part, out);
   return hipGetLastError();
 }
@@ -764,10 +790,10 @@ hipError_t launch_mix_f64(const bsdmrg_plan_s* P, const double* coef, const doub
                           hipStream_t s) {
   if (P->mix_items.empty()) return hipSuccess;
   if (P->mix_per == 8)
-    hipLaunchKernelGGL((mix_kernel<double, double, 8>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
+    hipLaunchKernelGGL((mix_kernel<double, double, 8, 4>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
                        P->d_mix_work, P->d_mix_terms, coef, T1, T2);
   else
-    hipLaunchKernelGGL((mix_kernel<double, double, 16>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
+    hipLaunchKernelGGL((mix_kernel<double, double, 16, 4>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
                        P->d_mix_work, P->d_mix_terms, coef, T1, T2);
   return hipGetLastError();
 }
@@ -775,10 +801,10 @@ hipError_t launch_mix_f32(const bsdmrg_plan_s* P, const double* coef, const floa
                           hipStream_t s) {
   if (P->mix_items.empty()) return hipSuccess;
   if (P->mix_per == 8)
-    hipLaunchKernelGGL((mix_kernel<float, float, 8>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
+    hipLaunchKernelGGL((mix_kernel<float, float, 8, 4>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
                        P->d_mix_work, P->d_mix_terms, coef, T1, T2);
   else
-    hipLaunchKernelGGL((mix_kernel<float, float, 16>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
+    hipLaunchKernelGGL((mix_kernel<float, float, 16, 4>), dim3((unsigned)P->mix_items.size()), dim3(NTHR), 0, s,
                        P->d_mix_work, P->d_mix_terms, coef, T1, T2);
   return hipGetLastError();
 }

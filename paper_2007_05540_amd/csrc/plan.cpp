@@ -240,9 +240,9 @@ static void plan_problem(bsdmrg_plan_s* P, int pi, const bsdmrg_problem& in) {
             const int task = (int)P->mix_tasks.size();
             P->mix_tasks.push_back(mt);
             // item size: up to kMixItemElems outputs, fewer for tasks with many
-            // terms (their loads come in rounds of two terms), so that no
-            // workgroup runs much longer than the others
-            const int64_t rounds = std::max<int64_t>(1, (mt.nterm + 1) / 2);
+            // terms (their loads come in rounds of four, then two, then one
+            // term), so that no workgroup runs much longer than the others
+            const int64_t rounds = std::max<int64_t>(1, mt.nterm / 4 + (mt.nterm % 4 + 1) / 2);
             const int64_t item_elems = (int64_t)P->mix_per * 256;
             int rows_per = std::max<int64_t>(1, item_elems / std::max<int64_t>(1, bc * rounds));
             auto gi = group_of.emplace(std::make_pair(iap, ic), (int32_t)(P->n_mix_groups + group_of.size())).first;
