@@ -854,7 +854,7 @@ bsdmrg_status bsdmrg_stage_timing(bsdmrg_plan_t P, int32_t precision, const doub
       HIPCHK(hipEventRecord(ev[0], s));
       for (int r = 0; r < reps; ++r) {
         if (stage == 0) HIPCHK(launch_coef(P, W1, W2, w.coef, s));
-        if (stage == 4) HIPCHK(launch_s3_reduce(P, w.part, out, s));
+        if (stage == 4) HIPCHK(launch_s3_reduce(P, w.part, out, precision == BSDMRG_F32, s));
         if (precision == BSDMRG_F64) {
           if (stage == 1) HIPCHK(launch_s1_f64(P, L, psi, w.T1, s));
           if (stage == 2) HIPCHK(launch_mix_f64(P, w.coef, w.T1, w.T2, s));

@@ -21,7 +21,10 @@ hipError_t launch_s3_gemm_f64(const bsdmrg_plan_s* P, const double* T2, const do
                               double* part, hipStream_t s);
 hipError_t launch_s3_gemm_f32(const bsdmrg_plan_s* P, const float* T2, const float* R, double* out,
                               double* part, hipStream_t s);
-hipError_t launch_s3_reduce(const bsdmrg_plan_s* P, const double* part, double* out, hipStream_t s);
+// f32_parts: the partials were written by the FP32 S3 launch (FP32 values in
+// the partial buffer); else FP64 partials.
+hipError_t launch_s3_reduce(const bsdmrg_plan_s* P, const double* part, double* out, bool f32_parts,
+                            hipStream_t s);
 hipError_t launch_mix_f64(const bsdmrg_plan_s* P, const double* coef, const double* T1, double* T2,
                           hipStream_t s);
 hipError_t launch_mix_f32(const bsdmrg_plan_s* P, const double* coef, const float* T1, float* T2,

@@ -99,6 +99,16 @@ struct Slice {
 // (two barriers per iteration): with the half-slice operand fragments this
 // leaves room for five workgroups of 64 x 64 FP32 tiles per CU instead of
 // four, and the next slice's loads still overlap the current MFMAs.
+// One result element of a tile: the output (type TO) or, for a piece of a
+// split K-list (cbuf != 0), the partial buffer, which holds the accumulation
+// type TC (an FP32 accumulator in half the bytes of an FP64 output), read
+// back by the fixed-order sum of the pieces.
+template <typename TC, typename TO>
+__device__ __forceinline__ void put_c(TO* __restrict__ C, TO* __restrict__ Cpart, int cbuf, int64_t idx, TC v) {
+  if (cbuf) ((TC*)Cpart)[idx] = v;
+  else C[idx] = (TO)v;
+}
+
 template <typename TC, typename TA, typename TB, typename TO, bool BT, bool AT, int TM, int NI, int NJ>
 __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask& task, const GemmSeg& first,
                                            const GemmSeg* __restrict__ segs, const TA* __restrict__ A,
@@ -260,7 +270,6 @@ __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask&
     }
   }
 
-  TO* Cp = (task.cbuf ? Cpart : C) + task.c_off;
 #pragma unroll
   for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -270,7 +279,8 @@ __device__ __forceinline__ void ggemm_wave(const GemmTile& tile, const GemmTask&
         for (int r = 0; r < 4; ++r) {
           const int row = tile.m0 + wm * WQ + i * 16 + Mfma<TC>::row(lane, r);
           const int col = tile.n0 + wn * WQ + j * 16 + l16;
-          if (row < task.M && col < task.N) Cp[(int64_t)row * task.ldc + col] = (TO)acc[i][j][r];
+          if (row < task.M && col < task.N)
+            put_c<TC, TO>(C, Cpart, task.cbuf, task.c_off + (int64_t)row * task.ldc + col, acc[i][j][r]);
         }
 }
 
@@ -462,10 +472,9 @@ __global__ __launch_bounds__(NTHR) void pgemm_kernel(const int32_t* __restrict__
   };
   // output block of a tile written as zeros (a task without K segments)
   auto zero_tile = [&](const PTile& r) {
-    TO* Cp = (r.cbuf ? Cpart : C) + r.c_off;
     for (int e = tid; e < TM * TM; e += NTHR) {
       const int row = r.m0 + e / TM, col = r.n0 + e % TM;
-      if (row < r.M && col < r.N) Cp[(int64_t)row * r.ldc + col] = (TO)0;
+      if (row < r.M && col < r.N) put_c<TC, TO>(C, Cpart, r.cbuf, r.c_off + (int64_t)row * r.ldc + col, (TC)0);
     }
   };
   // make tile index idx the load tile (record from nrec, which then
@@ -530,7 +539,6 @@ __global__ __launch_bounds__(NTHR) void pgemm_kernel(const int32_t* __restrict__
     else if (ni == 1 && nj == 1) pslice_mfma<TC, BT, AT, 1, 1>(as, bs, acc, wm, wn, l16, g4);
   };
   auto epilogue = [&]() {
-    TO* Cp = (crec.cbuf ? Cpart : C) + crec.c_off;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -540,7 +548,8 @@ __global__ __launch_bounds__(NTHR) void pgemm_kernel(const int32_t* __restrict__
           for (int r = 0; r < 4; ++r) {
             const int row = crec.m0 + wm * 32 + i * 16 + Mfma<TC>::row(lane, r);
             const int col = crec.n0 + wn * 32 + j * 16 + l16;
-            if (row < crec.M && col < crec.N) Cp[(int64_t)row * crec.ldc + col] = (TO)acc[i][j][r];
+            if (row < crec.M && col < crec.N)
+              put_c<TC, TO>(C, Cpart, crec.cbuf, crec.c_off + (int64_t)row * crec.ldc + col, acc[i][j][r]);
           }
         }
         acc[i][j] = V4{0, 0, 0, 0};
@@ -579,10 +588,10 @@ __global__ __launch_bounds__(NTHR) void pgemm_kernel(const int32_t* __restrict__
 // from the term's block base (scalar registers) plus a 32-bit byte offset
 // (source blocks below 2^29 elements: checked on the host).
 // coef == nullptr means unit coefficients (the split-K reduction).
-template <typename T, typename TACC, int PER, int TR>
+template <typename TS, typename T, typename TACC, int PER, int TR>
 __device__ __forceinline__ void mix_body(int64_t dst_off, int ld_dst, int cols, int row0, int nrows, int term0,
                                          int nterm, const MixTerm* __restrict__ terms,
-                                         const double* __restrict__ coef, const T* __restrict__ src,
+                                         const double* __restrict__ coef, const TS* __restrict__ src,
                                          T* __restrict__ dst) {
   const int n = nrows * cols;
   int rr[PER], cc[PER];
@@ -598,13 +607,13 @@ __device__ __forceinline__ void mix_body(int64_t dst_off, int ld_dst, int cols, 
   // time, then two, then one: the loads of a round are in flight together,
   // then they are added in term order; element offsets within a source block
   // are 32-bit
-  auto load = [&](const MixTerm& m, T* v) {
-    const T* sp = src + m.src_off;
+  auto load = [&](const MixTerm& m, TS* v) {
+    const TS* sp = src + m.src_off;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = threadIdx.x + q * NTHR;
-      v[q] = e < n ? *(const T*)((const char*)sp + (unsigned)(rr[q] * m.ld_src + cc[q]) * (unsigned)sizeof(T))
-                   : (T)0;
+      v[q] = e < n ? *(const TS*)((const char*)sp + (unsigned)(rr[q] * m.ld_src + cc[q]) * (unsigned)sizeof(TS))
+                   : (TS)0;
     }
   };
   int j = 0;
@@ -612,7 +621,7 @@ __device__ __forceinline__ void mix_body(int64_t dst_off, int ld_dst, int cols, 
     for (; j + 3 < nterm; j += 4) {
       const MixTerm m0 = terms[term0 + j], m1 = terms[term0 + j + 1];
       const MixTerm m2 = terms[term0 + j + 2], m3 = terms[term0 + j + 3];
-      T v0[PER], v1[PER], v2[PER], v3[PER];
+      TS v0[PER], v1[PER], v2[PER], v3[PER];
       load(m0, v0);
       load(m1, v1);
       load(m2, v2);
@@ -633,7 +642,7 @@ __device__ __forceinline__ void mix_body(int64_t dst_off, int ld_dst, int cols, 
   }
   for (; j + 1 < nterm; j += 2) {
     const MixTerm m0 = terms[term0 + j], m1 = terms[term0 + j + 1];
-    T v0[PER], v1[PER];
+    TS v0[PER], v1[PER];
     load(m0, v0);
     load(m1, v1);
     const TACC c0 = coef ? (TACC)coef[m0.coef] : (TACC)1;
@@ -645,7 +654,7 @@ __device__ __forceinline__ void mix_body(int64_t dst_off, int ld_dst, int cols, 
   }
   if (j < nterm) {
     const MixTerm m0 = terms[term0 + j];
-    T v0[PER];
+    TS v0[PER];
     load(m0, v0);
     const TACC c0 = coef ? (TACC)coef[m0.coef] : (TACC)1;
 #pragma unroll
@@ -667,7 +676,24 @@ __global__ __launch_bounds__(NTHR) void mix_kernel(const MixWork* __restrict__ w
                                                    const double* __restrict__ coef,
                                                    const T* __restrict__ src, T* __restrict__ dst) {
   const MixWork w = work[blockIdx.x];
-  mix_body<T, TACC, PER, TR>(w.dst_off, w.ld_dst, w.cols, w.row0, w.nrows, w.term0, w.nterm, terms, coef, src, dst);
+  mix_body<T, T, TACC, PER, TR>(w.dst_off, w.ld_dst, w.cols, w.row0, w.nrows, w.term0, w.nterm, terms, coef, src,
+                                dst);
+}
+
+// The fixed-order sum of FP32 split-K partials (the FP32 S3 launch) into the
+// FP64 output: the pieces added in order in FP32, like the K-list within a
+// piece (FP32 accumulation throughout the K-list), the sum stored widened.
+// Accumulating the loaded FP32 values directly keeps the loads of a round in
+// flight together (a widening of each value would be placed beside its
+// per-lane guarded load and wait for it).
+template <int PER>
+__global__ __launch_bounds__(NTHR) void split_sum_f32_kernel(const MixWork* __restrict__ work,
+                                                             const MixTerm* __restrict__ terms,
+                                                             const float* __restrict__ src,
+                                                             double* __restrict__ dst) {
+  const MixWork w = work[blockIdx.x];
+  mix_body<float, double, float, PER, 2>(w.dst_off, w.ld_dst, w.cols, w.row0, w.nrows, w.term0, w.nterm, terms,
+                                          nullptr, src, dst);
 }
 
 // The adjoint and environment launches: item and task tables.
@@ -678,8 +704,8 @@ __global__ __launch_bounds__(NTHR) void mix_table_kernel(const MixItem* __restri
                                                          const double* __restrict__ src, double* __restrict__ dst) {
   const MixItem it = items[blockIdx.x];
   const MixTask t = tasks[it.task];
-  mix_body<double, double, 16, 2>(t.dst_off, t.ld_dst, t.cols, it.row0, it.nrows, t.term0, t.nterm, terms, coef,
-                                  src, dst);
+  mix_body<double, double, double, 16, 2>(t.dst_off, t.ld_dst, t.cols, it.row0, it.nrows, t.term0, t.nterm, terms,
+                                          coef, src, dst);
 }
 
 // WW coefficients: coef[i] = sum over pairs W1[e1] * W2[e2] (fixed order).
@@ -746,8 +772,19 @@ hipError_t launch_mix_tables(const MixItem* items, size_t n_items, const MixTask
   return hipGetLastError();
 }
 
-hipError_t launch_s3_reduce(const bsdmrg_plan_s* P, const double* part, double* out, hipStream_t s) {
+hipError_t launch_s3_reduce(const bsdmrg_plan_s* P, const double* part, double* out, bool f32_parts,
+                            hipStream_t s) {
   if (P->red_items.empty()) return hipSuccess;
+  if (f32_parts) {
+    const float* pf = (const float*)part;
+    if (P->mix_per == 8)
+      hipLaunchKernelGGL(split_sum_f32_kernel<8>, dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
+                         P->d_red_work, P->d_red_terms, pf, out);
+    else
+      hipLaunchKernelGGL(split_sum_f32_kernel<16>, dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
+                         P->d_red_work, P->d_red_terms, pf, out);
+    return hipGetLastError();
+  }
   if (P->mix_per == 8)
     hipLaunchKernelGGL((mix_kernel<double, double, 8, 2>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
                        P->d_red_work, P->d_red_terms, (const double*)nullptr, part, out);
@@ -765,7 +802,7 @@ hipError_t launch_s3_f64(const bsdmrg_plan_s* P, const double* T2, const double*
                          double* part, hipStream_t s) {
   hipError_t e = launch_s3_gemm_f64(P, T2, R, out, part, s);
   if (e != hipSuccess) return e;
-  return launch_s3_reduce(P, part, out, s);
+  return launch_s3_reduce(P, part, out, false, s);
 }
 hipError_t launch_s3_gemm_f64(const bsdmrg_plan_s* P, const double* T2, const double* R, double* out,
                               double* part, hipStream_t s) {
@@ -779,7 +816,7 @@ hipError_t launch_s3_f32(const bsdmrg_plan_s* P, const float* T2, const float* R
                          double* part, hipStream_t s) {
   hipError_t e = launch_s3_gemm_f32(P, T2, R, out, part, s);
   if (e != hipSuccess) return e;
-  return launch_s3_reduce(P, part, out, s);
+  return launch_s3_reduce(P, part, out, true, s);
 }
 hipError_t launch_s3_gemm_f32(const bsdmrg_plan_s* P, const float* T2, const float* R, double* out,
                               double* part, hipStream_t s) {
