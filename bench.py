@@ -46,9 +46,10 @@ PEAK = {"f64": 78.6, "f32": 157.3}      # dense MFMA TFLOP/s, MI355X
 HBM_PEAK = 8000.0                       # GB/s
 # HBM bytes per launch of the FP32 S1 / S3 grouped GEMM on the m=1024, k=14
 # bond, from rocprofv3 FETCH_SIZE and WRITE_SIZE counters of the current
-# kernel (FETCH_SIZE scaled by 1.989 and WRITE_SIZE by 1.000, the ratios of
-# the known size of a plain device copy to what the counters read for it)
-HBM_TRAFFIC = {"s1": 74147896, "s3": 92643283}
+# kernel (FETCH_SIZE scaled by 1.997 and WRITE_SIZE by 1.000, the ratios of
+# the known bytes of the FP32 cast of L, a plain elementwise kernel, to what
+# the counters read for it)
+HBM_TRAFFIC = {"s1": 73920464, "s3": 78040370}
 
 
 def parse():
