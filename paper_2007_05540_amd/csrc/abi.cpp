@@ -72,7 +72,7 @@ struct Carve {
 struct ApplyWS {
   double* T1;
   double* T2;
-  double* part;     // split-K partial tiles of S3
+  double* part;     // split-K partial tiles of S3 (FP32 values in the FP32 product)
   double* coef;
   float* L32;
   float* R32;

@@ -236,7 +236,8 @@ struct bsdmrg_plan_s {
   int64_t psi_elems = 0, L_elems = 0, R_elems = 0, W1_elems = 0, W2_elems = 0;
   int64_t t1_elems = 0, t2_elems = 0, n_coefs = 0;
   bsd::Stage s1, s3;
-  // split-K of S3: partial tiles summed in fixed order by the mixing kernel
+  // split-K of S3: partial tiles (in the accumulation type) summed in fixed
+  // order by the mixing kernel (FP64) or the FP32 split sum
   int64_t s3_part_elems = 0;
   int32_t s3_split = 0;   // S3 split-K width (0: tasks not split)
   std::vector<bsd::MixTask> red_tasks;
