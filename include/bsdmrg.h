@@ -272,7 +272,9 @@ bsdmrg_status bsdmrg_eig_workspace(bsdmrg_plan_t plan, const bsdmrg_eig_opts* op
  * Gaussian vector (SplitMix64 + Box-Muller, key from seed, product index,
  * attempt; at most 3 attempts).  All orthogonalisation, Rayleigh quotients
  * and the energy are FP64.  With BSDMRG_F32_REFINE the products of the first
- * phase run in FP32 (FP32 MFMA, FP32 accumulation); when it ends (||q|| <=
+ * phase run in FP32 (FP32 MFMA, FP32 accumulation) and are kept in FP32
+ * (every product of the basis is read back and widened to FP64 for the dot
+ * products, the Gram matrix and the Ritz vector); when it ends (||q|| <=
  * tol_f32 or max_iter products) its basis is reduced as by a restart to x
  * and the previous Ritz vector, their products are recomputed in FP64, and
  * the solve goes on with FP64 products until ||q|| <= tol.

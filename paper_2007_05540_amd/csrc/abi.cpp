@@ -261,6 +261,16 @@ static void matvec(const bsdmrg_plan_s* P, int prec, const double* L, const doub
   }
 }
 
+// The FP32 product with its result stored in FP32: the products of the FP32
+// phase of a mixed Davidson solve, which are FP32-accurate.
+static void matvec_out32(const bsdmrg_plan_s* P, const ApplyWS& w, const double* psi, float* out, hipStream_t s) {
+  float* T1 = (float*)w.T1;
+  float* T2 = (float*)w.T2;
+  HIPCHK(launch_s1_f32(P, w.L32, psi, T1, s));
+  HIPCHK(launch_mix_f32(P, w.coef, T1, T2, s));
+  HIPCHK(launch_s3_f32_out32(P, T2, w.R32, out, w.part, s));
+}
+
 namespace bsd {
 int64_t heff_apply_bytes_prec(const bsdmrg_plan_s* P, int prec) {
   Carve c(nullptr, 0);
@@ -304,6 +314,8 @@ static EigWS carve_eig(const bsdmrg_plan_s* P, const bsdmrg_eig_opts* o, Carve& 
   d.B = B;
   d.V = c.take<double>((size_t)B * n);
   d.VA = c.take<double>((size_t)B * n);
+  d.VAf = (float*)d.VA;
+  d.va32 = false;
   d.x = c.take<double>(n);
   d.q = c.take<double>(n);
   d.part_a = c.take<double>((size_t)(B + 1) * nch);
@@ -475,41 +487,56 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
   cnt = SolveCounts{};
   for (size_t ph = 0; ph < phases.size(); ++ph) {
     const Phase& f = phases[ph];
+    // the FP32 phase stores the products in FP32 (they are FP32-accurate);
+    // every dot product, the Gram matrix and the Ritz vector stay FP64
+    DavBufs dp = d;
+    dp.va32 = f.prec == BSDMRG_F32;
+    auto product = [&](const double* x, int slot) {
+      if (dp.va32) matvec_out32(P, w.a, x, dp.VAf + (int64_t)slot * n, s);
+      else matvec(P, f.prec, L, R, w.a, x, d.VA + (int64_t)slot * n, s);
+    };
+    auto gram_row = [&](int cols, const double* y) {
+      if (dp.va32) HIPCHK(dav_dots(P, cols, dp.VAf, n, y, d.part_a, s));
+      else HIPCHK(dav_dots(P, cols, d.VA, n, y, d.part_a, s));
+    };
     int products = 0;
     int pend = -1, nextb = 0;   // buffer of the check in flight, next buffer
     int& counter = f.prec == BSDMRG_F64 ? cnt.it64 : cnt.it32;
     if (ph == 0) {
-      matvec(P, f.prec, L, R, w.a, d.V, d.VA, s);
+      product(d.V, 0);
       products = 1;
       ++step;
     } else {
       // switch: keep x and the previous Ritz vector (or x alone), then
       // recompute their products and the projected matrix in this precision
       const int nkeep = std::min({2, j, f.budget});
-      HIPCHK(dav_restart(P, d, j, nkeep, s));
-      HIPCHK(dav_rotate(P, d, j, nkeep, false, s));
+      HIPCHK(dav_restart(P, dp, j, nkeep, s));
+      HIPCHK(dav_rotate(P, dp, j, nkeep, false, s));
+      // the FP32 products shared this memory: clear it, since a product
+      // does not write the padding of its vector (which must stay zero)
+      if (phases[ph - 1].prec == BSDMRG_F32) HIPCHK(dav_fill_zero(d.VA, (int64_t)B * n, s));
       cnt.thick++;
       j = nkeep;
       for (int r = 0; r < j; ++r) {
-        matvec(P, f.prec, L, R, w.a, d.V + (int64_t)r * n, d.VA + (int64_t)r * n, s);
+        product(d.V + (int64_t)r * n, r);
         ++products;
         ++step;
         if (r + 1 < j) {
-          HIPCHK(dav_dots(P, r + 1, d.VA, n, d.V + (int64_t)r * n, d.part_a, s));
-          HIPCHK(dav_gram_eig(P, d, r, s));
+          gram_row(r + 1, d.V + (int64_t)r * n);
+          HIPCHK(dav_gram_eig(P, dp, r, s));
         }
       }
     }
     bool fresh = false;   // the newest vector is the raw t of the last step (and VA_i its raw product)
     for (;;) {
       const int i = j - 1;
-      if (fresh) HIPCHK(dav_fresh_dots(P, d, j, s));
-      else HIPCHK(dav_dots(P, j, d.VA, n, d.V + (int64_t)i * n, d.part_a, s));
+      if (fresh) HIPCHK(dav_fresh_dots(P, dp, j, s));
+      else gram_row(j, d.V + (int64_t)i * n);
       fresh = false;
-      HIPCHK(dav_gram_eig(P, d, i, s));
+      HIPCHK(dav_gram_eig(P, dp, i, s));
       const bool last = products >= f.budget || j >= dim;
       // q, t and (unless this is the last step) the first Gram-Schmidt dots v_c^T t
-      HIPCHK(dav_ritz(P, d, i, false, last ? nullptr : d.part_a, d.D, s));
+      HIPCHK(dav_ritz(P, dp, i, false, last ? nullptr : d.part_a, d.D, s));
       const int every = std::max(1, o->check_every);
       if (!o->fixed_iters && !last && products % every == 0) {
         bool stop = false;
@@ -519,7 +546,7 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
           pend = -1;
         }
         if (stop) {
-          HIPCHK(dav_ritz(P, d, i, true, nullptr, d.D, s));
+          HIPCHK(dav_ritz(P, dp, i, true, nullptr, d.D, s));
           break;
         }
         HIPCHK(hipMemcpyAsync(lag.h + (size_t)nextb * nch, d.part_res, nch * sizeof(double), hipMemcpyDeviceToHost,
@@ -530,14 +557,14 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
       }
       if (last) {
         if (!o->fixed_iters) (void)read_now(f.tol);   // also completes a check in flight
-        HIPCHK(dav_ritz(P, d, i, true, nullptr, d.D, s));
+        HIPCHK(dav_ritz(P, dp, i, true, nullptr, d.D, s));
         break;
       }
       if (thick && j == B) {
         // thick restart to x and the previous Ritz vector; the dots of t
         // against the new basis (and ||t||^2) are taken again
-        HIPCHK(dav_restart(P, d, j, 2, s));
-        HIPCHK(dav_rotate(P, d, j, 2, true, s));
+        HIPCHK(dav_restart(P, dp, j, 2, s));
+        HIPCHK(dav_rotate(P, dp, j, 2, true, s));
         cnt.thick++;
         j = 2;
         HIPCHK(dav_dots(P, j, d.V, n, d.q, d.part_a, s, true));
@@ -545,9 +572,9 @@ static void enqueue_solve(const bsdmrg_plan_s* P, const double* L, const double*
       // the first Gram-Schmidt pass; the second one (when needed) and the
       // normalisation are deferred to the Gram row of the next step, which
       // applies them to t and, H being linear, to the product of t
-      HIPCHK(dav_update(P, d, j, d.part_a, s));
-      HIPCHK(dav_finalize(P, d, j, step - 1, o->seed, o->restart_rtol, P->d_blk_off, P->d_blk_ptr, s));
-      matvec(P, f.prec, L, R, w.a, d.q, d.VA + (int64_t)j * n, s);
+      HIPCHK(dav_update(P, dp, j, d.part_a, s));
+      HIPCHK(dav_finalize(P, dp, j, step - 1, o->seed, o->restart_rtol, P->d_blk_off, P->d_blk_ptr, s));
+      product(d.q, j);
       fresh = true;
       ++j;
       ++products;

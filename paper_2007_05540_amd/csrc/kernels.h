@@ -21,6 +21,10 @@ hipError_t launch_s3_gemm_f64(const bsdmrg_plan_s* P, const double* T2, const do
                               double* part, hipStream_t s);
 hipError_t launch_s3_gemm_f32(const bsdmrg_plan_s* P, const float* T2, const float* R, double* out,
                               double* part, hipStream_t s);
+// S3 in FP32 with FP32 output (the products of the FP32 phase of a mixed
+// Davidson solve), split-K pieces summed
+hipError_t launch_s3_f32_out32(const bsdmrg_plan_s* P, const float* T2, const float* R, float* out, double* part,
+                               hipStream_t s);
 // f32_parts: the partials were written by the FP32 S3 launch (FP32 values in
 // the partial buffer); else FP64 partials.
 hipError_t launch_s3_reduce(const bsdmrg_plan_s* P, const double* part, double* out, bool f32_parts,
@@ -60,6 +64,8 @@ hipError_t launch_mix_tables(const MixItem* items, size_t n_items, const MixTask
 struct DavBufs {
   double* V;        // basis, B vectors of n elements
   double* VA;       // products
+  float* VAf;       // the products stored in FP32 (FP32 phase of a mixed solve; the memory of VA)
+  bool va32;        // the launches read and write VAf instead of VA
   double* x;
   double* q;
   double* part_a;   // (B + 1) * nchunk partial sums
@@ -87,6 +93,8 @@ hipError_t dav_fill_zero(double* x, int64_t n, hipStream_t s);
 // part[j] (j < J) = chunk partials of X_j^T y; with norm_col also ||y||^2 as column J
 hipError_t dav_dots(const bsdmrg_plan_s* P, int J, const double* X, int64_t xstride, const double* y,
                     double* part, hipStream_t s, bool norm_col = false);
+hipError_t dav_dots(const bsdmrg_plan_s* P, int J, const float* X, int64_t xstride, const double* y, double* part,
+                    hipStream_t s);
 // thick restart coefficients (nkeep 1 or 2 vectors out of j) and the new projected matrix
 hipError_t dav_restart(const bsdmrg_plan_s* P, const DavBufs& b, int j, int nkeep, hipStream_t s);
 // V (and VA) <- V S in place, nout output vectors from J inputs

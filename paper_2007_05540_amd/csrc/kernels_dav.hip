@@ -15,11 +15,13 @@ constexpr int kMaxBasisD = 64;   // largest basis (J) of the multi-dot kernels
 
 // Element i of a chunk-local array: a wave-uniform base plus a 32-bit byte
 // offset (chunks hold kChunk elements), so loads and stores take a scalar base.
-__device__ __forceinline__ double ld_at(const double* base, unsigned i) {
-  return *(const double*)((const char*)base + i * 8u);
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* base, unsigned i) {
+  return *(const T*)((const char*)base + i * (unsigned)sizeof(T));
 }
-__device__ __forceinline__ void st_at(double* base, unsigned i, double v) {
-  *(double*)((char*)base + i * 8u) = v;
+template <typename T>
+__device__ __forceinline__ void st_at(T* base, unsigned i, T v) {
+  *(T*)((char*)base + i * (unsigned)sizeof(T)) = v;
 }
 
 // Sum over the 64 lanes of a wave, the same value on every lane, in one
@@ -129,8 +131,9 @@ __global__ __launch_bounds__(DT) void psum_kernel(const DavProb* __restrict__ pr
 
 // part[j * nct + ch] = sum_{e in chunk ch} X_j[e] y[e], j < J (wave sums
 // per j, one barrier, the four wave sums added in order).
+template <typename TX>
 __global__ __launch_bounds__(DT) void dots_kernel(const Chunk* __restrict__ chunks, int nct, int J,
-                                                  const double* __restrict__ X, int64_t xstride,
+                                                  const TX* __restrict__ X, int64_t xstride,
                                                   const double* __restrict__ y, double* __restrict__ part,
                                                   int norm_col) {
   __shared__ double ws[kMaxBasisD + 1][4];
@@ -144,12 +147,12 @@ __global__ __launch_bounds__(DT) void dots_kernel(const Chunk* __restrict__ chun
   }
 #pragma unroll 4
   for (int j = 0; j < J; ++j) {
-    const double* Xj = X + j * xstride + ch.start;
+    const TX* Xj = X + j * xstride + ch.start;
     double s = 0.0;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = threadIdx.x + u * DT;
-      if (e < ch.len) s += ld_at(Xj, e) * yv[u];
+      if (e < ch.len) s += (double)ld_at(Xj, e) * yv[u];
     }
     s = wave_sum(s);
     if (lane == 0) ws[j][wave] = s;
@@ -599,9 +602,9 @@ __global__ __launch_bounds__(GE_T) void gram_eig_kernel(const DavProb* __restric
 // JR > 0 (J <= JR): the loop over the basis is unrolled JR times and the
 // chunk's basis values stay in registers for the Gram-Schmidt dots (the
 // same arithmetic in the same order as JR = 0).
-template <int JR>
+template <int JR, typename TV>
 __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chunks, int nct, int J, int B,
-                                                  const double* __restrict__ V, const double* __restrict__ VA,
+                                                  const double* __restrict__ V, const TV* __restrict__ VA,
                                                   int64_t stride, const double* __restrict__ svec,
                                                   const double* __restrict__ lam, double* __restrict__ x,
                                                   double* __restrict__ q, double* __restrict__ part,
@@ -636,13 +639,13 @@ __global__ __launch_bounds__(DT) void ritz_kernel(const Chunk* __restrict__ chun
           const double vv = ld_at(V + j * stride + ch.start, e);
           vr[j][u] = vv;
           xv += sv[j] * vv;
-          av += sv[j] * ld_at(VA + j * stride + ch.start, e);
+          av += sv[j] * (double)ld_at(VA + j * stride + ch.start, e);
         }
     } else {
 #pragma unroll 4
       for (int j = 0; j < J; ++j) {
         xv += sv[j] * ld_at(V + j * stride + ch.start, e);
-        av += sv[j] * ld_at(VA + j * stride + ch.start, e);
+        av += sv[j] * (double)ld_at(VA + j * stride + ch.start, e);
       }
     }
     const double r = av - l * xv;
@@ -793,8 +796,9 @@ __global__ __launch_bounds__(DT) void update_kernel(const Chunk* __restrict__ ch
 // (H is linear, so the product of the corrected vector is the corrected
 // product), s = scale[p]; both are stored, then the Gram row partials
 // part[c * nct + chunk] = sum over the chunk of (H v_c)[e] v_i[e], c <= i.
+template <typename TV>
 __global__ __launch_bounds__(DT) void fresh_dots_kernel(const Chunk* __restrict__ chunks, int nct, int J,
-                                                        double* __restrict__ V, double* __restrict__ VA,
+                                                        double* __restrict__ V, TV* __restrict__ VA,
                                                         int64_t stride, const double* __restrict__ q,
                                                         const double* __restrict__ scale,
                                                         const double* __restrict__ p2,
@@ -809,7 +813,7 @@ __global__ __launch_bounds__(DT) void fresh_dots_kernel(const Chunk* __restrict_
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double* Vi = V + i * stride + ch.start;
-  double* VAi = VA + i * stride + ch.start;
+  TV* VAi = VA + i * stride + ch.start;
   double yv[PER], av[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
@@ -817,28 +821,28 @@ __global__ __launch_bounds__(DT) void fresh_dots_kernel(const Chunk* __restrict_
     yv[u] = 0.0;
     av[u] = 0.0;
     if (e >= ch.len) continue;
-    double v = ld_at(q + ch.start, e), a = ld_at(VAi, e);
+    double v = ld_at(q + ch.start, e), a = (double)ld_at(VAi, e);
     if (two) {
       for (int k = 0; k < i; ++k) {
         v -= ck[k] * ld_at(V + k * stride + ch.start, e);
-        a -= ck[k] * ld_at(VA + k * stride + ch.start, e);
+        a -= ck[k] * (double)ld_at(VA + k * stride + ch.start, e);
       }
     }
     v *= sc;
-    a *= sc;
+    const TV at = (TV)(a * sc);   // the product as stored (FP32 in the FP32 phase)
     st_at(Vi, e, v);
-    st_at(VAi, e, a);
+    st_at(VAi, e, at);
     yv[u] = v;
-    av[u] = a;
+    av[u] = (double)at;
   }
 #pragma unroll 4
   for (int c = 0; c < i; ++c) {
-    const double* Xc = VA + c * stride + ch.start;
+    const TV* Xc = VA + c * stride + ch.start;
     double s = 0.0;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = threadIdx.x + u * DT;
-      if (e < ch.len) s += ld_at(Xc, e) * yv[u];
+      if (e < ch.len) s += (double)ld_at(Xc, e) * yv[u];
     }
     s = wave_sum(s);
     if (lane == 0) ws[c][wave] = s;
@@ -1049,9 +1053,10 @@ __global__ __launch_bounds__(GT) void restart_kernel(int j, int B, int nkeep, do
 // In-place rotation of the basis (and, when VA is non-null, of its
 // products): X_t <- sum_c S_ct X_c for t < nout, every input of an element
 // read before its outputs are written (each element belongs to one thread).
+template <typename TV>
 __global__ __launch_bounds__(DT) void rotate_kernel(const Chunk* __restrict__ chunks, int J, int B, int nout,
                                                     const double* __restrict__ S, double* __restrict__ V,
-                                                    double* __restrict__ VA, int64_t stride) {
+                                                    TV* __restrict__ VA, int64_t stride) {
   __shared__ double sc[2][kMaxBasis];
   const Chunk ch = chunks[blockIdx.x];
   if ((int)threadIdx.x < J) {
@@ -1069,7 +1074,7 @@ __global__ __launch_bounds__(DT) void rotate_kernel(const Chunk* __restrict__ ch
       o0 += sc[0][c] * v;
       o1 += sc[1][c] * v;
       if (VA) {
-        const double a = ld_at(VA + c * stride + ch.start, e);
+        const double a = (double)ld_at(VA + c * stride + ch.start, e);
         a0 += sc[0][c] * a;
         a1 += sc[1][c] * a;
       }
@@ -1077,8 +1082,8 @@ __global__ __launch_bounds__(DT) void rotate_kernel(const Chunk* __restrict__ ch
     st_at(V + ch.start, e, o0);
     if (nout == 2) st_at(V + stride + ch.start, e, o1);
     if (VA) {
-      st_at(VA + ch.start, e, a0);
-      if (nout == 2) st_at(VA + stride + ch.start, e, a1);
+      st_at(VA + ch.start, e, (TV)a0);
+      if (nout == 2) st_at(VA + stride + ch.start, e, (TV)a1);
     }
   }
 }
@@ -1128,8 +1133,16 @@ hipError_t dav_fill_zero(double* x, int64_t n, hipStream_t s) {
 hipError_t dav_dots(const bsdmrg_plan_s* P, int J, const double* X, int64_t xstride, const double* y,
                     double* part, hipStream_t s, bool norm_col) {
   if (J < 0 || J > kMaxBasisD || (norm_col && J >= kMaxBasisD + 1)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(dots_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), J, X,
+  hipLaunchKernelGGL(dots_kernel<double>, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), J, X,
                      xstride, y, part, norm_col ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t dav_dots(const bsdmrg_plan_s* P, int J, const float* X, int64_t xstride, const double* y, double* part,
+                    hipStream_t s) {
+  if (J < 0 || J > kMaxBasisD) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(dots_kernel<float>, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), J, X,
+                     xstride, y, part, 0);
   return hipGetLastError();
 }
 
@@ -1143,8 +1156,12 @@ hipError_t dav_restart(const bsdmrg_plan_s* P, const DavBufs& b, int j, int nkee
 hipError_t dav_rotate(const bsdmrg_plan_s* P, const DavBufs& b, int J, int nout, bool with_products,
                       hipStream_t s) {
   if (J < 1 || J > b.B || nout < 1 || nout > 2) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(rotate_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, J, b.B, nout, b.Srot, b.V,
-                     with_products ? b.VA : nullptr, b.n);
+  if (b.va32)
+    hipLaunchKernelGGL(rotate_kernel<float>, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, J, b.B, nout, b.Srot,
+                       b.V, with_products ? b.VAf : nullptr, b.n);
+  else
+    hipLaunchKernelGGL(rotate_kernel<double>, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, J, b.B, nout, b.Srot,
+                       b.V, with_products ? b.VA : nullptr, b.n);
   return hipGetLastError();
 }
 
@@ -1181,14 +1198,25 @@ hipError_t dav_gram_eig(const bsdmrg_plan_s* P, const DavBufs& b, int i, hipStre
 
 hipError_t dav_ritz(const bsdmrg_plan_s* P, const DavBufs& b, int i, bool want_x, double* part_d,
                     const double* D, hipStream_t s) {
-  if (i + 1 <= 16)
-    hipLaunchKernelGGL(ritz_kernel<16>, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), i + 1,
-                       b.B, b.V, b.VA, b.n, b.svec, b.lam, want_x ? b.x : nullptr, b.q, b.part_n0, part_d,
-                       b.part_res, D);
-  else
-    hipLaunchKernelGGL(ritz_kernel<0>, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), i + 1,
-                       b.B, b.V, b.VA, b.n, b.svec, b.lam, want_x ? b.x : nullptr, b.q, b.part_n0, part_d,
-                       b.part_res, D);
+  double* x = want_x ? b.x : nullptr;
+  const int J = i + 1;
+  const unsigned g = (unsigned)nchunks(P);
+  const int nct = (int)nchunks(P);
+  if (b.va32) {
+    if (J <= 16)
+      hipLaunchKernelGGL((ritz_kernel<16, float>), dim3(g), dim3(DT), 0, s, P->d_chunks, nct, J, b.B, b.V, b.VAf,
+                         b.n, b.svec, b.lam, x, b.q, b.part_n0, part_d, b.part_res, D);
+    else
+      hipLaunchKernelGGL((ritz_kernel<0, float>), dim3(g), dim3(DT), 0, s, P->d_chunks, nct, J, b.B, b.V, b.VAf,
+                         b.n, b.svec, b.lam, x, b.q, b.part_n0, part_d, b.part_res, D);
+  } else {
+    if (J <= 16)
+      hipLaunchKernelGGL((ritz_kernel<16, double>), dim3(g), dim3(DT), 0, s, P->d_chunks, nct, J, b.B, b.V, b.VA,
+                         b.n, b.svec, b.lam, x, b.q, b.part_n0, part_d, b.part_res, D);
+    else
+      hipLaunchKernelGGL((ritz_kernel<0, double>), dim3(g), dim3(DT), 0, s, P->d_chunks, nct, J, b.B, b.V, b.VA,
+                         b.n, b.svec, b.lam, x, b.q, b.part_n0, part_d, b.part_res, D);
+  }
   return hipGetLastError();
 }
 
@@ -1216,8 +1244,12 @@ hipError_t dav_finalize(const bsdmrg_plan_s* P, const DavBufs& b, int J, int ste
 
 hipError_t dav_fresh_dots(const bsdmrg_plan_s* P, const DavBufs& b, int J, hipStream_t s) {
   if (J < 1 || J > kMaxBasis || J > b.B) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fresh_dots_kernel, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), J, b.V,
-                     b.VA, b.n, b.q, b.scale, b.p2, b.cp, b.part_a);
+  if (b.va32)
+    hipLaunchKernelGGL(fresh_dots_kernel<float>, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), J,
+                       b.V, b.VAf, b.n, b.q, b.scale, b.p2, b.cp, b.part_a);
+  else
+    hipLaunchKernelGGL(fresh_dots_kernel<double>, dim3(nchunks(P)), dim3(DT), 0, s, P->d_chunks, (int)nchunks(P), J,
+                       b.V, b.VA, b.n, b.q, b.scale, b.p2, b.cp, b.part_a);
   return hipGetLastError();
 }
 

@@ -681,18 +681,19 @@ __global__ __launch_bounds__(NTHR) void mix_kernel(const MixWork* __restrict__ w
 }
 
 // The fixed-order sum of FP32 split-K partials (the FP32 S3 launch) into the
-// FP64 output: the pieces added in order in FP32, like the K-list within a
-// piece (FP32 accumulation throughout the K-list), the sum stored widened.
-// Accumulating the loaded FP32 values directly keeps the loads of a round in
-// flight together (a widening of each value would be placed beside its
-// per-lane guarded load and wait for it).
-template <int PER>
+// output (FP64, or FP32 for the products of the FP32 phase of a mixed
+// Davidson solve): the pieces added in order in FP32, like the K-list within
+// a piece (FP32 accumulation throughout the K-list).  Accumulating the loaded
+// FP32 values directly keeps the loads of a round in flight together (a
+// widening of each value would be placed beside its per-lane guarded load
+// and wait for it).
+template <int PER, typename TD>
 __global__ __launch_bounds__(NTHR) void split_sum_f32_kernel(const MixWork* __restrict__ work,
                                                              const MixTerm* __restrict__ terms,
                                                              const float* __restrict__ src,
-                                                             double* __restrict__ dst) {
+                                                             TD* __restrict__ dst) {
   const MixWork w = work[blockIdx.x];
-  mix_body<float, double, float, PER, 2>(w.dst_off, w.ld_dst, w.cols, w.row0, w.nrows, w.term0, w.nterm, terms,
+  mix_body<float, TD, float, PER, 2>(w.dst_off, w.ld_dst, w.cols, w.row0, w.nrows, w.term0, w.nterm, terms,
                                           nullptr, src, dst);
 }
 
@@ -778,10 +779,10 @@ hipError_t launch_s3_reduce(const bsdmrg_plan_s* P, const double* part, double* 
   if (f32_parts) {
     const float* pf = (const float*)part;
     if (P->mix_per == 8)
-      hipLaunchKernelGGL(split_sum_f32_kernel<8>, dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
+      hipLaunchKernelGGL((split_sum_f32_kernel<8, double>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
                          P->d_red_work, P->d_red_terms, pf, out);
     else
-      hipLaunchKernelGGL(split_sum_f32_kernel<16>, dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
+      hipLaunchKernelGGL((split_sum_f32_kernel<16, double>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
                          P->d_red_work, P->d_red_terms, pf, out);
     return hipGetLastError();
   }
@@ -821,6 +822,19 @@ hipError_t launch_s3_f32(const bsdmrg_plan_s* P, const float* T2, const float* R
 hipError_t launch_s3_gemm_f32(const bsdmrg_plan_s* P, const float* T2, const float* R, double* out,
                               double* part, hipStream_t s) {
   return launch_stage<float, float, float, double, true>(P->s3, T2, R, out, part, s);
+}
+hipError_t launch_s3_f32_out32(const bsdmrg_plan_s* P, const float* T2, const float* R, float* out, double* part,
+                               hipStream_t s) {
+  float* pf = (float*)part;
+  hipError_t e = launch_stage<float, float, float, float, true>(P->s3, T2, R, out, pf, s);
+  if (e != hipSuccess || P->red_items.empty()) return e;
+  if (P->mix_per == 8)
+    hipLaunchKernelGGL((split_sum_f32_kernel<8, float>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
+                       P->d_red_work, P->d_red_terms, pf, out);
+  else
+    hipLaunchKernelGGL((split_sum_f32_kernel<16, float>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
+                       P->d_red_work, P->d_red_terms, pf, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_mix_f64(const bsdmrg_plan_s* P, const double* coef, const double* T1, double* T2,

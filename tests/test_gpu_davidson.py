@@ -204,3 +204,23 @@ def test_c2_converged_fp64_and_mixed_energies_match_oracle(mods, c2_reference):
         assert abs(e[0] - lam) <= 1e-9 * abs(lam)
         assert err < 1e-8
     assert stmx[0]["iters_f32"] > 0
+
+
+def test_mixed_switch_after_restarts_matches_converged_oracle(mods):
+    """A mixed solve whose FP32 phase runs through several thick restarts
+    (basis 8, 40 FP32 products) before 3 FP64 refinement products: the FP32
+    products are stored in FP32 in the memory of the FP64 ones, and a product
+    leaves the padding of its vector unwritten, so the switch must leave that
+    padding zero again.  The refined energy is within 1e-9 relative of the
+    oracle's converged energy and the reported residual is small."""
+    lib, problems = mods
+    spec = synth.c2_bond(m=64, k=14, seed=1)
+    lam, _, ost, _ = oracle_solve(spec, 300, tol=1e-9, basis=32, keep=1)
+    assert ost["converged"]
+    plan, d = setup([spec], lib, problems)
+    o = lib.eig_opts(max_iter=40, fixed_iters=1, restart_keep=1, basis=8, precision=lib.F32_REFINE,
+                     refine_max_iter=3)
+    e, st, _ = run_eig(lib, plan, d, o)
+    assert st[0]["iters_f32"] == 40 and st[0]["thick_restarts"] >= 2
+    assert st[0]["residual"] < 1e-4
+    assert abs(e[0] - lam) <= 1e-9 * abs(lam)
