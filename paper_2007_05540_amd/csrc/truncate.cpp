@@ -3,7 +3,7 @@
 // (rows: the (a, s1) pairs with q_a + q_s1 = q; columns: the (s2, c) pairs
 // with q_c - q_s2 = q; both in lexicographic order of their sector indices),
 // each matrix is decomposed in FP64 on the device: QR with column pivoting
-// (one workgroup per matrix up to 256 columns, else one launch per step over
+// (one workgroup per matrix up to 64 columns, else one launch per step over
 // many workgroups) cut at the numerical rank, then block one-sided Jacobi on
 // R^T (block pairs of a step in parallel workgroups, columns in LDS) until a
 // sweep rotates nothing; the singular values of all charges are pooled and
@@ -48,8 +48,12 @@ struct TPlan {
 static size_t al(size_t b) { return (b + 255) / 256 * 256; }
 constexpr int kSvdMaxSweeps = 60;   // block-Jacobi sweeps (a converged matrix stops earlier)
 // Matrices with more columns than this are factorised by the multi-workgroup
-// QR (one launch per step and phase); smaller ones by one workgroup each.
-constexpr int64_t kQrBig = 256;
+// QR (one launch per step and phase, all such matrices of a truncation
+// together); smaller ones by one workgroup each, whose QR runs at the L2
+// bandwidth of one CU: above ~64 columns the per-column launches are faster
+// (6x6 J1-J2 sweeps at m = 512: truncations 0.90 s per sweep with the cut at
+// 256 columns, 0.77 s at 64; 4x16 Hubbard sweeps at m = 1024 -7%).
+constexpr int64_t kQrBig = 64;
 
 static TPlan make_tplan(const bsdmrg_leg* legs) {
   TPlan T;
