@@ -45,11 +45,12 @@ sys.path.insert(0, ROOT)
 PEAK = {"f64": 78.6, "f32": 157.3}      # dense MFMA TFLOP/s, MI355X
 HBM_PEAK = 8000.0                       # GB/s
 # HBM bytes per launch of the FP32 S1 / S3 grouped GEMM on the m=1024, k=14
-# bond, from rocprofv3 FETCH_SIZE and WRITE_SIZE counters of the current
-# kernel (FETCH_SIZE scaled by 1.997 and WRITE_SIZE by 1.000, the ratios of
-# the known bytes of the FP32 cast of L, a plain elementwise kernel, to what
-# the counters read for it)
-HBM_TRAFFIC = {"s1": 73920464, "s3": 78040370}
+# bond as the mixed eigensolve launches them (S3 with FP32 output), from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE counters of the current kernels
+# (FETCH_SIZE scaled by 1.997 and WRITE_SIZE by 1.000, the ratios of the
+# known bytes of the FP32 cast of L, a plain elementwise kernel, to what the
+# counters read for it)
+HBM_TRAFFIC = {"s1": 74163245, "s3": 77817309}
 
 
 def parse():
@@ -524,13 +525,16 @@ def stage_roofline(plan, info, dev, stream, reps=20):
     out = torch.zeros_like(dev["psi"])
     wsa = torch.empty(info["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
     stage, roof = {}, {}
-    for prec, name in ((lib.F32, "f32"), (lib.F64, "f64")):
+    # f32: the FP32 product of bsdmrg_heff_apply (FP64 output); f32_solve: the
+    # same stages as the FP32 phase of the mixed eigensolve runs them (S3 and
+    # its split-K sum write FP32 products)
+    for prec, name, peak in ((lib.F32, "f32", "f32"), (lib.F32_REFINE, "f32_solve", "f32"), (lib.F64, "f64", "f64")):
         ms = lib.stage_timing(plan, prec, dev["L"], dev["W1"], dev["W2"], dev["R"], dev["psi"], out, wsa, reps=reps,
                               stream=stream)
         stage[name] = {k: round(v, 5) for k, v in ms.items()}
         for st in ("s1", "s3"):
             tf = info["flops_" + st] / (ms[st] * 1e-3) / 1e12
-            roof[f"{st}_{name}"] = {"tflops": round(tf, 2), "frac": round(tf / PEAK[name], 4)}
+            roof[f"{st}_{name}"] = {"tflops": round(tf, 2), "frac": round(tf / PEAK[peak], 4)}
     del out, wsa
     return stage, roof
 
@@ -573,7 +577,7 @@ def main():
 
     # live per-kernel timing of one product (HIP events on the launch stream)
     stage, roofs = stage_roofline(plan, info, dev, stream)
-    s32 = stage["f32"]
+    s32 = stage["f32_solve"]   # the FP32 kernels of the timed mixed solve
     dom = "s1" if s32["s1"] >= s32["s3"] else "s3"
     dom_flops = info["flops_" + dom]
     achieved = dom_flops / (s32[dom] * 1e-3) / 1e12

@@ -484,8 +484,12 @@ bsdmrg_status bsdmrg_dense_apply(bsdmrg_op_t op, int32_t precision, const double
  * average duration in milliseconds per launch to ms[5] = {WW coefficients,
  * S1 grouped GEMM, S2 MPO mixing, S3 grouped GEMM (split-K pieces), S3
  * fixed-order sum of the split-K pieces}.  Same arguments and results as
- * bsdmrg_heff_apply (out holds the product afterwards).  Synchronises the
- * stream.  Errors: EINVAL, EHIP. */
+ * bsdmrg_heff_apply (out holds the product afterwards); precision may also
+ * be BSDMRG_F32_REFINE: the stages as the FP32 phase of a mixed eigensolve
+ * runs them (FP32 products: S3 and its sum write FP32 results into out
+ * while they are timed), the product afterwards as with BSDMRG_F32 (the
+ * padding of out is then zero).
+ * Synchronises the stream.  Errors: EINVAL, EHIP. */
 bsdmrg_status bsdmrg_stage_timing(bsdmrg_plan_t plan, int32_t precision, const double* L,
                                   const double* W1, const double* W2, const double* R,
                                   const double* psi, double* out, void* workspace,

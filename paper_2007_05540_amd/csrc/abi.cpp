@@ -865,10 +865,14 @@ bsdmrg_status bsdmrg_stage_timing(bsdmrg_plan_t P, int32_t precision, const doub
   hipEvent_t ev[2] = {nullptr, nullptr};
   bsdmrg_status st = guarded([&] {
     need_device(P);
-    if (precision != BSDMRG_F64 && precision != BSDMRG_F32)
-      throw Error{BSDMRG_EINVAL, "stage_timing: precision must be F64 or F32"};
+    if (precision != BSDMRG_F64 && precision != BSDMRG_F32 && precision != BSDMRG_F32_REFINE)
+      throw Error{BSDMRG_EINVAL, "stage_timing: precision must be F64, F32 or F32_REFINE"};
     if (!L || !W1 || !W2 || !R || !psi || !out || !ms || reps < 1)
       throw Error{BSDMRG_EINVAL, "stage_timing: bad arguments"};
+    // F32_REFINE: the stages as the FP32 phase of a mixed eigensolve runs
+    // them (S3 and its split-K sum write FP32 products, here into out)
+    const bool solve32 = precision == BSDMRG_F32_REFINE;
+    if (solve32) precision = BSDMRG_F32;
     check_ws(workspace, workspace_bytes, apply_bytes(P));
     Carve c(workspace, (size_t)workspace_bytes);
     ApplyWS w = carve_apply(P, c);
@@ -881,7 +885,10 @@ bsdmrg_status bsdmrg_stage_timing(bsdmrg_plan_t P, int32_t precision, const doub
       HIPCHK(hipEventRecord(ev[0], s));
       for (int r = 0; r < reps; ++r) {
         if (stage == 0) HIPCHK(launch_coef(P, W1, W2, w.coef, s));
-        if (stage == 4) HIPCHK(launch_s3_reduce(P, w.part, out, precision == BSDMRG_F32, s));
+        if (stage == 4) {
+          if (solve32) HIPCHK(launch_s3_reduce_out32(P, w.part, (float*)out, s));
+          else HIPCHK(launch_s3_reduce(P, w.part, out, precision == BSDMRG_F32, s));
+        }
         if (precision == BSDMRG_F64) {
           if (stage == 1) HIPCHK(launch_s1_f64(P, L, psi, w.T1, s));
           if (stage == 2) HIPCHK(launch_mix_f64(P, w.coef, w.T1, w.T2, s));
@@ -889,7 +896,10 @@ bsdmrg_status bsdmrg_stage_timing(bsdmrg_plan_t P, int32_t precision, const doub
         } else {
           if (stage == 1) HIPCHK(launch_s1_f32(P, w.L32, psi, T1f, s));
           if (stage == 2) HIPCHK(launch_mix_f32(P, w.coef, T1f, T2f, s));
-          if (stage == 3) HIPCHK(launch_s3_gemm_f32(P, T2f, w.R32, out, w.part, s));
+          if (stage == 3) {
+            if (solve32) HIPCHK(launch_s3_gemm_f32_out32(P, T2f, w.R32, (float*)out, w.part, s));
+            else HIPCHK(launch_s3_gemm_f32(P, T2f, w.R32, out, w.part, s));
+          }
         }
       }
       HIPCHK(hipEventRecord(ev[1], s));
@@ -897,6 +907,13 @@ bsdmrg_status bsdmrg_stage_timing(bsdmrg_plan_t P, int32_t precision, const doub
       float t = 0.f;
       HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
       ms[stage] = t / reps;
+    }
+    if (solve32) {
+      // out holds FP32 products, also where it has padding, which a product
+      // leaves unwritten: cleared, then the FP32 product as with F32
+      HIPCHK(dav_fill_zero(out, P->psi_elems, s));
+      matvec(P, BSDMRG_F32, L, R, w, psi, out, s);
+      HIPCHK(hipStreamSynchronize(s));
     }
   });
   for (auto e : ev)

@@ -25,6 +25,9 @@ hipError_t launch_s3_gemm_f32(const bsdmrg_plan_s* P, const float* T2, const flo
 // Davidson solve), split-K pieces summed
 hipError_t launch_s3_f32_out32(const bsdmrg_plan_s* P, const float* T2, const float* R, float* out, double* part,
                                hipStream_t s);
+hipError_t launch_s3_gemm_f32_out32(const bsdmrg_plan_s* P, const float* T2, const float* R, float* out,
+                                    double* part, hipStream_t s);
+hipError_t launch_s3_reduce_out32(const bsdmrg_plan_s* P, const double* part, float* out, hipStream_t s);
 // f32_parts: the partials were written by the FP32 S3 launch (FP32 values in
 // the partial buffer); else FP64 partials.
 hipError_t launch_s3_reduce(const bsdmrg_plan_s* P, const double* part, double* out, bool f32_parts,

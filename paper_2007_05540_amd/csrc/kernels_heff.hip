@@ -825,9 +825,17 @@ hipError_t launch_s3_gemm_f32(const bsdmrg_plan_s* P, const float* T2, const flo
 }
 hipError_t launch_s3_f32_out32(const bsdmrg_plan_s* P, const float* T2, const float* R, float* out, double* part,
                                hipStream_t s) {
-  float* pf = (float*)part;
-  hipError_t e = launch_stage<float, float, float, float, true>(P->s3, T2, R, out, pf, s);
-  if (e != hipSuccess || P->red_items.empty()) return e;
+  hipError_t e = launch_s3_gemm_f32_out32(P, T2, R, out, part, s);
+  if (e != hipSuccess) return e;
+  return launch_s3_reduce_out32(P, part, out, s);
+}
+hipError_t launch_s3_gemm_f32_out32(const bsdmrg_plan_s* P, const float* T2, const float* R, float* out,
+                                    double* part, hipStream_t s) {
+  return launch_stage<float, float, float, float, true>(P->s3, T2, R, out, (float*)part, s);
+}
+hipError_t launch_s3_reduce_out32(const bsdmrg_plan_s* P, const double* part, float* out, hipStream_t s) {
+  if (P->red_items.empty()) return hipSuccess;
+  const float* pf = (const float*)part;
   if (P->mix_per == 8)
     hipLaunchKernelGGL((split_sum_f32_kernel<8, float>), dim3((unsigned)P->red_items.size()), dim3(NTHR), 0, s,
                        P->d_red_work, P->d_red_terms, pf, out);

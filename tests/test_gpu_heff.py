@@ -210,6 +210,29 @@ def test_apply_deterministic(mods):
     assert torch.equal(outs[0], outs[1]) and torch.equal(outs[2], outs[3])
 
 
+def test_stage_timing_of_the_solve_stages(mods):
+    """bsdmrg_stage_timing with F32_REFINE times the stages as the FP32 phase
+    of a mixed eigensolve runs them (FP32 products: S3 and its split-K sum
+    write FP32 results) and leaves out holding the FP32 product, equal bit for
+    bit to bsdmrg_heff_apply's, as the F32 timing does; an unknown precision
+    is rejected."""
+    lib, problems = mods
+    spec = synth.c2_bond(m=1024, k=14, seed=1)
+    plan, ops, d = setup([spec], lib, problems)
+    info = plan.info()
+    assert info["s3_split_k"] > 0   # the split-K sum is among the timed stages
+    ws = torch.empty(info["apply_workspace_bytes"], dtype=torch.uint8, device="cuda")
+    ref = torch.zeros_like(d["psi"])
+    lib.heff_apply(plan, lib.F32, d["L"], d["W1"], d["W2"], d["R"], d["psi"], ref, ws)
+    for prec in (lib.F32, lib.F32_REFINE):
+        out = torch.zeros_like(d["psi"])
+        ms = lib.stage_timing(plan, prec, d["L"], d["W1"], d["W2"], d["R"], d["psi"], out, ws, reps=2)
+        assert all(ms[k] > 0.0 for k in ("s1", "s2", "s3", "s3_sum"))
+        assert torch.equal(out.cpu(), ref.cpu())
+    with pytest.raises(lib.BsdmrgError):
+        lib.stage_timing(plan, 7, d["L"], d["W1"], d["W2"], d["R"], d["psi"], ref, ws, reps=1)
+
+
 def test_apply_batch_equals_single(mods):
     lib, problems = mods
     specs = [synth.c2_bond(m=m, k=k, seed=s) for m, k, s in [(64, 10, 1), (128, 14, 2), (96, 18, 3)]]
